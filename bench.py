@@ -1,0 +1,198 @@
+"""Benchmark of the EP-HDC client-side path on one MI355X.
+
+One step = one request of the workload: HDC encoding of the queries (int8 MFMA) and
+homomorphic scoring against the device-resident encrypted model (fused batch-encode +
+ct x pt MAC kernel, then reduction + output transform), with every input already in HBM.
+Prints one JSON line (see the keys below).
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_2511_00737_amd as ep  # noqa: E402
+import synth  # noqa: E402
+
+METRIC = "encrypted HDC inferences/sec at N=8192 (batched vs plain GPU); p50/p99 latency"
+
+WORKLOADS = {
+    # small case the oracle finishes in seconds
+    "c1": dict(N=4096, L=3, F=512, D=2048, K=2, Q=64, images=False,
+               desc="BFV N=4096, 3x30-bit limbs, t=65537; HDC F=512 uniform uint8, D=2048, K=2; 64 queries"),
+    # the metric's workload: plain method on the GPU, one request per launch
+    "c2": dict(N=8192, L=4, F=2304, D=4096, K=7, Q=4096, images=True,
+               desc="BFV N=8192, 4x30-bit limbs, t=65537; HDC F=2304 (48x48 Gaussian-blob images), "
+                    "D=4096, K=7; 4096 queries per request, one request per launch"),
+}
+
+# Peak of the integer VALU for 30-bit modular multiplication on MI355X: 256 CUs x 64 lanes
+# x 2.4 GHz = 39.3 T 32-bit multiplies/s; a Shoup modular multiplication needs 3 of them.
+MUL32_PEAK = 256 * 64 * 2.4e9
+MODMUL_PEAK = MUL32_PEAK / 3
+
+
+def algorithmic_modmuls(N: int, L: int, G: int, M: int) -> float:
+    """Modular multiplications of one scoring launch: per plaintext one inverse transform
+    mod t and L forward transforms ((N/2) log2 N butterflies each) plus 2L*N MAC products."""
+    logn = int(math.log2(N))
+    per_pt = (L + 1) * (N // 2) * logn + 2 * L * N
+    return float(G) * M * per_pt
+
+
+def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np.ndarray, sample_m: int):
+    """The oracle, timed on the host: HDC encoding of a few queries and the MAC of query
+    group 0 over the first `sample_m` model ciphertexts, scaled to inferences/s."""
+    from oracle import bfv, hdc
+    from oracle.params import Params as OParams
+    o = OParams(N=prm.N, q=tuple(prm.q), F=prm.F, D=prm.D, K=prm.K)
+    s = bfv.secret_key(o, 0)
+    osub = OParams(N=prm.N, q=tuple(prm.q), F=prm.F, D=sample_m, K=prm.K)
+    model = bfv.encrypt_model(osub, s, C[:, :sample_m], 0)
+    nq = 16
+    t0 = time.perf_counter()
+    h16 = hdc.encode(x[:nq], base)
+    t_hdc = (time.perf_counter() - t0) / nq
+    h = np.zeros((o.B, sample_m), dtype=np.int8)
+    h[:nq] = h16[:, :sample_m]
+    t0 = time.perf_counter()
+    bfv.mac(osub, model, h, 0)
+    t_mac = time.perf_counter() - t0
+    t_group = t_mac * o.M / sample_m + t_hdc * o.B
+    return {"value": o.B / t_group, "unit": "inferences/s", "cores": 1, "kind": "oracle",
+            "sample": f"HDC encoding of {nq} queries and the ct x pt MAC of query group 0 "
+                      f"({o.B} queries) over model ciphertexts 0..{sample_m - 1} of {o.M}, "
+                      f"scaled linearly to the full model; numpy, single thread "
+                      f"(host has {os.cpu_count()} cores)",
+            "seconds": round(t_mac + t_hdc * nq, 2)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-m", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path shards by query group or model slice, "
+              "but no multi-GPU run is part of this benchmark", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    w = WORKLOADS[args.workload]
+    N, L, Q = w["N"], w["L"], w["Q"]
+    q = ep.default_primes(N, L)
+    prm = ep.Params(N=N, q=tuple(q), F=w["F"], D=w["D"], K=w["K"])
+    seed = args.seed
+    t0 = time.perf_counter()
+    x = synth.blob_images(seed, Q) if w["images"] else synth.uniform_features(seed, Q, w["F"])
+    base = synth.base_hypervectors(seed, w["F"], w["D"])
+    C = synth.class_hypervectors(seed, w["K"], w["D"])
+    t_inputs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sk, _ = ep.ephdc_keygen(prm, seed)
+    model = ep.ephdc_encrypt_model(prm, sk, C, seed)
+    t_encrypt = time.perf_counter() - t0
+    print(f"[bench] {args.workload}: inputs {t_inputs:.1f}s, keygen+encrypt {t_encrypt:.1f}s (host)",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda")
+    d_model = torch.from_numpy(model.view(np.int32)).to(dev)
+    sess = ep.Session(prm, d_model, max_Q=Q)
+    del d_model
+    stride = sess.hv_stride(Q)
+    G = sess.num_groups(Q)
+    d_x = torch.from_numpy(x).to(dev)
+    d_base = torch.from_numpy(base).to(dev)
+    d_hv = torch.empty((prm.D, stride), dtype=torch.int8, device=dev)
+    d_out = torch.empty((G, 2, L, N), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        ep.ephdc_encode_queries(sess, d_x, d_base, Q, d_hv)
+        ep.ephdc_score_encrypted(sess, d_hv, Q, d_out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # correctness check of this exact launch configuration: decrypted scores of every
+    # query equal the exact integer similarity (mod t) of the device-computed hypervectors
+    out = d_out.cpu().numpy().view(np.uint32)
+    hv = d_hv.cpu().numpy()[:, :Q].T.astype(np.float64)
+    scores, _ = ep.ephdc_decrypt_scores(prm, sk, out, Q)
+    want = (hv @ C.astype(np.float64).T).astype(np.int64) % 65537
+    want = np.where(want > 32768, want - 65537, want)
+    if not np.array_equal(scores, want):
+        print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
+        return 3
+
+    sess.profile(True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = sess.profile_read()
+    sess.profile(False)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    ms_step = wall * 1e3 / args.steps
+    value = Q * args.steps / wall
+
+    score_ms = prof["score"][0] / max(1, prof["score"][1])
+    modmuls = algorithmic_modmuls(N, L, G, prm.D)
+    achieved = modmuls / (score_ms * 1e-3)
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "inferences/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {w['desc']}", "queries_per_step": Q, "groups": G,
+                   "queries_per_ciphertext": ep.ephdc_queries_per_ct(prm),
+                   "model_ciphertexts": prm.D},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]},
+        "roofline": {"bound": "alu", "kernel": "k_score", "achieved": round(achieved / 1e12, 4),
+                     "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
+                     "frac": round(achieved / MODMUL_PEAK, 4), "traffic": None,
+                     "per_launch_modmuls": modmuls, "avg_launch_ms": round(score_ms, 4)},
+    }
+    sess.close()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

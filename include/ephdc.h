@@ -1,0 +1,213 @@
+/*
+ * ephdc.h - C ABI of the EP-HDC client-side encrypted hyperdimensional inference path
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method (EP-HDC, "client-side HE"): the server encrypts its class hypervectors
+ * once with BFV and ships them; the client encodes its plaintext queries into
+ * hypervectors, batch-encodes every query element into its own plaintext (each value
+ * repeated once per class), multiplies those plaintexts into the encrypted model and
+ * accumulates, and sends one score ciphertext per batch back to the server, which
+ * decrypts the similarity scores and takes the argmax (proposed method: client-side
+ * HE; packing and op counts: D ct x pt products, no rotation).
+ *
+ * Server-side calls (keygen, model encryption, decryption) work on host memory.
+ * Client-side calls work on device memory owned by the caller and are ordered on the
+ * HIP stream passed in (a hipStream_t, given as void*; NULL is the default stream).
+ *
+ * Conventions
+ *  - Every buffer is owned by the caller.  A session copies what it keeps (its own
+ *    transformed copy of the model and keys) and may be used only from one host
+ *    thread at a time.
+ *  - Residues are uint32 in [0, q); polynomials are N coefficients in degree order;
+ *    arrays are C-contiguous with the shapes given below.
+ *  - Errors: argument and parameter errors are returned before any work is queued.
+ *    HIP failures return EPHDC_ERR_HIP.  ephdc_last_error() gives a message for the
+ *    last failing call on the calling thread.
+ *  - Results are bit-exact functions of the inputs: independent of stream, batch
+ *    composition and kernel schedule.
+ */
+#ifndef EPHDC_H
+#define EPHDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EPHDC_OK = 0,
+  EPHDC_ERR_ARG = 1,         /* null pointer, size out of range */
+  EPHDC_ERR_PARAMS = 2,      /* parameter set fails validation (see ephdc_check_params) */
+  EPHDC_ERR_BUFFER = 3,      /* a caller buffer is too small */
+  EPHDC_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+  EPHDC_ERR_NOKEY = 5,       /* rotations needed (r > 1) but no Galois keys were given */
+  EPHDC_ERR_OOM = 6,         /* device allocation failed */
+  EPHDC_ERR_UNSUPPORTED = 7  /* valid parameters outside what the kernels implement */
+} ephdc_status;
+
+/*
+ * BFV + HDC parameters (symbols of the paper's table of symbols: N polynomial degree,
+ * log2 t message bits, D hypervector dimension, K = k classes).
+ *
+ *   N      ring degree; the kernels implement N in {4096, 8192, 16384}
+ *   L      number of ciphertext primes q[0..L-1], 1 <= L <= 16
+ *   alpha  number of special primes p[0..alpha-1] used only by key switching
+ *   dnum   key-switching digits (limb groups of ceil(L/dnum) primes); 0 when r == 1
+ *   q, p   the primes: distinct, prime, < 2^30, and = 1 (mod 2N)
+ *   t      plaintext modulus; must be 65537
+ *   F      features per query; D hypervector dimension; K classes
+ *   r      fold factor (power of two): r consecutive dimensions share one ciphertext,
+ *          in r blocks of W = N/(2r) slots per row; log2(r) rotate-and-sum steps fold
+ *          them (r = 1 is the paper's packing and needs no rotation)
+ *   qbits  1: binarised queries (+1 / -1); 2..8: clamp(H >> qshift) to qbits signed bits
+ *
+ * Derived: Bq = floor(W/K) queries per row, B = 2*Bq queries per ciphertext,
+ * M = ceil(D/r) model ciphertexts, G = ceil(Q/B) score ciphertexts for Q queries.
+ */
+typedef struct {
+  uint32_t N, L, alpha, dnum;
+  const uint32_t* q;
+  const uint32_t* p;
+  uint32_t t;
+  uint32_t F, D, K, r;
+  uint32_t qbits, qshift;
+} ephdc_params;
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* ephdc_last_error(void);
+
+/* Validates a parameter set: EPHDC_OK, or EPHDC_ERR_PARAMS with a message. */
+ephdc_status ephdc_check_params(const ephdc_params* prm);
+
+/* Derived sizes (0 on invalid parameters). */
+uint32_t ephdc_queries_per_ct(const ephdc_params* prm);            /* B */
+uint32_t ephdc_num_model_ct(const ephdc_params* prm);              /* M */
+uint32_t ephdc_num_groups(const ephdc_params* prm, uint32_t Q);    /* G */
+uint32_t ephdc_hv_stride(const ephdc_params* prm, uint32_t Q);     /* G*B: row length of the hv array */
+size_t   ephdc_galois_key_words(const ephdc_params* prm);          /* log2(r)*dnum*2*(L+alpha)*N */
+
+/* The `count` largest primes below 2^30 that are 1 mod 2N, after skipping `skip`, descending. */
+ephdc_status ephdc_default_primes(uint32_t N, uint32_t count, uint32_t skip, uint32_t* out);
+
+/* The discrete-Gaussian cumulative table used by the samplers: 39 thresholds T_{-19}..T_{19}
+ * (sigma = 3.2, support [-19, 19]; T_k = round(2^53 * P[e <= k]), T_19 = 2^53). */
+ephdc_status ephdc_gaussian_cdt(uint64_t out[39]);
+
+/* ------------------------------------------------------------------ server side (host memory) */
+
+/*
+ * Secret key and Galois (rotation) keys.  Server side of the protocol: the server owns
+ * the key and encrypts with it (BFV with a given secret key, Preliminary: HE).
+ *   sk           out, int8 [N], ternary {-1, 0, 1}; draws 0..N-1 of SplitMix64 stream
+ *                (seed, tag 4), value (u mod 3) - 1
+ *   galois_keys  out, uint32 [log2 r][dnum][2][L+alpha][N], coefficient domain, limbs in
+ *                the order q[0..L-1], p[0..alpha-1]; component 0 is b, 1 is a.  May be NULL
+ *                when r == 1.  Key (i, j) switches from sigma_g(s), g = 3^(W*2^i) mod 2N,
+ *                to s for digit j: b = -a*s + e + G_j*sigma_g(s), G_j = P (product of the
+ *                special primes) on the digit's limbs and 0 on all others; a uniform per
+ *                limb and e discrete Gaussian from stream (seed, tag 6), draws starting at
+ *                ((i*dnum + j) * (L+alpha+1)) * N.
+ */
+ephdc_status ephdc_keygen(const ephdc_params* prm, uint64_t seed, int8_t* sk, uint32_t* galois_keys);
+
+/*
+ * Encrypts the model: class hypervectors C int8 [K][D] -> M ciphertexts.
+ * Server side, done once; the ciphertexts are sent to the client (proposed method).
+ *   model_ct  out, uint32 [M][2][L][N], coefficient domain.
+ * Ciphertext m encodes the slot vector with C[c][m*r+u] at every query position of block u
+ * (the class HV replicated into every query slot) and is the secret-key encryption
+ * ([-a*s + e + Delta*mu]_q, a), Delta = floor(Q/t), with a uniform per limb and e
+ * discrete Gaussian drawn from stream (seed, tag 5) starting at m*(L+1)*N.
+ */
+ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, const int8_t* class_hv,
+                                 uint64_t seed, uint32_t* model_ct);
+
+/*
+ * Decrypts G = ceil(Q/B) score ciphertexts uint32 [G][2][L][N] (coefficient domain) and
+ * reads the similarity scores: scores int32 [Q][K], each the centred residue mod t of the
+ * integer dot product h . C[c], and argmax int32 [Q] (ties to the lowest class); argmax
+ * may be NULL.  Server side (proposed method: the server sees only the scores).
+ */
+ephdc_status ephdc_decrypt_scores(const ephdc_params* prm, const int8_t* sk, const uint32_t* score_ct,
+                                  uint32_t Q, int32_t* scores, int32_t* argmax);
+
+/* ------------------------------------------------------------------ client side (device memory) */
+
+typedef struct ephdc_session ephdc_session;
+
+/*
+ * Creates a client session on the current HIP device: copies the encrypted model
+ * (device pointer, uint32 [M][2][L][N], coefficient domain, model_words entries) into a
+ * device-resident evaluation-domain copy owned by the session, and likewise the Galois
+ * keys (device pointer, layout of ephdc_keygen, gk_words entries; required when r > 1,
+ * else may be NULL).  A buffer shorter than its layout needs gives EPHDC_ERR_BUFFER.
+ * max_Q bounds the batch size of later calls (sizes the session's scratch space).  The
+ * call is synchronous with respect to `stream`.
+ */
+ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
+                                  const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q, void* stream,
+                                  ephdc_session** out);
+ephdc_status ephdc_session_destroy(ephdc_session* s);
+/* Device bytes the session holds (model, keys, tables, scratch). */
+size_t ephdc_session_device_bytes(const ephdc_session* s);
+
+/*
+ * HDC encoding (random projection + quantisation, Preliminary: HDC encoding):
+ *   d_x     uint8 [Q][F] features, read as (x - 128)
+ *   d_base  int8 [F][D] base hypervectors
+ *   d_hv    out, int8 [D][ephdc_hv_stride(Q)] query hypervectors, dimension-major;
+ *           entry [j][q] = sign or Q-bit quantisation of sum_f (x[q][f]-128)*base[f][j],
+ *           and 0 for the padding queries q >= Q.
+ * Requires F % 16 == 0 and D % 64 == 0 (else EPHDC_ERR_UNSUPPORTED).  int8 MFMA on gfx950.
+ */
+ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const int8_t* d_base,
+                                  uint32_t Q, int8_t* d_hv, void* stream);
+
+/*
+ * Homomorphic scoring of Q query hypervectors (d_hv as written by ephdc_encode_queries,
+ * stride ephdc_hv_stride(Q)) against the encrypted model: for every group g of B queries
+ * and every model ciphertext m, batch-encode the query plaintext (slot scatter and
+ * inverse transform mod t, centred lift), multiply it into ciphertext m and accumulate;
+ * when r > 1, fold the r blocks with log2(r) rotate-and-sum steps (Galois automorphism
+ * and hybrid key switching).
+ *   d_score_ct  out, uint32 [G][2][L][N], coefficient domain: the client -> server message.
+ * Q must be <= the session's max_Q.  Asynchronous on `stream`.
+ */
+ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_t Q,
+                                   uint32_t* d_score_ct, void* stream);
+
+/*
+ * Debug: the lifted plaintext of query group g and model index m, reduced into every
+ * limb, uint32 [L][N] coefficient domain (the centred representative of
+ * Encode(slot vector) in (-t/2, t/2], mod q_l).  Exposes the batch-encoding step alone.
+ */
+ephdc_status ephdc_debug_plaintext(ephdc_session* s, const int8_t* d_hv, uint32_t Q, uint32_t g,
+                                   uint32_t m, uint32_t* d_out, void* stream);
+
+/*
+ * Debug: negacyclic products d_out[i] = d_a[i] * d_b[i] mod (X^N + 1, q_l), for `count`
+ * polynomial pairs uint32 [count][N] with pair i taken mod q[i % L] of the session's
+ * primes.  Runs the same forward / inverse transforms as the scoring path.
+ */
+ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const uint32_t* d_b,
+                                 uint32_t count, uint32_t* d_out, void* stream);
+
+/*
+ * Kernel timing (diagnostics for benchmarks).  While enabled, every kernel launched by the
+ * session is bracketed by HIP events recorded on the stream it runs on.  Reading waits for
+ * the recorded events, returns per-stage totals and resets them:
+ *   ms[0], count[0]  fused batch-encode + MAC kernel (k_score)
+ *   ms[1], count[1]  partial-sum reduction + output inverse transform (k_finish)
+ *   ms[2], count[2]  HDC encoding kernel (k_hdc_encode)
+ *   ms[3], count[3]  rotate-and-sum kernels (automorphism, key switching)
+ */
+ephdc_status ephdc_session_profile(ephdc_session* s, int enable);
+ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[4], uint64_t count[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPHDC_H */

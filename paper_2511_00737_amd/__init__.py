@@ -1,0 +1,315 @@
+"""Python binding of libephdc: EP-HDC client-side encrypted HDC inference on MI355X.
+
+A thin ctypes layer over the C ABI declared in include/ephdc.h.  Every entry point keeps
+its C name and only marshals arguments: host arrays are numpy, device buffers are torch
+tensors on the current HIP device (PyTorch is used for device memory and streams only).
+All computation happens in the library's host C++ (server side) or HIP kernels (client
+side).  Importing this module does not load the library; the first call does, and it
+raises if the library has not been built (python -m paper_2511_00737_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libephdc.so")
+
+OK, ERR_ARG, ERR_PARAMS, ERR_BUFFER, ERR_HIP, ERR_NOKEY, ERR_OOM, ERR_UNSUPPORTED = range(8)
+T_PLAIN = 65537
+
+
+class EphdcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ephdc status {status}: {msg}")
+        self.status = status
+
+
+class _CParams(C.Structure):
+    _fields_ = [("N", C.c_uint32), ("L", C.c_uint32), ("alpha", C.c_uint32), ("dnum", C.c_uint32),
+                ("q", C.POINTER(C.c_uint32)), ("p", C.POINTER(C.c_uint32)), ("t", C.c_uint32),
+                ("F", C.c_uint32), ("D", C.c_uint32), ("K", C.c_uint32), ("r", C.c_uint32),
+                ("qbits", C.c_uint32), ("qshift", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library (fails loudly when it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2511_00737_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(_CParams)
+        u32p, i8p, u8p, i32p, u64p = (C.POINTER(C.c_uint32), C.POINTER(C.c_int8), C.POINTER(C.c_uint8),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_uint64))
+        sig = {
+            "ephdc_last_error": (C.c_char_p, []),
+            "ephdc_check_params": (C.c_int, [P]),
+            "ephdc_queries_per_ct": (C.c_uint32, [P]),
+            "ephdc_num_model_ct": (C.c_uint32, [P]),
+            "ephdc_num_groups": (C.c_uint32, [P, C.c_uint32]),
+            "ephdc_hv_stride": (C.c_uint32, [P, C.c_uint32]),
+            "ephdc_galois_key_words": (C.c_size_t, [P]),
+            "ephdc_default_primes": (C.c_int, [C.c_uint32, C.c_uint32, C.c_uint32, u32p]),
+            "ephdc_gaussian_cdt": (C.c_int, [u64p]),
+            "ephdc_keygen": (C.c_int, [P, C.c_uint64, i8p, u32p]),
+            "ephdc_encrypt_model": (C.c_int, [P, i8p, i8p, C.c_uint64, u32p]),
+            "ephdc_decrypt_scores": (C.c_int, [P, i8p, u32p, C.c_uint32, i32p, i32p]),
+            "ephdc_session_create": (C.c_int, [P, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_uint32,
+                                               C.c_void_p, C.POINTER(C.c_void_p)]),
+            "ephdc_session_destroy": (C.c_int, [C.c_void_p]),
+            "ephdc_session_device_bytes": (C.c_size_t, [C.c_void_p]),
+            "ephdc_encode_queries": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                               C.c_void_p]),
+            "ephdc_score_encrypted": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+            "ephdc_debug_plaintext": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
+                                                C.c_void_p, C.c_void_p]),
+            "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                              C.c_void_p]),
+            "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
+            "ephdc_session_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), u64p]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int) -> None:
+    if st != OK:
+        raise EphdcError(st, lib().ephdc_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+# ------------------------------------------------------------------ parameters
+@dataclass
+class Params:
+    """The ephdc_params struct (see include/ephdc.h)."""
+    N: int
+    q: tuple
+    F: int
+    D: int
+    K: int
+    r: int = 1
+    p: tuple = ()
+    dnum: int = 0
+    t: int = T_PLAIN
+    qbits: int = 1
+    qshift: int = 0
+    _keep: list = field(default_factory=list, repr=False, compare=False)
+
+    @property
+    def L(self) -> int:
+        return len(self.q)
+
+    @property
+    def alpha(self) -> int:
+        return len(self.p)
+
+    def c(self) -> _CParams:
+        qa = (C.c_uint32 * max(1, len(self.q)))(*self.q)
+        pa = (C.c_uint32 * max(1, len(self.p)))(*self.p)
+        self._keep[:] = [qa, pa]
+        return _CParams(self.N, len(self.q), len(self.p), self.dnum, qa, pa, self.t, self.F, self.D, self.K,
+                        self.r, self.qbits, self.qshift)
+
+
+def default_primes(N: int, count: int, skip: int = 0) -> list[int]:
+    out = np.zeros(count, dtype=np.uint32)
+    _check(lib().ephdc_default_primes(N, count, skip, _ptr(out, C.c_uint32)))
+    return [int(x) for x in out]
+
+
+def ephdc_check_params(prm: Params) -> int:
+    c = prm.c()
+    return lib().ephdc_check_params(C.byref(c))
+
+
+def ephdc_queries_per_ct(prm: Params) -> int:
+    c = prm.c()
+    return lib().ephdc_queries_per_ct(C.byref(c))
+
+
+def ephdc_num_model_ct(prm: Params) -> int:
+    c = prm.c()
+    return lib().ephdc_num_model_ct(C.byref(c))
+
+
+def ephdc_num_groups(prm: Params, Q: int) -> int:
+    c = prm.c()
+    return lib().ephdc_num_groups(C.byref(c), Q)
+
+
+def ephdc_hv_stride(prm: Params, Q: int) -> int:
+    c = prm.c()
+    return lib().ephdc_hv_stride(C.byref(c), Q)
+
+
+def ephdc_galois_key_words(prm: Params) -> int:
+    c = prm.c()
+    return lib().ephdc_galois_key_words(C.byref(c))
+
+
+def ephdc_gaussian_cdt() -> list[int]:
+    out = np.zeros(39, dtype=np.uint64)
+    _check(lib().ephdc_gaussian_cdt(_ptr(out, C.c_uint64)))
+    return [int(x) for x in out]
+
+
+# ------------------------------------------------------------------ server side (host memory)
+def ephdc_keygen(prm: Params, seed: int):
+    """(sk int8 [N], galois_keys uint32 [log2 r][dnum][2][L+alpha][N] or None)."""
+    c = prm.c()
+    sk = np.zeros(prm.N, dtype=np.int8)
+    nwords = lib().ephdc_galois_key_words(C.byref(c)) if prm.r > 1 else 0
+    gk = np.zeros(nwords, dtype=np.uint32) if nwords else None
+    _check(lib().ephdc_keygen(C.byref(c), seed, _ptr(sk, C.c_int8),
+                              _ptr(gk, C.c_uint32) if gk is not None else None))
+    if gk is not None:
+        logr = prm.r.bit_length() - 1
+        gk = gk.reshape(logr, prm.dnum, 2, prm.L + prm.alpha, prm.N)
+    return sk, gk
+
+
+def ephdc_encrypt_model(prm: Params, sk: np.ndarray, class_hv: np.ndarray, seed: int) -> np.ndarray:
+    """Model ciphertexts uint32 [M][2][L][N], coefficient domain."""
+    c = prm.c()
+    M = lib().ephdc_num_model_ct(C.byref(c))
+    out = np.zeros((M, 2, prm.L, prm.N), dtype=np.uint32)
+    sk = np.ascontiguousarray(sk, dtype=np.int8)
+    chv = np.ascontiguousarray(class_hv, dtype=np.int8)
+    _check(lib().ephdc_encrypt_model(C.byref(c), _ptr(sk, C.c_int8), _ptr(chv, C.c_int8), seed,
+                                     _ptr(out, C.c_uint32)))
+    return out
+
+
+def ephdc_decrypt_scores(prm: Params, sk: np.ndarray, score_ct: np.ndarray, Q: int):
+    """(scores int32 [Q][K], argmax int32 [Q])."""
+    c = prm.c()
+    sc = np.zeros((Q, prm.K), dtype=np.int32)
+    am = np.zeros(Q, dtype=np.int32)
+    sk = np.ascontiguousarray(sk, dtype=np.int8)
+    cts = np.ascontiguousarray(score_ct, dtype=np.uint32)
+    _check(lib().ephdc_decrypt_scores(C.byref(c), _ptr(sk, C.c_int8), _ptr(cts, C.c_uint32), Q,
+                                      _ptr(sc, C.c_int32), _ptr(am, C.c_int32)))
+    return sc, am
+
+
+# ------------------------------------------------------------------ client side (device memory)
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dptr(t, nbytes: int | None = None) -> int:
+    """Device address of a contiguous CUDA tensor holding at least `nbytes` bytes."""
+    if not (t.is_cuda and t.is_contiguous()):
+        raise EphdcError(ERR_ARG, "expected a contiguous device tensor")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise EphdcError(ERR_BUFFER, f"device buffer holds {t.numel() * t.element_size()} bytes, needs {nbytes}")
+    return t.data_ptr()
+
+
+def _words(t) -> int:
+    return t.numel() * t.element_size() // 4
+
+
+class Session:
+    """Owns an ephdc_session: device-resident evaluation-domain model and keys."""
+
+    def __init__(self, prm: Params, d_model_ct, d_galois_keys=None, max_Q: int = 4096, stream=None):
+        self.prm = prm
+        self._c = prm.c()
+        h = C.c_void_p()
+        gk_ptr = _dptr(d_galois_keys) if d_galois_keys is not None else None
+        gk_words = _words(d_galois_keys) if d_galois_keys is not None else 0
+        _check(lib().ephdc_session_create(C.byref(self._c), _dptr(d_model_ct), _words(d_model_ct), gk_ptr,
+                                          gk_words, max_Q, _stream(stream), C.byref(h)))
+        self.handle = h
+        self.max_Q = max_Q
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib().ephdc_session_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self) -> int:
+        return lib().ephdc_session_device_bytes(self.handle)
+
+    def profile(self, enable: bool = True) -> None:
+        """Bracket every kernel launch with HIP events on its stream (see ephdc_session_profile)."""
+        _check(lib().ephdc_session_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} for score, finish, encode, rotate; resets the totals."""
+        ms = (C.c_double * 4)()
+        cnt = np.zeros(4, dtype=np.uint64)
+        _check(lib().ephdc_session_profile_read(self.handle, ms, _ptr(cnt, C.c_uint64)))
+        names = ("score", "finish", "encode", "rotate")
+        return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(names)}
+
+    def hv_stride(self, Q: int) -> int:
+        return lib().ephdc_hv_stride(C.byref(self._c), Q)
+
+    def num_groups(self, Q: int) -> int:
+        return lib().ephdc_num_groups(C.byref(self._c), Q)
+
+
+def ephdc_session_create(prm: Params, d_model_ct, d_galois_keys=None, max_Q: int = 4096, stream=None) -> Session:
+    return Session(prm, d_model_ct, d_galois_keys, max_Q, stream)
+
+
+def ephdc_session_destroy(s: Session) -> None:
+    s.close()
+
+
+def _sizes(s: Session, Q: int):
+    p = s.prm
+    stride = s.hv_stride(Q)
+    return stride, p.D * stride, s.num_groups(Q) * 2 * p.L * p.N * 4
+
+
+def ephdc_encode_queries(s: Session, d_x, d_base, Q: int, d_hv, stream=None) -> None:
+    p = s.prm
+    _, hv_bytes, _ = _sizes(s, Q)
+    _check(lib().ephdc_encode_queries(s.handle, _dptr(d_x, Q * p.F), _dptr(d_base, p.F * p.D), Q,
+                                      _dptr(d_hv, hv_bytes), _stream(stream)))
+
+
+def ephdc_score_encrypted(s: Session, d_hv, Q: int, d_score_ct, stream=None) -> None:
+    _, hv_bytes, out_bytes = _sizes(s, Q)
+    _check(lib().ephdc_score_encrypted(s.handle, _dptr(d_hv, hv_bytes), Q, _dptr(d_score_ct, out_bytes),
+                                       _stream(stream)))
+
+
+def ephdc_debug_plaintext(s: Session, d_hv, Q: int, g: int, m: int, d_out, stream=None) -> None:
+    p = s.prm
+    _, hv_bytes, _ = _sizes(s, Q)
+    _check(lib().ephdc_debug_plaintext(s.handle, _dptr(d_hv, hv_bytes), Q, g, m, _dptr(d_out, p.L * p.N * 4),
+                                       _stream(stream)))
+
+
+def ephdc_debug_polymul(s: Session, d_a, d_b, count: int, d_out, stream=None) -> None:
+    nb = count * s.prm.N * 4
+    _check(lib().ephdc_debug_polymul(s.handle, _dptr(d_a, nb), _dptr(d_b, nb), count, _dptr(d_out, nb),
+                                     _stream(stream)))

@@ -1,0 +1,357 @@
+// HIP kernels of the scoring path: batched transforms, the fused batch-encode + ct x pt
+// multiply-accumulate kernel, the partial-sum reduction and the debug entry kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "device_ntt.hpp"
+#include "launch.hpp"
+
+namespace ephdc_dev {
+
+// ------------------------------------------------------------------ batched transforms
+// One workgroup per polynomial; polynomial `poly` is taken mod modulus limb_base + poly % nlimb.
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t* __restrict__ in,
+                                                                   uint32_t* __restrict__ out,
+                                                                   const uint2* __restrict__ fwd_tw,
+                                                                   const PrimeConst* __restrict__ pcs,
+                                                                   uint32_t nlimb, uint32_t limb_base, int mont) {
+  using S = Shape<LOGN, LE>;
+  extern __shared__ uint32_t lds[];
+  const int tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
+  const PrimeConst pc = pcs[limb];
+  const uint32_t* src = in + poly * S::N;
+  uint32_t v[S::E];
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) v[i] = src[tid + i * S::T];
+  LdsPair lp{lds, lds + S::PADN, 0};
+  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)limb * S::N, pc.m, lp);
+  uint32_t* dst = out + poly * S::N + (size_t)tid * S::E;
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) {
+    uint32_t x = reduce4(v[i], pc.m);
+    if (mont) x = csub(mont_mul(x, pc.r2, pc.m, pc.mneg_inv), pc.m);
+    dst[i] = x;
+  }
+}
+
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_inv_batch(const uint32_t* __restrict__ in,
+                                                                   uint32_t* __restrict__ out,
+                                                                   const uint2* __restrict__ inv_tw,
+                                                                   const PrimeConst* __restrict__ pcs,
+                                                                   uint32_t nlimb, uint32_t limb_base) {
+  using S = Shape<LOGN, LE>;
+  extern __shared__ uint32_t lds[];
+  const int tid = threadIdx.x;
+  const size_t poly = blockIdx.x;
+  const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
+  const PrimeConst pc = pcs[limb];
+  const uint32_t* src = in + poly * S::N + (size_t)tid * S::E;
+  uint32_t v[S::E];
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) v[i] = src[i];
+  LdsPair lp{lds, lds + S::PADN, 0};
+  ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)limb * S::N, pc, lp);
+  uint32_t* dst = out + poly * S::N;
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = csub(v[i], pc.m);
+}
+
+// out = a * b (Montgomery: a in Montgomery form, b plain) mod the polynomial's modulus.
+__global__ void k_pointwise_mont(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                                 uint32_t* __restrict__ out, size_t n, uint32_t N,
+                                 const PrimeConst* __restrict__ pcs, uint32_t nlimb) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const PrimeConst& pc = pcs[(i / N) % nlimb];
+    out[i] = csub(mont_mul(a[i], b[i], pc.m, pc.mneg_inv), pc.m);
+  }
+}
+
+// ------------------------------------------------------------------ batch encoding
+// Slot values of query plaintext (g, m) at this thread's evaluation-side positions
+// tid*E + i, pre-multiplied by N^-1 mod t so the inverse transform needs no final scaling,
+// then the inverse transform mod t: mu in [0, t), coefficient layout tid + i*T.
+template <int LOGN, int LE>
+__device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const int8_t* __restrict__ hvg, uint32_t m,
+                                             const ScoreArgs& a, int tid, LdsPair& lp) {
+  using S = Shape<LOGN, LE>;
+  const uint32_t t = a.pct.m;
+  // the table row is re-read every call (it stays in L1) rather than held in registers
+  const uint32_t* ent = opaque(a.scatter) + tid * S::E;
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) {
+    uint32_t val = 0;
+    const uint32_t e = ent[i];
+    if (e != 0xFFFFFFFFu) {
+      const uint32_t j = m * a.r + (e >> 16);
+      if (j < a.D) {
+        const int h = hvg[j * a.hv_stride + (e & 0xFFFFu)];
+        const uint32_t x = h < 0 ? t + (uint32_t)h : (uint32_t)h;
+        val = mul_shoup(x, a.tninv, a.tninvp, t);
+      }
+    }
+    v[i] = val;
+  }
+  ntt_inverse<LOGN, LE, false>(v, tid, a.inv_t, a.pct, lp);
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
+}
+
+// Centred lift of mu in [0, t) into Z_m: mu if mu <= t/2, else m - (t - mu).
+__device__ __forceinline__ uint32_t lift(uint32_t mu, uint32_t t, uint32_t m) {
+  return mu > (t >> 1) ? m - (t - mu) : mu;
+}
+
+// ------------------------------------------------------------------ fused scoring kernel
+// Work item (split, group g, limb group): for m in the split's range, batch-encode query
+// plaintext (g, m), lift it into each limb of the group, transform it, and accumulate
+// ct_m[c][l] * pt[l] for c in {0, 1}.  Accumulators live in VGPRs for the whole range.
+template <int LOGN, int LE, int LG>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
+  using S = Shape<LOGN, LE>;
+  constexpr int E = S::E, N = S::N;
+  extern __shared__ uint32_t lds[];
+  LdsPair lp{lds, lds + S::PADN, 0};
+  const int tid = threadIdx.x;
+  const uint32_t w = blockIdx.x;
+  const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
+  const uint32_t g = rest % a.G, split = rest / a.G;
+  const uint32_t m0 = split * a.mchunk;
+  const uint32_t m1 = min(a.M, m0 + a.mchunk);
+  const uint32_t l0 = lgi * LG;
+
+  uint32_t acc[2][LG][E];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int li = 0; li < LG; ++li)
+#pragma unroll
+      for (int i = 0; i < E; ++i) acc[c][li][i] = 0;
+
+  const int8_t* hvg = a.hv + (size_t)g * a.B;
+  const uint32_t t = a.pct.m;
+
+  for (uint32_t m = m0; m < m1; ++m) {
+    uint32_t mu[E];
+    encode_query<LOGN, LE>(mu, hvg, m, a, tid, lp);
+#pragma unroll
+    for (int li = 0; li < LG; ++li) {
+      const uint32_t l = l0 + li;
+      const PrimeConst pc = a.pcs[l];
+      uint32_t p[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) p[i] = lift(mu[i], t, pc.m);
+      ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, lp);
+      const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
+      const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
+      const uint32_t m2 = 2 * pc.m;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        acc[0][li][i] = csub(acc[0][li][i] + mont_mul(ct0[i], p[i], pc.m, pc.mneg_inv), m2);
+        acc[1][li][i] = csub(acc[1][li][i] + mont_mul(ct1[i], p[i], pc.m, pc.mneg_inv), m2);
+      }
+    }
+  }
+#pragma unroll
+  for (int li = 0; li < LG; ++li) {
+    const uint32_t l = l0 + li;
+    const uint32_t mm = a.pcs[l].m;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t* dst = a.partial + ((((size_t)g * a.S + split) * 2 + c) * a.L + l) * N + (size_t)tid * E;
+#pragma unroll
+      for (int i = 0; i < E; ++i) dst[i] = csub(acc[c][li][i], mm);
+    }
+  }
+}
+
+// Sum the S partial accumulators of every (g, c, l) (evaluation domain) and either store
+// the sum (for the rotation steps) or transform it straight to the coefficient domain.
+template <int LOGN, int LE, bool INVERT>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish(const uint32_t* __restrict__ partial,
+                                                                uint32_t* __restrict__ out, uint32_t S_,
+                                                                uint32_t L, const uint2* __restrict__ inv_tw,
+                                                                const PrimeConst* __restrict__ pcs) {
+  using S = Shape<LOGN, LE>;
+  extern __shared__ uint32_t lds[];
+  const int tid = threadIdx.x;
+  const uint32_t poly = blockIdx.x;  // (g*2 + c)*L + l
+  const uint32_t l = poly % L, gc = poly / L;
+  const uint32_t c = gc % 2, g = gc / 2;
+  const PrimeConst pc = pcs[l];
+  uint32_t v[S::E];
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) v[i] = 0;
+  for (uint32_t sp = 0; sp < S_; ++sp) {
+    const uint32_t* src = partial + ((((size_t)g * S_ + sp) * 2 + c) * L + l) * S::N + (size_t)tid * S::E;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) v[i] = csub(v[i] + src[i], pc.m);
+  }
+  if constexpr (INVERT) {
+    LdsPair lp{lds, lds + S::PADN, 0};
+    ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)l * S::N, pc, lp);
+    uint32_t* dst = out + (size_t)poly * S::N;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = csub(v[i], pc.m);
+  } else {
+    uint32_t* dst = out + (size_t)poly * S::N + (size_t)tid * S::E;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) dst[i] = v[i];
+  }
+}
+
+// Debug: the lifted query plaintext (g, m) in every limb, coefficient domain [L][N].
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_debug_plaintext(ScoreArgs a, uint32_t g, uint32_t m,
+                                                                         uint32_t* __restrict__ out) {
+  using S = Shape<LOGN, LE>;
+  extern __shared__ uint32_t lds[];
+  LdsPair lp{lds, lds + S::PADN, 0};
+  const int tid = threadIdx.x;
+  uint32_t mu[S::E];
+  encode_query<LOGN, LE>(mu, a.hv + (size_t)g * a.B, m, a, tid, lp);
+  for (uint32_t l = 0; l < a.L; ++l) {
+    const uint32_t qm = a.pcs[l].m;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) out[(size_t)l * S::N + tid + i * S::T] = lift(mu[i], a.pct.m, qm);
+  }
+}
+
+}  // namespace ephdc_dev
+
+// ------------------------------------------------------------------ launchers
+namespace ephdc {
+
+using namespace ephdc_dev;
+
+template <int LOGN, int LE>
+static size_t lds_bytes() {
+  return 2 * sizeof(uint32_t) * Shape<LOGN, LE>::PADN;
+}
+
+// Raises the dynamic-LDS limit of every kernel instantiation once per process.
+template <int LOGN, int LE>
+static hipError_t prepare_shape() {
+  const int bytes = (int)lds_bytes<LOGN, LE>();
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
+  set((const void*)k_fwd_batch<LOGN, LE>);
+  set((const void*)k_inv_batch<LOGN, LE>);
+  set((const void*)k_score<LOGN, LE, 1>);
+  set((const void*)k_score<LOGN, LE, 2>);
+  set((const void*)k_score<LOGN, LE, 3>);
+  set((const void*)k_score<LOGN, LE, 4>);
+  set((const void*)k_finish<LOGN, LE, true>);
+  set((const void*)k_finish<LOGN, LE, false>);
+  set((const void*)k_debug_plaintext<LOGN, LE>);
+  return e;
+}
+
+hipError_t prepare_kernels() {
+  static hipError_t once = [] {
+    hipError_t e = prepare_shape<12, 3>();
+    if (e == hipSuccess) e = prepare_shape<13, 4>();
+    if (e == hipSuccess) e = prepare_shape<14, 4>();
+    return e;
+  }();
+  return once;
+}
+
+// Calls f with the compile-time shape (LOGN, LE) of a supported ring degree.
+template <class F>
+static hipError_t dispatch(int logn, F&& f) {
+  switch (logn) {
+    case 12: return f(std::integral_constant<int, 12>{}, std::integral_constant<int, 3>{});
+    case 13: return f(std::integral_constant<int, 13>{}, std::integral_constant<int, 4>{});
+    case 14: return f(std::integral_constant<int, 14>{}, std::integral_constant<int, 4>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool supported_logn(int logn) { return logn >= 12 && logn <= 14; }
+
+int max_limb_group(int logn) { return logn == 14 ? 1 : 4; }
+
+hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
+                            const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
+                            hipStream_t st) {
+  if (npolys == 0) return hipSuccess;
+  return dispatch(logn, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const size_t sh = lds_bytes<LN, LEv>();
+    k_fwd_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(in, out, tw, pcs, nlimb,
+                                                                                      limb_base, mont ? 1 : 0);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* itw,
+                            const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st) {
+  if (npolys == 0) return hipSuccess;
+  return dispatch(logn, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const size_t sh = lds_bytes<LN, LEv>();
+    k_inv_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(in, out, itw, pcs, nlimb,
+                                                                                      limb_base);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n, uint32_t N,
+                                 const PrimeConst* pcs, uint32_t nlimb, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  k_pointwise_mont<<<dim3(blocks), dim3(256), 0, st>>>(a, b, out, n, N, pcs, nlimb);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(int logn, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  return dispatch(logn, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const dim3 grid(nblocks), block(Shape<LN, LEv>::T);
+    const size_t sh = lds_bytes<LN, LEv>();
+    switch (lg) {
+      case 1: k_score<LN, LEv, 1><<<grid, block, sh, st>>>(a); break;
+      case 2: k_score<LN, LEv, 2><<<grid, block, sh, st>>>(a); break;
+      case 3: k_score<LN, LEv, 3><<<grid, block, sh, st>>>(a); break;
+      case 4: k_score<LN, LEv, 4><<<grid, block, sh, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S_,
+                         uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st) {
+  if (G == 0) return hipSuccess;
+  return dispatch(logn, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const dim3 grid(G * 2 * L), block(Shape<LN, LEv>::T);
+    const size_t sh = lds_bytes<LN, LEv>();
+    if (invert)
+      k_finish<LN, LEv, true><<<grid, block, sh, st>>>(partial, out, S_, L, itw, pcs);
+    else
+      k_finish<LN, LEv, false><<<grid, block, sh, st>>>(partial, out, S_, L, itw, pcs);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_debug_plaintext(int logn, const ScoreArgs& a, uint32_t g, uint32_t m, uint32_t* out,
+                                  hipStream_t st) {
+  return dispatch(logn, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const size_t sh = lds_bytes<LN, LEv>();
+    k_debug_plaintext<LN, LEv><<<dim3(1), dim3(Shape<LN, LEv>::T), sh, st>>>(a, g, m, out);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace ephdc

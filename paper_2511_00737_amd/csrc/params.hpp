@@ -1,0 +1,60 @@
+// Parameter validation and the EP-HDC slot layout, shared by the host-side crypto and the
+// session code of the library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ephdc.h"
+#include "host_math.hpp"
+
+namespace ephdc {
+
+// Thread-local error message behind ephdc_last_error().
+void set_error(const std::string& msg);
+ephdc_status fail(ephdc_status st, const std::string& msg);
+
+struct ParamSet {
+  uint32_t N = 0, L = 0, alpha = 0, dnum = 0, t = 0, F = 0, D = 0, K = 0, r = 0;
+  uint32_t qbits = 1, qshift = 0;
+  int logn = 0;
+  std::vector<uint32_t> q, p;  // ciphertext primes, special primes
+
+  uint32_t W() const { return N / (2 * r); }           // block width per row
+  uint32_t Bq() const { return W() / K; }              // queries per row
+  uint32_t B() const { return 2 * Bq(); }              // queries per ciphertext
+  uint32_t M() const { return (D + r - 1) / r; }       // model ciphertexts
+  uint32_t G(uint32_t Q) const { return (Q + B() - 1) / B(); }
+  uint32_t log2r() const { return (uint32_t)ilog2(r); }
+  uint32_t digit_size() const { return dnum ? (L + dnum - 1) / dnum : 0; }
+  uint32_t nmod() const { return L + alpha; }
+  uint32_t modulus(uint32_t i) const { return i < L ? q[i] : p[i - L]; }
+
+  // Validates and fills from the public struct; returns EPHDC_OK or an error (message set).
+  ephdc_status load(const ephdc_params* prm);
+};
+
+// Odd exponent e_s in [0, 2N) of the evaluation point zeta^(e_s) of slot s:
+// 3^s mod 2N for s < N/2, and -3^(s-N/2) mod 2N for the second half.
+std::vector<uint32_t> slot_exponents(uint32_t N);
+
+// Position of slot s in the bit-reversed evaluation order used by every transform of the
+// library (position x holds the value at zeta^(2*brev(x)+1)).
+std::vector<uint32_t> slot_positions(uint32_t N);
+
+// For every transform position x: which query slot feeds it, packed as
+// (query index inside the group) | (block u << 16), or 0xFFFFFFFF for a zero slot.
+std::vector<uint32_t> query_scatter_table(const ParamSet& P);
+
+// Slot index of (row rho, block u, query ql, class c).
+inline uint32_t slot_index(const ParamSet& P, uint32_t rho, uint32_t u, uint32_t ql, uint32_t c) {
+  return rho * (P.N / 2) + u * P.W() + ql * P.K + c;
+}
+
+// Galois element of rotate-and-sum step i: 3^(W * 2^i) mod 2N.
+inline uint32_t galois_element(const ParamSet& P, uint32_t i) {
+  return (uint32_t)powmod64(3, (uint64_t)P.W() << i, 2ull * P.N);
+}
+
+}  // namespace ephdc

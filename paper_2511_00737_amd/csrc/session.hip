@@ -1,0 +1,353 @@
+// Client side of the C ABI: sessions (device-resident evaluation-domain model, keys and
+// tables), HDC encoding and homomorphic scoring.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "launch.hpp"
+#include "params.hpp"
+
+using namespace ephdc;
+
+struct ephdc_session {
+  ParamSet P;
+  int device = 0;
+  uint32_t max_Q = 0;
+  uint32_t lg = 1, nlg = 1;        // limbs per fused work item, number of limb groups
+  // device memory owned by the session
+  uint2* d_fwd = nullptr;          // [nmod][N]
+  uint2* d_inv = nullptr;          // [nmod][N]
+  uint2* d_inv_t = nullptr;        // [N]
+  PrimeConst* d_pc = nullptr;      // [nmod]
+  uint32_t* d_scatter = nullptr;   // [N]
+  uint32_t* d_model = nullptr;     // [M][2][L][N] evaluation domain, Montgomery form
+  uint32_t* d_gk = nullptr;        // [log2r][dnum][2][nmod][N] evaluation domain, Montgomery form
+  uint32_t* d_partial = nullptr;   // scratch: partial accumulators
+  size_t partial_words = 0;
+  PrimeConst pct{};
+  uint32_t tninv = 0, tninvp = 0;
+  size_t device_bytes = 0;
+  // kernel timing: pairs of events per stage, resolved when read
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+};
+
+namespace {
+
+constexpr uint32_t kTargetBlocks = 256;  // one 1024-thread workgroup per CU on MI355X
+
+ephdc_status hip_fail(hipError_t e, const char* what) {
+  return fail(EPHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+template <class T>
+ephdc_status dev_alloc(ephdc_session* s, T** p, size_t count, const char* what) {
+  if (count == 0) { *p = nullptr; return EPHDC_OK; }
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(EPHDC_ERR_OOM, std::string("hipMalloc failed for ") + what);
+  }
+  s->device_bytes += count * sizeof(T);
+  return EPHDC_OK;
+}
+
+void drop_events(ephdc_session* s) {
+  for (auto& v : s->ev) {
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    v.clear();
+  }
+}
+
+// Records a start event for `stage` when profiling; returns the index to close with timed_end.
+hipEvent_t timed_begin(ephdc_session* s, hipStream_t hs) {
+  if (!s->profile) return nullptr;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  (void)hipEventRecord(e, hs);
+  return e;
+}
+
+void timed_end(ephdc_session* s, int stage, hipEvent_t start, hipStream_t hs) {
+  if (!s->profile || !start) return;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, hs);
+  s->ev[stage].emplace_back(start, e);
+}
+
+void free_session(ephdc_session* s) {
+  if (!s) return;
+  drop_events(s);
+  void* ptrs[] = {s->d_fwd, s->d_inv, s->d_inv_t, s->d_pc, s->d_scatter, s->d_model, s->d_gk, s->d_partial};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete s;
+}
+
+PrimeConst make_const(const HostNtt& T) {
+  PrimeConst pc{};
+  const uint32_t m = T.m;
+  uint32_t inv = 1;  // m^-1 mod 2^32 by Newton iteration
+  for (int i = 0; i < 5; ++i) inv *= 2u - m * inv;
+  pc.m = m;
+  pc.mneg_inv = (uint32_t)(0u - inv);
+  pc.r2 = (uint32_t)(((unsigned __int128)1 << 64) % m);
+  pc.ninv = T.ninv;
+  pc.ninvp = T.ninvp;
+  pc.ninv_w1 = (uint32_t)((uint64_t)T.ninv * T.iw[1] % m);
+  pc.ninv_w1p = T.shoup(pc.ninv_w1);
+  return pc;
+}
+
+// Work decomposition of one scoring launch: G groups x S splits of the M model
+// ciphertexts x nlg limb groups, aiming at kTargetBlocks workgroups.
+struct Schedule {
+  uint32_t G, S, mchunk;
+};
+
+Schedule schedule(const ephdc_session* s, uint32_t Q) {
+  Schedule sc{};
+  sc.G = s->P.G(Q);
+  const uint32_t M = s->P.M();
+  const uint32_t per = std::max<uint32_t>(1, sc.G * s->nlg);
+  uint32_t S = std::max<uint32_t>(1, (kTargetBlocks + per - 1) / per);
+  S = std::min(S, M);
+  sc.mchunk = (M + S - 1) / S;
+  sc.S = (M + sc.mchunk - 1) / sc.mchunk;
+  return sc;
+}
+
+ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, const Schedule& sc) {
+  const ParamSet& P = s->P;
+  ScoreArgs a{};
+  a.model = s->d_model;
+  a.hv = d_hv;
+  a.partial = s->d_partial;
+  a.scatter = s->d_scatter;
+  a.fwd_tw = s->d_fwd;
+  a.inv_t = s->d_inv_t;
+  a.pcs = s->d_pc;
+  a.pct = s->pct;
+  a.tninv = s->tninv;
+  a.tninvp = s->tninvp;
+  a.L = P.L;
+  a.M = P.M();
+  a.D = P.D;
+  a.r = P.r;
+  a.hv_stride = P.G(Q) * P.B();
+  a.B = P.B();
+  a.G = sc.G;
+  a.S = sc.S;
+  a.mchunk = sc.mchunk;
+  a.NLG = s->nlg;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
+                                  const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q, void* stream,
+                                  ephdc_session** out) {
+  if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  ParamSet P;
+  ephdc_status st = P.load(prm);
+  if (st != EPHDC_OK) return st;
+  if (!d_model_ct) return fail(EPHDC_ERR_ARG, "model is NULL");
+  if (!supported_logn(P.logn)) return fail(EPHDC_ERR_UNSUPPORTED, "kernels implement N in {4096, 8192, 16384}");
+  if (P.r > 1 && !d_galois_keys) return fail(EPHDC_ERR_NOKEY, "r > 1 needs Galois keys");
+  if (max_Q == 0) return fail(EPHDC_ERR_ARG, "max_Q must be positive");
+  if (model_words < (size_t)P.M() * 2 * P.L * P.N) return fail(EPHDC_ERR_BUFFER, "model buffer shorter than [M][2][L][N]");
+  if (P.r > 1 && gk_words < (size_t)P.log2r() * P.dnum * 2 * P.nmod() * P.N)
+    return fail(EPHDC_ERR_BUFFER, "Galois key buffer shorter than [log2 r][dnum][2][L+alpha][N]");
+  hipStream_t hs = (hipStream_t)stream;
+  HIP_TRY(prepare_kernels(), "kernel setup");
+
+  ephdc_session* s = new ephdc_session();
+  s->P = P;
+  s->max_Q = max_Q;
+  (void)hipGetDevice(&s->device);
+  const int cap = max_limb_group(P.logn);
+  s->lg = 1;
+  for (int g = cap; g >= 1; --g)
+    if (P.L % g == 0) { s->lg = (uint32_t)g; break; }
+  s->nlg = P.L / s->lg;
+
+  const uint32_t N = P.N, nm = P.nmod();
+  std::vector<uint2> fwd((size_t)nm * N), inv((size_t)nm * N), invt(N);
+  std::vector<PrimeConst> pcs(nm);
+  for (uint32_t i = 0; i < nm; ++i) {
+    uint32_t m = P.modulus(i);
+    HostNtt T(N, m, root_of_unity(2 * N, m));
+    for (uint32_t k = 0; k < N; ++k) {
+      fwd[(size_t)i * N + k] = make_uint2(T.fw[k], T.fwp[k]);
+      inv[(size_t)i * N + k] = make_uint2(T.iw[k], T.iwp[k]);
+    }
+    pcs[i] = make_const(T);
+  }
+  {
+    uint32_t zeta = (uint32_t)powmod64(3, (P.t - 1) / (2 * N), P.t);
+    HostNtt Tt(N, P.t, zeta);
+    for (uint32_t k = 0; k < N; ++k) invt[k] = make_uint2(Tt.iw[k], Tt.iwp[k]);
+    s->pct = make_const(Tt);
+    s->tninv = Tt.ninv;
+    s->tninvp = Tt.ninvp;
+  }
+  std::vector<uint32_t> scatter = query_scatter_table(P);
+
+  const size_t M = P.M();
+  const size_t model_copy_words = M * 2 * P.L * N;
+  const size_t key_words = P.r > 1 ? (size_t)P.log2r() * P.dnum * 2 * nm * N : 0;
+  const uint32_t Gmax = P.G(max_Q);
+  s->partial_words = ((size_t)kTargetBlocks + (size_t)Gmax * s->nlg) * 2 * P.L * N;
+
+  auto cleanup = [&](ephdc_status e) { free_session(s); return e; };
+  if ((st = dev_alloc(s, &s->d_fwd, fwd.size(), "twiddles")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_inv, inv.size(), "twiddles")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_inv_t, invt.size(), "twiddles")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_pc, pcs.size(), "constants")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_scatter, scatter.size(), "scatter table")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_model, model_copy_words, "model")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_gk, key_words, "Galois keys")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_partial, s->partial_words, "partial sums")) != EPHDC_OK) return cleanup(st);
+
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chk(hipMemcpyAsync(s->d_fwd, fwd.data(), fwd.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_inv, inv.data(), inv.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_inv_t, invt.data(), invt.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_pc, pcs.data(), pcs.size() * sizeof(PrimeConst), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_scatter, scatter.data(), scatter.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
+  if (e == hipSuccess)
+    e = launch_fwd_batch(P.logn, d_model_ct, s->d_model, M * 2 * P.L, s->d_fwd, s->d_pc, P.L, 0, true, hs);
+  if (e == hipSuccess && key_words)
+    e = launch_fwd_batch(P.logn, d_galois_keys, s->d_gk, key_words / N, s->d_fwd, s->d_pc, nm, 0, true, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  if (e != hipSuccess) {
+    free_session(s);
+    return hip_fail(e, "session setup");
+  }
+  *out = s;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_session_destroy(ephdc_session* s) {
+  if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
+  (void)hipDeviceSynchronize();
+  free_session(s);
+  return EPHDC_OK;
+}
+
+size_t ephdc_session_device_bytes(const ephdc_session* s) { return s ? s->device_bytes : 0; }
+
+ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const int8_t* d_base, uint32_t Q,
+                                  int8_t* d_hv, void* stream) {
+  if (!s || !d_x || !d_base || !d_hv) return fail(EPHDC_ERR_ARG, "NULL argument");
+  const ParamSet& P = s->P;
+  if (Q == 0 || Q > s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, max_Q]");
+  if (P.F % 16 != 0 || P.D % 64 != 0) return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F % 16 == 0 and D % 64 == 0");
+  if (((uintptr_t)d_x & 15) || ((uintptr_t)d_base & 3)) return fail(EPHDC_ERR_ARG, "x must be 16-byte and base 4-byte aligned");
+  if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
+  hipStream_t hs = (hipStream_t)stream;
+  hipEvent_t t0 = timed_begin(s, hs);
+  HIP_TRY(launch_hdc_encode(d_x, d_base, d_hv, Q, P.F, P.D, P.G(Q) * P.B(), P.qbits, P.qshift, hs),
+          "encode launch");
+  timed_end(s, 2, t0, hs);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_t Q, uint32_t* d_score_ct,
+                                   void* stream) {
+  if (!s || !d_hv || !d_score_ct) return fail(EPHDC_ERR_ARG, "NULL argument");
+  if (Q == 0 || Q > s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, max_Q]");
+  const ParamSet& P = s->P;
+  if (P.r > 1) return fail(EPHDC_ERR_UNSUPPORTED, "rotate-and-sum is not built yet");
+  hipStream_t hs = (hipStream_t)stream;
+  Schedule sc = schedule(s, Q);
+  if ((size_t)sc.G * sc.S * 2 * P.L * P.N > s->partial_words) return fail(EPHDC_ERR_BUFFER, "scratch too small");
+  if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
+  ScoreArgs a = score_args(s, d_hv, Q, sc);
+  hipEvent_t t0 = timed_begin(s, hs);
+  HIP_TRY(launch_score(P.logn, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
+  timed_end(s, 0, t0, hs);
+  hipEvent_t t1 = timed_begin(s, hs);
+  HIP_TRY(launch_finish(P.logn, true, s->d_partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
+          "finish launch");
+  timed_end(s, 1, t1, hs);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_session_profile(ephdc_session* s, int enable) {
+  if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
+  s->profile = enable != 0;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[4], uint64_t count[4]) {
+  if (!s || !ms || !count) return fail(EPHDC_ERR_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+    for (auto& pr : s->ev[k]) {
+      HIP_TRY(hipEventSynchronize(pr.second), "event sync");
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second), "event time");
+      ms[k] += t;
+      ++count[k];
+    }
+  }
+  drop_events(s);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_debug_plaintext(ephdc_session* s, const int8_t* d_hv, uint32_t Q, uint32_t g, uint32_t m,
+                                   uint32_t* d_out, void* stream) {
+  if (!s || !d_hv || !d_out) return fail(EPHDC_ERR_ARG, "NULL argument");
+  const ParamSet& P = s->P;
+  if (Q == 0 || g >= P.G(Q) || m >= P.M()) return fail(EPHDC_ERR_ARG, "g or m out of range");
+  Schedule sc = schedule(s, Q);
+  ScoreArgs a = score_args(s, d_hv, Q, sc);
+  HIP_TRY(launch_debug_plaintext(P.logn, a, g, m, d_out, (hipStream_t)stream), "debug launch");
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const uint32_t* d_b, uint32_t count,
+                                 uint32_t* d_out, void* stream) {
+  if (!s || !d_a || !d_b || !d_out) return fail(EPHDC_ERR_ARG, "NULL argument");
+  if (count == 0) return EPHDC_OK;
+  const ParamSet& P = s->P;
+  hipStream_t hs = (hipStream_t)stream;
+  const size_t n = (size_t)count * P.N;
+  uint32_t *ta = nullptr, *tb = nullptr;
+  if (hipMalloc((void**)&ta, n * 4) != hipSuccess || hipMalloc((void**)&tb, n * 4) != hipSuccess) {
+    if (ta) (void)hipFree(ta);
+    (void)hipGetLastError();
+    return fail(EPHDC_ERR_OOM, "debug buffers");
+  }
+  hipError_t e = launch_fwd_batch(P.logn, d_a, ta, count, s->d_fwd, s->d_pc, P.L, 0, true, hs);
+  if (e == hipSuccess) e = launch_fwd_batch(P.logn, d_b, tb, count, s->d_fwd, s->d_pc, P.L, 0, false, hs);
+  if (e == hipSuccess) e = launch_pointwise_mont(ta, tb, ta, n, P.N, s->d_pc, P.L, hs);
+  if (e == hipSuccess) e = launch_inv_batch(P.logn, ta, d_out, count, s->d_inv, s->d_pc, P.L, 0, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  (void)hipFree(ta);
+  (void)hipFree(tb);
+  if (e != hipSuccess) return hip_fail(e, "debug polymul");
+  return EPHDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+"""HIP path vs the oracle, element by element, through the C ABI (needs a gfx950 GPU).
+
+Sizes span several tiles of every kernel and end in ragged tails; every comparison is
+bit-exact (the whole path is integer arithmetic)."""
+import numpy as np
+import pytest
+
+import paper_2511_00737_amd as ep
+import synth
+from oracle import bfv, hdc, ntt, pipeline, slots
+from oracle.params import Params as OParams, default_primes
+
+from gpu_helpers import hv_layout, score_on_gpu, to_dev, to_host_u32, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def make(N, L, D, K, F=64, r=1, alpha=0, dnum=0, qbits=1, qshift=0):
+    primes = default_primes(N, L + alpha)
+    kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum, qbits=qbits,
+              qshift=qshift)
+    return OParams(**kw), ep.Params(**kw)
+
+
+@pytest.mark.parametrize("N,L", [(4096, 3), (8192, 4), (16384, 3)])
+def test_negacyclic_products_match_oracle(N, L):
+    torch = torch_cuda()
+    o, e = make(N, L, D=64, K=2)
+    rng = np.random.default_rng(N)
+    count = 2 * L + 1  # pair i is reduced mod q[i % L]; ends on a partial round of limbs
+    a = np.stack([rng.integers(0, o.q[i % L], N) for i in range(count)]).astype(np.uint32)
+    b = np.stack([rng.integers(0, o.q[i % L], N) for i in range(count)]).astype(np.uint32)
+    model = np.zeros((o.M, 2, L, N), dtype=np.uint32)
+    s = ep.Session(e, to_dev(model), max_Q=1)
+    try:
+        d_out = torch.empty((count, N), dtype=torch.int32, device="cuda")
+        ep.ephdc_debug_polymul(s, to_dev(a), to_dev(b), count, d_out)
+        got = to_host_u32(d_out)
+    finally:
+        s.close()
+    for i in range(count):
+        q = o.q[i % L]
+        assert np.array_equal(got[i].astype(np.int64), ntt.polymul(a[i], b[i], q)), i
+
+
+@pytest.mark.parametrize("N,K,D,r,Q", [(4096, 2, 64, 1, 64), (8192, 7, 96, 1, 3000), (4096, 3, 40, 4, 700),
+                                       (16384, 26, 30, 1, 700)])
+def test_batch_encoded_plaintexts_match_oracle(N, K, D, r, Q):
+    torch = torch_cuda()
+    o, e = make(N, 2, D=D, K=K, r=r, alpha=1 if r > 1 else 0, dnum=1 if r > 1 else 0)
+    rng = np.random.default_rng(D)
+    h = rng.choice(np.array([-1, 1], dtype=np.int8), (Q, D))
+    model = np.zeros((o.M, 2, o.L, N), dtype=np.uint32)
+    gk = np.zeros(ep.ephdc_galois_key_words(e), dtype=np.uint32) if r > 1 else None
+    s = ep.Session(e, to_dev(model), to_dev(gk) if gk is not None else None, max_Q=Q)
+    try:
+        d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
+        G = s.num_groups(Q)
+        for g, m in [(0, 0), (G - 1, o.M - 1), (G // 2, o.M // 2)]:
+            d_out = torch.empty((o.L, N), dtype=torch.int32, device="cuda")
+            ep.ephdc_debug_plaintext(s, d_hv, Q, g, m, d_out)
+            got = to_host_u32(d_out).astype(np.int64)
+            p = bfv.query_plaintext(o, h, g, m)
+            for l, q in enumerate(o.q):
+                assert np.array_equal(got[l], p % q), (g, m, l)
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("F,D,Q,qbits,qshift", [(64, 128, 100, 1, 0), (512, 2048, 64, 1, 0),
+                                                 (2304, 256, 333, 1, 0), (160, 192, 70, 4, 9)])
+def test_hdc_encoding_matches_oracle(F, D, Q, qbits, qshift):
+    torch = torch_cuda()
+    o, e = make(4096, 1, D=D, K=2, F=F, qbits=qbits, qshift=qshift)
+    x = synth.uniform_features(F + Q, Q, F)
+    base = synth.base_hypervectors(F + Q, F, D)
+    want = hdc.encode(x, base, qbits, qshift)
+    model = np.zeros((o.M, 2, o.L, o.N), dtype=np.uint32)
+    s = ep.Session(e, to_dev(model), max_Q=Q)
+    try:
+        stride = s.hv_stride(Q)
+        d_hv = torch.full((D, stride), 77, dtype=torch.int8, device="cuda")
+        ep.ephdc_encode_queries(s, to_dev(x), to_dev(base), Q, d_hv)
+        got = d_hv.cpu().numpy()
+    finally:
+        s.close()
+    assert np.array_equal(got[:, :Q], want.T)
+    assert not got[:, Q:].any()  # padding queries are zero
+
+
+@pytest.mark.parametrize("N,L,K,D,Q", [(4096, 3, 2, 37, 64), (4096, 2, 3, 50, 3000), (8192, 4, 7, 40, 2500),
+                                       (8192, 2, 2, 20, 9000), (16384, 2, 26, 12, 1000)])
+def test_score_ciphertexts_match_oracle(N, L, K, D, Q):
+    o, e = make(N, L, D=D, K=K)
+    torch_cuda()
+    rng = np.random.default_rng(N + D)
+    C = synth.class_hypervectors(D, K, D)
+    s = bfv.secret_key(o, 3)
+    model = bfv.encrypt_model(o, s, C, 3)
+    h = rng.choice(np.array([-1, 1], dtype=np.int8), (Q, D))
+    got = score_on_gpu(e, model.astype(np.uint32), h)
+    want = pipeline.score_ciphertexts(o, model, h)
+    assert got.shape == want.shape
+    assert np.array_equal(got.astype(np.int64), want)
+    scores, am = pipeline.decrypt_scores(o, s, want, Q)
+    assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
+
+
+def test_qbit_queries_score_exactly():
+    """8-bit queries (the paper's Q-bit quantisation): scores are exact residues of h . C."""
+    o, e = make(4096, 3, D=33, K=4)
+    torch_cuda()
+    rng = np.random.default_rng(5)
+    C = synth.class_hypervectors(6, o.K, o.D)
+    s = bfv.secret_key(o, 6)
+    model = bfv.encrypt_model(o, s, C, 6)
+    h = rng.integers(-128, 128, (900, o.D)).astype(np.int8)
+    got = score_on_gpu(e, model.astype(np.uint32), h)
+    assert np.array_equal(got.astype(np.int64), pipeline.score_ciphertexts(o, model, h))
+    scores, _ = pipeline.decrypt_scores(o, s, got.astype(np.int64), 900)
+    assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
