@@ -195,6 +195,18 @@ ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const ui
                                  uint32_t count, uint32_t* d_out, void* stream);
 
 /*
+ * Schedule of the fused scoring kernel (0 keeps a setting):
+ *   limb_group         limbs per work item, a divisor of L in 1..4
+ *   blocks             target workgroups per launch (<= 1024): the model ciphertexts are
+ *                      split into ranges until groups x ranges x limb groups reaches it
+ *   values_per_thread  transform values held per thread (8 or 16 at N = 8192; the
+ *                      workgroup has N / values_per_thread threads)
+ * Results do not depend on the schedule.
+ */
+ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks,
+                                uint32_t values_per_thread);
+
+/*
  * Kernel timing (diagnostics for benchmarks).  While enabled, every kernel launched by the
  * session is bracketed by HIP events recorded on the stream it runs on.  Reading waits for
  * the recorded events, returns per-stage totals and resets them:

@@ -73,6 +73,7 @@ def lib() -> C.CDLL:
             "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                               C.c_void_p]),
             "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
+            "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
             "ephdc_session_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), u64p]),
         }
         for name, (res, args) in sig.items():
@@ -255,6 +256,10 @@ class Session:
     @property
     def device_bytes(self) -> int:
         return lib().ephdc_session_device_bytes(self.handle)
+
+    def tune(self, limb_group: int = 0, blocks: int = 0, values_per_thread: int = 0) -> None:
+        """Schedule of the scoring kernel (see ephdc_session_tune); 0 keeps a setting."""
+        _check(lib().ephdc_session_tune(self.handle, limb_group, blocks, values_per_thread))
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every kernel launch with HIP events on its stream (see ephdc_session_profile)."""

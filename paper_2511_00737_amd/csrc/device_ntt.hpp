@@ -57,7 +57,7 @@ struct Shape {
   static constexpr int NFULL = LOGN / LE;
   static constexpr int REM = LOGN % LE;
   static constexpr int NPASS = NFULL + (REM ? 1 : 0);
-  static constexpr int PADN = N + (N >> 5);  // LDS words per exchange buffer
+  static constexpr int PADN = N + (N >> 4);  // LDS words per exchange buffer (padding <= 1/16)
   static constexpr int s0(int p) { return p * LE; }
   static constexpr int k(int p) { return p < NFULL ? LE : REM; }
 };
@@ -72,7 +72,7 @@ struct Shape {
 // depends only on i (their bit ranges never overlap), so every address derived from it by
 // shifts and the LDS padding splits into a per-thread base plus a compile-time offset.
 template <int LOGN, int LE, int P>
-__device__ __forceinline__ int tid_part(int tid) {
+__host__ __device__ constexpr int tid_part(int tid) {
   using S = Shape<LOGN, LE>;
   constexpr int k = S::k(P);
   constexpr int tl = LOGN - S::s0(P) - k;  // log2(tmin)
@@ -96,28 +96,130 @@ __host__ __device__ constexpr int i_part(int i) {
   }
 }
 
-__host__ __device__ constexpr int lds_pad(int x) { return x + (x >> 5); }
-
-// Forward pass P: Cooley-Tukey butterflies with twiddles tw[2^s + block] (= w^brev),
-// inputs and outputs in [0, 4m).
+// True when, in the layout of pass P, every wave owns exactly the contiguous block of
+// positions [w*64*E, (w+1)*64*E): exchanges between two such layouts never cross waves.
 template <int LOGN, int LE, int P>
-__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ tw,
-                                         uint32_t m) {
+__host__ __device__ constexpr bool wave_local() {
   using S = Shape<LOGN, LE>;
   constexpr int k = S::k(P);
+  constexpr int tl = LOGN - S::s0(P) - k;
+  if constexpr (P == S::NPASS - 1) {
+    return true;  // x = tid*E + i
+  } else {
+    // x = ((tid >> tl) << (tl+k)) | (tid & (2^tl-1)) | i-part; the wave index tid >> 6 must equal
+    // x >> (6 + LE) for every register, i.e. tl <= 6 and the group stride covers 64*E exactly
+    return tl <= 6 && (6 - tl) + (tl + k) == 6 + LE && (S::E >> k) == 1;
+  }
+}
+
+// LDS padding of an exchange: position x is stored at x + c*(x >> a).  Shifts distribute
+// over the disjoint tid / register parts of x, so the padded address is still a per-thread
+// base plus a compile-time offset.  Each exchange takes the (a, c) whose write layout and
+// read layout have the fewest bank conflicts (simulated at compile time for 32 banks per
+// half-wave and 64 banks per wave), with overhead c/2^a at most 1/16.
+struct Pad {
+  int a, c;
+};
+
+__host__ __device__ constexpr int padx(Pad p, int x) { return x + p.c * (x >> p.a); }
+
+// Sum over registers of the worst bank multiplicity of one wave's access.
+template <int LOGN, int LE, int P>
+__host__ __device__ constexpr int layout_conflicts(Pad p) {
+  using S = Shape<LOGN, LE>;
+  int total = 0;
+  for (int i = 0; i < S::E; ++i) {
+    int c32a[32] = {}, c32b[32] = {}, c64[64] = {};
+    int worst32 = 0, worst64 = 0;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int addr = padx(p, tid_part<LOGN, LE, P>(lane) | i_part<LOGN, LE, P>(i));
+      int& h = lane < 32 ? c32a[addr & 31] : c32b[addr & 31];
+      ++h;
+      if (h > worst32) worst32 = h;
+      if (++c64[addr & 63] > worst64) worst64 = c64[addr & 63];
+    }
+    total += worst32 + worst64;
+  }
+  return total;
+}
+
+//
+// Wave-local exchanges run without a workgroup barrier, so the LDS range a wave writes
+// must never overlap the range another wave may still be reading under a different
+// exchange's padding.  They therefore only use paddings of overhead exactly 1/16
+// ((a, c) = (4, 1) or (5, 2)): both map wave w's positions [64*E*w, 64*E*(w+1)) into the
+// same private range [68*E*w, 68*E*(w+1)).
+template <int LOGN, int LE, int PF, int PT>
+__host__ __device__ constexpr Pad exchange_pad() {
+  constexpr bool local = wave_local<LOGN, LE, PF>() && wave_local<LOGN, LE, PT>();
+  Pad best{4, 1};
+  int best_cost = 1 << 30, best_over = 1 << 30;
+  for (int a = 4; a <= 10; ++a)
+    for (int c = 1; c <= 2; ++c) {
+      if ((c << 4) > (1 << a)) continue;  // overhead c/2^a must stay <= 1/16
+      if (local && (c << 4) != (1 << a)) continue;
+      const Pad p{a, c};
+      const int cost = layout_conflicts<LOGN, LE, PF>(p) + layout_conflicts<LOGN, LE, PT>(p);
+      const int over = (c << 10) >> a;
+      if (cost < best_cost || (cost == best_cost && over < best_over)) {
+        best = p;
+        best_cost = cost;
+        best_over = over;
+      }
+    }
+  return best;
+}
+
+// Twiddles of pass P for this thread: for stage u of the pass, group e and sub-block v, the
+// entry table[2^s + block] of the lower butterfly element, s = s0 + u.  Loaded in one go so
+// that the loads can be issued ahead of the exchange that precedes the pass.
+template <int LOGN, int LE, int P>
+struct Tw {
+  using S = Shape<LOGN, LE>;
+  static constexpr int k = S::k(P);
+  static constexpr int G = S::E >> k;                 // groups per thread
+  static constexpr int COUNT = G * ((1 << k) - 1);   // sum over stages of G * 2^u
+  static constexpr int off(int u) { return G * ((1 << u) - 1); }
+  uint2 w[COUNT];
+};
+
+template <int LOGN, int LE, int P>
+__device__ __forceinline__ void load_tw(Tw<LOGN, LE, P>& t, int tid, const uint2* __restrict__ table) {
+  using S = Shape<LOGN, LE>;
+  using TW = Tw<LOGN, LE, P>;
+  constexpr int k = TW::k;
   constexpr int s0 = S::s0(P);
-  const uint32_t m2 = 2 * m;
-  const int xt = tid_part<LOGN, LE, P>(tid);
+  const int xt = (P == 0) ? 0 : tid_part<LOGN, LE, P>(tid);  // pass 0: blocks at stages < LE are uniform
 #pragma unroll
   for (int u = 0; u < k; ++u) {
     const int s = s0 + u;
+    const uint2* base = table + (1 << s) + (xt >> (LOGN - s));
+#pragma unroll
+    for (int e = 0; e < TW::G; ++e)
+#pragma unroll
+      for (int v = 0; v < (1 << u); ++v) {
+        const int i = (e << k) | (v << (k - u));
+        t.w[TW::off(u) + (e << u) + v] = base[i_part<LOGN, LE, P>(i) >> (LOGN - s)];
+      }
+  }
+}
+
+// Forward pass P: Cooley-Tukey butterflies, inputs and outputs in [0, 4m).
+template <int LOGN, int LE, int P>
+__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P>& t, uint32_t m) {
+  using S = Shape<LOGN, LE>;
+  using TW = Tw<LOGN, LE, P>;
+  constexpr int k = TW::k;
+  const uint32_t m2 = 2 * m;
+#pragma unroll
+  for (int u = 0; u < k; ++u) {
     const int h = 1 << (k - 1 - u);
-    const uint2* twb = tw + (1 << s) + (xt >> (LOGN - s));
 #pragma unroll
     for (int i = 0; i < S::E; ++i) {
       if (i & h) continue;
-      const uint2 w = twb[i_part<LOGN, LE, P>(i) >> (LOGN - s)];
-      uint32_t X = csub(v[i], m2);
+      const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
+      const uint2 w = t.w[TW::off(u) + (e << u) + vb];
+      const uint32_t X = csub(v[i], m2);
       const uint32_t Tm = mul_shoup(v[i + h], w.x, w.y, m);
       v[i] = X + Tm;
       v[i + h] = X - Tm + m2;
@@ -125,30 +227,28 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], int tid, const 
   }
 }
 
-// Inverse pass P: Gentleman-Sande butterflies with twiddles itw[2^s + block] (= w^-brev),
-// inputs and outputs in [0, 2m).  With SCALE, the last stage (s = 0) also multiplies by N^-1.
+// Inverse pass P: Gentleman-Sande butterflies, inputs and outputs in [0, 2m).  With SCALE,
+// the last stage (s = 0) also multiplies by N^-1.
 template <int LOGN, int LE, int P, bool SCALE>
-__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ itw,
-                                         const PrimeConst& pc) {
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P>& t, const PrimeConst& pc) {
   using S = Shape<LOGN, LE>;
-  constexpr int k = S::k(P);
+  using TW = Tw<LOGN, LE, P>;
+  constexpr int k = TW::k;
   constexpr int s0 = S::s0(P);
   const uint32_t m = pc.m, m2 = 2 * m;
-  const int xt = tid_part<LOGN, LE, P>(tid);
 #pragma unroll
   for (int u = k - 1; u >= 0; --u) {
-    const int s = s0 + u;
     const int h = 1 << (k - 1 - u);
-    const uint2* twb = itw + (1 << s) + (xt >> (LOGN - s));
 #pragma unroll
     for (int i = 0; i < S::E; ++i) {
       if (i & h) continue;
       const uint32_t U = v[i], V = v[i + h];
-      if (SCALE && s == 0) {
+      if (SCALE && s0 + u == 0) {
         v[i] = mul_shoup(U + V, pc.ninv, pc.ninvp, m);
         v[i + h] = mul_shoup(U - V + m2, pc.ninv_w1, pc.ninv_w1p, m);
       } else {
-        const uint2 w = twb[i_part<LOGN, LE, P>(i) >> (LOGN - s)];
+        const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
+        const uint2 w = t.w[TW::off(u) + (e << u) + vb];
         v[i] = csub(U + V, m2);
         v[i + h] = mul_shoup(U - V + m2, w.x, w.y, m);
       }
@@ -156,61 +256,108 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], int tid, const 
   }
 }
 
-// Moves values from the register layout of pass PF to that of pass PT through LDS.
-template <int LOGN, int LE, int PF, int PT>
-__device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], uint32_t* __restrict__ buf, int tid) {
-  using S = Shape<LOGN, LE>;
-  uint32_t* wb = buf + lds_pad(tid_part<LOGN, LE, PF>(tid));
-#pragma unroll
-  for (int i = 0; i < S::E; ++i) wb[lds_pad(i_part<LOGN, LE, PF>(i))] = v[i];
-  __syncthreads();
-  const uint32_t* rb = buf + lds_pad(tid_part<LOGN, LE, PT>(tid));
-#pragma unroll
-  for (int i = 0; i < S::E; ++i) v[i] = rb[lds_pad(i_part<LOGN, LE, PT>(i))];
-}
+// Workgroup barrier that waits only for this wave's LDS (and scalar-memory) operations:
+// vector-memory loads issued before it stay in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Exchange buffers alternate on every exchange, across calls too, so one barrier per
-// exchange suffices: a buffer is rewritten only after a later barrier has retired all
-// reads of its previous contents.
-struct LdsPair {
-  uint32_t* b0;
-  uint32_t* b1;
-  int sel;
-  __device__ __forceinline__ uint32_t* next() {
-    uint32_t* p = sel ? b1 : b0;
-    sel ^= 1;
-    return p;
-  }
+// Completion of this wave's own LDS operations (orders a wave-private write -> read).
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// LDS plan of one workgroup.  Exchanges between two wave-local layouts stay inside one
+// wave and use the wave's own region of the `local` buffer, with no workgroup barrier.
+// When three buffers (and the scatter table) fit in the 160 KB of LDS, cross-wave
+// exchanges alternate between g[0] and g[1] over all calls: a buffer is rewritten only
+// after the barrier of the following cross-wave exchange has retired every read of its
+// previous contents.  Otherwise they all use g[0] behind an extra leading barrier.
+// Cross-wave and wave-local exchanges never share a buffer.
+template <int LOGN, int LE>
+struct LdsPlan {
+  static constexpr int PADN = Shape<LOGN, LE>::PADN;
+  static constexpr int N = Shape<LOGN, LE>::N;
+  static constexpr bool three = (3 * PADN + N) * 4 <= 160 * 1024;
+  static constexpr int exchange_words = three ? 3 * PADN : 2 * PADN;
+  static constexpr bool table_in_lds = three;
+  static constexpr int words = exchange_words + (table_in_lds ? N : 0);
 };
 
-// Makes a pointer opaque to the optimiser so that table loads stay inside the calling loop
-// instead of being hoisted (and held in registers) across iterations.
-template <class T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
+// The dynamic LDS of every kernel.  Buffers are addressed as this symbol plus an integer
+// offset so that every access compiles to an LDS (ds_*) instruction.
+extern __shared__ uint32_t ephdc_lds[];
+
+// Which cross-wave buffer the next cross-wave exchange uses (alternates in the
+// three-buffer plan).
+struct LdsBufs {
+  int sel;
+};
+
+template <int LOGN, int LE, int PF, int PT>
+__device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int tid) {
+  using S = Shape<LOGN, LE>;
+  constexpr int P = S::PADN;
+  constexpr bool local = wave_local<LOGN, LE, PF>() && wave_local<LOGN, LE, PT>();
+  constexpr Pad pd = exchange_pad<LOGN, LE, PF, PT>();
+  int off;
+  if constexpr (local) {
+    off = LdsPlan<LOGN, LE>::three ? 2 * P : P;
+  } else if constexpr (LdsPlan<LOGN, LE>::three) {
+    off = b.sel * P;
+    b.sel ^= 1;
+  } else {
+    off = 0;
+    lds_barrier();  // every wave has finished reading the previous contents
+  }
+  uint32_t* wb = ephdc_lds + off + padx(pd, tid_part<LOGN, LE, PF>(tid));
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) wb[padx(pd, i_part<LOGN, LE, PF>(i))] = v[i];
+  if constexpr (local) lds_wave_sync();
+  else lds_barrier();
+  const uint32_t* rb = ephdc_lds + off + padx(pd, tid_part<LOGN, LE, PT>(tid));
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) v[i] = rb[padx(pd, i_part<LOGN, LE, PT>(i))];
 }
 
 template <int LOGN, int LE, int P = 0>
-__device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ tw,
-                                            uint32_t m, LdsPair& lds) {
-  if constexpr (P == 0) tw = opaque(tw);
-  fwd_pass<LOGN, LE, P>(v, tid, tw, m);
+__device__ __forceinline__ void ntt_forward_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P>& tw, int tid,
+                                                 const uint2* __restrict__ table, uint32_t m, LdsBufs& b) {
+  fwd_pass<LOGN, LE, P>(v, tw, m);
   if constexpr (P + 1 < Shape<LOGN, LE>::NPASS) {
-    exchange<LOGN, LE, P, P + 1>(v, lds.next(), tid);
-    ntt_forward<LOGN, LE, P + 1>(v, tid, tw, m, lds);
+    Tw<LOGN, LE, P + 1> nt;
+    load_tw<LOGN, LE, P + 1>(nt, tid, table);  // in flight across the exchange
+    exchange<LOGN, LE, P, P + 1>(v, b, tid);
+    ntt_forward_from<LOGN, LE, P + 1>(v, nt, tid, table, m, b);
   }
 }
 
-template <int LOGN, int LE, bool SCALE, int P = Shape<LOGN, LE>::NPASS - 1>
-__device__ __forceinline__ void ntt_inverse(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ itw,
-                                            const PrimeConst& pc, LdsPair& lds) {
-  if constexpr (P == Shape<LOGN, LE>::NPASS - 1) itw = opaque(itw);
-  inv_pass<LOGN, LE, P, SCALE>(v, tid, itw, pc);
+// Forward transform: coefficient layout (tid + i*T) -> evaluation layout (tid*E + i).
+template <int LOGN, int LE>
+__device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ table,
+                                            uint32_t m, LdsBufs& b) {
+  Tw<LOGN, LE, 0> t0;
+  load_tw<LOGN, LE, 0>(t0, tid, table);
+  ntt_forward_from<LOGN, LE, 0>(v, t0, tid, table, m, b);
+}
+
+template <int LOGN, int LE, bool SCALE, int P>
+__device__ __forceinline__ void ntt_inverse_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P>& tw, int tid,
+                                                 const uint2* __restrict__ table, const PrimeConst& pc, LdsBufs& b) {
+  inv_pass<LOGN, LE, P, SCALE>(v, tw, pc);
   if constexpr (P > 0) {
-    exchange<LOGN, LE, P, P - 1>(v, lds.next(), tid);
-    ntt_inverse<LOGN, LE, SCALE, P - 1>(v, tid, itw, pc, lds);
+    Tw<LOGN, LE, P - 1> nt;
+    load_tw<LOGN, LE, P - 1>(nt, tid, table);
+    exchange<LOGN, LE, P, P - 1>(v, b, tid);
+    ntt_inverse_from<LOGN, LE, SCALE, P - 1>(v, nt, tid, table, pc, b);
   }
 }
+
+// Inverse transform: evaluation layout (tid*E + i) -> coefficient layout (tid + i*T).
+template <int LOGN, int LE, bool SCALE>
+__device__ __forceinline__ void ntt_inverse(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ table,
+                                            const PrimeConst& pc, LdsBufs& b) {
+  constexpr int PL = Shape<LOGN, LE>::NPASS - 1;
+  Tw<LOGN, LE, PL> t0;
+  load_tw<LOGN, LE, PL>(t0, tid, table);
+  ntt_inverse_from<LOGN, LE, SCALE, PL>(v, t0, tid, table, pc, b);
+}
+
 
 }  // namespace ephdc_dev

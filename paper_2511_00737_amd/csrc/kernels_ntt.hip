@@ -14,12 +14,12 @@ namespace ephdc_dev {
 // One workgroup per polynomial; polynomial `poly` is taken mod modulus limb_base + poly % nlimb.
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t* __restrict__ in,
-                                                                   uint32_t* __restrict__ out,
-                                                                   const uint2* __restrict__ fwd_tw,
-                                                                   const PrimeConst* __restrict__ pcs,
-                                                                   uint32_t nlimb, uint32_t limb_base, int mont) {
+                                                                  uint32_t* __restrict__ out,
+                                                                  const uint2* __restrict__ fwd_tw,
+                                                                  const PrimeConst* __restrict__ pcs,
+                                                                  uint32_t nlimb, uint32_t limb_base, int mont) {
   using S = Shape<LOGN, LE>;
-  extern __shared__ uint32_t lds[];
+  LdsBufs b{0};
   const int tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
@@ -28,8 +28,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t*
   uint32_t v[S::E];
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = src[tid + i * S::T];
-  LdsPair lp{lds, lds + S::PADN, 0};
-  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)limb * S::N, pc.m, lp);
+  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)limb * S::N, pc.m, b);
   uint32_t* dst = out + poly * S::N + (size_t)tid * S::E;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
@@ -41,12 +40,12 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t*
 
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_inv_batch(const uint32_t* __restrict__ in,
-                                                                   uint32_t* __restrict__ out,
-                                                                   const uint2* __restrict__ inv_tw,
-                                                                   const PrimeConst* __restrict__ pcs,
-                                                                   uint32_t nlimb, uint32_t limb_base) {
+                                                                  uint32_t* __restrict__ out,
+                                                                  const uint2* __restrict__ inv_tw,
+                                                                  const PrimeConst* __restrict__ pcs,
+                                                                  uint32_t nlimb, uint32_t limb_base) {
   using S = Shape<LOGN, LE>;
-  extern __shared__ uint32_t lds[];
+  LdsBufs b{0};
   const int tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
@@ -55,8 +54,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_inv_batch(const uint32_t*
   uint32_t v[S::E];
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = src[i];
-  LdsPair lp{lds, lds + S::PADN, 0};
-  ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)limb * S::N, pc, lp);
+  ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)limb * S::N, pc, b);
   uint32_t* dst = out + poly * S::N;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = csub(v[i], pc.m);
@@ -72,21 +70,44 @@ __global__ void k_pointwise_mont(const uint32_t* __restrict__ a, const uint32_t*
   }
 }
 
+// The scatter table entry of register i of thread tid (position tid*E + i).  When the LDS
+// plan has room, the table is staged once per workgroup after the exchange buffers,
+// transposed to [i][tid] so that every read instruction touches consecutive words.
+template <int LOGN, int LE>
+__device__ __forceinline__ void stage_table(const uint32_t* __restrict__ scatter, int tid) {
+  using S = Shape<LOGN, LE>;
+  if constexpr (LdsPlan<LOGN, LE>::table_in_lds) {
+    uint32_t* tbl = ephdc_lds + LdsPlan<LOGN, LE>::exchange_words;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) tbl[i * S::T + tid] = scatter[tid * S::E + i];
+    lds_barrier();
+  }
+}
+
+template <int LOGN, int LE>
+__device__ __forceinline__ uint32_t table_entry(const uint32_t* __restrict__ scatter, int tid, int i) {
+  using S = Shape<LOGN, LE>;
+  if constexpr (LdsPlan<LOGN, LE>::table_in_lds) {
+    return ephdc_lds[LdsPlan<LOGN, LE>::exchange_words + i * S::T + tid];
+  } else {
+    return scatter[tid * S::E + i];
+  }
+}
+
 // ------------------------------------------------------------------ batch encoding
 // Slot values of query plaintext (g, m) at this thread's evaluation-side positions
-// tid*E + i, pre-multiplied by N^-1 mod t so the inverse transform needs no final scaling,
-// then the inverse transform mod t: mu in [0, t), coefficient layout tid + i*T.
+// tid*E + i (the slot feeding each position comes from the scatter table in LDS),
+// pre-multiplied by N^-1 mod t so that the inverse transform needs no final scaling; then
+// the inverse transform mod t: mu in [0, t), coefficient layout tid + i*T.
 template <int LOGN, int LE>
 __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const int8_t* __restrict__ hvg, uint32_t m,
-                                             const ScoreArgs& a, int tid, LdsPair& lp) {
+                                             const ScoreArgs& a, int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   const uint32_t t = a.pct.m;
-  // the table row is re-read every call (it stays in L1) rather than held in registers
-  const uint32_t* ent = opaque(a.scatter) + tid * S::E;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
     uint32_t val = 0;
-    const uint32_t e = ent[i];
+    const uint32_t e = table_entry<LOGN, LE>(a.scatter, tid, i);
     if (e != 0xFFFFFFFFu) {
       const uint32_t j = m * a.r + (e >> 16);
       if (j < a.D) {
@@ -97,7 +118,7 @@ __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const int8_
     }
     v[i] = val;
   }
-  ntt_inverse<LOGN, LE, false>(v, tid, a.inv_t, a.pct, lp);
+  ntt_inverse<LOGN, LE, false>(v, tid, a.inv_t, a.pct, b);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
 }
@@ -110,14 +131,16 @@ __device__ __forceinline__ uint32_t lift(uint32_t mu, uint32_t t, uint32_t m) {
 // ------------------------------------------------------------------ fused scoring kernel
 // Work item (split, group g, limb group): for m in the split's range, batch-encode query
 // plaintext (g, m), lift it into each limb of the group, transform it, and accumulate
-// ct_m[c][l] * pt[l] for c in {0, 1}.  Accumulators live in VGPRs for the whole range.
+// ct_m[c][l] * pt[l] for c in {0, 1}.  Accumulators live in VGPRs for the whole range;
+// the model values of a limb are requested before its transform so that their latency
+// overlaps the transform.
 template <int LOGN, int LE, int LG>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
   using S = Shape<LOGN, LE>;
   constexpr int E = S::E, N = S::N;
-  extern __shared__ uint32_t lds[];
-  LdsPair lp{lds, lds + S::PADN, 0};
+  LdsBufs b{0};
   const int tid = threadIdx.x;
+  stage_table<LOGN, LE>(a.scatter, tid);
   const uint32_t w = blockIdx.x;
   const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
   const uint32_t g = rest % a.G, split = rest / a.G;
@@ -138,22 +161,28 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
 
   for (uint32_t m = m0; m < m1; ++m) {
     uint32_t mu[E];
-    encode_query<LOGN, LE>(mu, hvg, m, a, tid, lp);
+    encode_query<LOGN, LE>(mu, hvg, m, a, tid, b);
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
       const uint32_t l = l0 + li;
       const PrimeConst pc = a.pcs[l];
+      const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
+      const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
+      uint32_t c0[E], c1[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        c0[i] = ct0[i];
+        c1[i] = ct1[i];
+      }
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = lift(mu[i], t, pc.m);
-      ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, lp);
-      const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
-      const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
+      ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, b);
       const uint32_t m2 = 2 * pc.m;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
-        acc[0][li][i] = csub(acc[0][li][i] + mont_mul(ct0[i], p[i], pc.m, pc.mneg_inv), m2);
-        acc[1][li][i] = csub(acc[1][li][i] + mont_mul(ct1[i], p[i], pc.m, pc.mneg_inv), m2);
+        acc[0][li][i] = csub(acc[0][li][i] + mont_mul(c0[i], p[i], pc.m, pc.mneg_inv), m2);
+        acc[1][li][i] = csub(acc[1][li][i] + mont_mul(c1[i], p[i], pc.m, pc.mneg_inv), m2);
       }
     }
   }
@@ -174,11 +203,10 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
 // the sum (for the rotation steps) or transform it straight to the coefficient domain.
 template <int LOGN, int LE, bool INVERT>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish(const uint32_t* __restrict__ partial,
-                                                                uint32_t* __restrict__ out, uint32_t S_,
-                                                                uint32_t L, const uint2* __restrict__ inv_tw,
-                                                                const PrimeConst* __restrict__ pcs) {
+                                                               uint32_t* __restrict__ out, uint32_t S_,
+                                                               uint32_t L, const uint2* __restrict__ inv_tw,
+                                                               const PrimeConst* __restrict__ pcs) {
   using S = Shape<LOGN, LE>;
-  extern __shared__ uint32_t lds[];
   const int tid = threadIdx.x;
   const uint32_t poly = blockIdx.x;  // (g*2 + c)*L + l
   const uint32_t l = poly % L, gc = poly / L;
@@ -193,8 +221,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish(const uint32_t* __
     for (int i = 0; i < S::E; ++i) v[i] = csub(v[i] + src[i], pc.m);
   }
   if constexpr (INVERT) {
-    LdsPair lp{lds, lds + S::PADN, 0};
-    ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)l * S::N, pc, lp);
+    LdsBufs b{0};
+    ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)l * S::N, pc, b);
     uint32_t* dst = out + (size_t)poly * S::N;
 #pragma unroll
     for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = csub(v[i], pc.m);
@@ -208,13 +236,13 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish(const uint32_t* __
 // Debug: the lifted query plaintext (g, m) in every limb, coefficient domain [L][N].
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_debug_plaintext(ScoreArgs a, uint32_t g, uint32_t m,
-                                                                         uint32_t* __restrict__ out) {
+                                                                        uint32_t* __restrict__ out) {
   using S = Shape<LOGN, LE>;
-  extern __shared__ uint32_t lds[];
-  LdsPair lp{lds, lds + S::PADN, 0};
+  LdsBufs b{0};
   const int tid = threadIdx.x;
+  stage_table<LOGN, LE>(a.scatter, tid);
   uint32_t mu[S::E];
-  encode_query<LOGN, LE>(mu, a.hv + (size_t)g * a.B, m, a, tid, lp);
+  encode_query<LOGN, LE>(mu, a.hv + (size_t)g * a.B, m, a, tid, b);
   for (uint32_t l = 0; l < a.L; ++l) {
     const uint32_t qm = a.pcs[l].m;
 #pragma unroll
@@ -229,9 +257,10 @@ namespace ephdc {
 
 using namespace ephdc_dev;
 
+// Dynamic LDS of every kernel of a shape (exchange buffers and, if it fits, the table).
 template <int LOGN, int LE>
 static size_t lds_bytes() {
-  return 2 * sizeof(uint32_t) * Shape<LOGN, LE>::PADN;
+  return sizeof(uint32_t) * LdsPlan<LOGN, LE>::words;
 }
 
 // Raises the dynamic-LDS limit of every kernel instantiation once per process.
@@ -257,6 +286,7 @@ static hipError_t prepare_shape() {
 hipError_t prepare_kernels() {
   static hipError_t once = [] {
     hipError_t e = prepare_shape<12, 3>();
+    if (e == hipSuccess) e = prepare_shape<13, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 4>();
     if (e == hipSuccess) e = prepare_shape<14, 4>();
     return e;
@@ -264,20 +294,35 @@ hipError_t prepare_kernels() {
   return once;
 }
 
-// Calls f with the compile-time shape (LOGN, LE) of a supported ring degree.
+// Calls f with the compile-time shape (LOGN, LE) of a supported ring degree; `le` selects
+// the values per thread (0: the default of the degree).
 template <class F>
-static hipError_t dispatch(int logn, F&& f) {
-  switch (logn) {
-    case 12: return f(std::integral_constant<int, 12>{}, std::integral_constant<int, 3>{});
-    case 13: return f(std::integral_constant<int, 13>{}, std::integral_constant<int, 4>{});
-    case 14: return f(std::integral_constant<int, 14>{}, std::integral_constant<int, 4>{});
+static hipError_t dispatch(int logn, int le, F&& f) {
+  using std::integral_constant;
+  switch (logn * 16 + le) {
+    case 12 * 16 + 0:
+    case 12 * 16 + 3: return f(integral_constant<int, 12>{}, integral_constant<int, 3>{});
+    case 13 * 16 + 3: return f(integral_constant<int, 13>{}, integral_constant<int, 3>{});
+    case 13 * 16 + 0:
+    case 13 * 16 + 4: return f(integral_constant<int, 13>{}, integral_constant<int, 4>{});
+    case 14 * 16 + 0:
+    case 14 * 16 + 4: return f(integral_constant<int, 14>{}, integral_constant<int, 4>{});
     default: return hipErrorInvalidValue;
   }
 }
 
+template <class F>
+static hipError_t dispatch(int logn, F&& f) {
+  return dispatch(logn, 0, f);
+}
+
+bool supported_shape(int logn, int le) {
+  return le == 0 || (logn == 12 && le == 3) || (logn == 13 && (le == 3 || le == 4)) || (logn == 14 && le == 4);
+}
+
 bool supported_logn(int logn) { return logn >= 12 && logn <= 14; }
 
-int max_limb_group(int logn) { return logn == 14 ? 1 : 4; }
+int max_limb_group(int logn) { return logn == 14 ? 1 : logn == 13 ? 2 : 4; }
 
 hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
@@ -312,9 +357,9 @@ hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_score(int logn, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-  return dispatch(logn, [&](auto lnc, auto lec) {
+  return dispatch(logn, le, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const dim3 grid(nblocks), block(Shape<LN, LEv>::T);
     const size_t sh = lds_bytes<LN, LEv>();

@@ -40,7 +40,8 @@ hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t 
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st);
 hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n, uint32_t N,
                                  const PrimeConst* pcs, uint32_t nlimb, hipStream_t st);
-hipError_t launch_score(int logn, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+bool supported_shape(int logn, int le);
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S,
                          uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st);
 hipError_t launch_debug_plaintext(int logn, const ScoreArgs& a, uint32_t g, uint32_t m, uint32_t* out,

@@ -16,6 +16,8 @@ struct ephdc_session {
   int device = 0;
   uint32_t max_Q = 0;
   uint32_t lg = 1, nlg = 1;        // limbs per fused work item, number of limb groups
+  uint32_t target_blocks = 256;    // workgroups per scoring launch the schedule aims at
+  uint32_t le = 0;                 // log2 values per thread of the scoring kernel (0: default)
   // device memory owned by the session
   uint2* d_fwd = nullptr;          // [nmod][N]
   uint2* d_inv = nullptr;          // [nmod][N]
@@ -36,7 +38,8 @@ struct ephdc_session {
 
 namespace {
 
-constexpr uint32_t kTargetBlocks = 256;  // one 1024-thread workgroup per CU on MI355X
+constexpr uint32_t kTargetBlocks = 256;  // one workgroup per CU on MI355X (256 CUs)
+constexpr uint32_t kMaxBlocks = 1024;    // largest schedule target the scratch is sized for
 
 ephdc_status hip_fail(hipError_t e, const char* what) {
   return fail(EPHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -123,7 +126,7 @@ Schedule schedule(const ephdc_session* s, uint32_t Q) {
   sc.G = s->P.G(Q);
   const uint32_t M = s->P.M();
   const uint32_t per = std::max<uint32_t>(1, sc.G * s->nlg);
-  uint32_t S = std::max<uint32_t>(1, (kTargetBlocks + per - 1) / per);
+  uint32_t S = std::max<uint32_t>(1, (s->target_blocks + per - 1) / per);
   S = std::min(S, M);
   sc.mchunk = (M + S - 1) / S;
   sc.S = (M + sc.mchunk - 1) / sc.mchunk;
@@ -214,7 +217,8 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   const size_t model_copy_words = M * 2 * P.L * N;
   const size_t key_words = P.r > 1 ? (size_t)P.log2r() * P.dnum * 2 * nm * N : 0;
   const uint32_t Gmax = P.G(max_Q);
-  s->partial_words = ((size_t)kTargetBlocks + (size_t)Gmax * s->nlg) * 2 * P.L * N;
+  // G*S <= target/nlg + G for any schedule, so this covers every target up to kMaxBlocks
+  s->partial_words = ((size_t)kMaxBlocks + (size_t)Gmax) * 2 * P.L * N;
 
   auto cleanup = [&](ephdc_status e) { free_session(s); return e; };
   if ((st = dev_alloc(s, &s->d_fwd, fwd.size(), "twiddles")) != EPHDC_OK) return cleanup(st);
@@ -283,12 +287,32 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
   if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
   ScoreArgs a = score_args(s, d_hv, Q, sc);
   hipEvent_t t0 = timed_begin(s, hs);
-  HIP_TRY(launch_score(P.logn, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
+  HIP_TRY(launch_score(P.logn, (int)s->le, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
   timed_end(s, 0, t0, hs);
   hipEvent_t t1 = timed_begin(s, hs);
   HIP_TRY(launch_finish(P.logn, true, s->d_partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
           "finish launch");
   timed_end(s, 1, t1, hs);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks, uint32_t values_per_thread) {
+  if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
+  if (values_per_thread) {
+    const int le = ilog2(values_per_thread);
+    if ((1u << le) != values_per_thread || !supported_shape(s->P.logn, le))
+      return fail(EPHDC_ERR_UNSUPPORTED, "no scoring kernel with that many values per thread for this N");
+    s->le = (uint32_t)le;
+  }
+  if (limb_group) {
+    if (limb_group > 4 || s->P.L % limb_group) return fail(EPHDC_ERR_ARG, "limb_group must divide L and be <= 4");
+    s->lg = limb_group;
+    s->nlg = s->P.L / limb_group;
+  }
+  if (blocks) {
+    if (blocks > kMaxBlocks) return fail(EPHDC_ERR_ARG, "blocks must be <= 1024");
+    s->target_blocks = blocks;
+  }
   return EPHDC_OK;
 }
 

@@ -119,3 +119,31 @@ def test_qbit_queries_score_exactly():
     assert np.array_equal(got.astype(np.int64), pipeline.score_ciphertexts(o, model, h))
     scores, _ = pipeline.decrypt_scores(o, s, got.astype(np.int64), 900)
     assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
+
+
+@pytest.mark.parametrize("N,L,K,D,Q", [(8192, 4, 7, 24, 2500), (4096, 3, 2, 30, 3000)])
+def test_every_schedule_gives_the_same_bits(N, L, K, D, Q):
+    """Schedule invariance (and a race canary): every shape, limb grouping and grid size
+    of the scoring kernel reproduces the oracle's score ciphertexts exactly."""
+    torch = torch_cuda()
+    o, e = make(N, L, D=D, K=K)
+    rng = np.random.default_rng(N + 7)
+    C = synth.class_hypervectors(8, K, D)
+    model = bfv.encrypt_model(o, bfv.secret_key(o, 8), C, 8)
+    h = rng.choice(np.array([-1, 1], dtype=np.int8), (Q, D))
+    want = pipeline.score_ciphertexts(o, model, h)
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=Q)
+    try:
+        d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
+        d_out = torch.empty(want.shape, dtype=torch.int32, device="cuda")
+        shapes = [16, 8] if N == 8192 else [8]
+        for vpt in shapes:
+            for lg in [g for g in (1, 2, 4) if L % g == 0] + ([3] if L % 3 == 0 else []):
+                for blocks in (7, 256, 1000):
+                    s.tune(lg, blocks, vpt)
+                    d_out.fill_(0)
+                    ep.ephdc_score_encrypted(s, d_hv, Q, d_out)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(to_host_u32(d_out).astype(np.int64), want), (vpt, lg, blocks)
+    finally:
+        s.close()
