@@ -42,12 +42,51 @@ MUL32_PEAK = 256 * 64 * 2.4e9
 MODMUL_PEAK = MUL32_PEAK / 3
 
 
-def algorithmic_modmuls(N: int, L: int, G: int, M: int) -> float:
-    """Modular multiplications of one scoring launch: per plaintext one inverse transform
-    mod t and L forward transforms ((N/2) log2 N butterflies each) plus 2L*N MAC products."""
-    logn = int(math.log2(N))
-    per_pt = (L + 1) * (N // 2) * logn + 2 * L * N
+def transform_mults(N: int) -> int:
+    """Modular multiplications of one length-N negacyclic transform: (N/2) log2 N butterflies."""
+    return (N // 2) * int(math.log2(N))
+
+
+def algorithmic_modmuls(kernel: str, N: int, L: int, G: int, M: int) -> float:
+    """Algorithmic modular multiplications of one launch over G groups x M plaintexts:
+    batch encoding is one inverse transform mod t per plaintext; the MAC is L forward
+    transforms plus 2L*N ct x pt products per plaintext (recomputed work not counted)."""
+    enc = transform_mults(N)
+    mac = L * transform_mults(N) + 2 * L * N
+    per_pt = {"k_encode_pt": enc, "k_mac": mac, "k_score": enc + mac}[kernel]
     return float(G) * M * per_pt
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 over the HIP sources; a traffic figure is valid only for the build it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_00737_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` recorded in profiles/<kernel>_<workload>_traffic.md by
+    two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain-copy calibration, or
+    None when the file is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np.ndarray, sample_m: int):
@@ -86,6 +125,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path shards by query group or model slice, "
@@ -96,6 +137,14 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}))
+        return 0
     w = WORKLOADS[args.workload]
     N, L, Q = w["N"], w["L"], w["Q"]
     q = ep.default_primes(N, L)
@@ -160,9 +209,15 @@ def main() -> int:
     ms_step = wall * 1e3 / args.steps
     value = Q * args.steps / wall
 
-    score_ms = prof["score"][0] / max(1, prof["score"][1])
-    modmuls = algorithmic_modmuls(N, L, G, prm.D)
-    achieved = modmuls / (score_ms * 1e-3)
+    def avg(stage):
+        tot, n = prof[stage]
+        return tot / n if n else 0.0
+
+    split = prof["mac"][1] > 0
+    kern, stage = ("k_mac", "mac") if split else ("k_score", "score")
+    k_ms = avg(stage)
+    modmuls = algorithmic_modmuls(kern, N, L, G, prm.D)
+    achieved = modmuls / (k_ms * 1e-3)
     result = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -178,15 +233,23 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "queries_per_step": Q, "groups": G,
                    "queries_per_ciphertext": ep.ephdc_queries_per_ct(prm),
-                   "model_ciphertexts": prm.D},
+                   "model_ciphertexts": prm.D, "schedule": "split" if split else "fused"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
-        "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]},
-        "roofline": {"bound": "alu", "kernel": "k_score", "achieved": round(achieved / 1e12, 4),
+        "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]},
+        "roofline": {"bound": "alu", "kernel": kern, "achieved": round(achieved / 1e12, 4),
                      "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
-                     "frac": round(achieved / MODMUL_PEAK, 4), "traffic": None,
-                     "per_launch_modmuls": modmuls, "avg_launch_ms": round(score_ms, 4)},
+                     "frac": round(achieved / MODMUL_PEAK, 4),
+                     "traffic": recorded_traffic(kern, args.workload),
+                     "per_launch_modmuls": modmuls, "avg_launch_ms": round(k_ms, 4)},
     }
+    if split:
+        e_ms = avg("encode_pt")
+        e_ops = algorithmic_modmuls("k_encode_pt", N, L, G, prm.D)
+        result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_pt",
+                                        "achieved": round(e_ops / (e_ms * 1e-3) / 1e12, 4),
+                                        "frac": round(e_ops / (e_ms * 1e-3) / MODMUL_PEAK, 4),
+                                        "avg_launch_ms": round(e_ms, 4)}
     sess.close()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m)

@@ -201,10 +201,14 @@ ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const ui
  *                      split into ranges until groups x ranges x limb groups reaches it
  *   values_per_thread  transform values held per thread (8 or 16 at N = 8192; the
  *                      workgroup has N / values_per_thread threads)
+ *   mode               1: one fused kernel batch-encodes and multiplies (the batch
+ *                      encoding is repeated per limb group); 2: split path, a batch-encode
+ *                      kernel writes each lifted plaintext once (into a session buffer of
+ *                      at most 512 MiB, allocated on first use) and a MAC kernel reads it
  * Results do not depend on the schedule.
  */
 ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks,
-                                uint32_t values_per_thread);
+                                uint32_t values_per_thread, uint32_t mode);
 
 /*
  * Kernel timing (diagnostics for benchmarks).  While enabled, every kernel launched by the
@@ -214,9 +218,11 @@ ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t 
  *   ms[1], count[1]  partial-sum reduction + output inverse transform (k_finish)
  *   ms[2], count[2]  HDC encoding kernel (k_hdc_encode)
  *   ms[3], count[3]  rotate-and-sum kernels (automorphism, key switching)
+ *   ms[4], count[4]  split path: batch-encode kernel (k_encode_pt)
+ *   ms[5], count[5]  split path: MAC kernel (k_mac)
  */
 ephdc_status ephdc_session_profile(ephdc_session* s, int enable);
-ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[4], uint64_t count[4]);
+ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[6], uint64_t count[6]);
 
 #ifdef __cplusplus
 }

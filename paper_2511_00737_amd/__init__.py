@@ -73,7 +73,7 @@ def lib() -> C.CDLL:
             "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                               C.c_void_p]),
             "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
-            "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
+            "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
             "ephdc_session_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), u64p]),
         }
         for name, (res, args) in sig.items():
@@ -257,20 +257,21 @@ class Session:
     def device_bytes(self) -> int:
         return lib().ephdc_session_device_bytes(self.handle)
 
-    def tune(self, limb_group: int = 0, blocks: int = 0, values_per_thread: int = 0) -> None:
-        """Schedule of the scoring kernel (see ephdc_session_tune); 0 keeps a setting."""
-        _check(lib().ephdc_session_tune(self.handle, limb_group, blocks, values_per_thread))
+    def tune(self, limb_group: int = 0, blocks: int = 0, values_per_thread: int = 0, mode: str | None = None) -> None:
+        """Schedule of the scoring kernel (see ephdc_session_tune); 0 / None keeps a setting."""
+        m = {None: 0, "fused": 1, "split": 2}[mode]
+        _check(lib().ephdc_session_tune(self.handle, limb_group, blocks, values_per_thread, m))
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every kernel launch with HIP events on its stream (see ephdc_session_profile)."""
         _check(lib().ephdc_session_profile(self.handle, 1 if enable else 0))
 
     def profile_read(self):
-        """{stage: (total ms, launches)} for score, finish, encode, rotate; resets the totals."""
-        ms = (C.c_double * 4)()
-        cnt = np.zeros(4, dtype=np.uint64)
+        """{stage: (total ms, launches)} per kernel stage (see ephdc_session_profile_read); resets them."""
+        ms = (C.c_double * 6)()
+        cnt = np.zeros(6, dtype=np.uint64)
         _check(lib().ephdc_session_profile_read(self.handle, ms, _ptr(cnt, C.c_uint64)))
-        names = ("score", "finish", "encode", "rotate")
+        names = ("score", "finish", "encode", "rotate", "encode_pt", "mac")
         return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(names)}
 
     def hv_stride(self, Q: int) -> int:

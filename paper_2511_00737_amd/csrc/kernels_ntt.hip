@@ -144,8 +144,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
   const uint32_t w = blockIdx.x;
   const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
   const uint32_t g = rest % a.G, split = rest / a.G;
-  const uint32_t m0 = split * a.mchunk;
-  const uint32_t m1 = min(a.M, m0 + a.mchunk);
+  const uint32_t m0 = a.m_base + split * a.mchunk;
+  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
   const uint32_t l0 = lgi * LG;
 
   uint32_t acc[2][LG][E];
@@ -177,6 +177,108 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = lift(mu[i], t, pc.m);
+      ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, b);
+      const uint32_t m2 = 2 * pc.m;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        acc[0][li][i] = csub(acc[0][li][i] + mont_mul(c0[i], p[i], pc.m, pc.mneg_inv), m2);
+        acc[1][li][i] = csub(acc[1][li][i] + mont_mul(c1[i], p[i], pc.m, pc.mneg_inv), m2);
+      }
+    }
+  }
+#pragma unroll
+  for (int li = 0; li < LG; ++li) {
+    const uint32_t l = l0 + li;
+    const uint32_t mm = a.pcs[l].m;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t* dst = a.partial + ((((size_t)g * a.S + split) * 2 + c) * a.L + l) * N + (size_t)tid * E;
+#pragma unroll
+      for (int i = 0; i < E; ++i) dst[i] = csub(acc[c][li][i], mm);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ split path
+// Batch encoding alone: work item (split, g) encodes query plaintexts (g, m) for m in the
+// split's range and stores their centred lifts, coefficient order, in a.pt[g][m][:].
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
+  using S = Shape<LOGN, LE>;
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  stage_table<LOGN, LE>(a.scatter, tid);
+  const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
+  const uint32_t m0 = a.m_base + split * a.mchunk;
+  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
+  const int8_t* hvg = a.hv + (size_t)g * a.B;
+  const uint32_t t = a.pct.m;
+  for (uint32_t m = m0; m < m1; ++m) {
+    uint32_t mu[S::E];
+    encode_query<LOGN, LE>(mu, hvg, m, a, tid, b);
+    int32_t* dst = a.pt + ((size_t)g * a.m_len + (m - a.m_base)) * S::N;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
+  }
+}
+
+// MAC alone: work item (split, g, limb group): for m in the split's range, read the lifted
+// plaintext (g, m), reduce it into each limb of the group, transform it and accumulate
+// ct_m[c][l] * pt[l].  The next plaintext and each limb's model values are requested ahead
+// of the transform that precedes their use.
+template <int LOGN, int LE, int LG>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
+  using S = Shape<LOGN, LE>;
+  constexpr int E = S::E, N = S::N;
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  const uint32_t w = blockIdx.x;
+  const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
+  const uint32_t g = rest % a.G, split = rest / a.G;
+  const uint32_t m0 = a.m_base + split * a.mchunk;
+  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
+  const uint32_t l0 = lgi * LG;
+
+  uint32_t acc[2][LG][E];
+#pragma unroll
+  for (int li = 0; li < LG; ++li)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t* src = a.partial + ((((size_t)g * a.S + split) * 2 + c) * a.L + l0 + li) * N + (size_t)tid * E;
+#pragma unroll
+      for (int i = 0; i < E; ++i) acc[c][li][i] = a.accumulate ? src[i] : 0u;
+    }
+
+  // plaintext (g, m) of the chunk starts at ((g * m_len) + (m - m_base)) * N
+  const int32_t* ptg = a.pt + (size_t)g * a.m_len * N + tid;
+  int32_t nxt[E];
+  if (m0 < m1) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m0 - a.m_base) * N + i * S::T];
+  }
+  for (uint32_t m = m0; m < m1; ++m) {
+    int32_t cur[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) cur[i] = nxt[i];
+    if (m + 1 < m1) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m + 1 - a.m_base) * N + i * S::T];
+    }
+#pragma unroll
+    for (int li = 0; li < LG; ++li) {
+      const uint32_t l = l0 + li;
+      const PrimeConst pc = a.pcs[l];
+      const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
+      const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
+      uint32_t c0[E], c1[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        c0[i] = ct0[i];
+        c1[i] = ct1[i];
+      }
+      uint32_t p[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
       ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, b);
       const uint32_t m2 = 2 * pc.m;
 #pragma unroll
@@ -277,6 +379,10 @@ static hipError_t prepare_shape() {
   set((const void*)k_score<LOGN, LE, 2>);
   set((const void*)k_score<LOGN, LE, 3>);
   set((const void*)k_score<LOGN, LE, 4>);
+  set((const void*)k_encode_pt<LOGN, LE>);
+  set((const void*)k_mac<LOGN, LE, 1>);
+  set((const void*)k_mac<LOGN, LE, 2>);
+  set((const void*)k_mac<LOGN, LE, 4>);
   set((const void*)k_finish<LOGN, LE, true>);
   set((const void*)k_finish<LOGN, LE, false>);
   set((const void*)k_debug_plaintext<LOGN, LE>);
@@ -322,7 +428,6 @@ bool supported_shape(int logn, int le) {
 
 bool supported_logn(int logn) { return logn >= 12 && logn <= 14; }
 
-int max_limb_group(int logn) { return logn == 14 ? 1 : logn == 13 ? 2 : 4; }
 
 hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
@@ -368,6 +473,31 @@ hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t n
       case 2: k_score<LN, LEv, 2><<<grid, block, sh, st>>>(a); break;
       case 3: k_score<LN, LEv, 3><<<grid, block, sh, st>>>(a); break;
       case 4: k_score<LN, LEv, 4><<<grid, block, sh, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  return dispatch(logn, le, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    k_encode_pt<LN, LEv><<<dim3(nblocks), dim3(Shape<LN, LEv>::T), lds_bytes<LN, LEv>(), st>>>(a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  return dispatch(logn, le, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const dim3 grid(nblocks), block(Shape<LN, LEv>::T);
+    const size_t sh = lds_bytes<LN, LEv>();
+    switch (lg) {
+      case 1: k_mac<LN, LEv, 1><<<grid, block, sh, st>>>(a); break;
+      case 2: k_mac<LN, LEv, 2><<<grid, block, sh, st>>>(a); break;
+      case 4: k_mac<LN, LEv, 4><<<grid, block, sh, st>>>(a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

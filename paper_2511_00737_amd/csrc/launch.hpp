@@ -20,6 +20,13 @@ struct ScoreArgs {
   PrimeConst pct;           // constants of t
   uint32_t tninv, tninvp;   // N^-1 mod t and Shoup companion
   uint32_t L, M, D, r, hv_stride, B, G, S, mchunk, NLG;
+  // work covers model ciphertexts [m_base, m_base + m_len); splits cut that range
+  uint32_t m_base, m_len;
+  // split path: lifted plaintext coefficients [G][m_len][N] (int32 in (-t/2, t/2]) written
+  // by the batch-encode kernel and read by the MAC kernel; with accumulate set, the MAC
+  // kernel adds to the partial sums already stored instead of overwriting them
+  int32_t* pt;
+  uint32_t accumulate;
 };
 
 }  // namespace ephdc_dev
@@ -31,7 +38,6 @@ using ephdc_dev::ScoreArgs;
 
 hipError_t prepare_kernels();
 bool supported_logn(int logn);
-int max_limb_group(int logn);
 
 hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
@@ -41,6 +47,9 @@ hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t 
 hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n, uint32_t N,
                                  const PrimeConst* pcs, uint32_t nlimb, hipStream_t st);
 hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+// split path: batch-encode every (g, m) plaintext of the launch into a.pt, then MAC
+hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 bool supported_shape(int logn, int le);
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S,
                          uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st);

@@ -11,6 +11,9 @@
 
 using namespace ephdc;
 
+// Profiling stages (see ephdc_session_profile_read).
+enum : int { kStFused = 0, kStFinish = 1, kStHdc = 2, kStRotate = 3, kStEncodePt = 4, kStMac = 5, kStages = 6 };
+
 struct ephdc_session {
   ParamSet P;
   int device = 0;
@@ -18,6 +21,9 @@ struct ephdc_session {
   uint32_t lg = 1, nlg = 1;        // limbs per fused work item, number of limb groups
   uint32_t target_blocks = 256;    // workgroups per scoring launch the schedule aims at
   uint32_t le = 0;                 // log2 values per thread of the scoring kernel (0: default)
+  bool split = false;              // batch-encode and MAC as two kernels (else one fused kernel)
+  int32_t* d_pt = nullptr;         // split path: lifted plaintexts of one chunk [G][m_len][N]
+  size_t pt_cap = 0;               // plaintexts d_pt holds
   // device memory owned by the session
   uint2* d_fwd = nullptr;          // [nmod][N]
   uint2* d_inv = nullptr;          // [nmod][N]
@@ -33,7 +39,7 @@ struct ephdc_session {
   size_t device_bytes = 0;
   // kernel timing: pairs of events per stage, resolved when read
   bool profile = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kStages];
 };
 
 namespace {
@@ -94,7 +100,7 @@ void timed_end(ephdc_session* s, int stage, hipEvent_t start, hipStream_t hs) {
 void free_session(ephdc_session* s) {
   if (!s) return;
   drop_events(s);
-  void* ptrs[] = {s->d_fwd, s->d_inv, s->d_inv_t, s->d_pc, s->d_scatter, s->d_model, s->d_gk, s->d_partial};
+  void* ptrs[] = {s->d_fwd, s->d_inv, s->d_inv_t, s->d_pc, s->d_scatter, s->d_model, s->d_gk, s->d_partial, s->d_pt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -156,7 +162,47 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   a.S = sc.S;
   a.mchunk = sc.mchunk;
   a.NLG = s->nlg;
+  a.m_base = 0;
+  a.m_len = P.M();
+  a.pt = s->d_pt;
+  a.accumulate = 0;
   return a;
+}
+
+constexpr size_t kPtBytes = (size_t)512 << 20;  // bound on the split path's plaintext buffer
+
+// Split path: the model range is processed in chunks of m_len ciphertexts so that the
+// lifted plaintexts of a chunk (G x m_len x N int32) fit the session's buffer; the MAC
+// kernel of every chunk after the first adds into the stored partial sums.
+hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, hipStream_t hs) {
+  const ParamSet& P = s->P;
+  const uint32_t M = P.M();
+  if (sc.G > s->pt_cap) return hipErrorInvalidValue;  // cannot happen: cap >= G(max_Q) >= G
+  const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, s->pt_cap / sc.G));
+  const uint32_t blocks_enc = std::max<uint32_t>(1, s->target_blocks);
+  for (uint32_t base = 0; base < M; base += mc) {
+    const uint32_t len = std::min(mc, M - base);
+    ScoreArgs c = a;
+    c.m_base = base;
+    c.m_len = len;
+    c.accumulate = base > 0;
+    // encode: G x Se work items over the chunk
+    uint32_t Se = std::max<uint32_t>(1, std::min(len, (blocks_enc + sc.G - 1) / sc.G));
+    c.mchunk = (len + Se - 1) / Se;
+    Se = (len + c.mchunk - 1) / c.mchunk;
+    hipEvent_t t0 = timed_begin(s, hs);
+    hipError_t e = launch_encode_pt(P.logn, (int)s->le, c, sc.G * Se, hs);
+    if (e != hipSuccess) return e;
+    timed_end(s, kStEncodePt, t0, hs);
+    // MAC: G x S x nlg work items; the S splits of every chunk cover the chunk
+    c.S = sc.S;
+    c.mchunk = (len + sc.S - 1) / sc.S;
+    t0 = timed_begin(s, hs);
+    e = launch_mac(P.logn, (int)s->le, (int)s->lg, c, sc.G * sc.S * s->nlg, hs);
+    if (e != hipSuccess) return e;
+    timed_end(s, kStMac, t0, hs);
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -185,11 +231,13 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   s->P = P;
   s->max_Q = max_Q;
   (void)hipGetDevice(&s->device);
-  const int cap = max_limb_group(P.logn);
+  // default schedule (measured on MI355X at N = 8192, L = 4, 4096 queries): split path,
+  // 8 values per thread, one limb per MAC work item, 512 workgroups
+  s->split = true;
+  s->le = P.logn == 13 ? 3 : 0;
   s->lg = 1;
-  for (int g = cap; g >= 1; --g)
-    if (P.L % g == 0) { s->lg = (uint32_t)g; break; }
-  s->nlg = P.L / s->lg;
+  s->nlg = P.L;
+  s->target_blocks = 512;
 
   const uint32_t N = P.N, nm = P.nmod();
   std::vector<uint2> fwd((size_t)nm * N), inv((size_t)nm * N), invt(N);
@@ -271,7 +319,7 @@ ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const in
   hipEvent_t t0 = timed_begin(s, hs);
   HIP_TRY(launch_hdc_encode(d_x, d_base, d_hv, Q, P.F, P.D, P.G(Q) * P.B(), P.qbits, P.qshift, hs),
           "encode launch");
-  timed_end(s, 2, t0, hs);
+  timed_end(s, kStHdc, t0, hs);
   return EPHDC_OK;
 }
 
@@ -286,18 +334,33 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
   if ((size_t)sc.G * sc.S * 2 * P.L * P.N > s->partial_words) return fail(EPHDC_ERR_BUFFER, "scratch too small");
   if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
   ScoreArgs a = score_args(s, d_hv, Q, sc);
-  hipEvent_t t0 = timed_begin(s, hs);
-  HIP_TRY(launch_score(P.logn, (int)s->le, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
-  timed_end(s, 0, t0, hs);
+  if (s->split) {
+    if (!s->d_pt) {
+      // at least one plaintext per group of the largest batch (max_Q) per chunk
+      const size_t cap = std::max<size_t>(P.G(s->max_Q), kPtBytes / (4 * (size_t)P.N));
+      ephdc_status st2 = dev_alloc(s, &s->d_pt, cap * P.N, "split-path plaintexts");
+      if (st2 != EPHDC_OK) return st2;
+      s->pt_cap = cap;
+    }
+    a.pt = s->d_pt;
+    HIP_TRY(score_split(s, a, sc, hs), "split score launch");
+  } else {
+    hipEvent_t t0 = timed_begin(s, hs);
+    HIP_TRY(launch_score(P.logn, (int)s->le, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
+    timed_end(s, kStFused, t0, hs);
+  }
   hipEvent_t t1 = timed_begin(s, hs);
   HIP_TRY(launch_finish(P.logn, true, s->d_partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
           "finish launch");
-  timed_end(s, 1, t1, hs);
+  timed_end(s, kStFinish, t1, hs);
   return EPHDC_OK;
 }
 
-ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks, uint32_t values_per_thread) {
+ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks, uint32_t values_per_thread,
+                                uint32_t mode) {
   if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
+  if (mode > 2) return fail(EPHDC_ERR_ARG, "mode must be 0 (keep), 1 (fused) or 2 (split)");
+  if (mode) s->split = mode == 2;
   if (values_per_thread) {
     const int le = ilog2(values_per_thread);
     if ((1u << le) != values_per_thread || !supported_shape(s->P.logn, le))
@@ -306,6 +369,7 @@ ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t 
   }
   if (limb_group) {
     if (limb_group > 4 || s->P.L % limb_group) return fail(EPHDC_ERR_ARG, "limb_group must divide L and be <= 4");
+    if (limb_group == 3 && s->split) return fail(EPHDC_ERR_UNSUPPORTED, "the split path takes limb groups of 1, 2 or 4");
     s->lg = limb_group;
     s->nlg = s->P.L / limb_group;
   }
@@ -322,9 +386,9 @@ ephdc_status ephdc_session_profile(ephdc_session* s, int enable) {
   return EPHDC_OK;
 }
 
-ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[4], uint64_t count[4]) {
+ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[6], uint64_t count[6]) {
   if (!s || !ms || !count) return fail(EPHDC_ERR_ARG, "NULL argument");
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kStages; ++k) {
     ms[k] = 0.0;
     count[k] = 0;
     for (auto& pr : s->ev[k]) {

@@ -137,13 +137,16 @@ def test_every_schedule_gives_the_same_bits(N, L, K, D, Q):
         d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
         d_out = torch.empty(want.shape, dtype=torch.int32, device="cuda")
         shapes = [16, 8] if N == 8192 else [8]
-        for vpt in shapes:
-            for lg in [g for g in (1, 2, 4) if L % g == 0] + ([3] if L % 3 == 0 else []):
-                for blocks in (7, 256, 1000):
-                    s.tune(lg, blocks, vpt)
-                    d_out.fill_(0)
-                    ep.ephdc_score_encrypted(s, d_hv, Q, d_out)
-                    torch.cuda.synchronize()
-                    assert np.array_equal(to_host_u32(d_out).astype(np.int64), want), (vpt, lg, blocks)
+        for mode in ("fused", "split"):
+            for vpt in shapes:
+                lgs = [g for g in (1, 2, 4) if L % g == 0] + ([3] if L % 3 == 0 and mode == "fused" else [])
+                for lg in lgs:
+                    for blocks in (7, 256, 1000):
+                        s.tune(lg, blocks, vpt, mode)
+                        d_out.fill_(0)
+                        ep.ephdc_score_encrypted(s, d_hv, Q, d_out)
+                        torch.cuda.synchronize()
+                        got = to_host_u32(d_out).astype(np.int64)
+                        assert np.array_equal(got, want), (mode, vpt, lg, blocks)
     finally:
         s.close()
