@@ -24,10 +24,10 @@ LIB = os.path.join(HERE, "libephdc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
-HIP_SOURCES = ["kernels_ntt.hip", "kernels_hdc.hip", "session.hip"]
+HIP_SOURCES = ["kernels_ntt.hip", "kernels_ks.hip", "kernels_hdc.hip", "session.hip"]
 CXX_SOURCES = ["host_crypto.cpp"]
 
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-fconstexpr-steps=20000000",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include")]
 CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-pthread", "-I", os.path.join(ROOT, "include")]

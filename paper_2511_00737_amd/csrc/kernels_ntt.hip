@@ -6,30 +6,45 @@
 #include <type_traits>
 
 #include "device_ntt.hpp"
+#include "kernel_common.hpp"
 #include "launch.hpp"
 
 namespace ephdc_dev {
 
 // ------------------------------------------------------------------ batched transforms
-// One workgroup per polynomial; polynomial `poly` is taken mod modulus limb_base + poly % nlimb.
+// One workgroup per polynomial; polynomial `poly` is taken mod modulus limb_base + poly % nlimb
+// and sits at in + (poly / per) * stride + (poly % per) * N (likewise for the output), so
+// that sub-arrays of interleaved buffers can be transformed in place or gathered.
+struct PolyMap {
+  uint32_t in_per, out_per;
+  size_t in_stride, out_stride;
+  __device__ __forceinline__ size_t in_off(size_t poly, int N) const {
+    return (poly / in_per) * in_stride + (poly % in_per) * (size_t)N;
+  }
+  __device__ __forceinline__ size_t out_off(size_t poly, int N) const {
+    return (poly / out_per) * out_stride + (poly % out_per) * (size_t)N;
+  }
+};
+
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t* __restrict__ in,
                                                                   uint32_t* __restrict__ out,
                                                                   const uint2* __restrict__ fwd_tw,
                                                                   const PrimeConst* __restrict__ pcs,
-                                                                  uint32_t nlimb, uint32_t limb_base, int mont) {
+                                                                  uint32_t nlimb, uint32_t limb_base, int mont,
+                                                                  PolyMap pm) {
   using S = Shape<LOGN, LE>;
   LdsBufs b{0};
   const int tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
   const PrimeConst pc = pcs[limb];
-  const uint32_t* src = in + poly * S::N;
+  const uint32_t* src = in + pm.in_off(poly, S::N);
   uint32_t v[S::E];
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = src[tid + i * S::T];
   ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)limb * S::N, pc.m, b);
-  uint32_t* dst = out + poly * S::N + (size_t)tid * S::E;
+  uint32_t* dst = out + pm.out_off(poly, S::N) + (size_t)tid * S::E;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
     uint32_t x = reduce4(v[i], pc.m);
@@ -43,19 +58,19 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_inv_batch(const uint32_t*
                                                                   uint32_t* __restrict__ out,
                                                                   const uint2* __restrict__ inv_tw,
                                                                   const PrimeConst* __restrict__ pcs,
-                                                                  uint32_t nlimb, uint32_t limb_base) {
+                                                                  uint32_t nlimb, uint32_t limb_base, PolyMap pm) {
   using S = Shape<LOGN, LE>;
   LdsBufs b{0};
   const int tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
   const PrimeConst pc = pcs[limb];
-  const uint32_t* src = in + poly * S::N + (size_t)tid * S::E;
+  const uint32_t* src = in + pm.in_off(poly, S::N) + (size_t)tid * S::E;
   uint32_t v[S::E];
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = src[i];
   ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)limb * S::N, pc, b);
-  uint32_t* dst = out + poly * S::N;
+  uint32_t* dst = out + pm.out_off(poly, S::N);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = csub(v[i], pc.m);
 }
@@ -224,9 +239,10 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
 
 // MAC alone: work item (split, g, limb group): for m in the split's range, read the lifted
 // plaintext (g, m), reduce it into each limb of the group, transform it and accumulate
-// ct_m[c][l] * pt[l].  The next plaintext and each limb's model values are requested ahead
-// of the transform that precedes their use.
-template <int LOGN, int LE, int LG>
+// ct_m[c][l] * pt[l].  With PF, the next plaintext and each limb's model values are
+// requested ahead of the transform that precedes their use (more registers: used where
+// the register budget allows it).
+template <int LOGN, int LE, int LG, bool PF>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
   using S = Shape<LOGN, LE>;
   constexpr int E = S::E, N = S::N;
@@ -252,17 +268,22 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
   // plaintext (g, m) of the chunk starts at ((g * m_len) + (m - m_base)) * N
   const int32_t* ptg = a.pt + (size_t)g * a.m_len * N + tid;
   int32_t nxt[E];
-  if (m0 < m1) {
+  if (PF && m0 < m1) {
 #pragma unroll
     for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m0 - a.m_base) * N + i * S::T];
   }
   for (uint32_t m = m0; m < m1; ++m) {
     int32_t cur[E];
+    if constexpr (PF) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) cur[i] = nxt[i];
-    if (m + 1 < m1) {
+      for (int i = 0; i < E; ++i) cur[i] = nxt[i];
+      if (m + 1 < m1) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m + 1 - a.m_base) * N + i * S::T];
+        for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m + 1 - a.m_base) * N + i * S::T];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cur[i] = ptg[(size_t)(m - a.m_base) * N + i * S::T];
     }
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
@@ -271,15 +292,24 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
       const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
       const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
       uint32_t c0[E], c1[E];
+      if constexpr (PF) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        c0[i] = ct0[i];
-        c1[i] = ct1[i];
+        for (int i = 0; i < E; ++i) {
+          c0[i] = ct0[i];
+          c1[i] = ct1[i];
+        }
       }
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
       ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, b);
+      if constexpr (!PF) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          c0[i] = ct0[i];
+          c1[i] = ct1[i];
+        }
+      }
       const uint32_t m2 = 2 * pc.m;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -299,6 +329,12 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
       for (int i = 0; i < E; ++i) dst[i] = csub(acc[c][li][i], mm);
     }
   }
+}
+
+// Prefetching fits the register budget except for the 1024-thread shape of N = 16384.
+template <int LOGN, int LE>
+constexpr bool mac_prefetch() {
+  return Shape<LOGN, LE>::T <= 512 || LE <= 3;
 }
 
 // Sum the S partial accumulators of every (g, c, l) (evaluation domain) and either store
@@ -359,12 +395,6 @@ namespace ephdc {
 
 using namespace ephdc_dev;
 
-// Dynamic LDS of every kernel of a shape (exchange buffers and, if it fits, the table).
-template <int LOGN, int LE>
-static size_t lds_bytes() {
-  return sizeof(uint32_t) * LdsPlan<LOGN, LE>::words;
-}
-
 // Raises the dynamic-LDS limit of every kernel instantiation once per process.
 template <int LOGN, int LE>
 static hipError_t prepare_shape() {
@@ -380,9 +410,9 @@ static hipError_t prepare_shape() {
   set((const void*)k_score<LOGN, LE, 3>);
   set((const void*)k_score<LOGN, LE, 4>);
   set((const void*)k_encode_pt<LOGN, LE>);
-  set((const void*)k_mac<LOGN, LE, 1>);
-  set((const void*)k_mac<LOGN, LE, 2>);
-  set((const void*)k_mac<LOGN, LE, 4>);
+  set((const void*)k_mac<LOGN, LE, 1, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_mac<LOGN, LE, 2, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_mac<LOGN, LE, 4, mac_prefetch<LOGN, LE>()>);
   set((const void*)k_finish<LOGN, LE, true>);
   set((const void*)k_finish<LOGN, LE, false>);
   set((const void*)k_debug_plaintext<LOGN, LE>);
@@ -391,65 +421,57 @@ static hipError_t prepare_shape() {
 
 hipError_t prepare_kernels() {
   static hipError_t once = [] {
+    hipError_t ks = prepare_ks_kernels();
+    if (ks != hipSuccess) return ks;
     hipError_t e = prepare_shape<12, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 4>();
     if (e == hipSuccess) e = prepare_shape<14, 4>();
+    if (e == hipSuccess) e = prepare_shape<14, 5>();
     return e;
   }();
   return once;
 }
 
-// Calls f with the compile-time shape (LOGN, LE) of a supported ring degree; `le` selects
-// the values per thread (0: the default of the degree).
-template <class F>
-static hipError_t dispatch(int logn, int le, F&& f) {
-  using std::integral_constant;
-  switch (logn * 16 + le) {
-    case 12 * 16 + 0:
-    case 12 * 16 + 3: return f(integral_constant<int, 12>{}, integral_constant<int, 3>{});
-    case 13 * 16 + 3: return f(integral_constant<int, 13>{}, integral_constant<int, 3>{});
-    case 13 * 16 + 0:
-    case 13 * 16 + 4: return f(integral_constant<int, 13>{}, integral_constant<int, 4>{});
-    case 14 * 16 + 0:
-    case 14 * 16 + 4: return f(integral_constant<int, 14>{}, integral_constant<int, 4>{});
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <class F>
-static hipError_t dispatch(int logn, F&& f) {
-  return dispatch(logn, 0, f);
-}
-
 bool supported_shape(int logn, int le) {
-  return le == 0 || (logn == 12 && le == 3) || (logn == 13 && (le == 3 || le == 4)) || (logn == 14 && le == 4);
+  return le == 0 || (logn == 12 && le == 3) || (logn == 13 && (le == 3 || le == 4)) ||
+         (logn == 14 && (le == 4 || le == 5));
 }
 
 bool supported_logn(int logn) { return logn >= 12 && logn <= 14; }
 
 
+static PolyMap make_map(const BatchMap& m, uint32_t N) {
+  PolyMap pm;
+  pm.in_per = m.in_per ? m.in_per : 1;
+  pm.out_per = m.out_per ? m.out_per : 1;
+  pm.in_stride = m.in_per ? m.in_stride : N;
+  pm.out_stride = m.out_per ? m.out_stride : N;
+  return pm;
+}
+
 hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
-                            hipStream_t st) {
+                            hipStream_t st, const BatchMap& map) {
   if (npolys == 0) return hipSuccess;
   return dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const size_t sh = lds_bytes<LN, LEv>();
-    k_fwd_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(in, out, tw, pcs, nlimb,
-                                                                                      limb_base, mont ? 1 : 0);
+    k_fwd_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(
+        in, out, tw, pcs, nlimb, limb_base, mont ? 1 : 0, make_map(map, 1u << LN));
     return hipGetLastError();
   });
 }
 
 hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* itw,
-                            const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st) {
+                            const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st,
+                            const BatchMap& map) {
   if (npolys == 0) return hipSuccess;
   return dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const size_t sh = lds_bytes<LN, LEv>();
-    k_inv_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(in, out, itw, pcs, nlimb,
-                                                                                      limb_base);
+    k_inv_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(
+        in, out, itw, pcs, nlimb, limb_base, make_map(map, 1u << LN));
     return hipGetLastError();
   });
 }
@@ -495,9 +517,9 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nbl
     const dim3 grid(nblocks), block(Shape<LN, LEv>::T);
     const size_t sh = lds_bytes<LN, LEv>();
     switch (lg) {
-      case 1: k_mac<LN, LEv, 1><<<grid, block, sh, st>>>(a); break;
-      case 2: k_mac<LN, LEv, 2><<<grid, block, sh, st>>>(a); break;
-      case 4: k_mac<LN, LEv, 4><<<grid, block, sh, st>>>(a); break;
+      case 1: k_mac<LN, LEv, 1, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
+      case 2: k_mac<LN, LEv, 2, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
+      case 4: k_mac<LN, LEv, 4, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -29,21 +29,59 @@ struct ScoreArgs {
   uint32_t accumulate;
 };
 
+// Constants of hybrid key switching (Shoup pairs (w, floor(w*2^32/m)) for the modulus
+// each multiplication is taken in).
+struct KsConst {
+  const uint2* up_inv;    // [L]: (Q_j/q_i)^-1 mod q_i, i in digit j
+  const uint2* up_mul;    // [dnum][ds][nmod]: (Q_j/q_i) mod m
+  const uint2* down_inv;  // [alpha]: (P/p_k)^-1 mod p_k
+  const uint2* down_mul;  // [alpha][L]: (P/p_k) mod q_i
+  const uint2* pinv;      // [L]: P^-1 mod q_i
+  uint32_t L, alpha, dnum, ds, nmod, G;
+};
+
+// Buffers of the rotate-and-sum steps (all evaluation domain unless noted).
+struct RotateArgs {
+  KsConst k;
+  const uint32_t* perm;    // [log2 r][N] automorphism permutations of evaluation points
+  const uint32_t* ksk;     // [log2 r][dnum][2][nmod][N] switching keys, Montgomery form
+  uint32_t* acc;           // [G][2][L][N] accumulators, updated in place
+  uint32_t* R;             // [G][2][L][N] rotated accumulators
+  uint32_t* D;             // [G][L][N] coefficient domain
+  uint32_t* Y;             // [G][dnum][nmod][N]
+  uint32_t* KS;            // [G][2][nmod][N]
+  uint32_t* XP;            // [G][2][alpha][N] coefficient domain
+  const uint2* fwd_tw;
+  const uint2* inv_tw;
+  const PrimeConst* pcs;
+};
+
 }  // namespace ephdc_dev
 
 namespace ephdc {
 
+using ephdc_dev::KsConst;
+using ephdc_dev::RotateArgs;
+
 using ephdc_dev::PrimeConst;
 using ephdc_dev::ScoreArgs;
+
+// Addressing of batched transforms: polynomial p is read from in + (p / in_per) * in_stride +
+// (p % in_per) * N (likewise written); in_per / out_per = 0 means densely packed.
+struct BatchMap {
+  uint32_t in_per = 0, out_per = 0;
+  size_t in_stride = 0, out_stride = 0;
+};
 
 hipError_t prepare_kernels();
 bool supported_logn(int logn);
 
 hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
-                            hipStream_t st);
+                            hipStream_t st, const BatchMap& map = BatchMap{});
 hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* itw,
-                            const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st);
+                            const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st,
+                            const BatchMap& map = BatchMap{});
 hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n, uint32_t N,
                                  const PrimeConst* pcs, uint32_t nlimb, hipStream_t st);
 hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
@@ -55,6 +93,9 @@ hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_
                          uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st);
 hipError_t launch_debug_plaintext(int logn, const ScoreArgs& a, uint32_t g, uint32_t m, uint32_t* out,
                                   hipStream_t st);
+
+// One rotate-and-sum step (Galois element of step `step`): acc <- acc + KeySwitch(sigma(acc)).
+hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipStream_t st);
 
 // HDC projection: hv[j][q] = quantise(sum_f (x[q][f]-128) * base[f][j]) for q < Q, 0 for Q <= q < stride.
 hipError_t launch_hdc_encode(const uint8_t* x, const int8_t* base, int8_t* hv, uint32_t Q, uint32_t F,

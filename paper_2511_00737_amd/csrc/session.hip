@@ -34,6 +34,11 @@ struct ephdc_session {
   uint32_t* d_gk = nullptr;        // [log2r][dnum][2][nmod][N] evaluation domain, Montgomery form
   uint32_t* d_partial = nullptr;   // scratch: partial accumulators
   size_t partial_words = 0;
+  // rotate-and-sum (r > 1)
+  uint32_t* d_perm = nullptr;      // [log2r][N] automorphism permutations of evaluation points
+  uint2* d_ksc = nullptr;          // key-switching constants, pointed into by ks
+  uint32_t* d_rot = nullptr;       // workspace: acc, R, D, Y, KS, XP sized for G(max_Q)
+  KsConst ks{};
   PrimeConst pct{};
   uint32_t tninv = 0, tninvp = 0;
   size_t device_bytes = 0;
@@ -100,7 +105,8 @@ void timed_end(ephdc_session* s, int stage, hipEvent_t start, hipStream_t hs) {
 void free_session(ephdc_session* s) {
   if (!s) return;
   drop_events(s);
-  void* ptrs[] = {s->d_fwd, s->d_inv, s->d_inv_t, s->d_pc, s->d_scatter, s->d_model, s->d_gk, s->d_partial, s->d_pt};
+  void* ptrs[] = {s->d_fwd,  s->d_inv,     s->d_inv_t, s->d_pc,   s->d_scatter, s->d_model,
+                  s->d_gk,   s->d_partial, s->d_pt,    s->d_perm, s->d_ksc,     s->d_rot};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -205,6 +211,92 @@ hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, hipStr
   return hipSuccess;
 }
 
+uint2 shoup_pair(uint64_t w, uint32_t m) {
+  w %= m;
+  return make_uint2((uint32_t)w, (uint32_t)((w << 32) / m));
+}
+
+// Key-switching constants of every digit and modulus, laid out as KsConst describes:
+// up_inv[L] | up_mul[dnum][ds][nmod] | down_inv[alpha] | down_mul[alpha][L] | pinv[L].
+std::vector<uint2> ks_constants(const ParamSet& P) {
+  const uint32_t L = P.L, A = P.alpha, dn = P.dnum, ds = P.digit_size(), nm = P.nmod();
+  std::vector<uint2> c;
+  c.reserve(L + (size_t)dn * ds * nm + A + (size_t)A * L + L);
+  // Q_j / q_i reduced mod m: product of the other limbs of digit j
+  auto qhat = [&](uint32_t j, uint32_t i, uint64_t m) {
+    uint64_t v = 1 % m;
+    for (uint32_t k = j * ds; k < std::min(L, (j + 1) * ds); ++k)
+      if (k != i) v = mulmod64(v, P.q[k] % m, m);
+    return v;
+  };
+  auto phat = [&](uint32_t kk, uint64_t m) {
+    uint64_t v = 1 % m;
+    for (uint32_t k = 0; k < A; ++k)
+      if (k != kk) v = mulmod64(v, P.p[k] % m, m);
+    return v;
+  };
+  for (uint32_t i = 0; i < L; ++i) c.push_back(shoup_pair(inv_mod(qhat(i / ds, i, P.q[i]), P.q[i]), P.q[i]));
+  for (uint32_t j = 0; j < dn; ++j)
+    for (uint32_t d = 0; d < ds; ++d)
+      for (uint32_t m = 0; m < nm; ++m) {
+        const uint32_t i = j * ds + d;
+        const uint32_t mod = P.modulus(m);
+        c.push_back(i < L ? shoup_pair(qhat(j, i, mod), mod) : make_uint2(0, 0));
+      }
+  for (uint32_t k = 0; k < A; ++k) c.push_back(shoup_pair(inv_mod(phat(k, P.p[k]), P.p[k]), P.p[k]));
+  for (uint32_t k = 0; k < A; ++k)
+    for (uint32_t i = 0; i < L; ++i) c.push_back(shoup_pair(phat(k, P.q[i]), P.q[i]));
+  for (uint32_t i = 0; i < L; ++i) {
+    uint64_t pm = 1;
+    for (uint32_t k = 0; k < A; ++k) pm = mulmod64(pm, P.p[k] % P.q[i], P.q[i]);
+    c.push_back(shoup_pair(inv_mod(pm, P.q[i]), P.q[i]));
+  }
+  return c;
+}
+
+// perm[i][x] = y with 2*brev(y)+1 = g_i * (2*brev(x)+1) mod 2N: evaluation position x of
+// sigma_g(a) holds a at the point that sigma_g maps position x's point to.
+std::vector<uint32_t> automorphism_perms(const ParamSet& P) {
+  const uint32_t N = P.N, lg = P.logn, steps = P.log2r();
+  std::vector<uint32_t> perm((size_t)steps * N);
+  for (uint32_t i = 0; i < steps; ++i) {
+    const uint64_t g = galois_element(P, i);
+    for (uint32_t x = 0; x < N; ++x) {
+      const uint64_t e = (g * (2ull * bitrev(x, lg) + 1)) % (2ull * N);
+      perm[(size_t)i * N + x] = bitrev((uint32_t)((e - 1) / 2), lg);
+    }
+  }
+  return perm;
+}
+
+// Words of the rotation workspace for G groups: acc, R [G][2][L][N]; D [G][L][N];
+// Y [G][dnum][nmod][N]; KS [G][2][nmod][N]; XP [G][2][alpha][N].
+size_t rotate_words(const ParamSet& P, uint32_t G) {
+  const size_t N = P.N;
+  return (size_t)G * N * (4 * P.L + P.L + (size_t)P.dnum * P.nmod() + 2 * P.nmod() + 2 * P.alpha);
+}
+
+RotateArgs rotate_args(const ephdc_session* s, uint32_t G) {
+  const ParamSet& P = s->P;
+  const size_t N = P.N;
+  RotateArgs r{};
+  r.k = s->ks;
+  r.k.G = G;
+  r.perm = s->d_perm;
+  r.ksk = s->d_gk;
+  uint32_t* w = s->d_rot;
+  r.acc = w;  w += (size_t)G * 2 * P.L * N;
+  r.R = w;    w += (size_t)G * 2 * P.L * N;
+  r.D = w;    w += (size_t)G * P.L * N;
+  r.Y = w;    w += (size_t)G * P.dnum * P.nmod() * N;
+  r.KS = w;   w += (size_t)G * 2 * P.nmod() * N;
+  r.XP = w;
+  r.fwd_tw = s->d_fwd;
+  r.inv_tw = s->d_inv;
+  r.pcs = s->d_pc;
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -277,6 +369,27 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   if ((st = dev_alloc(s, &s->d_model, model_copy_words, "model")) != EPHDC_OK) return cleanup(st);
   if ((st = dev_alloc(s, &s->d_gk, key_words, "Galois keys")) != EPHDC_OK) return cleanup(st);
   if ((st = dev_alloc(s, &s->d_partial, s->partial_words, "partial sums")) != EPHDC_OK) return cleanup(st);
+  std::vector<uint32_t> perm;
+  std::vector<uint2> ksc;
+  if (P.r > 1) {
+    perm = automorphism_perms(P);
+    ksc = ks_constants(P);
+    if ((st = dev_alloc(s, &s->d_perm, perm.size(), "automorphism tables")) != EPHDC_OK) return cleanup(st);
+    if ((st = dev_alloc(s, &s->d_ksc, ksc.size(), "key-switching constants")) != EPHDC_OK) return cleanup(st);
+    if ((st = dev_alloc(s, &s->d_rot, rotate_words(P, Gmax), "rotation workspace")) != EPHDC_OK) return cleanup(st);
+    KsConst& k = s->ks;
+    const uint2* c = s->d_ksc;
+    k.up_inv = c;    c += P.L;
+    k.up_mul = c;    c += (size_t)P.dnum * P.digit_size() * nm;
+    k.down_inv = c;  c += P.alpha;
+    k.down_mul = c;  c += (size_t)P.alpha * P.L;
+    k.pinv = c;
+    k.L = P.L;
+    k.alpha = P.alpha;
+    k.dnum = P.dnum;
+    k.ds = P.digit_size();
+    k.nmod = nm;
+  }
 
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -285,6 +398,10 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   chk(hipMemcpyAsync(s->d_inv_t, invt.data(), invt.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_pc, pcs.data(), pcs.size() * sizeof(PrimeConst), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_scatter, scatter.data(), scatter.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
+  if (P.r > 1) {
+    chk(hipMemcpyAsync(s->d_perm, perm.data(), perm.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
+    chk(hipMemcpyAsync(s->d_ksc, ksc.data(), ksc.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
+  }
   if (e == hipSuccess)
     e = launch_fwd_batch(P.logn, d_model_ct, s->d_model, M * 2 * P.L, s->d_fwd, s->d_pc, P.L, 0, true, hs);
   if (e == hipSuccess && key_words)
@@ -328,7 +445,6 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
   if (!s || !d_hv || !d_score_ct) return fail(EPHDC_ERR_ARG, "NULL argument");
   if (Q == 0 || Q > s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, max_Q]");
   const ParamSet& P = s->P;
-  if (P.r > 1) return fail(EPHDC_ERR_UNSUPPORTED, "rotate-and-sum is not built yet");
   hipStream_t hs = (hipStream_t)stream;
   Schedule sc = schedule(s, Q);
   if ((size_t)sc.G * sc.S * 2 * P.L * P.N > s->partial_words) return fail(EPHDC_ERR_BUFFER, "scratch too small");
@@ -349,10 +465,25 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
     HIP_TRY(launch_score(P.logn, (int)s->le, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
     timed_end(s, kStFused, t0, hs);
   }
+  if (P.r == 1) {
+    hipEvent_t t1 = timed_begin(s, hs);
+    HIP_TRY(launch_finish(P.logn, true, s->d_partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
+            "finish launch");
+    timed_end(s, kStFinish, t1, hs);
+    return EPHDC_OK;
+  }
+  // r > 1: sum the partials in the evaluation domain, fold the r blocks of every row with
+  // log2 r rotations, then return to the coefficient domain
+  RotateArgs ra = rotate_args(s, sc.G);
   hipEvent_t t1 = timed_begin(s, hs);
-  HIP_TRY(launch_finish(P.logn, true, s->d_partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
+  HIP_TRY(launch_finish(P.logn, false, s->d_partial, ra.acc, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
           "finish launch");
   timed_end(s, kStFinish, t1, hs);
+  hipEvent_t t2 = timed_begin(s, hs);
+  for (uint32_t i = 0; i < P.log2r(); ++i) HIP_TRY(launch_rotate_step(P.logn, ra, i, hs), "rotate launch");
+  HIP_TRY(launch_inv_batch(P.logn, ra.acc, d_score_ct, (size_t)sc.G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs),
+          "output transform launch");
+  timed_end(s, kStRotate, t2, hs);
   return EPHDC_OK;
 }
 

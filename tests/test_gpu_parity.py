@@ -150,3 +150,51 @@ def test_every_schedule_gives_the_same_bits(N, L, K, D, Q):
                         assert np.array_equal(got, want), (mode, vpt, lg, blocks)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("N,L,alpha,dnum,r,K,D,Q", [
+    (4096, 3, 1, 3, 2, 3, 40, 700),     # one limb per digit
+    (4096, 4, 2, 3, 4, 5, 33, 900),     # third digit empty (ds = 2), ragged model tail
+    (8192, 5, 2, 3, 4, 7, 48, 1300),    # ragged last digit
+    (4096, 2, 2, 1, 8, 2, 24, 300),     # one digit holding every limb
+])
+def test_rotate_and_sum_matches_oracle(N, L, alpha, dnum, r, K, D, Q):
+    """Folded packings: MAC, log2 r rotations with hybrid key switching and the output
+    transform reproduce the oracle's score ciphertexts, and they decrypt to h . C mod t."""
+    o, e = make(N, L, D=D, K=K, r=r, alpha=alpha, dnum=dnum)
+    torch_cuda()
+    rng = np.random.default_rng(N + r + D)
+    C = synth.class_hypervectors(r + D, K, D)
+    s = bfv.secret_key(o, 11)
+    model = bfv.encrypt_model(o, s, C, 11)
+    gk = bfv.galois_keys(o, s, 12)
+    h = rng.choice(np.array([-1, 1], dtype=np.int8), (Q, D))
+    got = score_on_gpu(e, model.astype(np.uint32), h, gk=gk.astype(np.uint32))
+    G = o.groups(Q)
+    check = sorted({0, G // 2, G - 1})
+    want = pipeline.score_ciphertexts(o, model, h, gk, groups=check)
+    assert got.shape == (G, 2, L, N)
+    for i, g in enumerate(check):
+        assert np.array_equal(got[g].astype(np.int64), want[i]), g
+    scores, _ = pipeline.decrypt_scores(o, s, got.astype(np.int64), Q)
+    assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
+
+
+def test_rotations_at_large_parameters():
+    """N = 16384 with 8 limbs, 2 special primes, 4 digits and r = 8 (three rotations):
+    sampled groups match the oracle bit for bit and every score decrypts exactly."""
+    N, L, alpha, dnum, r, K, D, Q = 16384, 8, 2, 4, 8, 26, 24, 200
+    o, e = make(N, L, D=D, K=K, r=r, alpha=alpha, dnum=dnum)
+    torch_cuda()
+    rng = np.random.default_rng(16384)
+    C = synth.class_hypervectors(26, K, D)
+    s = bfv.secret_key(o, 13)
+    model = bfv.encrypt_model(o, s, C, 13)
+    gk = bfv.galois_keys(o, s, 14)
+    h = rng.choice(np.array([-1, 1], dtype=np.int8), (Q, D))
+    got = score_on_gpu(e, model.astype(np.uint32), h, gk=gk.astype(np.uint32))
+    G = o.groups(Q)
+    want = pipeline.score_ciphertexts(o, model, h, gk, groups=[G - 1])
+    assert np.array_equal(got[G - 1].astype(np.int64), want[0])
+    scores, _ = pipeline.decrypt_scores(o, s, got.astype(np.int64), Q)
+    assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
