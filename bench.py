@@ -1,11 +1,12 @@
 """Benchmark of the EP-HDC client-side path on one MI355X.
 
 One step = one request of the workload: HDC encoding of the queries (int8 MFMA) and
-homomorphic scoring against the device-resident encrypted model (fused batch-encode +
-ct x pt MAC kernel, then reduction + output transform), with every input already in HBM.
+homomorphic scoring against the device-resident encrypted model (batch encoding, ct x pt
+MAC, reduction, rotate-and-sum when the packing folds r > 1 blocks per row, and the output
+transform), with every input already in HBM.
 Prints one JSON line (see the keys below).
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -34,6 +35,12 @@ WORKLOADS = {
     "c2": dict(N=8192, L=4, F=2304, D=4096, K=7, Q=4096, images=True,
                desc="BFV N=8192, 4x30-bit limbs, t=65537; HDC F=2304 (48x48 Gaussian-blob images), "
                     "D=4096, K=7; 4096 queries per request, one request per launch"),
+    # large parameters: 8 ciphertext limbs + 2 special primes, hybrid key switching with 4
+    # digits, 8 blocks folded per row (3 rotations per score ciphertext)
+    "c4": dict(N=16384, L=8, alpha=2, dnum=4, r=8, F=2304, D=10240, K=26, Q=16384, images=True, cpu_sample_m=24,
+               desc="BFV N=16384, 8x30-bit limbs + 2 special primes, dnum=4, t=65537; r=8 blocks per "
+                    "row folded by 3 rotate-and-sum steps; HDC F=2304 (48x48 Gaussian-blob images), "
+                    "D=10240, K=26; 16384 queries per request"),
 }
 
 # Peak of the integer VALU for 30-bit modular multiplication on MI355X: 256 CUs x 64 lanes
@@ -90,30 +97,40 @@ def recorded_traffic(kernel: str, workload: str):
 
 
 def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np.ndarray, sample_m: int):
-    """The oracle, timed on the host: HDC encoding of a few queries and the MAC of query
-    group 0 over the first `sample_m` model ciphertexts, scaled to inferences/s."""
+    """The oracle, timed on the host: HDC encoding of a few queries, the MAC of query group 0
+    over the first `sample_m` model ciphertexts (scaled to the whole model) and, for folded
+    packings, the rotate-and-sum of that group, turned into inferences/s."""
     from oracle import bfv, hdc
     from oracle.params import Params as OParams
-    o = OParams(N=prm.N, q=tuple(prm.q), F=prm.F, D=prm.D, K=prm.K)
+    kw = dict(N=prm.N, q=tuple(prm.q), p=tuple(prm.p), F=prm.F, K=prm.K, r=prm.r, dnum=prm.dnum)
+    o = OParams(D=prm.D, **kw)
     s = bfv.secret_key(o, 0)
-    osub = OParams(N=prm.N, q=tuple(prm.q), F=prm.F, D=sample_m, K=prm.K)
-    model = bfv.encrypt_model(osub, s, C[:, :sample_m], 0)
+    sample_m = min(sample_m, o.M)
+    osub = OParams(D=sample_m * o.r, **kw)
+    model = bfv.encrypt_model(osub, s, C[:, :sample_m * o.r], 0)
     nq = 16
     t0 = time.perf_counter()
     h16 = hdc.encode(x[:nq], base)
     t_hdc = (time.perf_counter() - t0) / nq
-    h = np.zeros((o.B, sample_m), dtype=np.int8)
-    h[:nq] = h16[:, :sample_m]
+    h = np.zeros((o.B, sample_m * o.r), dtype=np.int8)
+    h[:nq] = h16[:, :sample_m * o.r]
     t0 = time.perf_counter()
-    bfv.mac(osub, model, h, 0)
+    acc = bfv.mac(osub, model, h, 0)
     t_mac = time.perf_counter() - t0
-    t_group = t_mac * o.M / sample_m + t_hdc * o.B
+    t_rot = 0.0
+    if o.r > 1:
+        gk = bfv.galois_keys(o, s, 0)
+        t0 = time.perf_counter()
+        bfv.rotate_and_sum(o, acc, gk)
+        t_rot = time.perf_counter() - t0
+    t_group = t_mac * o.M / sample_m + t_rot + t_hdc * o.B
+    rot = f" and its rotate-and-sum ({o.log2r} rotations)" if o.r > 1 else ""
     return {"value": o.B / t_group, "unit": "inferences/s", "cores": 1, "kind": "oracle",
-            "sample": f"HDC encoding of {nq} queries and the ct x pt MAC of query group 0 "
-                      f"({o.B} queries) over model ciphertexts 0..{sample_m - 1} of {o.M}, "
-                      f"scaled linearly to the full model; numpy, single thread "
+            "sample": f"HDC encoding of {nq} queries, the ct x pt MAC of query group 0 "
+                      f"({o.B} queries) over model ciphertexts 0..{sample_m - 1} of {o.M} "
+                      f"scaled linearly to the full model{rot}; numpy, single thread "
                       f"(host has {os.cpu_count()} cores)",
-            "seconds": round(t_mac + t_hdc * nq, 2)}
+            "seconds": round(t_mac + t_rot + t_hdc * nq, 2)}
 
 
 def main() -> int:
@@ -123,7 +140,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-m", type=int, default=256)
+    ap.add_argument("--cpu-sample-m", type=int, default=0,
+                    help="model ciphertexts in the oracle's timed sample (0: the workload's default)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
@@ -147,8 +165,11 @@ def main() -> int:
         return 0
     w = WORKLOADS[args.workload]
     N, L, Q = w["N"], w["L"], w["Q"]
-    q = ep.default_primes(N, L)
-    prm = ep.Params(N=N, q=tuple(q), F=w["F"], D=w["D"], K=w["K"])
+    alpha, r = w.get("alpha", 0), w.get("r", 1)
+    primes = ep.default_primes(N, L + alpha)
+    prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=w["F"], D=w["D"], K=w["K"], r=r,
+                    dnum=w.get("dnum", 0))
+    M = ep.ephdc_num_model_ct(prm)
     seed = args.seed
     t0 = time.perf_counter()
     x = synth.blob_images(seed, Q) if w["images"] else synth.uniform_features(seed, Q, w["F"])
@@ -156,7 +177,7 @@ def main() -> int:
     C = synth.class_hypervectors(seed, w["K"], w["D"])
     t_inputs = time.perf_counter() - t0
     t0 = time.perf_counter()
-    sk, _ = ep.ephdc_keygen(prm, seed)
+    sk, gk = ep.ephdc_keygen(prm, seed)
     model = ep.ephdc_encrypt_model(prm, sk, C, seed)
     t_encrypt = time.perf_counter() - t0
     print(f"[bench] {args.workload}: inputs {t_inputs:.1f}s, keygen+encrypt {t_encrypt:.1f}s (host)",
@@ -164,8 +185,9 @@ def main() -> int:
 
     dev = torch.device("cuda")
     d_model = torch.from_numpy(model.view(np.int32)).to(dev)
-    sess = ep.Session(prm, d_model, max_Q=Q)
-    del d_model
+    d_gk = torch.from_numpy(gk.view(np.int32)).to(dev) if r > 1 else None
+    sess = ep.Session(prm, d_model, d_gk, max_Q=Q)
+    del d_model, d_gk, model
     stride = sess.hv_stride(Q)
     G = sess.num_groups(Q)
     d_x = torch.from_numpy(x).to(dev)
@@ -209,14 +231,16 @@ def main() -> int:
     ms_step = wall * 1e3 / args.steps
     value = Q * args.steps / wall
 
-    def avg(stage):
-        tot, n = prof[stage]
-        return tot / n if n else 0.0
+    def per_launch(kernel, stage):
+        """(algorithmic modmuls of one launch, average launch ms): a step may cut the model
+        range into several equal chunks, each one launch of the kernel."""
+        tot_ms, n = prof[stage]
+        per_step = algorithmic_modmuls(kernel, N, L, G, M)
+        return per_step * args.steps / n, tot_ms / n
 
     split = prof["mac"][1] > 0
     kern, stage = ("k_mac", "mac") if split else ("k_score", "score")
-    k_ms = avg(stage)
-    modmuls = algorithmic_modmuls(kern, N, L, G, prm.D)
+    modmuls, k_ms = per_launch(kern, stage)
     achieved = modmuls / (k_ms * 1e-3)
     result = {
         "metric": METRIC,
@@ -233,10 +257,12 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "queries_per_step": Q, "groups": G,
                    "queries_per_ciphertext": ep.ephdc_queries_per_ct(prm),
-                   "model_ciphertexts": prm.D, "schedule": "split" if split else "fused"},
+                   "model_ciphertexts": M, "rotations_per_group": int(math.log2(r)),
+                   "schedule": "split" if split else "fused"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
-        "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
+        "launches_per_step": {k: v[1] // args.steps for k, v in prof.items() if v[1]},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": round(achieved / 1e12, 4),
                      "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
                      "frac": round(achieved / MODMUL_PEAK, 4),
@@ -244,15 +270,14 @@ def main() -> int:
                      "per_launch_modmuls": modmuls, "avg_launch_ms": round(k_ms, 4)},
     }
     if split:
-        e_ms = avg("encode_pt")
-        e_ops = algorithmic_modmuls("k_encode_pt", N, L, G, prm.D)
+        e_ops, e_ms = per_launch("k_encode_pt", "encode_pt")
         result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_pt",
                                         "achieved": round(e_ops / (e_ms * 1e-3) / 1e12, 4),
                                         "frac": round(e_ops / (e_ms * 1e-3) / MODMUL_PEAK, 4),
                                         "avg_launch_ms": round(e_ms, 4)}
     sess.close()
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m)
+        result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m or w.get("cpu_sample_m", 256))
     print(json.dumps(result), flush=True)
     return 0
 
