@@ -224,6 +224,70 @@ ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t 
 ephdc_status ephdc_session_profile(ephdc_session* s, int enable);
 ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[6], uint64_t count[6]);
 
+/* ---------------------------------------------------------------- request batches
+ * Many clients' requests scored together: every kernel stage of the scoring path runs as one
+ * persistent launch over the work items (request, query group, model-ciphertext segment,
+ * limb group) of all requests, so requests of 1 query and of thousands, and models of
+ * different K, D and r, share the GPU in the same launches.  Requests whose sessions have
+ * different N or ciphertext primes are scored by one launch sequence per parameter set.
+ * The batched form computes exactly the per-request ciphertexts of ephdc_score_encrypted.
+ */
+typedef struct {
+  ephdc_session* session;  /* the tenant: encrypted model, Galois keys, tables */
+  const uint8_t* d_x;      /* [Q][F] features to HDC-encode first, or NULL when d_hv holds them */
+  const int8_t* d_base;    /* [F][D] base hypervectors (read only with d_x) */
+  int8_t* d_hv;            /* [D][ephdc_hv_stride(Q)] query hypervectors */
+  uint32_t Q;              /* 1 <= Q <= the session's max_Q */
+  uint32_t* d_score_ct;    /* out: [G][2][L][N] score ciphertexts, coefficient domain */
+} ephdc_request;
+
+typedef struct ephdc_batch ephdc_batch;
+
+/*
+ * Plans a batch: validates every request, builds the work lists and uploads them, and
+ * allocates the batch's device memory (partial sums, plaintext chunk buffer, rotation
+ * workspace of folded requests).  The batch borrows the sessions and every buffer named by
+ * the requests; the caller keeps them alive and unmodified in shape until destroy.
+ * Errors: EPHDC_ERR_ARG (NULL, empty, Q out of range), EPHDC_ERR_UNSUPPORTED (sessions on
+ * different devices, encoding constraints of ephdc_encode_queries), EPHDC_ERR_OOM.
+ */
+ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out);
+ephdc_status ephdc_batch_destroy(ephdc_batch* b);
+size_t ephdc_batch_device_bytes(const ephdc_batch* b);
+
+/*
+ * Schedule of a batch, five values (0 keeps a setting; results never depend on it):
+ *   [0] mode               1 fused (one persistent batch-encode + MAC launch), 2 split
+ *                          (batch-encode launch + MAC launch per chunk of plaintexts)
+ *   [1] values_per_thread  transform values per thread (as in ephdc_session_tune)
+ *   [2] limb_group         limbs per MAC work item (1, 2 or 4, dividing L)
+ *   [3] seg_len            model ciphertexts per work item
+ *   [4] grid               workgroups of each persistent launch
+ * A change drops a captured graph.  ephdc_batch_schedule reads the current values.
+ */
+ephdc_status ephdc_batch_tune(ephdc_batch* b, const uint32_t schedule[5]);
+ephdc_status ephdc_batch_schedule(const ephdc_batch* b, uint32_t schedule[5]);
+
+/*
+ * Autotuner: times candidate schedules of this batch on `stream` (coordinate descent over
+ * the five settings, each candidate run once to warm up and timed over `reps` runs with
+ * HIP events) and keeps the fastest.  Writes its schedule and mean time per run.
+ */
+ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, uint32_t schedule[5],
+                                  double* best_ms);
+
+/* Enqueues the whole batch on `stream` (replays the captured graph if there is one). */
+ephdc_status ephdc_batch_run(ephdc_batch* b, void* stream);
+
+/*
+ * Captures the batch's launches on `stream` (not the null stream) into a HIP graph; later
+ * ephdc_batch_run calls replay it with one launch call.  The graph holds kernel nodes only.
+ */
+ephdc_status ephdc_batch_capture(ephdc_batch* b, void* stream);
+
+/* Convenience: plan, run on `stream`, wait for it and free the plan. */
+ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,11 @@ class _CParams(C.Structure):
                 ("qbits", C.c_uint32), ("qshift", C.c_uint32)]
 
 
+class _CRequest(C.Structure):
+    _fields_ = [("session", C.c_void_p), ("d_x", C.c_void_p), ("d_base", C.c_void_p), ("d_hv", C.c_void_p),
+                ("Q", C.c_uint32), ("d_score_ct", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -75,6 +80,15 @@ def lib() -> C.CDLL:
             "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
             "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
             "ephdc_session_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), u64p]),
+            "ephdc_batch_create": (C.c_int, [C.POINTER(_CRequest), C.c_uint32, C.POINTER(C.c_void_p)]),
+            "ephdc_batch_destroy": (C.c_int, [C.c_void_p]),
+            "ephdc_batch_device_bytes": (C.c_size_t, [C.c_void_p]),
+            "ephdc_batch_tune": (C.c_int, [C.c_void_p, u32p]),
+            "ephdc_batch_schedule": (C.c_int, [C.c_void_p, u32p]),
+            "ephdc_batch_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, u32p, C.POINTER(C.c_double)]),
+            "ephdc_batch_run": (C.c_int, [C.c_void_p, C.c_void_p]),
+            "ephdc_batch_capture": (C.c_int, [C.c_void_p, C.c_void_p]),
+            "ephdc_score_many": (C.c_int, [C.POINTER(_CRequest), C.c_uint32, C.c_void_p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -319,3 +333,90 @@ def ephdc_debug_polymul(s: Session, d_a, d_b, count: int, d_out, stream=None) ->
     nb = count * s.prm.N * 4
     _check(lib().ephdc_debug_polymul(s.handle, _dptr(d_a, nb), _dptr(d_b, nb), count, _dptr(d_out, nb),
                                      _stream(stream)))
+
+
+# ------------------------------------------------------------------ request batches
+@dataclass
+class Request:
+    """One client request of a batch (see ephdc_request): device tensors of the request."""
+    session: "Session"
+    d_hv: object
+    Q: int
+    d_score_ct: object
+    d_x: object = None
+    d_base: object = None
+
+
+def _c_requests(reqs):
+    arr = (_CRequest * len(reqs))()
+    for i, r in enumerate(reqs):
+        s, p = r.session, r.session.prm
+        _, hv_bytes, out_bytes = _sizes(s, r.Q)
+        arr[i].session = s.handle
+        arr[i].d_x = _dptr(r.d_x, r.Q * p.F) if r.d_x is not None else None
+        arr[i].d_base = _dptr(r.d_base, p.F * p.D) if r.d_x is not None else None
+        arr[i].d_hv = _dptr(r.d_hv, hv_bytes)
+        arr[i].Q = r.Q
+        arr[i].d_score_ct = _dptr(r.d_score_ct, out_bytes)
+    return arr
+
+
+class Batch:
+    """Owns an ephdc_batch: the work lists of many requests scored by shared launches."""
+
+    def __init__(self, reqs):
+        self.reqs = list(reqs)  # keeps the sessions and tensors alive
+        arr = _c_requests(self.reqs)
+        h = C.c_void_p()
+        _check(lib().ephdc_batch_create(arr, len(self.reqs), C.byref(h)))
+        self.handle = h
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib().ephdc_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self) -> int:
+        return lib().ephdc_batch_device_bytes(self.handle)
+
+    def tune(self, mode: str | None = None, values_per_thread: int = 0, limb_group: int = 0, seg_len: int = 0,
+             grid: int = 0) -> None:
+        sc = np.array([{None: 0, "fused": 1, "split": 2}[mode], values_per_thread, limb_group, seg_len, grid],
+                      dtype=np.uint32)
+        _check(lib().ephdc_batch_tune(self.handle, _ptr(sc, C.c_uint32)))
+
+    def schedule(self) -> dict:
+        sc = np.zeros(5, dtype=np.uint32)
+        _check(lib().ephdc_batch_schedule(self.handle, _ptr(sc, C.c_uint32)))
+        return {"mode": {1: "fused", 2: "split"}[int(sc[0])], "values_per_thread": int(sc[1]),
+                "limb_group": int(sc[2]), "seg_len": int(sc[3]), "grid": int(sc[4])}
+
+    def autotune(self, reps: int = 2, stream=None):
+        """(schedule dict, ms per run of the best schedule)."""
+        sc = np.zeros(5, dtype=np.uint32)
+        ms = C.c_double()
+        _check(lib().ephdc_batch_autotune(self.handle, _stream(stream), reps, _ptr(sc, C.c_uint32), C.byref(ms)))
+        return self.schedule(), ms.value
+
+    def run(self, stream=None) -> None:
+        _check(lib().ephdc_batch_run(self.handle, _stream(stream)))
+
+    def capture(self, stream) -> None:
+        """Capture the batch into a HIP graph on `stream` (a torch.cuda.Stream, not the null stream)."""
+        _check(lib().ephdc_batch_capture(self.handle, _stream(stream)))
+
+
+def ephdc_batch_create(reqs) -> Batch:
+    return Batch(reqs)
+
+
+def ephdc_score_many(reqs, stream=None) -> None:
+    reqs = list(reqs)
+    _check(lib().ephdc_score_many(_c_requests(reqs), len(reqs), _stream(stream)))

@@ -1,0 +1,496 @@
+// Request batches: many clients' requests scored by persistent launches over one work list
+// per parameter set (N and ciphertext primes), optionally captured in a HIP graph, with a
+// schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <vector>
+
+#include "session.hpp"
+
+using namespace ephdc;
+
+namespace {
+
+// Plaintext chunk buffer of the split path: at most this many bytes, and at least one
+// segment of the longest allowed length.
+constexpr size_t kBatchPtBytes = (size_t)1 << 30;
+constexpr uint32_t kMaxSegLen = 1024;
+
+// One parameter set of the batch and the device-side work list of its requests.
+struct Part {
+  int logn = 0;
+  uint32_t N = 0, L = 0;
+  const ephdc_session* ref = nullptr;  // twiddles and constants come from this session
+  std::vector<uint32_t> reqs;          // indices into ephdc_batch::reqs
+  std::vector<std::pair<uint32_t, uint32_t>> chunks;  // split path: segment ranges
+  uint32_t nseg = 0, nfin = 0, nslot = 0;
+  ReqDesc* d_reqs = nullptr;
+  Segment* d_segs = nullptr;
+  FinishItem* d_fin = nullptr;
+  uint32_t* d_partial = nullptr;
+  size_t seg_cap = 0, fin_cap = 0, partial_cap = 0;  // allocated element counts
+  int32_t* d_pt = nullptr;
+  size_t pt_cap = 0;  // plaintexts d_pt holds
+};
+
+}  // namespace
+
+struct ephdc_batch {
+  std::vector<ephdc_request> reqs;
+  std::vector<Part> parts;
+  std::vector<uint32_t*> rot_ws;  // per request: rotation workspace (r > 1), else nullptr
+  int device = 0;
+  // schedule
+  uint32_t mode = 2, vpt = 0, lg = 1, seg_len = 128, grid = 512;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t device_bytes = 0;
+  std::vector<void*> owned;  // every device allocation of the batch
+};
+
+namespace {
+
+template <class T>
+ephdc_status balloc(ephdc_batch* b, T** p, size_t count, const char* what) {
+  *p = nullptr;
+  if (count == 0) return EPHDC_OK;
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(EPHDC_ERR_OOM, std::string("hipMalloc failed for ") + what);
+  }
+  b->owned.push_back((void*)*p);
+  b->device_bytes += count * sizeof(T);
+  return EPHDC_OK;
+}
+
+template <class T>
+void bfree(ephdc_batch* b, T*& p, size_t count) {
+  if (!p) return;
+  auto it = std::find(b->owned.begin(), b->owned.end(), (void*)p);
+  if (it != b->owned.end()) b->owned.erase(it);
+  (void)hipFree(p);
+  b->device_bytes -= count * sizeof(T);
+  p = nullptr;
+}
+
+void drop_graph(ephdc_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+void free_batch(ephdc_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  for (void* p : b->owned) (void)hipFree(p);
+  delete b;
+}
+
+// log2 values per thread of the batch's kernels: the setting, else 8 values below
+// N = 16384 and 16 there (the shapes measured fastest for the split path).
+int batch_le(const ephdc_batch* b, int logn) { return b->vpt ? ilog2(b->vpt) : (logn >= 14 ? 4 : 3); }
+
+// Builds the segments and output items of one parameter set under the batch's schedule and
+// uploads them (growing the device arrays when needed).
+//   segment order: request, then model range, then group -- the groups of a request that
+//   read the same model ciphertexts run side by side, so the model tile is shared in L2;
+//   slot numbering: request, then group, then range -- the slots of one output are adjacent.
+ephdc_status plan_part(ephdc_batch* b, Part& pt) {
+  std::vector<ReqDesc> rd;
+  std::vector<Segment> segs;
+  std::vector<FinishItem> fin;
+  uint32_t slot = 0;
+  for (uint32_t li = 0; li < pt.reqs.size(); ++li) {
+    const uint32_t ri = pt.reqs[li];
+    const ephdc_request& rq = b->reqs[ri];
+    const ephdc_session* s = rq.session;
+    const ParamSet& P = s->P;
+    const uint32_t G = P.G(rq.Q), M = P.M();
+    ReqDesc d{};
+    d.model = s->d_model;
+    d.hv = rq.d_hv;
+    d.scatter = s->d_scatter;
+    d.out = P.r == 1 ? rq.d_score_ct : b->rot_ws[ri];
+    d.D = P.D;
+    d.r = P.r;
+    d.B = P.B();
+    d.hv_stride = G * P.B();
+    rd.push_back(d);
+    // S near-equal ranges of at most seg_len ciphertexts, none of them empty
+    const uint32_t len = (M + (M + b->seg_len - 1) / b->seg_len - 1) / ((M + b->seg_len - 1) / b->seg_len);
+    const uint32_t S = (M + len - 1) / len;
+    for (uint32_t g = 0; g < G; ++g) fin.push_back(FinishItem{li, g, slot + g * S, S});
+    for (uint32_t sp = 0; sp < S; ++sp) {
+      const uint32_t m0 = sp * len, m1 = std::min(M, m0 + len);
+      for (uint32_t g = 0; g < G; ++g) segs.push_back(Segment{li, g, m0, m1, 0, slot + g * S + sp});
+    }
+    slot += G * S;
+  }
+  // split path: consecutive segments fill the plaintext buffer chunk by chunk
+  pt.chunks.clear();
+  size_t used = 0;
+  uint32_t begin = 0;
+  for (uint32_t i = 0; i < segs.size(); ++i) {
+    const uint32_t n = segs[i].m1 - segs[i].m0;
+    if (used + n > pt.pt_cap && i > begin) {
+      pt.chunks.emplace_back(begin, i);
+      begin = i;
+      used = 0;
+    }
+    segs[i].pt = (uint32_t)used;
+    used += n;
+  }
+  if (begin < segs.size()) pt.chunks.emplace_back(begin, (uint32_t)segs.size());
+  pt.nseg = (uint32_t)segs.size();
+  pt.nfin = (uint32_t)fin.size();
+  pt.nslot = slot;
+
+  ephdc_status st;
+  if (pt.seg_cap < segs.size()) {
+    bfree(b, pt.d_segs, pt.seg_cap);
+    if ((st = balloc(b, &pt.d_segs, segs.size(), "work list")) != EPHDC_OK) return st;
+    pt.seg_cap = segs.size();
+  }
+  if (pt.fin_cap < fin.size()) {
+    bfree(b, pt.d_fin, pt.fin_cap);
+    if ((st = balloc(b, &pt.d_fin, fin.size(), "output list")) != EPHDC_OK) return st;
+    pt.fin_cap = fin.size();
+  }
+  const size_t pw = (size_t)slot * 2 * pt.L * pt.N;
+  if (pt.partial_cap < pw) {
+    bfree(b, pt.d_partial, pt.partial_cap);
+    if ((st = balloc(b, &pt.d_partial, pw, "partial sums")) != EPHDC_OK) return st;
+    pt.partial_cap = pw;
+  }
+  if (!pt.d_reqs && (st = balloc(b, &pt.d_reqs, rd.size(), "request table")) != EPHDC_OK) return st;
+  hipError_t e = hipMemcpy(pt.d_reqs, rd.data(), rd.size() * sizeof(ReqDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pt.d_segs, segs.data(), segs.size() * sizeof(Segment), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pt.d_fin, fin.data(), fin.size() * sizeof(FinishItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "work list upload");
+  return EPHDC_OK;
+}
+
+ephdc_status plan(ephdc_batch* b) {
+  drop_graph(b);
+  for (Part& pt : b->parts) {
+    ephdc_status st = plan_part(b, pt);
+    if (st != EPHDC_OK) return st;
+  }
+  return EPHDC_OK;
+}
+
+ListArgs list_args(const ephdc_batch* b, const Part& pt) {
+  const ephdc_session* s = pt.ref;
+  ListArgs a{};
+  a.reqs = pt.d_reqs;
+  a.segs = pt.d_segs;
+  a.nseg = pt.nseg;
+  a.NLG = pt.L / b->lg;
+  a.L = pt.L;
+  a.fin = pt.d_fin;
+  a.nfin = pt.nfin;
+  a.pt = pt.d_pt;
+  a.partial = pt.d_partial;
+  a.fwd_tw = s->d_fwd;
+  a.inv_tw = s->d_inv;
+  a.pcs = s->d_pc;
+  a.ts.inv_t = s->d_inv_t;
+  a.ts.pct = s->pct;
+  a.ts.tninv = s->tninv;
+  a.ts.tninvp = s->tninvp;
+  return a;
+}
+
+hipError_t enqueue(const ephdc_batch* b, hipStream_t hs) {
+  hipError_t e = hipSuccess;
+  for (const ephdc_request& rq : b->reqs) {
+    if (!rq.d_x) continue;
+    const ParamSet& P = rq.session->P;
+    e = launch_hdc_encode(rq.d_x, rq.d_base, rq.d_hv, rq.Q, P.F, P.D, P.G(rq.Q) * P.B(), P.qbits, P.qshift, hs);
+    if (e != hipSuccess) return e;
+  }
+  for (const Part& pt : b->parts) {
+    const int le = batch_le(b, pt.logn);
+    ListArgs a = list_args(b, pt);
+    const uint32_t items = pt.nseg * a.NLG;
+    if (b->mode == 1) {
+      e = launch_score_list(pt.logn, le, (int)b->lg, a, std::min(b->grid, items), hs);
+      if (e != hipSuccess) return e;
+    } else {
+      for (const auto& ch : pt.chunks) {
+        ListArgs c = a;
+        c.segs = pt.d_segs + ch.first;
+        c.nseg = ch.second - ch.first;
+        e = launch_encode_list(pt.logn, le, c, std::min(b->grid, c.nseg), hs);
+        if (e == hipSuccess) e = launch_mac_list(pt.logn, le, (int)b->lg, c, std::min(b->grid, c.nseg * c.NLG), hs);
+        if (e != hipSuccess) return e;
+      }
+    }
+    e = launch_finish_list(pt.logn, a, hs);
+    if (e != hipSuccess) return e;
+    // folded requests: rotate-and-sum on their own workspace, then the output transform
+    for (uint32_t ri : pt.reqs) {
+      const ephdc_request& rq = b->reqs[ri];
+      const ephdc_session* s = rq.session;
+      const ParamSet& P = s->P;
+      if (P.r == 1) continue;
+      const uint32_t G = P.G(rq.Q);
+      RotateArgs ra = rotate_args(s, b->rot_ws[ri], G);
+      for (uint32_t i = 0; i < P.log2r() && e == hipSuccess; ++i) e = launch_rotate_step(P.logn, ra, i, hs);
+      if (e == hipSuccess)
+        e = launch_inv_batch(P.logn, ra.acc, rq.d_score_ct, (size_t)G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q; }
+
+ephdc_status check_schedule(const ephdc_batch* b, const uint32_t sc[5]) {
+  if (sc[0] > 2) return fail(EPHDC_ERR_ARG, "mode must be 0 (keep), 1 (fused) or 2 (split)");
+  for (const Part& pt : b->parts) {
+    if (sc[1]) {
+      const int le = ilog2(sc[1]);
+      if ((1u << le) != sc[1] || !supported_shape(pt.logn, le))
+        return fail(EPHDC_ERR_UNSUPPORTED, "no kernel with that many values per thread for this N");
+    }
+    if (sc[2] && (!(sc[2] == 1 || sc[2] == 2 || sc[2] == 4) || pt.L % sc[2]))
+      return fail(EPHDC_ERR_ARG, "limb_group must be 1, 2 or 4 and divide L");
+  }
+  if (sc[3] > kMaxSegLen) return fail(EPHDC_ERR_ARG, "seg_len must be <= 1024");
+  if (sc[4] > (1u << 20)) return fail(EPHDC_ERR_ARG, "grid must be <= 2^20");
+  return EPHDC_OK;
+}
+
+ephdc_status apply_schedule(ephdc_batch* b, const uint32_t sc[5]) {
+  ephdc_status st = check_schedule(b, sc);
+  if (st != EPHDC_OK) return st;
+  const uint32_t old_seg = b->seg_len;
+  if (sc[0]) b->mode = sc[0];
+  if (sc[1]) b->vpt = sc[1];
+  if (sc[2]) b->lg = sc[2];
+  if (sc[3]) b->seg_len = sc[3];
+  if (sc[4]) b->grid = sc[4];
+  drop_graph(b);
+  if (b->seg_len != old_seg) return plan(b);
+  return EPHDC_OK;
+}
+
+void read_schedule(const ephdc_batch* b, uint32_t sc[5]) {
+  sc[0] = b->mode;
+  sc[1] = b->vpt;  // 0: the per-N default
+  sc[2] = b->lg;
+  sc[3] = b->seg_len;
+  sc[4] = b->grid;
+}
+
+}  // namespace
+
+extern "C" {
+
+ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out) {
+  if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!reqs || n_req == 0) return fail(EPHDC_ERR_ARG, "no requests");
+  for (uint32_t i = 0; i < n_req; ++i) {
+    const ephdc_request& r = reqs[i];
+    if (!r.session || !r.d_hv || !r.d_score_ct) return fail(EPHDC_ERR_ARG, "request with a NULL session or buffer");
+    const ParamSet& P = r.session->P;
+    if (r.Q == 0 || r.Q > r.session->max_Q) return fail(EPHDC_ERR_ARG, "request Q must be in [1, the session's max_Q]");
+    if ((uint64_t)P.D * P.G(r.Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
+    if (r.session->device != reqs[0].session->device) return fail(EPHDC_ERR_UNSUPPORTED, "sessions on different devices");
+    if (r.d_x) {
+      if (!r.d_base) return fail(EPHDC_ERR_ARG, "d_x without d_base");
+      if (P.F % 16 != 0 || P.D % 64 != 0) return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F % 16 == 0 and D % 64 == 0");
+      if (((uintptr_t)r.d_x & 15) || ((uintptr_t)r.d_base & 3))
+        return fail(EPHDC_ERR_ARG, "x must be 16-byte and base 4-byte aligned");
+    }
+  }
+  ephdc_batch* b = new ephdc_batch();
+  b->reqs.assign(reqs, reqs + n_req);
+  b->device = reqs[0].session->device;
+  b->rot_ws.assign(n_req, nullptr);
+  ephdc_status st = EPHDC_OK;
+  for (uint32_t i = 0; i < n_req && st == EPHDC_OK; ++i) {
+    const ephdc_session* s = reqs[i].session;
+    Part* pt = nullptr;
+    for (Part& p : b->parts)
+      if (same_chain(p.ref->P, s->P)) pt = &p;
+    if (!pt) {
+      b->parts.emplace_back();
+      pt = &b->parts.back();
+      pt->ref = s;
+      pt->logn = s->P.logn;
+      pt->N = s->P.N;
+      pt->L = s->P.L;
+      pt->pt_cap = std::max<size_t>(kMaxSegLen, kBatchPtBytes / (4 * (size_t)pt->N));
+    }
+    pt->reqs.push_back(i);
+    if (s->P.r > 1) st = balloc(b, &b->rot_ws[i], rotate_words(s->P, s->P.G(reqs[i].Q)), "rotation workspace");
+  }
+  // the default schedule: split path, one limb per MAC item, 128-ciphertext segments
+  for (Part& pt : b->parts) {
+    if (st != EPHDC_OK) break;
+    st = balloc(b, &pt.d_pt, pt.pt_cap * pt.N, "plaintext chunk buffer");
+  }
+  if (st == EPHDC_OK) st = plan(b);
+  if (st != EPHDC_OK) {
+    free_batch(b);
+    return st;
+  }
+  *out = b;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_batch_destroy(ephdc_batch* b) {
+  if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+  return EPHDC_OK;
+}
+
+size_t ephdc_batch_device_bytes(const ephdc_batch* b) { return b ? b->device_bytes : 0; }
+
+ephdc_status ephdc_batch_tune(ephdc_batch* b, const uint32_t schedule[5]) {
+  if (!b || !schedule) return fail(EPHDC_ERR_ARG, "NULL argument");
+  return apply_schedule(b, schedule);
+}
+
+ephdc_status ephdc_batch_schedule(const ephdc_batch* b, uint32_t schedule[5]) {
+  if (!b || !schedule) return fail(EPHDC_ERR_ARG, "NULL argument");
+  read_schedule(b, schedule);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_batch_run(ephdc_batch* b, void* stream) {
+  if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
+  hipStream_t hs = (hipStream_t)stream;
+  if (b->exec) {
+    HIP_TRY(hipGraphLaunch(b->exec, hs), "graph launch");
+    return EPHDC_OK;
+  }
+  HIP_TRY(enqueue(b, hs), "batch launch");
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_batch_capture(ephdc_batch* b, void* stream) {
+  if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
+  if (!stream) return fail(EPHDC_ERR_ARG, "capture needs a stream other than the null stream");
+  hipStream_t hs = (hipStream_t)stream;
+  drop_graph(b);
+  HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeRelaxed), "begin capture");
+  hipError_t e = enqueue(b, hs);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(hs, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e != hipSuccess ? e : e2, "batch capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "graph instantiate");
+  }
+  b->graph = g;
+  b->exec = x;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, uint32_t schedule[5],
+                                  double* best_ms) {
+  if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
+  if (reps == 0) reps = 2;
+  hipStream_t hs = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  hipError_t ee = hipEventCreate(&e1);
+  if (ee != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(ee, "event");
+  }
+  auto cleanup = [&](ephdc_status st) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+  };
+  drop_graph(b);
+  // mean ms per run of the current schedule (+inf if it cannot run)
+  auto measure = [&](double& ms) -> ephdc_status {
+    if (enqueue(b, hs) != hipSuccess) return hip_fail(hipGetLastError(), "autotune launch");
+    (void)hipEventRecord(e0, hs);
+    for (uint32_t k = 0; k < reps; ++k)
+      if (enqueue(b, hs) != hipSuccess) return hip_fail(hipGetLastError(), "autotune launch");
+    (void)hipEventRecord(e1, hs);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune sync");
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    ms = t / reps;
+    return EPHDC_OK;
+  };
+  uint32_t cur[5];
+  read_schedule(b, cur);
+  double best = 0;
+  ephdc_status st = measure(best);
+  if (st != EPHDC_OK) return cleanup(st);
+  // candidate values of each setting
+  std::vector<uint32_t> vpts;
+  for (uint32_t v : {8u, 16u, 32u}) {
+    bool ok = true;
+    for (const Part& pt : b->parts) ok = ok && supported_shape(pt.logn, ilog2(v));
+    if (ok) vpts.push_back(v);
+  }
+  std::vector<uint32_t> lgs;
+  for (uint32_t g : {1u, 2u, 4u}) {
+    bool ok = true;
+    for (const Part& pt : b->parts) ok = ok && pt.L % g == 0;
+    if (ok) lgs.push_back(g);
+  }
+  const std::vector<uint32_t> cand[5] = {{2, 1}, vpts, lgs, {64, 128, 256, 512}, {256, 512, 1024, 2048}};
+  const int order[] = {3, 4, 2, 1, 0, 3, 4};
+  for (int k : order) {
+    for (uint32_t v : cand[k]) {
+      if (v == cur[k]) continue;
+      uint32_t trial[5] = {0, 0, 0, 0, 0};
+      trial[k] = v;
+      if (apply_schedule(b, trial) != EPHDC_OK) continue;
+      double ms = 0;
+      st = measure(ms);
+      if (st != EPHDC_OK) {
+        apply_schedule(b, cur);
+        return cleanup(st);
+      }
+      if (ms < best) {
+        best = ms;
+        cur[k] = v;
+      }
+    }
+    st = apply_schedule(b, cur);
+    if (st != EPHDC_OK) return cleanup(st);
+  }
+  if (schedule) read_schedule(b, schedule);
+  if (best_ms) *best_ms = best;
+  return cleanup(EPHDC_OK);
+}
+
+ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream) {
+  ephdc_batch* b = nullptr;
+  ephdc_status st = ephdc_batch_create(reqs, n_req, &b);
+  if (st != EPHDC_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  hipError_t e = enqueue(b, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  free_batch(b);
+  if (e != hipSuccess) return hip_fail(e, "score_many");
+  return EPHDC_OK;
+}
+
+}  // extern "C"

@@ -110,30 +110,41 @@ __device__ __forceinline__ uint32_t table_entry(const uint32_t* __restrict__ sca
 }
 
 // ------------------------------------------------------------------ batch encoding
+// Where the slot values of one query group come from: hypervector column block hvg (the
+// group's first query), dimensions m*r + u < D, row pitch hv_stride.
+struct QuerySrc {
+  const int8_t* hvg;
+  uint32_t D, r, hv_stride;
+};
+
+// Constants of the plaintext side (mod t).
+using TSide = TSideArgs;
+
 // Slot values of query plaintext (g, m) at this thread's evaluation-side positions
-// tid*E + i (the slot feeding each position comes from the scatter table in LDS),
+// tid*E + i (the slot feeding each position comes from the scatter table),
 // pre-multiplied by N^-1 mod t so that the inverse transform needs no final scaling; then
 // the inverse transform mod t: mu in [0, t), coefficient layout tid + i*T.
 template <int LOGN, int LE>
-__device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const int8_t* __restrict__ hvg, uint32_t m,
-                                             const ScoreArgs& a, int tid, LdsBufs& b) {
+__device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const QuerySrc& q,
+                                             const uint32_t* scatter, const TSide& ts, uint32_t m,
+                                             int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
-  const uint32_t t = a.pct.m;
+  const uint32_t t = ts.pct.m;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
     uint32_t val = 0;
-    const uint32_t e = table_entry<LOGN, LE>(a.scatter, tid, i);
+    const uint32_t e = table_entry<LOGN, LE>(scatter, tid, i);
     if (e != 0xFFFFFFFFu) {
-      const uint32_t j = m * a.r + (e >> 16);
-      if (j < a.D) {
-        const int h = hvg[j * a.hv_stride + (e & 0xFFFFu)];
+      const uint32_t j = m * q.r + (e >> 16);
+      if (j < q.D) {
+        const int h = q.hvg[j * q.hv_stride + (e & 0xFFFFu)];
         const uint32_t x = h < 0 ? t + (uint32_t)h : (uint32_t)h;
-        val = mul_shoup(x, a.tninv, a.tninvp, t);
+        val = mul_shoup(x, ts.tninv, ts.tninvp, t);
       }
     }
     v[i] = val;
   }
-  ntt_inverse<LOGN, LE, false>(v, tid, a.inv_t, a.pct, b);
+  ntt_inverse<LOGN, LE, false>(v, tid, ts.inv_t, ts.pct, b);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
 }
@@ -143,46 +154,64 @@ __device__ __forceinline__ uint32_t lift(uint32_t mu, uint32_t t, uint32_t m) {
   return mu > (t >> 1) ? m - (t - mu) : mu;
 }
 
-// ------------------------------------------------------------------ fused scoring kernel
-// Work item (split, group g, limb group): for m in the split's range, batch-encode query
-// plaintext (g, m), lift it into each limb of the group, transform it, and accumulate
-// ct_m[c][l] * pt[l] for c in {0, 1}.  Accumulators live in VGPRs for the whole range;
-// the model values of a limb are requested before its transform so that their latency
-// overlaps the transform.
-template <int LOGN, int LE, int LG>
-__global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
-  using S = Shape<LOGN, LE>;
-  constexpr int E = S::E, N = S::N;
-  LdsBufs b{0};
-  const int tid = threadIdx.x;
-  stage_table<LOGN, LE>(a.scatter, tid);
-  const uint32_t w = blockIdx.x;
-  const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
-  const uint32_t g = rest % a.G, split = rest / a.G;
-  const uint32_t m0 = a.m_base + split * a.mchunk;
-  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
-  const uint32_t l0 = lgi * LG;
+// ------------------------------------------------------------------ scoring work items
+// One MAC work item: model ciphertexts [m0, m1) of one query group, limbs [l0, l0 + LG),
+// accumulated into the item's slot [2][L][N] (evaluation domain).
+struct MacItem {
+  const uint32_t* model;  // [M][2][L][N] evaluation domain, Montgomery form
+  uint32_t* slot;         // partial sums of this item
+  uint32_t L, m0, m1, l0;
+};
 
-  uint32_t acc[2][LG][E];
+template <int LG, int E>
+__device__ __forceinline__ void zero_acc(uint32_t (&acc)[2][LG][E]) {
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int li = 0; li < LG; ++li)
 #pragma unroll
       for (int i = 0; i < E; ++i) acc[c][li][i] = 0;
+}
 
-  const int8_t* hvg = a.hv + (size_t)g * a.B;
-  const uint32_t t = a.pct.m;
+template <int LOGN, int LE, int LG>
+__device__ __forceinline__ void store_acc(const uint32_t (&acc)[2][LG][1 << LE], const MacItem& it,
+                                          const PrimeConst* __restrict__ pcs, int tid) {
+  using S = Shape<LOGN, LE>;
+#pragma unroll
+  for (int li = 0; li < LG; ++li) {
+    const uint32_t l = it.l0 + li;
+    const uint32_t mm = pcs[l].m;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t* dst = it.slot + ((size_t)c * it.L + l) * S::N + (size_t)tid * S::E;
+#pragma unroll
+      for (int i = 0; i < S::E; ++i) dst[i] = csub(acc[c][li][i], mm);
+    }
+  }
+}
 
-  for (uint32_t m = m0; m < m1; ++m) {
+// Fused item: for m in [m0, m1), batch-encode query plaintext (g, m), lift it into each
+// limb of the group, transform it, and accumulate ct_m[c][l] * pt[l] for c in {0, 1}.
+// Accumulators live in VGPRs for the whole range; the model values of a limb are requested
+// before its transform so that their latency overlaps the transform.
+template <int LOGN, int LE, int LG>
+__device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q, const uint32_t* __restrict__ scatter,
+                                           const TSide& ts, const uint2* __restrict__ fwd_tw,
+                                           const PrimeConst* __restrict__ pcs, int tid, LdsBufs& b) {
+  using S = Shape<LOGN, LE>;
+  constexpr int E = S::E, N = S::N;
+  uint32_t acc[2][LG][E];
+  zero_acc(acc);
+  const uint32_t t = ts.pct.m;
+  for (uint32_t m = it.m0; m < it.m1; ++m) {
     uint32_t mu[E];
-    encode_query<LOGN, LE>(mu, hvg, m, a, tid, b);
+    encode_query<LOGN, LE>(mu, q, scatter, ts, m, tid, b);
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
-      const uint32_t l = l0 + li;
-      const PrimeConst pc = a.pcs[l];
-      const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
-      const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
+      const uint32_t l = it.l0 + li;
+      const PrimeConst pc = pcs[l];
+      const uint32_t* ct0 = it.model + (((size_t)m * 2 + 0) * it.L + l) * N + (size_t)tid * E;
+      const uint32_t* ct1 = it.model + (((size_t)m * 2 + 1) * it.L + l) * N + (size_t)tid * E;
       uint32_t c0[E], c1[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -192,7 +221,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = lift(mu[i], t, pc.m);
-      ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, b);
+      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc.m, b);
       const uint32_t m2 = 2 * pc.m;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -201,96 +230,74 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
       }
     }
   }
-#pragma unroll
-  for (int li = 0; li < LG; ++li) {
-    const uint32_t l = l0 + li;
-    const uint32_t mm = a.pcs[l].m;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      uint32_t* dst = a.partial + ((((size_t)g * a.S + split) * 2 + c) * a.L + l) * N + (size_t)tid * E;
-#pragma unroll
-      for (int i = 0; i < E; ++i) dst[i] = csub(acc[c][li][i], mm);
-    }
-  }
+  store_acc<LOGN, LE, LG>(acc, it, pcs, tid);
 }
 
-// ------------------------------------------------------------------ split path
-// Batch encoding alone: work item (split, g) encodes query plaintexts (g, m) for m in the
-// split's range and stores their centred lifts, coefficient order, in a.pt[g][m][:].
+// Batch encoding alone: query plaintexts (g, m) for m in [m0, m1), stored as centred lifts
+// (int32 in (-t/2, t/2]), coefficient order, at dst + (m - m0) * N.  The table and output
+// pointers are deliberately not __restrict__: that would let the compiler keep a global
+// scatter table in registers across the loop and spill at 1024 threads.
 template <int LOGN, int LE>
-__global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
+__device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* scatter, const TSide& ts,
+                                            uint32_t m0, uint32_t m1, int32_t* dst, int tid,
+                                            LdsBufs& b) {
   using S = Shape<LOGN, LE>;
-  LdsBufs b{0};
-  const int tid = threadIdx.x;
-  stage_table<LOGN, LE>(a.scatter, tid);
-  const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
-  const uint32_t m0 = a.m_base + split * a.mchunk;
-  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
-  const int8_t* hvg = a.hv + (size_t)g * a.B;
-  const uint32_t t = a.pct.m;
+  const uint32_t t = ts.pct.m;
   for (uint32_t m = m0; m < m1; ++m) {
     uint32_t mu[S::E];
-    encode_query<LOGN, LE>(mu, hvg, m, a, tid, b);
-    int32_t* dst = a.pt + ((size_t)g * a.m_len + (m - a.m_base)) * S::N;
+    encode_query<LOGN, LE>(mu, q, scatter, ts, m, tid, b);
+    int32_t* d = dst + (size_t)(m - m0) * S::N;
 #pragma unroll
-    for (int i = 0; i < S::E; ++i) dst[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
+    for (int i = 0; i < S::E; ++i) d[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
   }
 }
 
-// MAC alone: work item (split, g, limb group): for m in the split's range, read the lifted
-// plaintext (g, m), reduce it into each limb of the group, transform it and accumulate
-// ct_m[c][l] * pt[l].  With PF, the next plaintext and each limb's model values are
-// requested ahead of the transform that precedes their use (more registers: used where
-// the register budget allows it).
+// MAC alone: for m in [m0, m1), read the lifted plaintext (pt + (m - m0) * N), reduce it
+// into each limb of the group, transform it and accumulate ct_m[c][l] * pt[l]; with
+// accumulate set the item adds to the sums already in its slot.  With PF, the next
+// plaintext and each limb's model values are requested ahead of the transform that
+// precedes their use (more registers: used where the register budget allows it).
 template <int LOGN, int LE, int LG, bool PF>
-__global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
+__device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
+                                         const uint2* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
+                                         int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   constexpr int E = S::E, N = S::N;
-  LdsBufs b{0};
-  const int tid = threadIdx.x;
-  const uint32_t w = blockIdx.x;
-  const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
-  const uint32_t g = rest % a.G, split = rest / a.G;
-  const uint32_t m0 = a.m_base + split * a.mchunk;
-  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
-  const uint32_t l0 = lgi * LG;
-
   uint32_t acc[2][LG][E];
 #pragma unroll
   for (int li = 0; li < LG; ++li)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const uint32_t* src = a.partial + ((((size_t)g * a.S + split) * 2 + c) * a.L + l0 + li) * N + (size_t)tid * E;
+      const uint32_t* src = it.slot + ((size_t)c * it.L + it.l0 + li) * N + (size_t)tid * E;
 #pragma unroll
-      for (int i = 0; i < E; ++i) acc[c][li][i] = a.accumulate ? src[i] : 0u;
+      for (int i = 0; i < E; ++i) acc[c][li][i] = accumulate ? src[i] : 0u;
     }
 
-  // plaintext (g, m) of the chunk starts at ((g * m_len) + (m - m_base)) * N
-  const int32_t* ptg = a.pt + (size_t)g * a.m_len * N + tid;
+  const int32_t* ptt = pt + tid;
   int32_t nxt[E];
-  if (PF && m0 < m1) {
+  if (PF && it.m0 < it.m1) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m0 - a.m_base) * N + i * S::T];
+    for (int i = 0; i < E; ++i) nxt[i] = ptt[i * S::T];
   }
-  for (uint32_t m = m0; m < m1; ++m) {
+  for (uint32_t m = it.m0; m < it.m1; ++m) {
     int32_t cur[E];
     if constexpr (PF) {
 #pragma unroll
       for (int i = 0; i < E; ++i) cur[i] = nxt[i];
-      if (m + 1 < m1) {
+      if (m + 1 < it.m1) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) nxt[i] = ptg[(size_t)(m + 1 - a.m_base) * N + i * S::T];
+        for (int i = 0; i < E; ++i) nxt[i] = ptt[(size_t)(m + 1 - it.m0) * N + i * S::T];
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < E; ++i) cur[i] = ptg[(size_t)(m - a.m_base) * N + i * S::T];
+      for (int i = 0; i < E; ++i) cur[i] = ptt[(size_t)(m - it.m0) * N + i * S::T];
     }
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
-      const uint32_t l = l0 + li;
-      const PrimeConst pc = a.pcs[l];
-      const uint32_t* ct0 = a.model + (((size_t)m * 2 + 0) * a.L + l) * N + (size_t)tid * E;
-      const uint32_t* ct1 = a.model + (((size_t)m * 2 + 1) * a.L + l) * N + (size_t)tid * E;
+      const uint32_t l = it.l0 + li;
+      const PrimeConst pc = pcs[l];
+      const uint32_t* ct0 = it.model + (((size_t)m * 2 + 0) * it.L + l) * N + (size_t)tid * E;
+      const uint32_t* ct1 = it.model + (((size_t)m * 2 + 1) * it.L + l) * N + (size_t)tid * E;
       uint32_t c0[E], c1[E];
       if constexpr (PF) {
 #pragma unroll
@@ -302,7 +309,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
-      ntt_forward<LOGN, LE>(p, tid, a.fwd_tw + (size_t)l * N, pc.m, b);
+      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc.m, b);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -318,23 +325,166 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
       }
     }
   }
-#pragma unroll
-  for (int li = 0; li < LG; ++li) {
-    const uint32_t l = l0 + li;
-    const uint32_t mm = a.pcs[l].m;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      uint32_t* dst = a.partial + ((((size_t)g * a.S + split) * 2 + c) * a.L + l) * N + (size_t)tid * E;
-#pragma unroll
-      for (int i = 0; i < E; ++i) dst[i] = csub(acc[c][li][i], mm);
-    }
-  }
+  store_acc<LOGN, LE, LG>(acc, it, pcs, tid);
+}
+
+// ------------------------------------------------------------------ single-request kernels
+// Work item w of a launch: limb group w % NLG, then group g, then split of the model range.
+__device__ __forceinline__ TSide tside(const ScoreArgs& a) { return TSide{a.inv_t, a.pct, a.tninv, a.tninvp}; }
+
+__device__ __forceinline__ QuerySrc query_src(const ScoreArgs& a, uint32_t g) {
+  return QuerySrc{a.hv + (size_t)g * a.B, a.D, a.r, a.hv_stride};
+}
+
+template <int LOGN, int LG>
+__device__ __forceinline__ MacItem single_item(const ScoreArgs& a, uint32_t w, uint32_t& g, uint32_t& split) {
+  const uint32_t lgi = w % a.NLG, rest = w / a.NLG;
+  g = rest % a.G;
+  split = rest / a.G;
+  MacItem it;
+  it.model = a.model;
+  it.slot = a.partial + ((size_t)g * a.S + split) * 2 * a.L * ((size_t)1 << LOGN);
+  it.L = a.L;
+  it.m0 = a.m_base + split * a.mchunk;
+  it.m1 = min(a.m_base + a.m_len, it.m0 + a.mchunk);
+  it.l0 = lgi * LG;
+  return it;
+}
+
+template <int LOGN, int LE, int LG>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  stage_table<LOGN, LE>(a.scatter, tid);
+  uint32_t g, split;
+  const MacItem it = single_item<LOGN, LG>(a, blockIdx.x, g, split);
+  score_item<LOGN, LE, LG>(it, query_src(a, g), a.scatter, tside(a), a.fwd_tw, a.pcs, tid, b);
+}
+
+// Split path, batch encoding: work item (split, g) writes plaintexts (g, m) of the split's
+// range to a.pt[g][m - m_base][:].
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
+  using S = Shape<LOGN, LE>;
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  stage_table<LOGN, LE>(a.scatter, tid);
+  const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
+  const uint32_t m0 = a.m_base + split * a.mchunk;
+  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
+  int32_t* dst = a.pt + ((size_t)g * a.m_len + (m0 - a.m_base)) * S::N;
+  encode_item<LOGN, LE>(query_src(a, g), a.scatter, tside(a), m0, m1, dst, tid, b);
+}
+
+// Split path, MAC: work item (split, g, limb group) over the split's range of the chunk.
+template <int LOGN, int LE, int LG, bool PF>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  uint32_t g, split;
+  const MacItem it = single_item<LOGN, LG>(a, blockIdx.x, g, split);
+  const int32_t* pt = a.pt + ((size_t)g * a.m_len + (it.m0 - a.m_base)) * ((size_t)1 << LOGN);
+  mac_item<LOGN, LE, LG, PF>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
 }
 
 // Prefetching fits the register budget except for the 1024-thread shape of N = 16384.
 template <int LOGN, int LE>
 constexpr bool mac_prefetch() {
   return Shape<LOGN, LE>::T <= 512 || LE <= 3;
+}
+
+// ------------------------------------------------------------------ request-list kernels
+// Persistent kernels over the segments of many requests (one launch for all of them):
+// workgroup w takes items w, w + gridDim.x, ...  Every request of a list shares N and the
+// ciphertext moduli; K, D and the model differ, so the scatter table is restaged whenever
+// the request's table changes.
+template <int LOGN, int LE>
+__device__ __forceinline__ void restage(const uint32_t* scatter, const uint32_t*& staged, int tid) {
+  if (scatter != staged) {
+    lds_barrier();  // every wave is done reading the previous table
+    stage_table<LOGN, LE>(scatter, tid);
+    staged = scatter;
+  }
+}
+
+__device__ __forceinline__ QuerySrc query_src(const ReqDesc& r, uint32_t g) {
+  return QuerySrc{r.hv + (size_t)g * r.B, r.D, r.r, r.hv_stride};
+}
+
+template <int LOGN, int LE, int LG>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_score_list(ListArgs a) {
+  using S = Shape<LOGN, LE>;
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  const uint32_t* staged = nullptr;
+  const uint32_t n = a.nseg * a.NLG;
+  for (uint32_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const Segment sg = a.segs[w / a.NLG];
+    const ReqDesc r = a.reqs[sg.req];
+    restage<LOGN, LE>(r.scatter, staged, tid);
+    const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG};
+    score_item<LOGN, LE, LG>(it, query_src(r, sg.g), r.scatter, a.ts, a.fwd_tw, a.pcs, tid, b);
+  }
+}
+
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_list(ListArgs a) {
+  using S = Shape<LOGN, LE>;
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  const uint32_t* staged = nullptr;
+  for (uint32_t w = blockIdx.x; w < a.nseg; w += gridDim.x) {
+    const Segment sg = a.segs[w];
+    const ReqDesc r = a.reqs[sg.req];
+    restage<LOGN, LE>(r.scatter, staged, tid);
+    encode_item<LOGN, LE>(query_src(r, sg.g), r.scatter, a.ts, sg.m0, sg.m1, a.pt + (size_t)sg.pt * S::N, tid, b);
+  }
+}
+
+template <int LOGN, int LE, int LG, bool PF>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
+  using S = Shape<LOGN, LE>;
+  LdsBufs b{0};
+  const int tid = threadIdx.x;
+  const uint32_t n = a.nseg * a.NLG;
+  for (uint32_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const Segment sg = a.segs[w / a.NLG];
+    const ReqDesc r = a.reqs[sg.req];
+    const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG};
+    mac_item<LOGN, LE, LG, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+  }
+}
+
+// Finish of a request list: polynomial (c, l) of output item (request, g) sums the slots
+// of the group's segments; requests with r = 1 are transformed to the coefficient domain,
+// folded ones (r > 1) stay in the evaluation domain for their rotations.
+template <int LOGN, int LE>
+__global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish_list(ListArgs a) {
+  using S = Shape<LOGN, LE>;
+  const int tid = threadIdx.x;
+  const uint32_t poly = blockIdx.x % (2 * a.L), item = blockIdx.x / (2 * a.L);
+  const uint32_t l = poly % a.L;
+  const FinishItem f = a.fin[item];
+  const ReqDesc r = a.reqs[f.req];
+  const PrimeConst pc = a.pcs[l];
+  uint32_t v[S::E];
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) v[i] = 0;
+  for (uint32_t sl = f.slot0; sl < f.slot0 + f.nslot; ++sl) {
+    const uint32_t* src = a.partial + ((size_t)sl * 2 * a.L + poly) * S::N + (size_t)tid * S::E;
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) v[i] = csub(v[i] + src[i], pc.m);
+  }
+  uint32_t* out = r.out + ((size_t)f.g * 2 * a.L + poly) * S::N;
+  if (r.r == 1) {
+    LdsBufs b{0};
+    ntt_inverse<LOGN, LE, true>(v, tid, a.inv_tw + (size_t)l * S::N, pc, b);
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) out[tid + i * S::T] = csub(v[i], pc.m);
+  } else {
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) out[(size_t)tid * S::E + i] = v[i];
+  }
 }
 
 // Sum the S partial accumulators of every (g, c, l) (evaluation domain) and either store
@@ -380,7 +530,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_debug_plaintext(ScoreArgs
   const int tid = threadIdx.x;
   stage_table<LOGN, LE>(a.scatter, tid);
   uint32_t mu[S::E];
-  encode_query<LOGN, LE>(mu, a.hv + (size_t)g * a.B, m, a, tid, b);
+  encode_query<LOGN, LE>(mu, query_src(a, g), a.scatter, tside(a), m, tid, b);
   for (uint32_t l = 0; l < a.L; ++l) {
     const uint32_t qm = a.pcs[l].m;
 #pragma unroll
@@ -416,6 +566,14 @@ static hipError_t prepare_shape() {
   set((const void*)k_finish<LOGN, LE, true>);
   set((const void*)k_finish<LOGN, LE, false>);
   set((const void*)k_debug_plaintext<LOGN, LE>);
+  set((const void*)k_score_list<LOGN, LE, 1>);
+  set((const void*)k_score_list<LOGN, LE, 2>);
+  set((const void*)k_score_list<LOGN, LE, 4>);
+  set((const void*)k_encode_list<LOGN, LE>);
+  set((const void*)k_mac_list<LOGN, LE, 1, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_mac_list<LOGN, LE, 2, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_mac_list<LOGN, LE, 4, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_finish_list<LOGN, LE>);
   return e;
 }
 
@@ -537,6 +695,56 @@ hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_
       k_finish<LN, LEv, true><<<grid, block, sh, st>>>(partial, out, S_, L, itw, pcs);
     else
       k_finish<LN, LEv, false><<<grid, block, sh, st>>>(partial, out, S_, L, itw, pcs);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_score_list(int logn, int le, int lg, const ListArgs& a, uint32_t grid, hipStream_t st) {
+  if (grid == 0 || a.nseg == 0) return hipSuccess;
+  return dispatch(logn, le, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const dim3 g(grid), block(Shape<LN, LEv>::T);
+    const size_t sh = lds_bytes<LN, LEv>();
+    switch (lg) {
+      case 1: k_score_list<LN, LEv, 1><<<g, block, sh, st>>>(a); break;
+      case 2: k_score_list<LN, LEv, 2><<<g, block, sh, st>>>(a); break;
+      case 4: k_score_list<LN, LEv, 4><<<g, block, sh, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_encode_list(int logn, int le, const ListArgs& a, uint32_t grid, hipStream_t st) {
+  if (grid == 0 || a.nseg == 0) return hipSuccess;
+  return dispatch(logn, le, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    k_encode_list<LN, LEv><<<dim3(grid), dim3(Shape<LN, LEv>::T), lds_bytes<LN, LEv>(), st>>>(a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_mac_list(int logn, int le, int lg, const ListArgs& a, uint32_t grid, hipStream_t st) {
+  if (grid == 0 || a.nseg == 0) return hipSuccess;
+  return dispatch(logn, le, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    const dim3 g(grid), block(Shape<LN, LEv>::T);
+    const size_t sh = lds_bytes<LN, LEv>();
+    switch (lg) {
+      case 1: k_mac_list<LN, LEv, 1, mac_prefetch<LN, LEv>()><<<g, block, sh, st>>>(a); break;
+      case 2: k_mac_list<LN, LEv, 2, mac_prefetch<LN, LEv>()><<<g, block, sh, st>>>(a); break;
+      case 4: k_mac_list<LN, LEv, 4, mac_prefetch<LN, LEv>()><<<g, block, sh, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_finish_list(int logn, const ListArgs& a, hipStream_t st) {
+  if (a.nfin == 0) return hipSuccess;
+  return dispatch(logn, [&](auto lnc, auto lec) {
+    constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
+    k_finish_list<LN, LEv><<<dim3(a.nfin * 2 * a.L), dim3(Shape<LN, LEv>::T), lds_bytes<LN, LEv>(), st>>>(a);
     return hipGetLastError();
   });
 }

@@ -29,6 +29,48 @@ struct ScoreArgs {
   uint32_t accumulate;
 };
 
+// ---- request lists (many requests scored by one launch of each kernel)
+// One request of a list.  `out` receives [G][2][L][N]: coefficient-domain score
+// ciphertexts when r == 1, evaluation-domain sums (the input of rotate-and-sum) otherwise.
+struct ReqDesc {
+  const uint32_t* model;    // [M][2][L][N] evaluation domain, Montgomery form
+  const int8_t* hv;         // [D][hv_stride]
+  const uint32_t* scatter;  // [N] slot source table of the request's (K, r)
+  uint32_t* out;
+  uint32_t D, r, B, hv_stride;
+};
+
+// A segment: model ciphertexts [m0, m1) of group g of request `req`; its plaintexts sit at
+// plaintext index `pt` of the chunk buffer and its partial sums in slot `slot`.
+struct Segment {
+  uint32_t req, g, m0, m1, pt, slot;
+};
+
+// Output item: group g of request `req`, the sum of slots [slot0, slot0 + nslot).
+struct FinishItem {
+  uint32_t req, g, slot0, nslot;
+};
+
+struct TSideArgs {
+  const uint2* inv_t;
+  PrimeConst pct;
+  uint32_t tninv, tninvp;
+};
+
+struct ListArgs {
+  const ReqDesc* reqs;
+  const Segment* segs;      // the segments of this launch
+  uint32_t nseg, NLG, L;
+  const FinishItem* fin;
+  uint32_t nfin;
+  int32_t* pt;              // split path: lifted plaintexts of the launch's segments
+  uint32_t* partial;        // [slots][2][L][N]
+  const uint2* fwd_tw;
+  const uint2* inv_tw;
+  const PrimeConst* pcs;
+  TSideArgs ts;
+};
+
 // Constants of hybrid key switching (Shoup pairs (w, floor(w*2^32/m)) for the modulus
 // each multiplication is taken in).
 struct KsConst {
@@ -60,7 +102,11 @@ struct RotateArgs {
 
 namespace ephdc {
 
+using ephdc_dev::FinishItem;
 using ephdc_dev::KsConst;
+using ephdc_dev::ListArgs;
+using ephdc_dev::ReqDesc;
+using ephdc_dev::Segment;
 using ephdc_dev::RotateArgs;
 
 using ephdc_dev::PrimeConst;
@@ -93,6 +139,12 @@ hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_
                          uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st);
 hipError_t launch_debug_plaintext(int logn, const ScoreArgs& a, uint32_t g, uint32_t m, uint32_t* out,
                                   hipStream_t st);
+
+// Request lists: persistent launches over `grid` workgroups.
+hipError_t launch_score_list(int logn, int le, int lg, const ListArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_encode_list(int logn, int le, const ListArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_mac_list(int logn, int le, int lg, const ListArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_finish_list(int logn, const ListArgs& a, hipStream_t st);
 
 // One rotate-and-sum step (Galois element of step `step`): acc <- acc + KeySwitch(sigma(acc)).
 hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipStream_t st);

@@ -6,74 +6,11 @@
 #include <cstring>
 #include <vector>
 
-#include "launch.hpp"
-#include "params.hpp"
+#include "session.hpp"
 
 using namespace ephdc;
 
-// Profiling stages (see ephdc_session_profile_read).
-enum : int { kStFused = 0, kStFinish = 1, kStHdc = 2, kStRotate = 3, kStEncodePt = 4, kStMac = 5, kStages = 6 };
-
-struct ephdc_session {
-  ParamSet P;
-  int device = 0;
-  uint32_t max_Q = 0;
-  uint32_t lg = 1, nlg = 1;        // limbs per fused work item, number of limb groups
-  uint32_t target_blocks = 256;    // workgroups per scoring launch the schedule aims at
-  uint32_t le = 0;                 // log2 values per thread of the scoring kernel (0: default)
-  bool split = false;              // batch-encode and MAC as two kernels (else one fused kernel)
-  int32_t* d_pt = nullptr;         // split path: lifted plaintexts of one chunk [G][m_len][N]
-  size_t pt_cap = 0;               // plaintexts d_pt holds
-  // device memory owned by the session
-  uint2* d_fwd = nullptr;          // [nmod][N]
-  uint2* d_inv = nullptr;          // [nmod][N]
-  uint2* d_inv_t = nullptr;        // [N]
-  PrimeConst* d_pc = nullptr;      // [nmod]
-  uint32_t* d_scatter = nullptr;   // [N]
-  uint32_t* d_model = nullptr;     // [M][2][L][N] evaluation domain, Montgomery form
-  uint32_t* d_gk = nullptr;        // [log2r][dnum][2][nmod][N] evaluation domain, Montgomery form
-  uint32_t* d_partial = nullptr;   // scratch: partial accumulators
-  size_t partial_words = 0;
-  // rotate-and-sum (r > 1)
-  uint32_t* d_perm = nullptr;      // [log2r][N] automorphism permutations of evaluation points
-  uint2* d_ksc = nullptr;          // key-switching constants, pointed into by ks
-  uint32_t* d_rot = nullptr;       // workspace: acc, R, D, Y, KS, XP sized for G(max_Q)
-  KsConst ks{};
-  PrimeConst pct{};
-  uint32_t tninv = 0, tninvp = 0;
-  size_t device_bytes = 0;
-  // kernel timing: pairs of events per stage, resolved when read
-  bool profile = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kStages];
-};
-
 namespace {
-
-constexpr uint32_t kTargetBlocks = 256;  // one workgroup per CU on MI355X (256 CUs)
-constexpr uint32_t kMaxBlocks = 1024;    // largest schedule target the scratch is sized for
-
-ephdc_status hip_fail(hipError_t e, const char* what) {
-  return fail(EPHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define HIP_TRY(expr, what)                          \
-  do {                                               \
-    hipError_t _e = (expr);                          \
-    if (_e != hipSuccess) return hip_fail(_e, what); \
-  } while (0)
-
-template <class T>
-ephdc_status dev_alloc(ephdc_session* s, T** p, size_t count, const char* what) {
-  if (count == 0) { *p = nullptr; return EPHDC_OK; }
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(EPHDC_ERR_OOM, std::string("hipMalloc failed for ") + what);
-  }
-  s->device_bytes += count * sizeof(T);
-  return EPHDC_OK;
-}
 
 void drop_events(ephdc_session* s) {
   for (auto& v : s->ev) {
@@ -269,6 +206,10 @@ std::vector<uint32_t> automorphism_perms(const ParamSet& P) {
   return perm;
 }
 
+}  // namespace
+
+namespace ephdc {
+
 // Words of the rotation workspace for G groups: acc, R [G][2][L][N]; D [G][L][N];
 // Y [G][dnum][nmod][N]; KS [G][2][nmod][N]; XP [G][2][alpha][N].
 size_t rotate_words(const ParamSet& P, uint32_t G) {
@@ -276,7 +217,7 @@ size_t rotate_words(const ParamSet& P, uint32_t G) {
   return (size_t)G * N * (4 * P.L + P.L + (size_t)P.dnum * P.nmod() + 2 * P.nmod() + 2 * P.alpha);
 }
 
-RotateArgs rotate_args(const ephdc_session* s, uint32_t G) {
+RotateArgs rotate_args(const ephdc_session* s, uint32_t* workspace, uint32_t G) {
   const ParamSet& P = s->P;
   const size_t N = P.N;
   RotateArgs r{};
@@ -284,7 +225,7 @@ RotateArgs rotate_args(const ephdc_session* s, uint32_t G) {
   r.k.G = G;
   r.perm = s->d_perm;
   r.ksk = s->d_gk;
-  uint32_t* w = s->d_rot;
+  uint32_t* w = workspace;
   r.acc = w;  w += (size_t)G * 2 * P.L * N;
   r.R = w;    w += (size_t)G * 2 * P.L * N;
   r.D = w;    w += (size_t)G * P.L * N;
@@ -297,7 +238,7 @@ RotateArgs rotate_args(const ephdc_session* s, uint32_t G) {
   return r;
 }
 
-}  // namespace
+}  // namespace ephdc
 
 extern "C" {
 
@@ -474,7 +415,7 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
   }
   // r > 1: sum the partials in the evaluation domain, fold the r blocks of every row with
   // log2 r rotations, then return to the coefficient domain
-  RotateArgs ra = rotate_args(s, sc.G);
+  RotateArgs ra = rotate_args(s, s->d_rot, sc.G);
   hipEvent_t t1 = timed_begin(s, hs);
   HIP_TRY(launch_finish(P.logn, false, s->d_partial, ra.acc, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
           "finish launch");

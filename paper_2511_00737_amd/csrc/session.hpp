@@ -1,0 +1,82 @@
+// Session state shared by the single-request entry points (session.hip) and the request
+// lists of batches and the serving loop (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "launch.hpp"
+#include "params.hpp"
+
+// Profiling stages (see ephdc_session_profile_read).
+enum : int { kStFused = 0, kStFinish = 1, kStHdc = 2, kStRotate = 3, kStEncodePt = 4, kStMac = 5, kStages = 6 };
+
+struct ephdc_session {
+  ephdc::ParamSet P;
+  int device = 0;
+  uint32_t max_Q = 0;
+  uint32_t lg = 1, nlg = 1;        // limbs per fused work item, number of limb groups
+  uint32_t target_blocks = 256;    // workgroups per scoring launch the schedule aims at
+  uint32_t le = 0;                 // log2 values per thread of the scoring kernel (0: default)
+  bool split = false;              // batch-encode and MAC as two kernels (else one fused kernel)
+  int32_t* d_pt = nullptr;         // split path: lifted plaintexts of one chunk [G][m_len][N]
+  size_t pt_cap = 0;               // plaintexts d_pt holds
+  // device memory owned by the session
+  uint2* d_fwd = nullptr;          // [nmod][N]
+  uint2* d_inv = nullptr;          // [nmod][N]
+  uint2* d_inv_t = nullptr;        // [N]
+  ephdc::PrimeConst* d_pc = nullptr;  // [nmod]
+  uint32_t* d_scatter = nullptr;   // [N]
+  uint32_t* d_model = nullptr;     // [M][2][L][N] evaluation domain, Montgomery form
+  uint32_t* d_gk = nullptr;        // [log2r][dnum][2][nmod][N] evaluation domain, Montgomery form
+  uint32_t* d_partial = nullptr;   // scratch: partial accumulators
+  size_t partial_words = 0;
+  // rotate-and-sum (r > 1)
+  uint32_t* d_perm = nullptr;      // [log2r][N] automorphism permutations of evaluation points
+  uint2* d_ksc = nullptr;          // key-switching constants, pointed into by ks
+  uint32_t* d_rot = nullptr;       // workspace: acc, R, D, Y, KS, XP sized for G(max_Q)
+  ephdc::KsConst ks{};
+  ephdc::PrimeConst pct{};
+  uint32_t tninv = 0, tninvp = 0;
+  size_t device_bytes = 0;
+  // kernel timing: pairs of events per stage, resolved when read
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kStages];
+};
+
+namespace ephdc {
+
+inline constexpr uint32_t kTargetBlocks = 256;  // one workgroup per CU on MI355X (256 CUs)
+inline constexpr uint32_t kMaxBlocks = 1024;    // largest schedule target the scratch is sized for
+
+inline ephdc_status hip_fail(hipError_t e, const char* what) {
+  return fail(EPHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+template <class T>
+inline ephdc_status dev_alloc(ephdc_session* s, T** p, size_t count, const char* what) {
+  if (count == 0) { *p = nullptr; return EPHDC_OK; }
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(EPHDC_ERR_OOM, std::string("hipMalloc failed for ") + what);
+  }
+  s->device_bytes += count * sizeof(T);
+  return EPHDC_OK;
+}
+
+// Rotation workspace and arguments for G groups of a folded (r > 1) session.
+size_t rotate_words(const ParamSet& P, uint32_t G);
+RotateArgs rotate_args(const ephdc_session* s, uint32_t* workspace, uint32_t G);
+
+}  // namespace ephdc

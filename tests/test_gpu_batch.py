@@ -1,0 +1,198 @@
+"""Request batches through the C ABI (needs a gfx950 GPU): many requests of different sizes,
+models (K, D, r) and ring dimensions scored by shared persistent launches give, request by
+request, the oracle's score ciphertexts -- under every schedule, and on every replay of a
+captured HIP graph."""
+import numpy as np
+import pytest
+
+import paper_2511_00737_amd as ep
+import synth
+from oracle import bfv, hdc, pipeline
+from oracle.params import Params as OParams, default_primes
+
+from gpu_helpers import hv_layout, to_dev, to_host_u32, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+# (N, L, K, D, r, alpha, dnum): tenants sharing N = 4096 (one with a folded packing), and
+# one at N = 8192, so the batch has two parameter sets
+TENANTS = [(4096, 3, 2, 64, 1, 0, 0), (4096, 3, 5, 100, 1, 0, 0), (4096, 3, 3, 40, 4, 1, 3),
+           (8192, 4, 7, 48, 1, 0, 0)]
+# (tenant, Q, encode inside the batch)
+REQUESTS = [(0, 1, True), (1, 7, False), (2, 300, False), (0, 1500, True), (3, 2500, False), (1, 3000, False),
+            (2, 5, False), (3, 1, False), (0, 64, False)]
+F = 64
+
+
+class Tenant:
+    def __init__(self, i, N, L, K, D, r, alpha, dnum):
+        primes = default_primes(N, L + alpha)
+        kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum)
+        self.o, self.e = OParams(**kw), ep.Params(**kw)
+        self.sk = bfv.secret_key(self.o, 20 + i)
+        self.C = synth.class_hypervectors(30 + i, K, D)
+        self.model = bfv.encrypt_model(self.o, self.sk, self.C, 40 + i)
+        self.gk = bfv.galois_keys(self.o, self.sk, 50 + i) if r > 1 else None
+        self.base = synth.base_hypervectors(60 + i, F, D)
+
+
+@pytest.fixture(scope="module")
+def world():
+    torch = torch_cuda()
+    tenants = [Tenant(i, *t) for i, t in enumerate(TENANTS)]
+    sessions = []
+    for i, t in enumerate(tenants):
+        max_Q = max(Q for ti, Q, _ in REQUESTS if ti == i)
+        sessions.append(ep.Session(t.e, to_dev(t.model.astype(np.uint32)),
+                                   to_dev(t.gk.astype(np.uint32)) if t.gk is not None else None, max_Q=max_Q))
+    reqs, want_h = [], []
+    for k, (ti, Q, enc) in enumerate(REQUESTS):
+        t, s = tenants[ti], sessions[ti]
+        G = s.num_groups(Q)
+        out = torch.zeros((G, 2, t.o.L, t.o.N), dtype=torch.int32, device="cuda")
+        if enc:
+            x = synth.uniform_features(70 + k, Q, F)
+            h = hdc.encode(x, t.base)
+            d_hv = torch.full((t.o.D, s.hv_stride(Q)), 99, dtype=torch.int8, device="cuda")
+            reqs.append(ep.Request(s, d_hv, Q, out, d_x=to_dev(x), d_base=to_dev(t.base)))
+        else:
+            h = np.random.default_rng(k).choice(np.array([-1, 1], dtype=np.int8), (Q, t.o.D))
+            reqs.append(ep.Request(s, to_dev(hv_layout(h, s.hv_stride(Q))), Q, out))
+        want_h.append(h)
+    # oracle, on the first and last groups of every request (all groups when few)
+    want = []
+    for (ti, Q, _), h in zip(REQUESTS, want_h):
+        t = tenants[ti]
+        G = t.o.groups(Q)
+        groups = sorted({0, G - 1})
+        want.append((groups, pipeline.score_ciphertexts(t.o, t.model, h, t.gk, groups=groups)))
+    yield dict(torch=torch, tenants=tenants, sessions=sessions, reqs=reqs, h=want_h, want=want)
+    for s in sessions:
+        s.close()
+
+
+def _outputs(w):
+    w["torch"].cuda.synchronize()
+    return [to_host_u32(r.d_score_ct).astype(np.int64) for r in w["reqs"]]
+
+
+def _check(w, got, tag):
+    for k, (g_out, (groups, want)) in enumerate(zip(got, w["want"])):
+        for i, g in enumerate(groups):
+            assert np.array_equal(g_out[g], want[i]), (tag, k, g)
+
+
+def _clear(w):
+    for r in w["reqs"]:
+        r.d_score_ct.fill_(0)
+
+
+def test_batch_matches_oracle_and_single_requests(world):
+    w = world
+    _clear(w)
+    b = ep.Batch(w["reqs"])
+    try:
+        b.run()
+        got = _outputs(w)
+    finally:
+        b.close()
+    _check(w, got, "default")
+    # hypervectors encoded inside the batch
+    for (ti, Q, enc), r, h in zip(REQUESTS, w["reqs"], w["h"]):
+        if enc:
+            assert np.array_equal(r.d_hv.cpu().numpy()[:, :Q], h.T)
+    # every group of every request equals the single-request path, and decrypts exactly
+    torch = w["torch"]
+    for k, ((ti, Q, _), r) in enumerate(zip(REQUESTS, w["reqs"])):
+        t, s = w["tenants"][ti], w["sessions"][ti]
+        one = torch.empty_like(r.d_score_ct)
+        ep.ephdc_score_encrypted(s, r.d_hv, Q, one)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(one).astype(np.int64), got[k]), k
+        scores, _ = pipeline.decrypt_scores(t.o, t.sk, got[k], Q)
+        assert np.array_equal(scores, hdc.scores_mod_t(w["h"][k], t.C, 65537)), k
+
+
+def test_score_many_matches_oracle(world):
+    w = world
+    _clear(w)
+    ep.ephdc_score_many(w["reqs"])
+    _check(w, _outputs(w), "score_many")
+
+
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_every_batch_schedule_gives_the_same_bits(world, mode):
+    w = world
+    b = ep.Batch(w["reqs"])
+    try:
+        for vpt in (8,):
+            for lg in (1,):
+                for seg_len in (64, 1024):
+                    for grid in (7, 512):
+                        b.tune(mode=mode, values_per_thread=vpt, limb_group=lg, seg_len=seg_len, grid=grid)
+                        _clear(w)
+                        b.run()
+                        _check(w, _outputs(w), (mode, vpt, lg, seg_len, grid))
+    finally:
+        b.close()
+
+
+def test_limb_groups_and_shapes_at_n8192(world):
+    """A batch of the N = 8192 tenant alone: every values-per-thread shape and limb group."""
+    w = world
+    idx = [k for k, (ti, _, _) in enumerate(REQUESTS) if ti == 3]
+    reqs = [w["reqs"][k] for k in idx]
+    b = ep.Batch(reqs)
+    try:
+        for mode in ("split", "fused"):
+            for vpt in (8, 16):
+                for lg in (1, 2, 4):
+                    b.tune(mode=mode, values_per_thread=vpt, limb_group=lg, seg_len=32, grid=300)
+                    for r in reqs:
+                        r.d_score_ct.fill_(0)
+                    b.run()
+                    w["torch"].cuda.synchronize()
+                    for k in idx:
+                        got = to_host_u32(w["reqs"][k].d_score_ct).astype(np.int64)
+                        groups, want = w["want"][k]
+                        for i, g in enumerate(groups):
+                            assert np.array_equal(got[g], want[i]), (mode, vpt, lg, k, g)
+    finally:
+        b.close()
+
+
+def test_captured_graph_replays_match(world):
+    """Every replay of the captured graph, with eager work on the same buffers between
+    replays, reproduces the oracle's ciphertexts."""
+    w = world
+    torch = w["torch"]
+    st = torch.cuda.Stream()
+    b = ep.Batch(w["reqs"])
+    try:
+        b.tune(mode="split", seg_len=64, grid=256)
+        b.capture(st)
+        for rep in range(3):
+            _clear(w)
+            torch.cuda.synchronize()
+            b.run(st)
+            st.synchronize()
+            _check(w, _outputs(w), ("replay", rep))
+            # eager work between replays: a single-request score into the first output
+            r0 = w["reqs"][0]
+            ep.ephdc_score_encrypted(r0.session, r0.d_hv, r0.Q, r0.d_score_ct)
+            torch.cuda.synchronize()
+    finally:
+        b.close()
+
+
+def test_autotuner_keeps_a_valid_schedule(world):
+    w = world
+    b = ep.Batch(w["reqs"])
+    try:
+        sched, ms = b.autotune(reps=1)
+        assert ms > 0 and sched["mode"] in ("split", "fused")
+        _clear(w)
+        b.run()
+        _check(w, _outputs(w), ("autotuned", sched))
+    finally:
+        b.close()
