@@ -288,6 +288,56 @@ ephdc_status ephdc_batch_capture(ephdc_batch* b, void* stream);
 /* Convenience: plan, run on `stream`, wait for it and free the plan. */
 ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream);
 
+/* ---------------------------------------------------------------- serving loop
+ * A server keeps tenants' sessions (device-resident encrypted models and Galois keys) and
+ * scores requests as they arrive: a scheduler thread takes the waiting requests in arrival
+ * order into a batch while the batch's device memory (query hypervectors, partial sums,
+ * plaintext chunks, rotation workspace) fits the free part of the server's budget, and
+ * launches it on a free stream; requests that arrive while batches run are admitted as
+ * streams and memory free up, so their work overlaps on the device (continuous batching).
+ * Each request's score ciphertexts equal those of ephdc_score_encrypted for it alone.
+ */
+typedef struct ephdc_server ephdc_server;
+
+/*
+ * budget_bytes  device memory for requests in flight (>= 64 MiB), allocated with the first
+ *               tenant; a request that cannot fit even an empty budget is rejected
+ * streams       batches in flight at once (1..8)
+ * max_batch     requests per batch (0: 64)
+ */
+ephdc_status ephdc_server_create(size_t budget_bytes, uint32_t streams, uint32_t max_batch, ephdc_server** out);
+
+/* Registers a tenant: its session and its base hypervectors d_base int8 [F][D] (device,
+ * borrowed until the server is destroyed).  Every tenant lives on the first one's device. */
+ephdc_status ephdc_server_add_tenant(ephdc_server* sv, ephdc_session* s, const int8_t* d_base, uint32_t* tenant);
+
+/*
+ * Queues a request: d_x uint8 [Q][F] features (device, 16-byte aligned, unchanged until the
+ * request is done), out d_score_ct uint32 [G][2][L][N].  Returns a ticket at once.
+ * Errors (synchronous): EPHDC_ERR_ARG (unknown tenant, Q outside [1, max_Q], NULL),
+ * EPHDC_ERR_UNSUPPORTED (encoding constraints).
+ */
+ephdc_status ephdc_server_submit(ephdc_server* sv, uint32_t tenant, const uint8_t* d_x, uint32_t Q,
+                                 uint32_t* d_score_ct, uint64_t* ticket);
+
+/* State of a ticket: 0 waiting, 1 in flight, 2 done, -status when it failed or was rejected
+ * (-EPHDC_ERR_OOM: larger than the budget); times[3] = submit, admit, done in seconds since
+ * the server was created (0 when not reached). */
+ephdc_status ephdc_server_query(ephdc_server* sv, uint64_t ticket, int32_t* state, double times[3]);
+
+/* Waits until the ticket is done (ticket 0: until nothing waits or runs); timeout_s <= 0
+ * waits without limit.  Returns the request's failure status if it failed. */
+ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout_s);
+
+/* Counters: [0] submitted [1] completed [2] rejected [3] waiting [4] batches in flight
+ * [5] batches launched [6] mean requests per batch [7] p50 latency ms [8] p99 latency ms
+ * (submit to done, completed requests) [9] peak device bytes in use [10] budget bytes
+ * [11] seconds since creation. */
+ephdc_status ephdc_server_stats(ephdc_server* sv, double out[12]);
+
+/* Drains the queue and every batch in flight, then frees the server (not the tenants). */
+ephdc_status ephdc_server_destroy(ephdc_server* sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -89,6 +89,14 @@ def lib() -> C.CDLL:
             "ephdc_batch_run": (C.c_int, [C.c_void_p, C.c_void_p]),
             "ephdc_batch_capture": (C.c_int, [C.c_void_p, C.c_void_p]),
             "ephdc_score_many": (C.c_int, [C.POINTER(_CRequest), C.c_uint32, C.c_void_p]),
+            "ephdc_server_create": (C.c_int, [C.c_size_t, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
+            "ephdc_server_add_tenant": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, u32p]),
+            "ephdc_server_submit": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                              u64p]),
+            "ephdc_server_query": (C.c_int, [C.c_void_p, C.c_uint64, i32p, C.POINTER(C.c_double)]),
+            "ephdc_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double]),
+            "ephdc_server_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+            "ephdc_server_destroy": (C.c_int, [C.c_void_p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -420,3 +428,63 @@ def ephdc_batch_create(reqs) -> Batch:
 def ephdc_score_many(reqs, stream=None) -> None:
     reqs = list(reqs)
     _check(lib().ephdc_score_many(_c_requests(reqs), len(reqs), _stream(stream)))
+
+
+# ------------------------------------------------------------------ serving loop
+class Server:
+    """Owns an ephdc_server: tenants, a request queue and a native scheduler thread."""
+
+    STATS = ("submitted", "completed", "rejected", "waiting", "in_flight", "batches", "mean_batch",
+             "p50_ms", "p99_ms", "peak_bytes", "budget_bytes", "uptime_s")
+
+    def __init__(self, budget_bytes: int, streams: int = 2, max_batch: int = 0):
+        h = C.c_void_p()
+        _check(lib().ephdc_server_create(budget_bytes, streams, max_batch, C.byref(h)))
+        self.handle = h
+        self._keep = {}  # tenant sessions / bases and request buffers stay alive here
+
+    def add_tenant(self, session: "Session", d_base) -> int:
+        p = session.prm
+        t = C.c_uint32()
+        _check(lib().ephdc_server_add_tenant(self.handle, session.handle, _dptr(d_base, p.F * p.D), C.byref(t)))
+        self._keep[("tenant", t.value)] = (session, d_base)
+        return t.value
+
+    def submit(self, tenant: int, d_x, Q: int, d_score_ct) -> int:
+        session = self._keep[("tenant", tenant)][0] if ("tenant", tenant) in self._keep else None
+        if session is None:
+            raise EphdcError(ERR_ARG, "unknown tenant")
+        p = session.prm
+        _, _, out_bytes = _sizes(session, Q)
+        tk = C.c_uint64()
+        _check(lib().ephdc_server_submit(self.handle, tenant, _dptr(d_x, Q * p.F), Q, _dptr(d_score_ct, out_bytes),
+                                         C.byref(tk)))
+        self._keep[("req", tk.value)] = (d_x, d_score_ct)
+        return tk.value
+
+    def query(self, ticket: int):
+        """(state, (t_submit, t_admit, t_done)); state 0 waiting, 1 in flight, 2 done, <0 failed."""
+        st = C.c_int32()
+        tm = (C.c_double * 3)()
+        _check(lib().ephdc_server_query(self.handle, ticket, C.byref(st), tm))
+        return st.value, (tm[0], tm[1], tm[2])
+
+    def wait(self, ticket: int = 0, timeout_s: float = 0.0) -> None:
+        _check(lib().ephdc_server_wait(self.handle, ticket, timeout_s))
+
+    def stats(self) -> dict:
+        out = (C.c_double * 12)()
+        _check(lib().ephdc_server_stats(self.handle, out))
+        return {k: out[i] for i, k in enumerate(self.STATS)}
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib().ephdc_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,32 +9,35 @@
 #include <map>
 #include <vector>
 
+#include "batch.hpp"
 #include "session.hpp"
 
 using namespace ephdc;
 
 namespace {
 
-// Plaintext chunk buffer of the split path: at most this many bytes, and at least one
-// segment of the longest allowed length.
-constexpr size_t kBatchPtBytes = (size_t)1 << 30;
 constexpr uint32_t kMaxSegLen = 1024;
+constexpr size_t kAlign = 256;
 
-// One parameter set of the batch and the device-side work list of its requests.
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// One parameter set of the batch and its work list (host copy and device copy).
 struct Part {
   int logn = 0;
   uint32_t N = 0, L = 0;
   const ephdc_session* ref = nullptr;  // twiddles and constants come from this session
   std::vector<uint32_t> reqs;          // indices into ephdc_batch::reqs
+  std::vector<ReqDesc> rd;
+  std::vector<Segment> segs;
+  std::vector<FinishItem> fin;
   std::vector<std::pair<uint32_t, uint32_t>> chunks;  // split path: segment ranges
-  uint32_t nseg = 0, nfin = 0, nslot = 0;
+  uint32_t nslot = 0;
+  size_t pt_cap = 0;  // plaintexts of the chunk buffer
   ReqDesc* d_reqs = nullptr;
   Segment* d_segs = nullptr;
   FinishItem* d_fin = nullptr;
   uint32_t* d_partial = nullptr;
-  size_t seg_cap = 0, fin_cap = 0, partial_cap = 0;  // allocated element counts
   int32_t* d_pt = nullptr;
-  size_t pt_cap = 0;  // plaintexts d_pt holds
 };
 
 }  // namespace
@@ -44,39 +47,18 @@ struct ephdc_batch {
   std::vector<Part> parts;
   std::vector<uint32_t*> rot_ws;  // per request: rotation workspace (r > 1), else nullptr
   int device = 0;
+  size_t pt_bytes = 0;            // bound on each part's plaintext chunk buffer
   // schedule
   uint32_t mode = 2, vpt = 0, lg = 1, seg_len = 128, grid = 512;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  size_t device_bytes = 0;
-  std::vector<void*> owned;  // every device allocation of the batch
+  // device memory: one block, owned (hipMalloc) or lent by the caller
+  void* mem = nullptr;
+  size_t mem_bytes = 0;
+  bool owned = false;
 };
 
 namespace {
-
-template <class T>
-ephdc_status balloc(ephdc_batch* b, T** p, size_t count, const char* what) {
-  *p = nullptr;
-  if (count == 0) return EPHDC_OK;
-  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(EPHDC_ERR_OOM, std::string("hipMalloc failed for ") + what);
-  }
-  b->owned.push_back((void*)*p);
-  b->device_bytes += count * sizeof(T);
-  return EPHDC_OK;
-}
-
-template <class T>
-void bfree(ephdc_batch* b, T*& p, size_t count) {
-  if (!p) return;
-  auto it = std::find(b->owned.begin(), b->owned.end(), (void*)p);
-  if (it != b->owned.end()) b->owned.erase(it);
-  (void)hipFree(p);
-  b->device_bytes -= count * sizeof(T);
-  p = nullptr;
-}
 
 void drop_graph(ephdc_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -85,102 +67,146 @@ void drop_graph(ephdc_batch* b) {
   b->graph = nullptr;
 }
 
-void free_batch(ephdc_batch* b) {
-  if (!b) return;
-  drop_graph(b);
-  for (void* p : b->owned) (void)hipFree(p);
-  delete b;
-}
-
 // log2 values per thread of the batch's kernels: the setting, else 8 values below
 // N = 16384 and 16 there (the shapes measured fastest for the split path).
 int batch_le(const ephdc_batch* b, int logn) { return b->vpt ? ilog2(b->vpt) : (logn >= 14 ? 4 : 3); }
 
-// Builds the segments and output items of one parameter set under the batch's schedule and
-// uploads them (growing the device arrays when needed).
+bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q; }
+
+// Splits the requests into parameter sets.
+void group_parts(ephdc_batch* b) {
+  b->parts.clear();
+  for (uint32_t i = 0; i < b->reqs.size(); ++i) {
+    const ephdc_session* s = b->reqs[i].session;
+    Part* pt = nullptr;
+    for (Part& p : b->parts)
+      if (same_chain(p.ref->P, s->P)) pt = &p;
+    if (!pt) {
+      b->parts.emplace_back();
+      pt = &b->parts.back();
+      pt->ref = s;
+      pt->logn = s->P.logn;
+      pt->N = s->P.N;
+      pt->L = s->P.L;
+    }
+    pt->reqs.push_back(i);
+  }
+}
+
+// Host work lists of one parameter set under the batch's schedule:
 //   segment order: request, then model range, then group -- the groups of a request that
 //   read the same model ciphertexts run side by side, so the model tile is shared in L2;
 //   slot numbering: request, then group, then range -- the slots of one output are adjacent.
-ephdc_status plan_part(ephdc_batch* b, Part& pt) {
-  std::vector<ReqDesc> rd;
-  std::vector<Segment> segs;
-  std::vector<FinishItem> fin;
+void build_part(const ephdc_batch* b, Part& pt) {
+  pt.rd.clear();
+  pt.segs.clear();
+  pt.fin.clear();
   uint32_t slot = 0;
+  size_t total = 0;
   for (uint32_t li = 0; li < pt.reqs.size(); ++li) {
-    const uint32_t ri = pt.reqs[li];
-    const ephdc_request& rq = b->reqs[ri];
-    const ephdc_session* s = rq.session;
-    const ParamSet& P = s->P;
+    const ephdc_request& rq = b->reqs[pt.reqs[li]];
+    const ParamSet& P = rq.session->P;
     const uint32_t G = P.G(rq.Q), M = P.M();
     ReqDesc d{};
-    d.model = s->d_model;
+    d.model = rq.session->d_model;
     d.hv = rq.d_hv;
-    d.scatter = s->d_scatter;
-    d.out = P.r == 1 ? rq.d_score_ct : b->rot_ws[ri];
+    d.scatter = rq.session->d_scatter;
+    d.out = rq.d_score_ct;  // folded requests: replaced by their workspace once carved
     d.D = P.D;
     d.r = P.r;
     d.B = P.B();
     d.hv_stride = G * P.B();
-    rd.push_back(d);
+    pt.rd.push_back(d);
     // S near-equal ranges of at most seg_len ciphertexts, none of them empty
-    const uint32_t len = (M + (M + b->seg_len - 1) / b->seg_len - 1) / ((M + b->seg_len - 1) / b->seg_len);
+    const uint32_t n = (M + b->seg_len - 1) / b->seg_len;
+    const uint32_t len = (M + n - 1) / n;
     const uint32_t S = (M + len - 1) / len;
-    for (uint32_t g = 0; g < G; ++g) fin.push_back(FinishItem{li, g, slot + g * S, S});
+    for (uint32_t g = 0; g < G; ++g) pt.fin.push_back(FinishItem{li, g, slot + g * S, S});
     for (uint32_t sp = 0; sp < S; ++sp) {
       const uint32_t m0 = sp * len, m1 = std::min(M, m0 + len);
-      for (uint32_t g = 0; g < G; ++g) segs.push_back(Segment{li, g, m0, m1, 0, slot + g * S + sp});
+      for (uint32_t g = 0; g < G; ++g) pt.segs.push_back(Segment{li, g, m0, m1, 0, slot + g * S + sp});
     }
     slot += G * S;
+    total += (size_t)G * M;
   }
+  pt.nslot = slot;
   // split path: consecutive segments fill the plaintext buffer chunk by chunk
+  pt.pt_cap = std::min<size_t>(total, std::max<size_t>(kMaxSegLen, b->pt_bytes / (4 * (size_t)pt.N)));
   pt.chunks.clear();
   size_t used = 0;
   uint32_t begin = 0;
-  for (uint32_t i = 0; i < segs.size(); ++i) {
-    const uint32_t n = segs[i].m1 - segs[i].m0;
+  for (uint32_t i = 0; i < pt.segs.size(); ++i) {
+    const uint32_t n = pt.segs[i].m1 - pt.segs[i].m0;
     if (used + n > pt.pt_cap && i > begin) {
       pt.chunks.emplace_back(begin, i);
       begin = i;
       used = 0;
     }
-    segs[i].pt = (uint32_t)used;
+    pt.segs[i].pt = (uint32_t)used;
     used += n;
   }
-  if (begin < segs.size()) pt.chunks.emplace_back(begin, (uint32_t)segs.size());
-  pt.nseg = (uint32_t)segs.size();
-  pt.nfin = (uint32_t)fin.size();
-  pt.nslot = slot;
-
-  ephdc_status st;
-  if (pt.seg_cap < segs.size()) {
-    bfree(b, pt.d_segs, pt.seg_cap);
-    if ((st = balloc(b, &pt.d_segs, segs.size(), "work list")) != EPHDC_OK) return st;
-    pt.seg_cap = segs.size();
-  }
-  if (pt.fin_cap < fin.size()) {
-    bfree(b, pt.d_fin, pt.fin_cap);
-    if ((st = balloc(b, &pt.d_fin, fin.size(), "output list")) != EPHDC_OK) return st;
-    pt.fin_cap = fin.size();
-  }
-  const size_t pw = (size_t)slot * 2 * pt.L * pt.N;
-  if (pt.partial_cap < pw) {
-    bfree(b, pt.d_partial, pt.partial_cap);
-    if ((st = balloc(b, &pt.d_partial, pw, "partial sums")) != EPHDC_OK) return st;
-    pt.partial_cap = pw;
-  }
-  if (!pt.d_reqs && (st = balloc(b, &pt.d_reqs, rd.size(), "request table")) != EPHDC_OK) return st;
-  hipError_t e = hipMemcpy(pt.d_reqs, rd.data(), rd.size() * sizeof(ReqDesc), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(pt.d_segs, segs.data(), segs.size() * sizeof(Segment), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(pt.d_fin, fin.data(), fin.size() * sizeof(FinishItem), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "work list upload");
-  return EPHDC_OK;
+  if (begin < pt.segs.size()) pt.chunks.emplace_back(begin, (uint32_t)pt.segs.size());
 }
 
-ephdc_status plan(ephdc_batch* b) {
-  drop_graph(b);
+// Places every device array of the batch in one block starting at `base` (nullptr: only
+// measures); returns the bytes needed.
+size_t carve(ephdc_batch* b, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
   for (Part& pt : b->parts) {
-    ephdc_status st = plan_part(b, pt);
-    if (st != EPHDC_OK) return st;
+    pt.d_reqs = (ReqDesc*)take(pt.rd.size() * sizeof(ReqDesc));
+    pt.d_segs = (Segment*)take(pt.segs.size() * sizeof(Segment));
+    pt.d_fin = (FinishItem*)take(pt.fin.size() * sizeof(FinishItem));
+    pt.d_partial = (uint32_t*)take((size_t)pt.nslot * 2 * pt.L * pt.N * 4);
+    pt.d_pt = (int32_t*)take(b->mode == 2 ? pt.pt_cap * pt.N * 4 : 0);
+  }
+  b->rot_ws.assign(b->reqs.size(), nullptr);
+  for (uint32_t i = 0; i < b->reqs.size(); ++i) {
+    const ephdc_request& rq = b->reqs[i];
+    const ParamSet& P = rq.session->P;
+    if (P.r > 1) b->rot_ws[i] = (uint32_t*)take(rotate_words(P, P.G(rq.Q)) * 4);
+  }
+  return off;
+}
+
+// Builds the lists, places them in the batch's block (growing an owned block, failing on
+// a lent one that is too small) and uploads them on `hs` (stream-ordered).
+ephdc_status plan(ephdc_batch* b, hipStream_t hs) {
+  drop_graph(b);
+  for (Part& pt : b->parts) build_part(b, pt);
+  const size_t need = carve(b, nullptr);
+  if (need > b->mem_bytes) {
+    if (!b->owned && b->mem) return fail(EPHDC_ERR_BUFFER, "batch memory block too small for this schedule");
+    if (b->mem) {
+      (void)hipStreamSynchronize(hs);
+      (void)hipFree(b->mem);
+      b->mem = nullptr;
+      b->mem_bytes = 0;
+    }
+    if (hipMalloc(&b->mem, need) != hipSuccess) {
+      b->mem = nullptr;
+      (void)hipGetLastError();
+      return fail(EPHDC_ERR_OOM, "hipMalloc failed for the batch");
+    }
+    b->mem_bytes = need;
+    b->owned = true;
+  }
+  carve(b, (char*)b->mem);
+  for (Part& pt : b->parts) {
+    for (uint32_t li = 0; li < pt.reqs.size(); ++li) {
+      const uint32_t ri = pt.reqs[li];
+      if (b->rot_ws[ri]) pt.rd[li].out = b->rot_ws[ri];
+    }
+    hipError_t e = hipMemcpyAsync(pt.d_reqs, pt.rd.data(), pt.rd.size() * sizeof(ReqDesc), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pt.d_segs, pt.segs.data(), pt.segs.size() * sizeof(Segment), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pt.d_fin, pt.fin.data(), pt.fin.size() * sizeof(FinishItem), hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "work list upload");
   }
   return EPHDC_OK;
 }
@@ -190,11 +216,11 @@ ListArgs list_args(const ephdc_batch* b, const Part& pt) {
   ListArgs a{};
   a.reqs = pt.d_reqs;
   a.segs = pt.d_segs;
-  a.nseg = pt.nseg;
+  a.nseg = (uint32_t)pt.segs.size();
   a.NLG = pt.L / b->lg;
   a.L = pt.L;
   a.fin = pt.d_fin;
-  a.nfin = pt.nfin;
+  a.nfin = (uint32_t)pt.fin.size();
   a.pt = pt.d_pt;
   a.partial = pt.d_partial;
   a.fwd_tw = s->d_fwd;
@@ -207,7 +233,11 @@ ListArgs list_args(const ephdc_batch* b, const Part& pt) {
   return a;
 }
 
-hipError_t enqueue(const ephdc_batch* b, hipStream_t hs) {
+}  // namespace
+
+namespace ephdc {
+
+hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
   hipError_t e = hipSuccess;
   for (const ephdc_request& rq : b->reqs) {
     if (!rq.d_x) continue;
@@ -218,7 +248,7 @@ hipError_t enqueue(const ephdc_batch* b, hipStream_t hs) {
   for (const Part& pt : b->parts) {
     const int le = batch_le(b, pt.logn);
     ListArgs a = list_args(b, pt);
-    const uint32_t items = pt.nseg * a.NLG;
+    const uint32_t items = a.nseg * a.NLG;
     if (b->mode == 1) {
       e = launch_score_list(pt.logn, le, (int)b->lg, a, std::min(b->grid, items), hs);
       if (e != hipSuccess) return e;
@@ -251,7 +281,9 @@ hipError_t enqueue(const ephdc_batch* b, hipStream_t hs) {
   return hipSuccess;
 }
 
-bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q; }
+}  // namespace ephdc
+
+namespace {
 
 ephdc_status check_schedule(const ephdc_batch* b, const uint32_t sc[5]) {
   if (sc[0] > 2) return fail(EPHDC_ERR_ARG, "mode must be 0 (keep), 1 (fused) or 2 (split)");
@@ -269,17 +301,19 @@ ephdc_status check_schedule(const ephdc_batch* b, const uint32_t sc[5]) {
   return EPHDC_OK;
 }
 
-ephdc_status apply_schedule(ephdc_batch* b, const uint32_t sc[5]) {
+// Applies a schedule; the work lists are rebuilt (on `hs`, after the work already queued
+// there) when the segment length or the mode changes.
+ephdc_status apply_schedule(ephdc_batch* b, const uint32_t sc[5], hipStream_t hs) {
   ephdc_status st = check_schedule(b, sc);
   if (st != EPHDC_OK) return st;
-  const uint32_t old_seg = b->seg_len;
+  const uint32_t old_seg = b->seg_len, old_mode = b->mode;
   if (sc[0]) b->mode = sc[0];
   if (sc[1]) b->vpt = sc[1];
   if (sc[2]) b->lg = sc[2];
   if (sc[3]) b->seg_len = sc[3];
   if (sc[4]) b->grid = sc[4];
   drop_graph(b);
-  if (b->seg_len != old_seg) return plan(b);
+  if (b->seg_len != old_seg || b->mode != old_mode) return plan(b, hs);
   return EPHDC_OK;
 }
 
@@ -293,11 +327,9 @@ void read_schedule(const ephdc_batch* b, uint32_t sc[5]) {
 
 }  // namespace
 
-extern "C" {
+namespace ephdc {
 
-ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out) {
-  if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
-  *out = nullptr;
+ephdc_status check_requests(const ephdc_request* reqs, uint32_t n_req) {
   if (!reqs || n_req == 0) return fail(EPHDC_ERR_ARG, "no requests");
   for (uint32_t i = 0; i < n_req; ++i) {
     const ephdc_request& r = reqs[i];
@@ -313,54 +345,93 @@ ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc
         return fail(EPHDC_ERR_ARG, "x must be 16-byte and base 4-byte aligned");
     }
   }
+  return EPHDC_OK;
+}
+
+static ephdc_batch* new_batch(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode,
+                              uint32_t seg_len) {
   ephdc_batch* b = new ephdc_batch();
   b->reqs.assign(reqs, reqs + n_req);
   b->device = reqs[0].session->device;
-  b->rot_ws.assign(n_req, nullptr);
-  ephdc_status st = EPHDC_OK;
-  for (uint32_t i = 0; i < n_req && st == EPHDC_OK; ++i) {
-    const ephdc_session* s = reqs[i].session;
-    Part* pt = nullptr;
-    for (Part& p : b->parts)
-      if (same_chain(p.ref->P, s->P)) pt = &p;
-    if (!pt) {
-      b->parts.emplace_back();
-      pt = &b->parts.back();
-      pt->ref = s;
-      pt->logn = s->P.logn;
-      pt->N = s->P.N;
-      pt->L = s->P.L;
-      pt->pt_cap = std::max<size_t>(kMaxSegLen, kBatchPtBytes / (4 * (size_t)pt->N));
-    }
-    pt->reqs.push_back(i);
-    if (s->P.r > 1) st = balloc(b, &b->rot_ws[i], rotate_words(s->P, s->P.G(reqs[i].Q)), "rotation workspace");
-  }
-  // the default schedule: split path, one limb per MAC item, 128-ciphertext segments
-  for (Part& pt : b->parts) {
-    if (st != EPHDC_OK) break;
-    st = balloc(b, &pt.d_pt, pt.pt_cap * pt.N, "plaintext chunk buffer");
-  }
-  if (st == EPHDC_OK) st = plan(b);
+  b->pt_bytes = pt_bytes;
+  b->mode = mode;
+  b->seg_len = seg_len;
+  group_parts(b);
+  return b;
+}
+
+size_t batch_bytes(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode, uint32_t seg_len) {
+  ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len);
+  for (Part& pt : b->parts) build_part(b, pt);
+  const size_t need = carve(b, nullptr);
+  delete b;
+  return need;
+}
+
+ephdc_status batch_new(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode, uint32_t seg_len,
+                       void* mem, size_t mem_bytes, hipStream_t hs, ephdc_batch** out) {
+  *out = nullptr;
+  ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len);
+  b->mem = mem;
+  b->mem_bytes = mem ? mem_bytes : 0;
+  b->owned = false;
+  ephdc_status st = plan(b, hs);
   if (st != EPHDC_OK) {
-    free_batch(b);
+    batch_free(b);
     return st;
   }
   *out = b;
   return EPHDC_OK;
 }
 
+void batch_free(ephdc_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->owned && b->mem) (void)hipFree(b->mem);
+  delete b;
+}
+
+}  // namespace ephdc
+
+extern "C" {
+
+ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out) {
+  if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  ephdc_status st = check_requests(reqs, n_req);
+  if (st != EPHDC_OK) return st;
+  // default schedule: split path, one limb per MAC item, 128-ciphertext segments, plaintext
+  // chunks of at most 1 GiB
+  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, nullptr, 0, nullptr, out);
+  if (st == EPHDC_OK) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+      batch_free(*out);
+      *out = nullptr;
+      return hip_fail(e, "batch setup");
+    }
+  }
+  return st;
+}
+
 ephdc_status ephdc_batch_destroy(ephdc_batch* b) {
   if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
   (void)hipDeviceSynchronize();
-  free_batch(b);
+  batch_free(b);
   return EPHDC_OK;
 }
 
-size_t ephdc_batch_device_bytes(const ephdc_batch* b) { return b ? b->device_bytes : 0; }
+size_t ephdc_batch_device_bytes(const ephdc_batch* b) { return b ? b->mem_bytes : 0; }
 
 ephdc_status ephdc_batch_tune(ephdc_batch* b, const uint32_t schedule[5]) {
   if (!b || !schedule) return fail(EPHDC_ERR_ARG, "NULL argument");
-  return apply_schedule(b, schedule);
+  (void)hipDeviceSynchronize();  // no launch of this batch may still read its work lists
+  ephdc_status st = apply_schedule(b, schedule, nullptr);
+  if (st == EPHDC_OK) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(e, "batch tune");
+  }
+  return st;
 }
 
 ephdc_status ephdc_batch_schedule(const ephdc_batch* b, uint32_t schedule[5]) {
@@ -376,7 +447,7 @@ ephdc_status ephdc_batch_run(ephdc_batch* b, void* stream) {
     HIP_TRY(hipGraphLaunch(b->exec, hs), "graph launch");
     return EPHDC_OK;
   }
-  HIP_TRY(enqueue(b, hs), "batch launch");
+  HIP_TRY(batch_enqueue(b, hs), "batch launch");
   return EPHDC_OK;
 }
 
@@ -386,7 +457,7 @@ ephdc_status ephdc_batch_capture(ephdc_batch* b, void* stream) {
   hipStream_t hs = (hipStream_t)stream;
   drop_graph(b);
   HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeRelaxed), "begin capture");
-  hipError_t e = enqueue(b, hs);
+  hipError_t e = batch_enqueue(b, hs);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(hs, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -421,16 +492,16 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
     (void)hipEventDestroy(e1);
     return st;
   };
+  (void)hipDeviceSynchronize();
   drop_graph(b);
-  // mean ms per run of the current schedule (+inf if it cannot run)
+  // mean ms per run of the current schedule
   auto measure = [&](double& ms) -> ephdc_status {
-    if (enqueue(b, hs) != hipSuccess) return hip_fail(hipGetLastError(), "autotune launch");
-    (void)hipEventRecord(e0, hs);
-    for (uint32_t k = 0; k < reps; ++k)
-      if (enqueue(b, hs) != hipSuccess) return hip_fail(hipGetLastError(), "autotune launch");
-    (void)hipEventRecord(e1, hs);
-    hipError_t e = hipEventSynchronize(e1);
-    if (e != hipSuccess) return hip_fail(e, "autotune sync");
+    hipError_t e = batch_enqueue(b, hs);
+    if (e == hipSuccess) e = hipEventRecord(e0, hs);
+    for (uint32_t k = 0; k < reps && e == hipSuccess; ++k) e = batch_enqueue(b, hs);
+    if (e == hipSuccess) e = hipEventRecord(e1, hs);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune run");
     float t = 0.f;
     (void)hipEventElapsedTime(&t, e0, e1);
     ms = t / reps;
@@ -441,7 +512,6 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
   double best = 0;
   ephdc_status st = measure(best);
   if (st != EPHDC_OK) return cleanup(st);
-  // candidate values of each setting
   std::vector<uint32_t> vpts;
   for (uint32_t v : {8u, 16u, 32u}) {
     bool ok = true;
@@ -461,11 +531,14 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
       if (v == cur[k]) continue;
       uint32_t trial[5] = {0, 0, 0, 0, 0};
       trial[k] = v;
-      if (apply_schedule(b, trial) != EPHDC_OK) continue;
+      if (apply_schedule(b, trial, hs) != EPHDC_OK) {
+        apply_schedule(b, cur, hs);
+        continue;
+      }
       double ms = 0;
       st = measure(ms);
       if (st != EPHDC_OK) {
-        apply_schedule(b, cur);
+        apply_schedule(b, cur, hs);
         return cleanup(st);
       }
       if (ms < best) {
@@ -473,23 +546,26 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
         cur[k] = v;
       }
     }
-    st = apply_schedule(b, cur);
+    st = apply_schedule(b, cur, hs);
     if (st != EPHDC_OK) return cleanup(st);
   }
+  HIP_TRY(hipStreamSynchronize(hs), "autotune sync");
   if (schedule) read_schedule(b, schedule);
   if (best_ms) *best_ms = best;
   return cleanup(EPHDC_OK);
 }
 
 ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream) {
-  ephdc_batch* b = nullptr;
-  ephdc_status st = ephdc_batch_create(reqs, n_req, &b);
+  ephdc_status st = check_requests(reqs, n_req);
   if (st != EPHDC_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
-  hipError_t e = enqueue(b, hs);
-  if (e == hipSuccess) e = hipStreamSynchronize(hs);
-  free_batch(b);
-  if (e != hipSuccess) return hip_fail(e, "score_many");
+  ephdc_batch* b = nullptr;
+  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, nullptr, 0, hs, &b);
+  if (st != EPHDC_OK) return st;
+  hipError_t e = batch_enqueue(b, hs);
+  hipError_t e2 = hipStreamSynchronize(hs);
+  batch_free(b);
+  if (e != hipSuccess || e2 != hipSuccess) return hip_fail(e != hipSuccess ? e : e2, "score_many");
   return EPHDC_OK;
 }
 

@@ -1,0 +1,448 @@
+// Serving loop: device-resident tenants (encrypted models, Galois keys), requests admitted by
+// their device-memory footprint, and continuous batching -- a scheduler thread turns the
+// requests waiting at each moment into a batch on one of several streams, so requests that
+// arrive while others run are admitted as soon as a stream and memory free up, and their
+// work overlaps on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "batch.hpp"
+#include "session.hpp"
+
+using namespace ephdc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit allocator over one device block; blocks are returned in any order and merged.
+class Arena {
+ public:
+  void init(char* base, size_t bytes) {
+    base_ = base;
+    free_.clear();
+    free_[0] = bytes;
+    used_ = 0;
+  }
+  bool ready() const { return base_ != nullptr; }
+  char* base() const { return base_; }
+  // offset of a block of `bytes`, or SIZE_MAX when no free range is large enough
+  size_t get(size_t bytes) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_ += bytes;
+        return off;
+      }
+    }
+    return SIZE_MAX;
+  }
+  void put(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  char* base_ = nullptr;
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+struct Tenant {
+  ephdc_session* s;
+  const int8_t* d_base;
+};
+
+struct Req {
+  uint64_t ticket;
+  uint32_t tenant, Q;
+  const uint8_t* d_x;
+  uint32_t* d_out;
+  size_t hv_bytes;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int state = 0;  // 0 waiting, 1 in flight, 2 done, < 0 failed (negated status)
+};
+
+struct Inflight {
+  ephdc_batch* batch = nullptr;
+  int stream = -1;
+  hipEvent_t done = nullptr;
+  size_t off = 0, bytes = 0;
+  std::vector<uint64_t> tickets;
+};
+
+}  // namespace
+
+struct ephdc_server {
+  // configuration
+  size_t budget = 0;
+  uint32_t nstreams = 2, max_batch = 64;
+  size_t pt_bytes = (size_t)256 << 20;
+  // state (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::vector<Tenant> tenants;
+  std::map<uint64_t, Req> reqs;
+  std::deque<uint64_t> waiting;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  // device side (scheduler thread)
+  int device = -1;
+  void* mem = nullptr;
+  Arena arena;
+  std::vector<hipStream_t> streams;
+  std::vector<bool> stream_busy;
+  std::list<Inflight> inflight;
+  std::thread worker;
+  std::string worker_error;
+  // statistics
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batched_requests = 0;
+  size_t peak_bytes = 0;
+  std::vector<double> latencies;  // seconds, completed requests
+};
+
+namespace {
+
+double now_s(const ephdc_server* sv) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+}
+
+// Device memory of one request outside the batch block: its query hypervectors.
+size_t hv_bytes(const ephdc_session* s, uint32_t Q) { return (size_t)s->P.D * s->P.G(Q) * s->P.B(); }
+
+// Completes every in-flight batch whose event has fired; returns whether any did.
+bool reap(ephdc_server* sv, std::unique_lock<std::mutex>&) {
+  bool any = false;
+  for (auto it = sv->inflight.begin(); it != sv->inflight.end();) {
+    const hipError_t q = hipEventQuery(it->done);
+    if (q == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    const double t = now_s(sv);
+    for (uint64_t tk : it->tickets) {
+      Req& r = sv->reqs[tk];
+      if (q == hipSuccess) {
+        r.state = 2;
+        r.t_done = t;
+        sv->latencies.push_back(t - r.t_submit);
+        ++sv->completed;
+      } else {
+        r.state = -EPHDC_ERR_HIP;
+        r.t_done = t;
+      }
+    }
+    batch_free(it->batch);
+    (void)hipEventDestroy(it->done);
+    sv->arena.put(it->off, it->bytes);
+    sv->stream_busy[it->stream] = false;
+    it = sv->inflight.erase(it);
+    any = true;
+  }
+  if (any) sv->done_cv.notify_all();
+  return any;
+}
+
+// Forms and launches one batch from the head of the waiting queue on stream `si`: requests
+// are taken in arrival order while the batch's footprint fits the free device memory.
+// Returns false when nothing could be admitted.
+bool admit(ephdc_server* sv, int si) {
+  std::vector<uint64_t> take;
+  std::vector<ephdc_request> rq;
+  size_t hv_total = 0, need = 0;
+  const size_t free_bytes = sv->budget - sv->arena.used();
+  while (!sv->waiting.empty() && take.size() < sv->max_batch) {
+    Req& r = sv->reqs[sv->waiting.front()];
+    const Tenant& t = sv->tenants[r.tenant];
+    ephdc_request e{};
+    e.session = t.s;
+    e.d_x = r.d_x;
+    e.d_base = t.d_base;
+    e.d_hv = reinterpret_cast<int8_t*>(0x1000);  // placeholder: placed after measuring
+    e.Q = r.Q;
+    e.d_score_ct = r.d_out;
+    rq.push_back(e);
+    const size_t hv = align_up(r.hv_bytes);
+    const size_t bb = batch_bytes(rq.data(), (uint32_t)rq.size(), sv->pt_bytes, 2, 128);
+    const size_t total = bb + hv_total + hv;
+    if (total > free_bytes) {
+      rq.pop_back();
+      if (take.empty() && hv + batch_bytes(&e, 1, sv->pt_bytes, 2, 128) > sv->budget) {
+        // larger than the whole budget: can never be admitted
+        r.state = -EPHDC_ERR_OOM;
+        r.t_done = now_s(sv);
+        ++sv->rejected;
+        sv->waiting.pop_front();
+        sv->done_cv.notify_all();
+        continue;
+      }
+      break;
+    }
+    hv_total += hv;
+    need = total;
+    take.push_back(r.ticket);
+    sv->waiting.pop_front();
+  }
+  if (take.empty()) return false;
+  const size_t off = sv->arena.get(need);
+  if (off == SIZE_MAX) {  // fragmented: put the requests back and wait for a completion
+    for (auto it = take.rbegin(); it != take.rend(); ++it) sv->waiting.push_front(*it);
+    return false;
+  }
+  char* base = sv->arena.base() + off;
+  size_t hv_off = 0;
+  for (size_t i = 0; i < take.size(); ++i) {
+    rq[i].d_hv = reinterpret_cast<int8_t*>(base + hv_off);
+    hv_off += align_up(sv->reqs[take[i]].hv_bytes);
+  }
+  hipStream_t hs = sv->streams[si];
+  ephdc_batch* b = nullptr;
+  ephdc_status st = batch_new(rq.data(), (uint32_t)rq.size(), sv->pt_bytes, 2, 128, base + hv_off, need - hv_off, hs, &b);
+  hipEvent_t ev = nullptr;
+  hipError_t e = hipSuccess;
+  if (st == EPHDC_OK) e = batch_enqueue(b, hs);
+  if (st == EPHDC_OK && e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (st == EPHDC_OK && e == hipSuccess) e = hipEventRecord(ev, hs);
+  const double t = now_s(sv);
+  if (st != EPHDC_OK || e != hipSuccess) {
+    // the launch failed: fail these requests, release their memory once the stream is idle
+    (void)hipStreamSynchronize(hs);
+    if (b) batch_free(b);
+    if (ev) (void)hipEventDestroy(ev);
+    sv->arena.put(off, need);
+    for (uint64_t tk : take) {
+      sv->reqs[tk].state = st != EPHDC_OK ? -(int)st : -EPHDC_ERR_HIP;
+      sv->reqs[tk].t_done = t;
+    }
+    sv->done_cv.notify_all();
+    return true;
+  }
+  for (uint64_t tk : take) {
+    sv->reqs[tk].state = 1;
+    sv->reqs[tk].t_admit = t;
+  }
+  Inflight f;
+  f.batch = b;
+  f.stream = si;
+  f.done = ev;
+  f.off = off;
+  f.bytes = need;
+  f.tickets = std::move(take);
+  sv->stream_busy[si] = true;
+  sv->inflight.push_back(std::move(f));
+  ++sv->batches;
+  sv->batched_requests += sv->inflight.back().tickets.size();
+  sv->peak_bytes = std::max(sv->peak_bytes, sv->arena.used());
+  return true;
+}
+
+void worker_main(ephdc_server* sv) {
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (hipSetDevice(sv->device) != hipSuccess) {
+    sv->worker_error = "hipSetDevice failed";
+    return;
+  }
+  while (true) {
+    reap(sv, lk);
+    if (sv->stop && sv->waiting.empty() && sv->inflight.empty()) break;
+    bool progressed = false;
+    for (int si = 0; si < (int)sv->streams.size() && !sv->waiting.empty(); ++si)
+      if (!sv->stream_busy[si] && admit(sv, si)) progressed = true;
+    if (progressed) continue;
+    // wait for a submission, or poll the in-flight batches
+    if (sv->inflight.empty())
+      sv->cv.wait(lk, [&] { return sv->stop || !sv->waiting.empty(); });
+    else
+      sv->cv.wait_for(lk, std::chrono::microseconds(100));
+  }
+}
+
+// Allocates the device block and streams and starts the scheduler (on the first tenant).
+ephdc_status start(ephdc_server* sv, int device) {
+  sv->device = device;
+  HIP_TRY(hipSetDevice(device), "set device");
+  if (hipMalloc(&sv->mem, sv->budget) != hipSuccess) {
+    sv->mem = nullptr;
+    (void)hipGetLastError();
+    return fail(EPHDC_ERR_OOM, "hipMalloc failed for the server's request memory");
+  }
+  sv->arena.init((char*)sv->mem, sv->budget);
+  for (uint32_t i = 0; i < sv->nstreams; ++i) {
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
+    sv->streams.push_back(s);
+    sv->stream_busy.push_back(false);
+  }
+  sv->worker = std::thread(worker_main, sv);
+  return EPHDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ephdc_status ephdc_server_create(size_t budget_bytes, uint32_t streams, uint32_t max_batch, ephdc_server** out) {
+  if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (budget_bytes < ((size_t)64 << 20)) return fail(EPHDC_ERR_ARG, "budget must be at least 64 MiB");
+  if (streams < 1 || streams > 8) return fail(EPHDC_ERR_ARG, "streams must be in [1, 8]");
+  ephdc_server* sv = new ephdc_server();
+  sv->budget = budget_bytes;
+  sv->nstreams = streams;
+  sv->max_batch = max_batch ? max_batch : 64;
+  sv->pt_bytes = std::min<size_t>((size_t)256 << 20, budget_bytes / 8);
+  *out = sv;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_add_tenant(ephdc_server* sv, ephdc_session* s, const int8_t* d_base, uint32_t* tenant) {
+  if (!sv || !s || !tenant) return fail(EPHDC_ERR_ARG, "NULL argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (sv->stop) return fail(EPHDC_ERR_ARG, "server is shutting down");
+  if (!sv->tenants.empty() && s->device != sv->device)
+    return fail(EPHDC_ERR_UNSUPPORTED, "every tenant of a server lives on one device");
+  if (sv->tenants.empty()) {
+    lk.unlock();
+    ephdc_status st = start(sv, s->device);
+    if (st != EPHDC_OK) return st;
+    lk.lock();
+  }
+  *tenant = (uint32_t)sv->tenants.size();
+  sv->tenants.push_back(Tenant{s, d_base});
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_submit(ephdc_server* sv, uint32_t tenant, const uint8_t* d_x, uint32_t Q, uint32_t* d_score_ct,
+                                 uint64_t* ticket) {
+  if (!sv || !d_x || !d_score_ct || !ticket) return fail(EPHDC_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->stop) return fail(EPHDC_ERR_ARG, "server is shutting down");
+  if (tenant >= sv->tenants.size()) return fail(EPHDC_ERR_ARG, "unknown tenant");
+  const Tenant& t = sv->tenants[tenant];
+  if (!t.d_base) return fail(EPHDC_ERR_ARG, "tenant has no base hypervectors");
+  const ParamSet& P = t.s->P;
+  if (Q == 0 || Q > t.s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, the tenant session's max_Q]");
+  if (P.F % 16 != 0 || P.D % 64 != 0) return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F % 16 == 0 and D % 64 == 0");
+  if ((uintptr_t)d_x & 15) return fail(EPHDC_ERR_ARG, "x must be 16-byte aligned");
+  Req r;
+  r.ticket = sv->next_ticket++;
+  r.tenant = tenant;
+  r.Q = Q;
+  r.d_x = d_x;
+  r.d_out = d_score_ct;
+  r.hv_bytes = hv_bytes(t.s, Q);
+  r.t_submit = now_s(sv);
+  sv->reqs.emplace(r.ticket, r);
+  sv->waiting.push_back(r.ticket);
+  ++sv->submitted;
+  *ticket = r.ticket;
+  sv->cv.notify_all();
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_query(ephdc_server* sv, uint64_t ticket, int32_t* state, double times[3]) {
+  if (!sv || !state) return fail(EPHDC_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(EPHDC_ERR_ARG, "unknown ticket");
+  *state = it->second.state;
+  if (times) {
+    times[0] = it->second.t_submit;
+    times[1] = it->second.t_admit;
+    times[2] = it->second.t_done;
+  }
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout_s) {
+  if (!sv) return fail(EPHDC_ERR_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto finished = [&] {
+    if (ticket == 0) return sv->waiting.empty() && sv->inflight.empty();
+    auto it = sv->reqs.find(ticket);
+    return it == sv->reqs.end() || it->second.state >= 2 || it->second.state < 0;
+  };
+  if (ticket != 0 && sv->reqs.find(ticket) == sv->reqs.end()) return fail(EPHDC_ERR_ARG, "unknown ticket");
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+  while (!finished()) {
+    if (timeout_s > 0 && std::chrono::steady_clock::now() >= deadline)
+      return fail(EPHDC_ERR_HIP, "wait timed out");
+    sv->done_cv.wait_for(lk, std::chrono::milliseconds(1));
+  }
+  if (ticket != 0) {
+    const int st = sv->reqs[ticket].state;
+    if (st < 0) return fail((ephdc_status)(-st), "request failed");
+  }
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_stats(ephdc_server* sv, double out[12]) {
+  if (!sv || !out) return fail(EPHDC_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::vector<double> l = sv->latencies;
+  std::sort(l.begin(), l.end());
+  auto pct = [&](double p) {
+    if (l.empty()) return 0.0;
+    const size_t i = std::min(l.size() - 1, (size_t)(p * (double)(l.size() - 1) + 0.5));
+    return l[i] * 1e3;
+  };
+  out[0] = (double)sv->submitted;
+  out[1] = (double)sv->completed;
+  out[2] = (double)sv->rejected;
+  out[3] = (double)sv->waiting.size();
+  out[4] = (double)sv->inflight.size();
+  out[5] = (double)sv->batches;
+  out[6] = sv->batches ? (double)sv->batched_requests / (double)sv->batches : 0.0;
+  out[7] = pct(0.50);
+  out[8] = pct(0.99);
+  out[9] = (double)sv->peak_bytes;
+  out[10] = (double)sv->budget;
+  out[11] = now_s(sv);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_destroy(ephdc_server* sv) {
+  if (!sv) return fail(EPHDC_ERR_ARG, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+    sv->cv.notify_all();
+  }
+  if (sv->worker.joinable()) sv->worker.join();
+  for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+  if (sv->mem) (void)hipFree(sv->mem);
+  delete sv;
+  return EPHDC_OK;
+}
+
+}  // extern "C"

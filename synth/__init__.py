@@ -113,6 +113,14 @@ def loguniform_batch_sizes(seed: int, n: int, hi: int = 4096) -> np.ndarray:
     return np.clip(np.floor(np.exp(u * math.log(hi))).astype(np.int64), 1, hi)
 
 
+def batch_mix(seed: int, n: int, n_models: int, hi: int = 4096):
+    """n requests of a batch: (batch sizes floor(exp(U[0, ln hi])), model index U{0..n_models-1});
+    the sizes are draws 0..n-1 of the trace stream and the model choices draws n..2n-1."""
+    sizes = loguniform_batch_sizes(seed, n, hi)
+    models = ints(seed, TAG_TRACE, 0, n_models - 1, (n,), start=n)
+    return sizes, models
+
+
 def poisson_trace(seed: int, rate: float, duration: float, qmin: int, qmax: int,
                   n_tenants: int):
     """Poisson arrivals: (arrival time s, tenant, batch size) triples, sorted by time.

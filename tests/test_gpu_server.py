@@ -1,0 +1,137 @@
+"""Serving loop on the GPU (C ABI): requests of several tenants arriving while others run
+are scored by continuous batches; each result equals the request scored alone, bit for
+bit, and decrypts to the exact scores; admission respects the device-memory budget."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2511_00737_amd as ep
+import synth
+from oracle import bfv, hdc, pipeline
+from oracle.params import Params as OParams, default_primes
+
+from gpu_helpers import to_dev, to_host_u32, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+F = 64
+# (N, L, K, D, r, alpha, dnum)
+TENANTS = [(4096, 3, 2, 64, 1, 0, 0), (4096, 3, 3, 128, 2, 1, 3), (8192, 4, 7, 64, 1, 0, 0)]
+
+
+class Tenant:
+    def __init__(self, i, N, L, K, D, r, alpha, dnum, max_Q):
+        torch = torch_cuda()
+        primes = default_primes(N, L + alpha)
+        kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum)
+        self.o, self.e = OParams(**kw), ep.Params(**kw)
+        self.sk = bfv.secret_key(self.o, 80 + i)
+        self.C = synth.class_hypervectors(81 + i, K, D)
+        self.model = bfv.encrypt_model(self.o, self.sk, self.C, 82 + i)
+        self.gk = bfv.galois_keys(self.o, self.sk, 83 + i) if r > 1 else None
+        self.base = synth.base_hypervectors(84 + i, F, D)
+        self.d_base = to_dev(self.base)
+        self.s = ep.Session(self.e, to_dev(self.model.astype(np.uint32)),
+                            to_dev(self.gk.astype(np.uint32)) if self.gk is not None else None, max_Q=max_Q)
+        self.torch = torch
+
+    def out(self, Q):
+        return self.torch.zeros((self.s.num_groups(Q), 2, self.o.L, self.o.N), dtype=self.torch.int32, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def tenants():
+    ts = [Tenant(i, *t, max_Q=1500) for i, t in enumerate(TENANTS)]
+    yield ts
+    for t in ts:
+        t.s.close()
+
+
+def test_results_are_the_same_alone_and_in_the_mix(tenants):
+    torch = tenants[0].torch
+    rng = np.random.default_rng(2026)
+    sv = ep.Server(1 << 30, streams=2, max_batch=8)
+    try:
+        ids = [sv.add_tenant(t.s, t.d_base) for t in tenants]
+        jobs = []
+        for k in range(40):
+            ti = int(rng.integers(0, len(tenants)))
+            Q = int(rng.integers(1, 1500))
+            t = tenants[ti]
+            x = synth.uniform_features(900 + k, Q, F)
+            d_x, out = to_dev(x), t.out(Q)
+            tk = sv.submit(ids[ti], d_x, Q, out)
+            jobs.append((tk, ti, Q, x, d_x, out))
+            if k % 5 == 4:
+                time.sleep(0.002)  # later requests arrive while earlier batches run
+        sv.wait(0, timeout_s=120)
+        stats = sv.stats()
+        assert stats["completed"] == 40 and stats["rejected"] == 0
+        assert stats["batches"] >= 2 and stats["p99_ms"] >= stats["p50_ms"] > 0
+        for tk, ti, Q, x, d_x, out in jobs:
+            state, (ts, ta, td) = sv.query(tk)
+            assert state == 2 and ts <= ta <= td
+    finally:
+        sv.close()
+    # each request alone, through the single-request entry points
+    for n, (tk, ti, Q, x, d_x, out) in enumerate(jobs):
+        t = tenants[ti]
+        d_hv = torch.empty((t.o.D, t.s.hv_stride(Q)), dtype=torch.int8, device="cuda")
+        alone = t.out(Q)
+        ep.ephdc_encode_queries(t.s, d_x, t.d_base, Q, d_hv)
+        ep.ephdc_score_encrypted(t.s, d_hv, Q, alone)
+        torch.cuda.synchronize()
+        got = to_host_u32(out).astype(np.int64)
+        assert np.array_equal(got, to_host_u32(alone).astype(np.int64)), n
+        if n % 8 == 0:  # and against the oracle: exact scores, and the last group's ciphertext
+            h = hdc.encode(x, t.base)
+            scores, _ = pipeline.decrypt_scores(t.o, t.sk, got, Q)
+            assert np.array_equal(scores, hdc.scores_mod_t(h, t.C, 65537)), n
+            G = t.o.groups(Q)
+            want = pipeline.score_ciphertexts(t.o, t.model, h, t.gk, groups=[G - 1])
+            assert np.array_equal(got[G - 1], want[0]), n
+
+
+def test_admission_by_device_memory(tenants):
+    """A 64 MiB budget where one request of an N = 8192, D = 2048 tenant takes about 44 MiB
+    (query hypervectors, partial sums, plaintext chunk): at most two fit at once, so the
+    requests are admitted in several batches without ever exceeding the budget, and a
+    request too large for the whole budget is rejected while the others complete."""
+    torch = tenants[0].torch
+    budget = 64 << 20
+    primes = default_primes(8192, 4)
+    prm = ep.Params(N=8192, q=tuple(primes), F=F, D=2048, K=2)
+    sk, _ = ep.ephdc_keygen(prm, 7)
+    C = synth.class_hypervectors(7, 2, 2048)
+    base = synth.base_hypervectors(7, F, 2048)
+    sess = ep.Session(prm, to_dev(ep.ephdc_encrypt_model(prm, sk, C, 7)), max_Q=4096)
+    big_prm = ep.Params(N=8192, q=tuple(primes), F=F, D=8192, K=2)
+    big = ep.Session(big_prm, torch.zeros((8192, 2, 4, 8192), dtype=torch.int32, device="cuda"), max_Q=4096)
+    sv = ep.Server(budget, streams=2, max_batch=64)
+    try:
+        tid = sv.add_tenant(sess, to_dev(base))
+        bid = sv.add_tenant(big, torch.zeros((F, 8192), dtype=torch.int8, device="cuda"))
+        jobs = []
+        for k in range(5):
+            Q = 300 + 211 * k
+            x = synth.uniform_features(1100 + k, Q, F)
+            out = torch.zeros((sess.num_groups(Q), 2, 4, 8192), dtype=torch.int32, device="cuda")
+            jobs.append((sv.submit(tid, to_dev(x), Q, out), Q, x, out))
+        big_out = torch.zeros((big.num_groups(4096), 2, 4, 8192), dtype=torch.int32, device="cuda")
+        btk = sv.submit(bid, torch.zeros((4096, F), dtype=torch.uint8, device="cuda"), 4096, big_out)
+        sv.wait(0, timeout_s=120)
+        assert sv.query(btk)[0] == -ep.ERR_OOM
+        with pytest.raises(ep.EphdcError):
+            sv.wait(btk)
+        stats = sv.stats()
+        assert stats["completed"] == 5 and stats["rejected"] == 1
+        assert 0 < stats["peak_bytes"] <= budget and stats["batches"] >= 3
+        for tk, Q, x, out in jobs:
+            assert sv.query(tk)[0] == 2
+            scores, _ = ep.ephdc_decrypt_scores(prm, sk, to_host_u32(out), Q)
+            assert np.array_equal(scores, hdc.scores_mod_t(hdc.encode(x, base), C, 65537))
+    finally:
+        sv.close()
+        sess.close()
+        big.close()
