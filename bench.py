@@ -41,6 +41,14 @@ WORKLOADS = {
                     "(K in {2, 7} x D in {2048, 4096, 10240}) at BFV N=8192, 4x30-bit limbs; HDC F=2304 "
                     "(48x48 Gaussian-blob images); one graph-captured batch of persistent launches, "
                     "autotuned schedule"),
+    # serving: Poisson arrivals over 32 device-resident tenants, half at N = 8192 (the six
+    # batching models) and half at N = 16384 with 8+2 limbs and r = 4 (two rotations)
+    "c5": dict(serving=True, rate=2000.0, duration=5.0, qmax=512, tenants=32, F=2304,
+               models=[(K, D) for K in (2, 7) for D in (2048, 4096, 10240)],
+               desc="serving: Poisson arrivals, requests of U{1..512} queries, 32 tenants with device-resident "
+                    "encrypted models (16 at BFV N=8192 / 4 limbs cycling K in {2, 7} x D in {2048, 4096, 10240}; "
+                    "16 at N=16384 / 8+2 limbs, dnum=4, r=4 cycling the same (K, D)), HBM-budget admission, "
+                    "continuous batching on 2 streams"),
     # large parameters: 8 ciphertext limbs + 2 special primes, hybrid key switching with 4
     # digits, 8 blocks folded per row (3 rotations per score ciphertext)
     "c4": dict(N=16384, L=8, alpha=2, dnum=4, r=8, F=2304, D=10240, K=26, Q=16384, images=True, cpu_sample_m=24,
@@ -255,6 +263,116 @@ def bench_batched(args, w) -> int:
     return 0
 
 
+def bench_serving(args, w) -> int:
+    """The serving workload: a Poisson trace replayed against the native serving loop.
+    Requests are submitted at their arrival times (device-resident features); the report
+    gives completed inferences/s over the run, submit-to-done latency p50/p99 and the time
+    requests waited for admission, at the trace's rate and, with --rates, at lower ones."""
+    import torch
+    dev = torch.device("cuda")
+    F, seed = w["F"], args.seed
+    t0 = time.perf_counter()
+    pool = torch.from_numpy(synth.blob_images(seed, w["qmax"])).to(dev)
+    bases = {}
+    tenants = []
+    for k in range(w["tenants"]):
+        K, D = w["models"][k % len(w["models"])]
+        if k < w["tenants"] // 2:
+            N, L, alpha, r, dnum = 8192, 4, 0, 1, 0
+        else:
+            N, L, alpha, r, dnum = 16384, 8, 2, 4, 4
+        primes = ep.default_primes(N, L + alpha)
+        prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum)
+        sk, gk = ep.ephdc_keygen(prm, seed + 100 + k)
+        C = synth.class_hypervectors(seed + 100 + k, K, D)
+        model = ep.ephdc_encrypt_model(prm, sk, C, seed + 100 + k)
+        d_model = torch.from_numpy(model.view(np.int32)).to(dev)
+        d_gk = torch.from_numpy(gk.view(np.int32)).to(dev) if gk is not None else None
+        sess = ep.Session(prm, d_model, d_gk, max_Q=w["qmax"])
+        del d_model, d_gk, model
+        if D not in bases:
+            bases[D] = torch.from_numpy(synth.base_hypervectors(seed, F, D)).to(dev)
+        tenants.append(dict(prm=prm, sk=sk, C=C, sess=sess, base=bases[D]))
+    torch.cuda.synchronize()
+    model_bytes = sum(t["sess"].device_bytes for t in tenants)
+    print(f"[bench] c5: {len(tenants)} tenants, {model_bytes / 2**30:.1f} GiB of sessions, "
+          f"setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def run(rate, duration, budget):
+        trace = synth.poisson_trace(seed, rate, duration, 1, w["qmax"], len(tenants))
+        sv = ep.Server(budget, streams=2, max_batch=64)
+        ids = [sv.add_tenant(t["sess"], t["base"]) for t in tenants]
+        live, check, tickets = {}, [], []
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        for i, (ta, ti, Q) in enumerate(trace):
+            delay = start + ta - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            t = tenants[ti]
+            out = torch.empty((t["sess"].num_groups(Q), 2, t["prm"].L, t["prm"].N), dtype=torch.int32, device=dev)
+            tk = sv.submit(ids[ti], pool[:Q], Q, out)
+            live[tk] = (out, Q, ti)
+            tickets.append(tk)
+            if i % 200 == 0:  # release finished outputs now and then; keep a few to check
+                for k in [k for k in live if sv.query(k)[0] == 2]:
+                    item = live.pop(k)
+                    if len(check) < 4 and k % 7 == 0:
+                        check.append(item)
+        t_submitted = time.perf_counter() - start
+        sv.wait(0, timeout_s=600)
+        wall = time.perf_counter() - start
+        stats = sv.stats()
+        waits = []
+        for tk in tickets:
+            st, (ts, tad, td) = sv.query(tk)
+            if st == 2:
+                waits.append(tad - ts)
+        for out_k, q_k, ti_k in check + [live[k] for k in list(live)[:4]]:
+            t = tenants[ti_k]
+            scores, _ = ep.ephdc_decrypt_scores(t["prm"], t["sk"], out_k.cpu().numpy().view(np.uint32), q_k)
+            hv = torch.empty((t["prm"].D, t["sess"].hv_stride(q_k)), dtype=torch.int8, device=dev)
+            ep.ephdc_encode_queries(t["sess"], pool[:q_k], t["base"], q_k, hv)
+            torch.cuda.synchronize()
+            h = hv.cpu().numpy()[:, :q_k].T.astype(np.float64)
+            want = (h @ t["C"].astype(np.float64).T).astype(np.int64) % 65537
+            if not np.array_equal(scores, np.where(want > 32768, want - 65537, want)):
+                raise RuntimeError("served scores differ from h.C mod t")
+        sv.close()
+        total_q = sum(q for _, _, q in trace)
+        return {"rate_req_s": rate, "requests": len(trace), "queries": total_q,
+                "offered_inferences_s": round(total_q / duration, 1),
+                "value": round(total_q / wall, 1), "wall_s": round(wall, 3), "submit_s": round(t_submitted, 3),
+                "p50_ms": round(stats["p50_ms"], 3), "p99_ms": round(stats["p99_ms"], 3),
+                "admission_wait_ms_mean": round(1e3 * float(np.mean(waits)), 3) if waits else 0.0,
+                "admission_wait_ms_p99": round(1e3 * float(np.percentile(waits, 99)), 3) if waits else 0.0,
+                "rejected": int(stats["rejected"]), "batches": int(stats["batches"]),
+                "mean_requests_per_batch": round(stats["mean_batch"], 2),
+                "peak_request_bytes": int(stats["peak_bytes"]), "budget_bytes": int(stats["budget_bytes"]),
+                "stable": wall <= duration * 1.2}
+
+    budget = 32 << 30
+    main_run = run(w["rate"], args.duration or w["duration"], budget)
+    print(f"[bench] c5 at {w['rate']} req/s: {main_run}", file=sys.stderr, flush=True)
+    sweep = []
+    for rate in [float(x) for x in args.rates.split(",") if x]:
+        sweep.append(run(rate, args.duration or w["duration"], budget))
+        print(f"[bench] c5 at {rate} req/s: {sweep[-1]}", file=sys.stderr, flush=True)
+    result = {
+        "metric": METRIC, "value": main_run["value"], "unit": "inferences/s", "n_gpus": 1,
+        "steps": main_run["requests"], "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"c5: {w['desc']}", "rate_req_s": w["rate"], "tenants": len(tenants),
+                   "session_bytes": int(model_bytes)},
+        "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
+        "serving": main_run, "rate_sweep": sweep,
+    }
+    for t in tenants:
+        t["sess"].close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +383,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-m", type=int, default=0,
                     help="model ciphertexts in the oracle's timed sample (0: the workload's default)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--duration", type=float, default=0.0, help="serving: trace length in seconds")
+    ap.add_argument("--rates", default="", help="serving: comma-separated extra arrival rates (req/s)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -288,6 +408,8 @@ def main() -> int:
     w = WORKLOADS[args.workload]
     if "requests" in w:
         return bench_batched(args, w)
+    if w.get("serving"):
+        return bench_serving(args, w)
     N, L, Q = w["N"], w["L"], w["Q"]
     alpha, r = w.get("alpha", 0), w.get("r", 1)
     primes = ep.default_primes(N, L + alpha)

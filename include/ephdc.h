@@ -143,8 +143,9 @@ typedef struct ephdc_session ephdc_session;
  * device-resident evaluation-domain copy owned by the session, and likewise the Galois
  * keys (device pointer, layout of ephdc_keygen, gk_words entries; required when r > 1,
  * else may be NULL).  A buffer shorter than its layout needs gives EPHDC_ERR_BUFFER.
- * max_Q bounds the batch size of later calls (sizes the session's scratch space).  The
- * call is synchronous with respect to `stream`.
+ * max_Q bounds the batch size of later calls; it sizes the scratch space of
+ * ephdc_score_encrypted, which is allocated on that call's first use (batches and the
+ * serving loop bring their own).  The call is synchronous with respect to `stream`.
  */
 ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
                                   const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q, void* stream,

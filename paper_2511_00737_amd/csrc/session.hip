@@ -309,7 +309,6 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   if ((st = dev_alloc(s, &s->d_scatter, scatter.size(), "scatter table")) != EPHDC_OK) return cleanup(st);
   if ((st = dev_alloc(s, &s->d_model, model_copy_words, "model")) != EPHDC_OK) return cleanup(st);
   if ((st = dev_alloc(s, &s->d_gk, key_words, "Galois keys")) != EPHDC_OK) return cleanup(st);
-  if ((st = dev_alloc(s, &s->d_partial, s->partial_words, "partial sums")) != EPHDC_OK) return cleanup(st);
   std::vector<uint32_t> perm;
   std::vector<uint2> ksc;
   if (P.r > 1) {
@@ -317,7 +316,6 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
     ksc = ks_constants(P);
     if ((st = dev_alloc(s, &s->d_perm, perm.size(), "automorphism tables")) != EPHDC_OK) return cleanup(st);
     if ((st = dev_alloc(s, &s->d_ksc, ksc.size(), "key-switching constants")) != EPHDC_OK) return cleanup(st);
-    if ((st = dev_alloc(s, &s->d_rot, rotate_words(P, Gmax), "rotation workspace")) != EPHDC_OK) return cleanup(st);
     KsConst& k = s->ks;
     const uint2* c = s->d_ksc;
     k.up_inv = c;    c += P.L;
@@ -389,6 +387,16 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
   hipStream_t hs = (hipStream_t)stream;
   Schedule sc = schedule(s, Q);
   if ((size_t)sc.G * sc.S * 2 * P.L * P.N > s->partial_words) return fail(EPHDC_ERR_BUFFER, "scratch too small");
+  // the single-request scratch is allocated on first use, so that sessions used only through
+  // batches and the serving loop hold no more than their model, keys and tables
+  if (!s->d_partial) {
+    ephdc_status st2 = dev_alloc(s, &s->d_partial, s->partial_words, "partial sums");
+    if (st2 != EPHDC_OK) return st2;
+  }
+  if (P.r > 1 && !s->d_rot) {
+    ephdc_status st2 = dev_alloc(s, &s->d_rot, rotate_words(P, P.G(s->max_Q)), "rotation workspace");
+    if (st2 != EPHDC_OK) return st2;
+  }
   if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
   ScoreArgs a = score_args(s, d_hv, Q, sc);
   if (s->split) {
