@@ -211,7 +211,7 @@ def bench_batched(args, w) -> int:
 
         batch = ep.Batch(reqs)
         t0 = time.perf_counter()
-        sched, tuned_ms = batch.autotune(reps=1, stream=stream)
+        sched, tuned_ms = batch.autotune(reps=2, stream=stream)
         t_tune = time.perf_counter() - t0
         print(f"[bench] c3: autotuned {sched} ({tuned_ms:.2f} ms/run) in {t_tune:.1f}s", file=sys.stderr, flush=True)
         batch.capture(stream)

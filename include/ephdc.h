@@ -133,6 +133,16 @@ ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, cons
 ephdc_status ephdc_decrypt_scores(const ephdc_params* prm, const int8_t* sk, const uint32_t* score_ct,
                                   uint32_t Q, int32_t* scores, int32_t* argmax);
 
+/*
+ * The same for queries q_first .. q_first + Q - 1 of a ciphertext sequence (query q of the
+ * sequence sits in ciphertext q / B): score_ct holds ciphertexts 0 .. ceil((q_first+Q)/B)-1
+ * of it, and only those from q_first / B on are read.  Rows of scores / argmax start at
+ * q_first.  Used for requests packed into shared ciphertexts (ephdc_batch_create_packed,
+ * packed serving), whose queries start inside a ciphertext.
+ */
+ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, const uint32_t* score_ct,
+                                     uint32_t q_first, uint32_t Q, int32_t* scores, int32_t* argmax);
+
 /* ------------------------------------------------------------------ client side (device memory) */
 
 typedef struct ephdc_session ephdc_session;
@@ -286,6 +296,21 @@ ephdc_status ephdc_batch_run(ephdc_batch* b, void* stream);
  */
 ephdc_status ephdc_batch_capture(ephdc_batch* b, void* stream);
 
+/*
+ * A packed batch: the requests of each session are placed one after another in one query
+ * sequence, so requests of a few queries share ciphertexts instead of each filling (and
+ * paying for) its own.  Every request must carry its features (d_x, d_base); its d_hv is
+ * not used, and its d_score_ct must hold ephdc_num_groups(Q) + 1 ciphertexts.  Each run
+ * writes to it the n_ct ciphertexts of the sequence that hold the request's queries, the
+ * first query at position q_first of the first of them (read the scores with
+ * ephdc_decrypt_scores_at(..., q_first, Q, ...)); query_offset is the request's first query
+ * in its session's whole sequence.  Decrypted scores are those of the request alone; the
+ * ciphertexts also carry the scores of the requests they are shared with.
+ */
+ephdc_status ephdc_batch_create_packed(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out);
+ephdc_status ephdc_batch_packing(const ephdc_batch* b, uint32_t i, uint32_t* query_offset, uint32_t* q_first,
+                                 uint32_t* n_ct);
+
 /* Convenience: plan, run on `stream`, wait for it and free the plan. */
 ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream);
 
@@ -335,6 +360,21 @@ ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout
  * (submit to done, completed requests) [9] peak device bytes in use [10] budget bytes
  * [11] seconds since creation. */
 ephdc_status ephdc_server_stats(ephdc_server* sv, double out[12]);
+
+/*
+ * Packing (set before the first request): the requests of one tenant in a batch share
+ * ciphertexts -- their queries are placed one after another in one query sequence, so a
+ * ciphertext's B query positions serve several requests.  A request's d_score_ct must then
+ * hold ephdc_num_groups(Q) + 1 ciphertexts; it receives the n_ct ciphertexts of the sequence
+ * that hold its queries, the first of them at position q_first (ephdc_server_result), to be
+ * read with ephdc_decrypt_scores_at(..., q_first, Q, ...).  Decrypted scores are those of
+ * the request alone; the ciphertexts also carry the other requests' scores.
+ */
+ephdc_status ephdc_server_set_packing(ephdc_server* sv, int enable);
+
+/* Where a done request's scores sit: q_first and the number of ciphertexts written
+ * (without packing q_first = 0 and n_ct = ephdc_num_groups(Q)). */
+ephdc_status ephdc_server_result(ephdc_server* sv, uint64_t ticket, uint32_t* q_first, uint32_t* n_ct);
 
 /* Drains the queue and every batch in flight, then frees the server (not the tenants). */
 ephdc_status ephdc_server_destroy(ephdc_server* sv);

@@ -66,6 +66,7 @@ def lib() -> C.CDLL:
             "ephdc_keygen": (C.c_int, [P, C.c_uint64, i8p, u32p]),
             "ephdc_encrypt_model": (C.c_int, [P, i8p, i8p, C.c_uint64, u32p]),
             "ephdc_decrypt_scores": (C.c_int, [P, i8p, u32p, C.c_uint32, i32p, i32p]),
+            "ephdc_decrypt_scores_at": (C.c_int, [P, i8p, u32p, C.c_uint32, C.c_uint32, i32p, i32p]),
             "ephdc_session_create": (C.c_int, [P, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_uint32,
                                                C.c_void_p, C.POINTER(C.c_void_p)]),
             "ephdc_session_destroy": (C.c_int, [C.c_void_p]),
@@ -89,6 +90,10 @@ def lib() -> C.CDLL:
             "ephdc_batch_run": (C.c_int, [C.c_void_p, C.c_void_p]),
             "ephdc_batch_capture": (C.c_int, [C.c_void_p, C.c_void_p]),
             "ephdc_score_many": (C.c_int, [C.POINTER(_CRequest), C.c_uint32, C.c_void_p]),
+            "ephdc_batch_create_packed": (C.c_int, [C.POINTER(_CRequest), C.c_uint32, C.POINTER(C.c_void_p)]),
+            "ephdc_batch_packing": (C.c_int, [C.c_void_p, C.c_uint32, u32p, u32p, u32p]),
+            "ephdc_server_set_packing": (C.c_int, [C.c_void_p, C.c_int]),
+            "ephdc_server_result": (C.c_int, [C.c_void_p, C.c_uint64, u32p, u32p]),
             "ephdc_server_create": (C.c_int, [C.c_size_t, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
             "ephdc_server_add_tenant": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, u32p]),
             "ephdc_server_submit": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
@@ -230,6 +235,22 @@ def ephdc_decrypt_scores(prm: Params, sk: np.ndarray, score_ct: np.ndarray, Q: i
     return sc, am
 
 
+def ephdc_decrypt_scores_at(prm: Params, sk: np.ndarray, score_ct: np.ndarray, q_first: int, Q: int):
+    """Scores of queries q_first .. q_first+Q-1 of a ciphertext sequence (see the header)."""
+    c = prm.c()
+    sc = np.zeros((Q, prm.K), dtype=np.int32)
+    am = np.zeros(Q, dtype=np.int32)
+    sk = np.ascontiguousarray(sk, dtype=np.int8)
+    cts = np.ascontiguousarray(score_ct, dtype=np.uint32)
+    B = lib().ephdc_queries_per_ct(C.byref(c))
+    need = -(-(q_first + Q) // B) * 2 * prm.L * prm.N
+    if cts.size < need:
+        raise EphdcError(ERR_BUFFER, f"score_ct holds {cts.size} words, needs {need}")
+    _check(lib().ephdc_decrypt_scores_at(C.byref(c), _ptr(sk, C.c_int8), _ptr(cts, C.c_uint32), q_first, Q,
+                                         _ptr(sc, C.c_int32), _ptr(am, C.c_int32)))
+    return sc, am
+
+
 # ------------------------------------------------------------------ client side (device memory)
 def _stream(stream=None) -> int:
     import torch
@@ -355,15 +376,17 @@ class Request:
     d_base: object = None
 
 
-def _c_requests(reqs):
+def _c_requests(reqs, packed: bool = False):
     arr = (_CRequest * len(reqs))()
     for i, r in enumerate(reqs):
         s, p = r.session, r.session.prm
         _, hv_bytes, out_bytes = _sizes(s, r.Q)
+        if packed:  # one more ciphertext: the request's queries may straddle a boundary
+            out_bytes += 2 * p.L * p.N * 4
         arr[i].session = s.handle
         arr[i].d_x = _dptr(r.d_x, r.Q * p.F) if r.d_x is not None else None
         arr[i].d_base = _dptr(r.d_base, p.F * p.D) if r.d_x is not None else None
-        arr[i].d_hv = _dptr(r.d_hv, hv_bytes)
+        arr[i].d_hv = _dptr(r.d_hv, hv_bytes) if r.d_hv is not None else None
         arr[i].Q = r.Q
         arr[i].d_score_ct = _dptr(r.d_score_ct, out_bytes)
     return arr
@@ -372,12 +395,20 @@ def _c_requests(reqs):
 class Batch:
     """Owns an ephdc_batch: the work lists of many requests scored by shared launches."""
 
-    def __init__(self, reqs):
+    def __init__(self, reqs, packed: bool = False):
         self.reqs = list(reqs)  # keeps the sessions and tensors alive
-        arr = _c_requests(self.reqs)
+        self.packed = packed
+        arr = _c_requests(self.reqs, packed)
         h = C.c_void_p()
-        _check(lib().ephdc_batch_create(arr, len(self.reqs), C.byref(h)))
+        create = lib().ephdc_batch_create_packed if packed else lib().ephdc_batch_create
+        _check(create(arr, len(self.reqs), C.byref(h)))
         self.handle = h
+
+    def packing(self, i: int):
+        """(query_offset, q_first, n_ct) of request i of a packed batch (see the header)."""
+        v = [C.c_uint32() for _ in range(3)]
+        _check(lib().ephdc_batch_packing(self.handle, i, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def close(self) -> None:
         if self.handle:
@@ -442,6 +473,18 @@ class Server:
         _check(lib().ephdc_server_create(budget_bytes, streams, max_batch, C.byref(h)))
         self.handle = h
         self._keep = {}  # tenant sessions / bases and request buffers stay alive here
+        self.pack = False
+
+    def set_packing(self, enable: bool = True) -> None:
+        """Requests of one tenant share ciphertexts within a batch (before the first submit)."""
+        _check(lib().ephdc_server_set_packing(self.handle, 1 if enable else 0))
+        self.pack = bool(enable)
+
+    def result(self, ticket: int):
+        """(q_first, n_ct) of a done request: where its queries sit in its output."""
+        a, b = C.c_uint32(), C.c_uint32()
+        _check(lib().ephdc_server_result(self.handle, ticket, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def add_tenant(self, session: "Session", d_base) -> int:
         p = session.prm
@@ -456,6 +499,8 @@ class Server:
             raise EphdcError(ERR_ARG, "unknown tenant")
         p = session.prm
         _, _, out_bytes = _sizes(session, Q)
+        if self.pack:
+            out_bytes += 2 * p.L * p.N * 4
         tk = C.c_uint64()
         _check(lib().ephdc_server_submit(self.handle, tenant, _dptr(d_x, Q * p.F), Q, _dptr(d_score_ct, out_bytes),
                                          C.byref(tk)))

@@ -43,7 +43,12 @@ struct Part {
 }  // namespace
 
 struct ephdc_batch {
+  // the requests the kernels see: the caller's, or with packing one per session holding
+  // the queries of all of that session's requests side by side
   std::vector<ephdc_request> reqs;
+  bool packed = false;
+  std::vector<ephdc_request> orig;  // packing: the caller's requests
+  std::vector<uint32_t> vreq, qoff;  // packing: virtual request and first query of each
   std::vector<Part> parts;
   std::vector<uint32_t*> rot_ws;  // per request: rotation workspace (r > 1), else nullptr
   int device = 0;
@@ -164,6 +169,15 @@ size_t carve(ephdc_batch* b, char* base) {
     pt.d_partial = (uint32_t*)take((size_t)pt.nslot * 2 * pt.L * pt.N * 4);
     pt.d_pt = (int32_t*)take(b->mode == 2 ? pt.pt_cap * pt.N * 4 : 0);
   }
+  if (b->packed) {
+    // the packed query hypervectors [D][G * B] and score ciphertexts [G][2][L][N]
+    for (ephdc_request& rq : b->reqs) {
+      const ParamSet& P = rq.session->P;
+      const size_t G = P.G(rq.Q);
+      rq.d_hv = (int8_t*)take((size_t)P.D * G * P.B());
+      rq.d_score_ct = (uint32_t*)take(G * 2 * P.L * P.N * 4);
+    }
+  }
   b->rot_ws.assign(b->reqs.size(), nullptr);
   for (uint32_t i = 0; i < b->reqs.size(); ++i) {
     const ephdc_request& rq = b->reqs[i];
@@ -199,7 +213,8 @@ ephdc_status plan(ephdc_batch* b, hipStream_t hs) {
   for (Part& pt : b->parts) {
     for (uint32_t li = 0; li < pt.reqs.size(); ++li) {
       const uint32_t ri = pt.reqs[li];
-      if (b->rot_ws[ri]) pt.rd[li].out = b->rot_ws[ri];
+      pt.rd[li].hv = b->reqs[ri].d_hv;
+      pt.rd[li].out = b->rot_ws[ri] ? b->rot_ws[ri] : b->reqs[ri].d_score_ct;
     }
     hipError_t e = hipMemcpyAsync(pt.d_reqs, pt.rd.data(), pt.rd.size() * sizeof(ReqDesc), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
@@ -245,6 +260,20 @@ hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
     e = launch_hdc_encode(rq.d_x, rq.d_base, rq.d_hv, rq.Q, P.F, P.D, P.G(rq.Q) * P.B(), P.qbits, P.qshift, hs);
     if (e != hipSuccess) return e;
   }
+  // packing: each request's queries are encoded into its columns of the session's packed
+  // buffer, in request order; an encode may zero a few columns past its own (up to its last
+  // 64-query tile), which the next request of the session overwrites, and the session's last
+  // request zeroes the padding up to the end of the rows
+  for (uint32_t i = 0; i < b->orig.size(); ++i) {
+    const ephdc_request& rq = b->orig[i];
+    const ephdc_request& v = b->reqs[b->vreq[i]];
+    const ParamSet& P = rq.session->P;
+    const uint32_t stride = P.G(v.Q) * P.B(), off = b->qoff[i];
+    const bool last = off + rq.Q == v.Q;
+    const uint32_t ncols = last ? stride - off : std::min(stride - off, (rq.Q + 63u) & ~63u);
+    e = launch_hdc_encode(rq.d_x, rq.d_base, v.d_hv + off, rq.Q, P.F, P.D, stride, P.qbits, P.qshift, hs, ncols);
+    if (e != hipSuccess) return e;
+  }
   for (const Part& pt : b->parts) {
     const int le = batch_le(b, pt.logn);
     ListArgs a = list_args(b, pt);
@@ -277,6 +306,17 @@ hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
         e = launch_inv_batch(P.logn, ra.acc, rq.d_score_ct, (size_t)G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs);
       if (e != hipSuccess) return e;
     }
+  }
+  // packing: every request receives the ciphertexts of its session's sequence that hold
+  // its queries
+  for (uint32_t i = 0; i < b->orig.size() && e == hipSuccess; ++i) {
+    const ephdc_request& rq = b->orig[i];
+    const ephdc_request& v = b->reqs[b->vreq[i]];
+    const ParamSet& P = rq.session->P;
+    const uint32_t g0 = b->qoff[i] / P.B(), g1 = (b->qoff[i] + rq.Q - 1) / P.B();
+    const size_t ct_words = (size_t)2 * P.L * P.N;
+    e = hipMemcpyAsync(rq.d_score_ct, v.d_score_ct + g0 * ct_words, (g1 - g0 + 1) * ct_words * 4,
+                       hipMemcpyDeviceToDevice, hs);
   }
   return hipSuccess;
 }
@@ -329,11 +369,13 @@ void read_schedule(const ephdc_batch* b, uint32_t sc[5]) {
 
 namespace ephdc {
 
-ephdc_status check_requests(const ephdc_request* reqs, uint32_t n_req) {
+ephdc_status check_requests(const ephdc_request* reqs, uint32_t n_req, bool packed) {
   if (!reqs || n_req == 0) return fail(EPHDC_ERR_ARG, "no requests");
   for (uint32_t i = 0; i < n_req; ++i) {
     const ephdc_request& r = reqs[i];
-    if (!r.session || !r.d_hv || !r.d_score_ct) return fail(EPHDC_ERR_ARG, "request with a NULL session or buffer");
+    if (!r.session) return fail(EPHDC_ERR_ARG, "request with a NULL session");
+    if (packed && (!r.d_x || !r.d_score_ct)) return fail(EPHDC_ERR_ARG, "packed requests need d_x and d_score_ct");
+    if (!packed && (!r.d_hv || !r.d_score_ct)) return fail(EPHDC_ERR_ARG, "request with a NULL buffer");
     const ParamSet& P = r.session->P;
     if (r.Q == 0 || r.Q > r.session->max_Q) return fail(EPHDC_ERR_ARG, "request Q must be in [1, the session's max_Q]");
     if ((uint64_t)P.D * P.G(r.Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
@@ -349,9 +391,27 @@ ephdc_status check_requests(const ephdc_request* reqs, uint32_t n_req) {
 }
 
 static ephdc_batch* new_batch(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode,
-                              uint32_t seg_len) {
+                              uint32_t seg_len, bool packed) {
   ephdc_batch* b = new ephdc_batch();
-  b->reqs.assign(reqs, reqs + n_req);
+  b->packed = packed;
+  if (packed) {
+    // one virtual request per session, in order of first appearance
+    b->orig.assign(reqs, reqs + n_req);
+    for (uint32_t i = 0; i < n_req; ++i) {
+      uint32_t v = 0;
+      while (v < b->reqs.size() && b->reqs[v].session != reqs[i].session) ++v;
+      if (v == b->reqs.size()) {
+        ephdc_request e{};
+        e.session = reqs[i].session;
+        b->reqs.push_back(e);
+      }
+      b->vreq.push_back(v);
+      b->qoff.push_back(b->reqs[v].Q);
+      b->reqs[v].Q += reqs[i].Q;
+    }
+  } else {
+    b->reqs.assign(reqs, reqs + n_req);
+  }
   b->device = reqs[0].session->device;
   b->pt_bytes = pt_bytes;
   b->mode = mode;
@@ -360,8 +420,9 @@ static ephdc_batch* new_batch(const ephdc_request* reqs, uint32_t n_req, size_t 
   return b;
 }
 
-size_t batch_bytes(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode, uint32_t seg_len) {
-  ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len);
+size_t batch_bytes(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode, uint32_t seg_len,
+                   bool packed) {
+  ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len, packed);
   for (Part& pt : b->parts) build_part(b, pt);
   const size_t need = carve(b, nullptr);
   delete b;
@@ -369,9 +430,18 @@ size_t batch_bytes(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, u
 }
 
 ephdc_status batch_new(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, uint32_t mode, uint32_t seg_len,
-                       void* mem, size_t mem_bytes, hipStream_t hs, ephdc_batch** out) {
+                       bool packed, void* mem, size_t mem_bytes, hipStream_t hs, ephdc_batch** out) {
   *out = nullptr;
-  ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len);
+  ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len, packed);
+  if (packed) {
+    for (const ephdc_request& v : b->reqs) {
+      const ParamSet& P = v.session->P;
+      if ((uint64_t)P.D * P.G(v.Q) * P.B() >= (1ull << 31)) {
+        delete b;
+        return fail(EPHDC_ERR_UNSUPPORTED, "packed requests of one session: D * hv stride must be < 2^31");
+      }
+    }
+  }
   b->mem = mem;
   b->mem_bytes = mem ? mem_bytes : 0;
   b->owned = false;
@@ -382,6 +452,14 @@ ephdc_status batch_new(const ephdc_request* reqs, uint32_t n_req, size_t pt_byte
   }
   *out = b;
   return EPHDC_OK;
+}
+
+void batch_packing(const ephdc_batch* b, uint32_t i, uint32_t* query_offset, uint32_t* q_first, uint32_t* n_ct) {
+  const ParamSet& P = b->orig[i].session->P;
+  const uint32_t off = b->qoff[i], B = P.B();
+  *query_offset = off;
+  *q_first = off % B;
+  *n_ct = (off + b->orig[i].Q - 1) / B - off / B + 1;
 }
 
 void batch_free(ephdc_batch* b) {
@@ -398,11 +476,11 @@ extern "C" {
 ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out) {
   if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
   *out = nullptr;
-  ephdc_status st = check_requests(reqs, n_req);
+  ephdc_status st = check_requests(reqs, n_req, false);
   if (st != EPHDC_OK) return st;
   // default schedule: split path, one limb per MAC item, 128-ciphertext segments, plaintext
   // chunks of at most 1 GiB
-  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, nullptr, 0, nullptr, out);
+  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, false, nullptr, 0, nullptr, out);
   if (st == EPHDC_OK) {
     hipError_t e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
@@ -555,12 +633,38 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
   return cleanup(EPHDC_OK);
 }
 
+ephdc_status ephdc_batch_create_packed(const ephdc_request* reqs, uint32_t n_req, ephdc_batch** out) {
+  if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  ephdc_status st = check_requests(reqs, n_req, true);
+  if (st != EPHDC_OK) return st;
+  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, true, nullptr, 0, nullptr, out);
+  if (st == EPHDC_OK) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+      batch_free(*out);
+      *out = nullptr;
+      return hip_fail(e, "batch setup");
+    }
+  }
+  return st;
+}
+
+ephdc_status ephdc_batch_packing(const ephdc_batch* b, uint32_t i, uint32_t* query_offset, uint32_t* q_first,
+                                 uint32_t* n_ct) {
+  if (!b || !query_offset || !q_first || !n_ct) return fail(EPHDC_ERR_ARG, "NULL argument");
+  if (!b->packed) return fail(EPHDC_ERR_ARG, "not a packed batch");
+  if (i >= b->orig.size()) return fail(EPHDC_ERR_ARG, "request index out of range");
+  batch_packing(b, i, query_offset, q_first, n_ct);
+  return EPHDC_OK;
+}
+
 ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream) {
-  ephdc_status st = check_requests(reqs, n_req);
+  ephdc_status st = check_requests(reqs, n_req, false);
   if (st != EPHDC_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
   ephdc_batch* b = nullptr;
-  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, nullptr, 0, hs, &b);
+  st = batch_new(reqs, n_req, (size_t)1 << 30, 2, 128, false, nullptr, 0, hs, &b);
   if (st != EPHDC_OK) return st;
   hipError_t e = batch_enqueue(b, hs);
   hipError_t e2 = hipStreamSynchronize(hs);

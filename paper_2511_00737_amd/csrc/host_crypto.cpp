@@ -349,12 +349,19 @@ ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, cons
 
 ephdc_status ephdc_decrypt_scores(const ephdc_params* prm, const int8_t* sk, const uint32_t* score_ct,
                                   uint32_t Q, int32_t* scores, int32_t* argmax) {
+  return ephdc_decrypt_scores_at(prm, sk, score_ct, 0, Q, scores, argmax);
+}
+
+ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, const uint32_t* score_ct,
+                                     uint32_t q_first, uint32_t Q, int32_t* scores, int32_t* argmax) {
   ParamSet P;
   ephdc_status st = P.load(prm);
   if (st != EPHDC_OK) return st;
   if (!sk || !score_ct || !scores) return fail(EPHDC_ERR_ARG, "NULL buffer");
+  if (Q == 0) return EPHDC_OK;
   HostTables H(P);
-  const uint32_t N = P.N, L = P.L, G = P.G(Q), t = P.t;
+  const uint32_t N = P.N, L = P.L, t = P.t;
+  const uint32_t g_first = q_first / P.B(), G = P.G(q_first + Q) - g_first;
   // CRT constants: Qhat_l = Q/q_l (big), Qhat_l^-1 mod q_l, Q (big)
   std::vector<Big> Qhat(L);
   std::vector<uint32_t> Qhat_inv(L);
@@ -376,7 +383,7 @@ ephdc_status ephdc_decrypt_scores(const ephdc_params* prm, const int8_t* sk, con
     H.mod[l].forward(S[l].data());
   }
   parallel_for(G, [&](size_t gi) {
-    const uint32_t g = (uint32_t)gi;
+    const uint32_t g = g_first + (uint32_t)gi;
     std::vector<std::vector<uint32_t>> x(L, std::vector<uint32_t>(N));
     std::vector<uint32_t> tmp(N);
     for (uint32_t l = 0; l < L; ++l) {
@@ -410,8 +417,10 @@ ephdc_status ephdc_decrypt_scores(const ephdc_params* prm, const int8_t* sk, con
     H.tt.forward(mu.data());  // slot s now sits at position pos[s]
     const uint32_t B = P.B(), Bq = P.Bq();
     for (uint32_t qi = 0; qi < B; ++qi) {
-      uint32_t qq = g * B + qi;
-      if (qq >= Q) break;
+      const uint32_t qg = g * B + qi;  // index in the ciphertext sequence
+      if (qg < q_first) continue;
+      if (qg >= q_first + Q) break;
+      const uint32_t qq = qg - q_first;
       uint32_t rho = qi / Bq, ql = qi % Bq;
       int32_t best = 0;
       for (uint32_t c = 0; c < P.K; ++c) {

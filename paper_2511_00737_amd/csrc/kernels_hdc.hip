@@ -24,7 +24,7 @@ constexpr int PITCH = 80;   // LDS row pitch in bytes
 
 __global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
                                                     int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
-                                                    uint32_t stride, uint32_t qbits, uint32_t qshift) {
+                                                    uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift) {
   __shared__ __attribute__((aligned(16))) uint8_t a_lds[HT * PITCH];  // [j][f]
   __shared__ __attribute__((aligned(16))) uint8_t b_lds[HT * PITCH];  // [q][f]
   const int tid = threadIdx.x;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ 
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const uint32_t q = q0 + wq + 16 * b + (lane & 15);
-      if (q >= stride) continue;
+      if (q >= ncols) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t j = j0 + wj + 16 * a + 4 * (lane >> 4) + i;
@@ -106,10 +106,11 @@ __global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ 
 namespace ephdc {
 
 hipError_t launch_hdc_encode(const uint8_t* x, const int8_t* base, int8_t* hv, uint32_t Q, uint32_t F, uint32_t D,
-                             uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st) {
-  if (stride == 0) return hipSuccess;
-  dim3 grid(D / ephdc_dev::HT, (stride + ephdc_dev::HT - 1) / ephdc_dev::HT);
-  ephdc_dev::k_hdc_encode<<<grid, dim3(256), 0, st>>>(x, base, hv, Q, F, D, stride, qbits, qshift);
+                             uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st, uint32_t ncols) {
+  if (ncols == 0 || ncols > stride) ncols = stride;
+  if (ncols == 0) return hipSuccess;
+  dim3 grid(D / ephdc_dev::HT, (ncols + ephdc_dev::HT - 1) / ephdc_dev::HT);
+  ephdc_dev::k_hdc_encode<<<grid, dim3(256), 0, st>>>(x, base, hv, Q, F, D, stride, ncols, qbits, qshift);
   return hipGetLastError();
 }
 

@@ -353,11 +353,13 @@ __device__ __forceinline__ MacItem single_item(const ScoreArgs& a, uint32_t w, u
 
 template <int LOGN, int LE, int LG>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score(ScoreArgs a) {
+  const uint32_t w = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
+  if (w == 0xFFFFFFFFu) return;  // a slot past the last item: the whole workgroup leaves
   LdsBufs b{0};
   const int tid = threadIdx.x;
   stage_table<LOGN, LE>(a.scatter, tid);
   uint32_t g, split;
-  const MacItem it = single_item<LOGN, LG>(a, blockIdx.x, g, split);
+  const MacItem it = single_item<LOGN, LG>(a, w, g, split);
   score_item<LOGN, LE, LG>(it, query_src(a, g), a.scatter, tside(a), a.fwd_tw, a.pcs, tid, b);
 }
 
@@ -379,10 +381,12 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
 // Split path, MAC: work item (split, g, limb group) over the split's range of the chunk.
 template <int LOGN, int LE, int LG, bool PF>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
+  const uint32_t w = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
+  if (w == 0xFFFFFFFFu) return;  // a slot past the last item: the whole workgroup leaves
   LdsBufs b{0};
   const int tid = threadIdx.x;
   uint32_t g, split;
-  const MacItem it = single_item<LOGN, LG>(a, blockIdx.x, g, split);
+  const MacItem it = single_item<LOGN, LG>(a, w, g, split);
   const int32_t* pt = a.pt + ((size_t)g * a.m_len + (it.m0 - a.m_base)) * ((size_t)1 << LOGN);
   mac_item<LOGN, LE, LG, PF>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
 }
@@ -417,8 +421,10 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score_list(ListArgs a) {
   LdsBufs b{0};
   const int tid = threadIdx.x;
   const uint32_t* staged = nullptr;
-  const uint32_t n = a.nseg * a.NLG;
-  for (uint32_t w = blockIdx.x; w < n; w += gridDim.x) {
+  const uint32_t nd = a.xm.slots();
+  for (uint32_t d = blockIdx.x; d < nd; d += gridDim.x) {
+    const uint32_t w = a.xm.item(d);
+    if (w == 0xFFFFFFFFu) continue;
     const Segment sg = a.segs[w / a.NLG];
     const ReqDesc r = a.reqs[sg.req];
     restage<LOGN, LE>(r.scatter, staged, tid);
@@ -446,8 +452,10 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
   using S = Shape<LOGN, LE>;
   LdsBufs b{0};
   const int tid = threadIdx.x;
-  const uint32_t n = a.nseg * a.NLG;
-  for (uint32_t w = blockIdx.x; w < n; w += gridDim.x) {
+  const uint32_t nd = a.xm.slots();
+  for (uint32_t d = blockIdx.x; d < nd; d += gridDim.x) {
+    const uint32_t w = a.xm.item(d);
+    if (w == 0xFFFFFFFFu) continue;
     const Segment sg = a.segs[w / a.NLG];
     const ReqDesc r = a.reqs[sg.req];
     const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG};
@@ -642,11 +650,23 @@ hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+XcdMap make_xcd_map(uint32_t n) {
+  XcdMap m{0, n};
+#ifndef EPHDC_NO_XCD_ORDER
+  m.on = n >= 64 ? 1u : 0u;
+#endif
+  return m;
+}
+
+hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
+  ScoreArgs a = a0;
+  const XcdMap xm = make_xcd_map(nblocks);
+  a.xcd = xm.on;
+  a.nitems = nblocks;
   return dispatch(logn, le, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
-    const dim3 grid(nblocks), block(Shape<LN, LEv>::T);
+    const dim3 grid(xm.slots()), block(Shape<LN, LEv>::T);
     const size_t sh = lds_bytes<LN, LEv>();
     switch (lg) {
       case 1: k_score<LN, LEv, 1><<<grid, block, sh, st>>>(a); break;
@@ -668,11 +688,15 @@ hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nbloc
   });
 }
 
-hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
+  ScoreArgs a = a0;
+  const XcdMap xm = make_xcd_map(nblocks);
+  a.xcd = xm.on;
+  a.nitems = nblocks;
   return dispatch(logn, le, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
-    const dim3 grid(nblocks), block(Shape<LN, LEv>::T);
+    const dim3 grid(xm.slots()), block(Shape<LN, LEv>::T);
     const size_t sh = lds_bytes<LN, LEv>();
     switch (lg) {
       case 1: k_mac<LN, LEv, 1, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
@@ -699,8 +723,18 @@ hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_
   });
 }
 
-hipError_t launch_score_list(int logn, int le, int lg, const ListArgs& a, uint32_t grid, hipStream_t st) {
-  if (grid == 0 || a.nseg == 0) return hipSuccess;
+// Persistent list launches: the grid is rounded up to a multiple of 8 so that a workgroup
+// stays on one XCD for all of its dispatch slots.
+static uint32_t list_grid(uint32_t grid, uint32_t slots) {
+  grid = std::min(grid, slots);
+  return (grid + 7u) & ~7u;
+}
+
+hipError_t launch_score_list(int logn, int le, int lg, const ListArgs& a0, uint32_t grid, hipStream_t st) {
+  if (grid == 0 || a0.nseg == 0) return hipSuccess;
+  ListArgs a = a0;
+  a.xm = make_xcd_map(a.nseg * a.NLG);
+  grid = list_grid(grid, a.xm.slots());
   return dispatch(logn, le, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const dim3 g(grid), block(Shape<LN, LEv>::T);
@@ -724,8 +758,11 @@ hipError_t launch_encode_list(int logn, int le, const ListArgs& a, uint32_t grid
   });
 }
 
-hipError_t launch_mac_list(int logn, int le, int lg, const ListArgs& a, uint32_t grid, hipStream_t st) {
-  if (grid == 0 || a.nseg == 0) return hipSuccess;
+hipError_t launch_mac_list(int logn, int le, int lg, const ListArgs& a0, uint32_t grid, hipStream_t st) {
+  if (grid == 0 || a0.nseg == 0) return hipSuccess;
+  ListArgs a = a0;
+  a.xm = make_xcd_map(a.nseg * a.NLG);
+  grid = list_grid(grid, a.xm.slots());
   return dispatch(logn, le, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const dim3 g(grid), block(Shape<LN, LEv>::T);

@@ -27,6 +27,27 @@ struct ScoreArgs {
   // kernel adds to the partial sums already stored instead of overwriting them
   int32_t* pt;
   uint32_t accumulate;
+  // XCD-aware order of the MAC / fused work items (see XcdMap); xcd = 0: block = item
+  uint32_t xcd, nitems;
+};
+
+// Workgroups are dispatched to the 8 XCDs of the chip round robin (workgroup d runs on XCD
+// d % 8), and each XCD has its own L2.  Work items that read the same data (the limb items
+// of one plaintext, the group items of one model range) are consecutive in item order, so
+// with `on` set, XCD x takes the contiguous item range [x n / 8, (x + 1) n / 8): dispatch
+// slot d holds item floor((d % 8) n / 8) + d / 8, and slots past the end of their range
+// hold none.  The workgroups running at once on one XCD then work on neighbouring items
+// and share their inputs in that XCD's L2, and every XCD gets n / 8 items (+-1).
+struct XcdMap {
+  uint32_t on, n;
+  __host__ __device__ uint32_t item(uint32_t d) const {
+    if (!on) return d < n ? d : 0xFFFFFFFFu;
+    const uint64_t x = d & 7u, y = d >> 3;
+    const uint64_t start = x * n / 8u, end = (x + 1u) * n / 8u;
+    return start + y < end ? (uint32_t)(start + y) : 0xFFFFFFFFu;
+  }
+  // dispatch slots that cover every item
+  __host__ __device__ uint32_t slots() const { return on ? 8u * ((n + 7u) / 8u) : n; }
 };
 
 // ---- request lists (many requests scored by one launch of each kernel)
@@ -61,6 +82,7 @@ struct ListArgs {
   const ReqDesc* reqs;
   const Segment* segs;      // the segments of this launch
   uint32_t nseg, NLG, L;
+  XcdMap xm;                // order of the MAC / fused items (nseg * NLG of them)
   const FinishItem* fin;
   uint32_t nfin;
   int32_t* pt;              // split path: lifted plaintexts of the launch's segments
@@ -107,6 +129,7 @@ using ephdc_dev::KsConst;
 using ephdc_dev::ListArgs;
 using ephdc_dev::ReqDesc;
 using ephdc_dev::Segment;
+using ephdc_dev::XcdMap;
 using ephdc_dev::RotateArgs;
 
 using ephdc_dev::PrimeConst;
@@ -118,6 +141,9 @@ struct BatchMap {
   uint32_t in_per = 0, out_per = 0;
   size_t in_stride = 0, out_stride = 0;
 };
+
+// XCD-aware item order for n items (identity below 64 items).
+XcdMap make_xcd_map(uint32_t n);
 
 hipError_t prepare_kernels();
 bool supported_logn(int logn);
@@ -149,8 +175,11 @@ hipError_t launch_finish_list(int logn, const ListArgs& a, hipStream_t st);
 // One rotate-and-sum step (Galois element of step `step`): acc <- acc + KeySwitch(sigma(acc)).
 hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipStream_t st);
 
-// HDC projection: hv[j][q] = quantise(sum_f (x[q][f]-128) * base[f][j]) for q < Q, 0 for Q <= q < stride.
+// HDC projection: hv[j][q] = quantise(sum_f (x[q][f]-128) * base[f][j]) for q < Q, 0 for
+// Q <= q < ncols (rows of pitch `stride`; ncols = 0 means the whole row).  Columns past
+// ncols are not touched, so requests can be encoded side by side into one buffer.
 hipError_t launch_hdc_encode(const uint8_t* x, const int8_t* base, int8_t* hv, uint32_t Q, uint32_t F,
-                             uint32_t D, uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st);
+                             uint32_t D, uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st,
+                             uint32_t ncols = 0);
 
 }  // namespace ephdc

@@ -88,6 +88,7 @@ struct Req {
   const uint8_t* d_x;
   uint32_t* d_out;
   size_t hv_bytes;
+  uint32_t q_first = 0, n_ct = 0;  // where the request's queries sit in its output
   double t_submit = 0, t_admit = 0, t_done = 0;
   int state = 0;  // 0 waiting, 1 in flight, 2 done, < 0 failed (negated status)
 };
@@ -106,6 +107,7 @@ struct ephdc_server {
   // configuration
   size_t budget = 0;
   uint32_t nstreams = 2, max_batch = 64;
+  bool pack = false;  // requests of one tenant share ciphertexts within a batch
   size_t pt_bytes = (size_t)256 << 20;
   // state (guarded by mu)
   std::mutex mu;
@@ -181,6 +183,11 @@ bool admit(ephdc_server* sv, int si) {
   std::vector<ephdc_request> rq;
   size_t hv_total = 0, need = 0;
   const size_t free_bytes = sv->budget - sv->arena.used();
+  // footprint of a candidate list: with packing the batch holds the packed hypervectors
+  // itself, else every request's hypervectors come on top of the batch block
+  auto footprint = [&](const std::vector<ephdc_request>& l, size_t hv) {
+    return batch_bytes(l.data(), (uint32_t)l.size(), sv->pt_bytes, 2, 128, sv->pack) + (sv->pack ? 0 : hv);
+  };
   while (!sv->waiting.empty() && take.size() < sv->max_batch) {
     Req& r = sv->reqs[sv->waiting.front()];
     const Tenant& t = sv->tenants[r.tenant];
@@ -193,11 +200,10 @@ bool admit(ephdc_server* sv, int si) {
     e.d_score_ct = r.d_out;
     rq.push_back(e);
     const size_t hv = align_up(r.hv_bytes);
-    const size_t bb = batch_bytes(rq.data(), (uint32_t)rq.size(), sv->pt_bytes, 2, 128);
-    const size_t total = bb + hv_total + hv;
+    const size_t total = footprint(rq, hv_total + hv);
     if (total > free_bytes) {
       rq.pop_back();
-      if (take.empty() && hv + batch_bytes(&e, 1, sv->pt_bytes, 2, 128) > sv->budget) {
+      if (take.empty() && footprint({e}, hv) > sv->budget) {
         // larger than the whole budget: can never be admitted
         r.state = -EPHDC_ERR_OOM;
         r.t_done = now_s(sv);
@@ -221,16 +227,31 @@ bool admit(ephdc_server* sv, int si) {
   }
   char* base = sv->arena.base() + off;
   size_t hv_off = 0;
-  for (size_t i = 0; i < take.size(); ++i) {
-    rq[i].d_hv = reinterpret_cast<int8_t*>(base + hv_off);
-    hv_off += align_up(sv->reqs[take[i]].hv_bytes);
+  if (!sv->pack) {
+    for (size_t i = 0; i < take.size(); ++i) {
+      rq[i].d_hv = reinterpret_cast<int8_t*>(base + hv_off);
+      hv_off += align_up(sv->reqs[take[i]].hv_bytes);
+    }
   }
   hipStream_t hs = sv->streams[si];
   ephdc_batch* b = nullptr;
-  ephdc_status st = batch_new(rq.data(), (uint32_t)rq.size(), sv->pt_bytes, 2, 128, base + hv_off, need - hv_off, hs, &b);
+  ephdc_status st = batch_new(rq.data(), (uint32_t)rq.size(), sv->pt_bytes, 2, 128, sv->pack, base + hv_off,
+                              need - hv_off, hs, &b);
   hipEvent_t ev = nullptr;
   hipError_t e = hipSuccess;
   if (st == EPHDC_OK) e = batch_enqueue(b, hs);
+  if (st == EPHDC_OK) {
+    for (size_t i = 0; i < take.size(); ++i) {
+      Req& r = sv->reqs[take[i]];
+      if (sv->pack) {
+        uint32_t qoff = 0;
+        batch_packing(b, (uint32_t)i, &qoff, &r.q_first, &r.n_ct);
+      } else {
+        r.q_first = 0;
+        r.n_ct = sv->tenants[r.tenant].s->P.G(r.Q);
+      }
+    }
+  }
   if (st == EPHDC_OK && e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (st == EPHDC_OK && e == hipSuccess) e = hipEventRecord(ev, hs);
   const double t = now_s(sv);
@@ -322,6 +343,25 @@ ephdc_status ephdc_server_create(size_t budget_bytes, uint32_t streams, uint32_t
   sv->max_batch = max_batch ? max_batch : 64;
   sv->pt_bytes = std::min<size_t>((size_t)256 << 20, budget_bytes / 8);
   *out = sv;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_set_packing(ephdc_server* sv, int enable) {
+  if (!sv) return fail(EPHDC_ERR_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->submitted) return fail(EPHDC_ERR_ARG, "packing must be set before the first request");
+  sv->pack = enable != 0;
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_result(ephdc_server* sv, uint64_t ticket, uint32_t* q_first, uint32_t* n_ct) {
+  if (!sv || !q_first || !n_ct) return fail(EPHDC_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(EPHDC_ERR_ARG, "unknown ticket");
+  if (it->second.state != 2) return fail(EPHDC_ERR_ARG, "request not done");
+  *q_first = it->second.q_first;
+  *n_ct = it->second.n_ct;
   return EPHDC_OK;
 }
 

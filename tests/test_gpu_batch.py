@@ -196,3 +196,55 @@ def test_autotuner_keeps_a_valid_schedule(world):
         _check(w, _outputs(w), ("autotuned", sched))
     finally:
         b.close()
+
+
+# tenants whose D allows encoding inside the batch (D % 64 == 0), one of them folded (r = 2)
+PACK_TENANTS = [(4096, 3, 2, 64, 1, 0, 0), (4096, 3, 3, 128, 2, 1, 3), (8192, 4, 7, 64, 1, 0, 0)]
+PACK_REQUESTS = [(0, 300), (1, 7), (0, 1), (2, 700), (1, 333), (0, 2000), (2, 1), (1, 250), (0, 64), (2, 900)]
+
+
+def test_packed_batch_matches_oracle():
+    """Packing: requests of one session share ciphertexts.  Each request receives the
+    ciphertexts of its session's query sequence that hold its queries -- equal bit for bit
+    to the oracle's ciphertexts of the concatenated sequence -- and decrypting them at its
+    offset gives exactly its own scores."""
+    torch = torch_cuda()
+    tenants = [Tenant(10 + i, *t) for i, t in enumerate(PACK_TENANTS)]
+    sessions = []
+    for i, t in enumerate(tenants):
+        mq = max(Q for ti, Q in PACK_REQUESTS if ti == i)
+        sessions.append(ep.Session(t.e, to_dev(t.model.astype(np.uint32)),
+                                   to_dev(t.gk.astype(np.uint32)) if t.gk is not None else None, max_Q=mq))
+    try:
+        reqs, hs = [], []
+        for k, (ti, Q) in enumerate(PACK_REQUESTS):
+            t, s = tenants[ti], sessions[ti]
+            x = synth.uniform_features(300 + k, Q, F)
+            hs.append(hdc.encode(x, t.base))
+            out = torch.zeros((s.num_groups(Q) + 1, 2, t.o.L, t.o.N), dtype=torch.int32, device="cuda")
+            reqs.append(ep.Request(s, None, Q, out, d_x=to_dev(x), d_base=to_dev(t.base)))
+        b = ep.Batch(reqs, packed=True)
+        try:
+            for rep in range(2):  # a second run reproduces the first
+                for r in reqs:
+                    r.d_score_ct.fill_(0)
+                b.run()
+                torch.cuda.synchronize()
+                seq = {i: np.concatenate([hs[k] for k, (ti, _) in enumerate(PACK_REQUESTS) if ti == i])
+                       for i in range(len(tenants))}
+                for k, ((ti, Q), r) in enumerate(zip(PACK_REQUESTS, reqs)):
+                    t = tenants[ti]
+                    off, qf, nct = b.packing(k)
+                    B = t.o.B
+                    assert qf == off % B and nct == (off + Q - 1) // B - off // B + 1
+                    got = to_host_u32(r.d_score_ct)[:nct]
+                    want = pipeline.score_ciphertexts(t.o, t.model, seq[ti], t.gk,
+                                                      groups=list(range(off // B, off // B + nct)))
+                    assert np.array_equal(got.astype(np.int64), want), (rep, k)
+                    scores, _ = ep.ephdc_decrypt_scores_at(t.e, t.sk.astype(np.int8), got, qf, Q)
+                    assert np.array_equal(scores, hdc.scores_mod_t(hs[k], t.C, 65537)), (rep, k)
+        finally:
+            b.close()
+    finally:
+        for s in sessions:
+            s.close()

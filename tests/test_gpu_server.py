@@ -135,3 +135,38 @@ def test_admission_by_device_memory(tenants):
         sv.close()
         sess.close()
         big.close()
+
+
+def test_packed_serving_gives_each_request_its_scores(tenants):
+    """With packing, requests of a tenant share ciphertexts; each request's output holds the
+    ciphertexts with its queries, and decrypting them at its offset gives its own scores."""
+    torch = tenants[0].torch
+    rng = np.random.default_rng(77)
+    sv = ep.Server(1 << 30, streams=2, max_batch=16)
+    try:
+        sv.set_packing(True)
+        ids = [sv.add_tenant(t.s, t.d_base) for t in tenants]
+        jobs = []
+        for k in range(30):
+            ti = int(rng.integers(0, len(tenants)))
+            Q = int(rng.integers(1, 700))
+            t = tenants[ti]
+            x = synth.uniform_features(1300 + k, Q, F)
+            out = torch.zeros((t.s.num_groups(Q) + 1, 2, t.o.L, t.o.N), dtype=torch.int32, device="cuda")
+            jobs.append((sv.submit(ids[ti], to_dev(x), Q, out), ti, Q, x, out))
+            if k % 6 == 5:
+                time.sleep(0.002)
+        sv.wait(0, timeout_s=120)
+        assert sv.stats()["completed"] == 30
+        shared = 0
+        for tk, ti, Q, x, out in jobs:
+            t = tenants[ti]
+            qf, nct = sv.result(tk)
+            shared += qf > 0
+            assert nct == (qf + Q - 1) // t.o.B + 1
+            got = to_host_u32(out)[:nct]
+            scores, _ = ep.ephdc_decrypt_scores_at(t.e, t.sk.astype(np.int8), got, qf, Q)
+            assert np.array_equal(scores, hdc.scores_mod_t(hdc.encode(x, t.base), t.C, 65537)), tk
+        assert shared > 0  # some requests did share a ciphertext with an earlier one
+    finally:
+        sv.close()

@@ -135,3 +135,22 @@ def test_decrypt_matches_oracle_on_valid_and_random_ciphertexts():
     want, wam = pipeline.decrypt_scores(o, run["s"], junk, min(Qn, o.B))
     assert np.array_equal(sc2, want)
     assert np.array_equal(am2, wam)
+
+
+def test_decrypt_at_an_offset_reads_the_same_rows():
+    """Queries q_first .. q_first+Q-1 of a ciphertext sequence (packed requests) decrypt to
+    the oracle's rows of the whole sequence, including a range that starts inside one
+    ciphertext and ends inside a later one."""
+    o, e = _pair(64, L=3, D=9, K=3)
+    assert o.B == 20
+    Qn = 57  # three ciphertexts, the last one partly used
+    x = synth.uniform_features(37, Qn, o.F)
+    base = synth.base_hypervectors(37, o.F, o.D)
+    C = synth.class_hypervectors(37, o.K, o.D)
+    run = pipeline.run(o, x, base, C, seed=37)
+    cts = run["score_ct"].astype(np.uint32)
+    sk = run["s"].astype(np.int8)
+    for q_first, Q in [(0, Qn), (13, 20), (20, 20), (39, 18), (56, 1)]:
+        sc, am = ep.ephdc_decrypt_scores_at(e, sk, cts, q_first, Q)
+        assert np.array_equal(sc, run["scores"][q_first:q_first + Q]), (q_first, Q)
+        assert np.array_equal(am, run["argmax"][q_first:q_first + Q]), (q_first, Q)
