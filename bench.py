@@ -217,28 +217,49 @@ def bench_batched(args, w) -> int:
         batch.capture(stream)
         for _ in range(args.warmup):
             batch.run(stream)
-        wall, lat = timed(lambda: batch.run(stream), args.steps)
-    # the batch reproduces the plain form bit for bit, and decrypts to h . C mod t
+        unpacked_wall, unpacked_lat = timed(lambda: batch.run(stream), max(1, args.steps // 2))
+        # the same requests packed: one query sequence per model, shared ciphertexts
+        outs_p = [torch.empty((r.d_score_ct.shape[0] + 1,) + tuple(r.d_score_ct.shape[1:]), dtype=torch.int32,
+                              device=dev) for r in reqs]
+        preqs = [ep.Request(r.session, None, r.Q, o, d_x=r.d_x, d_base=r.d_base) for r, o in zip(reqs, outs_p)]
+        pbatch = ep.Batch(preqs, packed=True)
+        t0 = time.perf_counter()
+        psched, ptuned_ms = pbatch.autotune(reps=2, stream=stream)
+        t_ptune = time.perf_counter() - t0
+        print(f"[bench] c3 packed: autotuned {psched} ({ptuned_ms:.2f} ms/run) in {t_ptune:.1f}s",
+              file=sys.stderr, flush=True)
+        pbatch.capture(stream)
+        for _ in range(args.warmup):
+            pbatch.run(stream)
+        wall, lat = timed(lambda: pbatch.run(stream), args.steps)
+    # the unpacked batch reproduces the plain form bit for bit; the packed one gives every
+    # request its exact scores
     for r, p in zip(reqs, plain_out):
         if not torch.equal(r.d_score_ct, p):
             print("[bench] batched ciphertexts differ from the plain form", file=sys.stderr)
             return 3
-    for i in range(0, nreq, 32):
+    for i in range(0, nreq, 16):
         r, t = reqs[i], tenants[int(midx[i])]
-        scores, _ = ep.ephdc_decrypt_scores(t["prm"], t["sk"], r.d_score_ct.cpu().numpy().view(np.uint32), r.Q)
         hv = r.d_hv.cpu().numpy()[:, :r.Q].T.astype(np.float64)
         want = (hv @ t["C"].astype(np.float64).T).astype(np.int64) % 65537
-        if not np.array_equal(scores, np.where(want > 32768, want - 65537, want)):
+        want = np.where(want > 32768, want - 65537, want)
+        scores, _ = ep.ephdc_decrypt_scores(t["prm"], t["sk"], r.d_score_ct.cpu().numpy().view(np.uint32), r.Q)
+        off, qf, nct = pbatch.packing(i)
+        pscores, _ = ep.ephdc_decrypt_scores_at(t["prm"], t["sk"], outs_p[i][:nct].cpu().numpy().view(np.uint32),
+                                                qf, r.Q)
+        if not (np.array_equal(scores, want) and np.array_equal(pscores, want)):
             print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
             return 3
     total_q = int(sizes.sum())
     plain_value = total_q * len(plain_lat) / plain_wall
+    unpacked_value = total_q * len(unpacked_lat) / unpacked_wall
     value = total_q * args.steps / wall
-    modmuls = 0.0
-    for i in range(nreq):
-        prm = tenants[int(midx[i])]["prm"]
-        G = ep.ephdc_num_groups(prm, int(sizes[i]))
-        modmuls += algorithmic_modmuls("k_score", N, L, G, ep.ephdc_num_model_ct(prm))
+    modmuls = 0.0  # algorithmic work of the packed batch: one query sequence per model
+    for k, t in enumerate(tenants):
+        Qk = int(sizes[midx == k].sum())
+        if Qk:
+            G = ep.ephdc_num_groups(t["prm"], Qk)
+            modmuls += algorithmic_modmuls("k_score", N, L, G, ep.ephdc_num_model_ct(t["prm"]))
     ms_step = wall * 1e3 / args.steps
     achieved = modmuls / (ms_step * 1e-3)
     result = {
@@ -246,9 +267,13 @@ def bench_batched(args, w) -> int:
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "requests": nreq, "queries_per_step": total_q,
-                   "schedule": sched, "autotune_s": round(t_tune, 1)},
+                   "form": "packed batch: the requests of each model share ciphertexts; one graph replay",
+                   "schedule": psched, "autotune_s": round(t_ptune, 1)},
         "plain": {"value": round(plain_value, 1), "unit": "inferences/s", "ms_per_step": round(plain_wall * 1e3 / len(plain_lat), 4),
                   "form": "the same requests one after another: encode + score call per request, no graph"},
+        "batched_unpacked": {"value": round(unpacked_value, 1), "unit": "inferences/s",
+                             "ms_per_step": round(unpacked_wall * 1e3 / len(unpacked_lat), 4), "schedule": sched,
+                             "form": "one graph replay of persistent launches, each request in its own ciphertexts"},
         "speedup_vs_plain": round(value / plain_value, 3),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4)},
         "roofline": {"bound": "alu", "kernel": "whole batched path (batch-encode + MAC dominate)",
@@ -257,6 +282,7 @@ def bench_batched(args, w) -> int:
                      "per_step_modmuls": modmuls},
     }
     batch.close()
+    pbatch.close()
     for t in tenants:
         t["sess"].close()
     print(json.dumps(result), flush=True)
@@ -298,9 +324,11 @@ def bench_serving(args, w) -> int:
     print(f"[bench] c5: {len(tenants)} tenants, {model_bytes / 2**30:.1f} GiB of sessions, "
           f"setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
-    def run(rate, duration, budget):
+    def run(rate, duration, budget, pack=True):
         trace = synth.poisson_trace(seed, rate, duration, 1, w["qmax"], len(tenants))
         sv = ep.Server(budget, streams=2, max_batch=64)
+        if pack:
+            sv.set_packing(True)
         ids = [sv.add_tenant(t["sess"], t["base"]) for t in tenants]
         live, check, tickets = {}, [], []
         torch.cuda.synchronize()
@@ -310,7 +338,8 @@ def bench_serving(args, w) -> int:
             if delay > 0:
                 time.sleep(delay)
             t = tenants[ti]
-            out = torch.empty((t["sess"].num_groups(Q), 2, t["prm"].L, t["prm"].N), dtype=torch.int32, device=dev)
+            out = torch.empty((t["sess"].num_groups(Q) + (1 if pack else 0), 2, t["prm"].L, t["prm"].N),
+                              dtype=torch.int32, device=dev)
             tk = sv.submit(ids[ti], pool[:Q], Q, out)
             live[tk] = (out, Q, ti)
             tickets.append(tk)
@@ -318,7 +347,7 @@ def bench_serving(args, w) -> int:
                 for k in [k for k in live if sv.query(k)[0] == 2]:
                     item = live.pop(k)
                     if len(check) < 4 and k % 7 == 0:
-                        check.append(item)
+                        check.append((k, item))
         t_submitted = time.perf_counter() - start
         sv.wait(0, timeout_s=600)
         wall = time.perf_counter() - start
@@ -328,9 +357,10 @@ def bench_serving(args, w) -> int:
             st, (ts, tad, td) = sv.query(tk)
             if st == 2:
                 waits.append(tad - ts)
-        for out_k, q_k, ti_k in check + [live[k] for k in list(live)[:4]]:
+        for tk_k, (out_k, q_k, ti_k) in check + [(k, live[k]) for k in list(live)[:4]]:
             t = tenants[ti_k]
-            scores, _ = ep.ephdc_decrypt_scores(t["prm"], t["sk"], out_k.cpu().numpy().view(np.uint32), q_k)
+            qf, nct = sv.result(tk_k)
+            scores, _ = ep.ephdc_decrypt_scores_at(t["prm"], t["sk"], out_k[:nct].cpu().numpy().view(np.uint32), qf, q_k)
             hv = torch.empty((t["prm"].D, t["sess"].hv_stride(q_k)), dtype=torch.int8, device=dev)
             ep.ephdc_encode_queries(t["sess"], pool[:q_k], t["base"], q_k, hv)
             torch.cuda.synchronize()
@@ -349,7 +379,7 @@ def bench_serving(args, w) -> int:
                 "rejected": int(stats["rejected"]), "batches": int(stats["batches"]),
                 "mean_requests_per_batch": round(stats["mean_batch"], 2),
                 "peak_request_bytes": int(stats["peak_bytes"]), "budget_bytes": int(stats["budget_bytes"]),
-                "stable": wall <= duration * 1.2}
+                "stable": wall <= duration * 1.2, "packing": pack}
 
     budget = 32 << 30
     main_run = run(w["rate"], args.duration or w["duration"], budget)
@@ -358,6 +388,8 @@ def bench_serving(args, w) -> int:
     for rate in [float(x) for x in args.rates.split(",") if x]:
         sweep.append(run(rate, args.duration or w["duration"], budget))
         print(f"[bench] c5 at {rate} req/s: {sweep[-1]}", file=sys.stderr, flush=True)
+    unpacked = run(w["rate"], args.duration or w["duration"], budget, pack=False)
+    print(f"[bench] c5 unpacked at {w['rate']} req/s: {unpacked}", file=sys.stderr, flush=True)
     result = {
         "metric": METRIC, "value": main_run["value"], "unit": "inferences/s", "n_gpus": 1,
         "steps": main_run["requests"], "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -365,7 +397,7 @@ def bench_serving(args, w) -> int:
         "config": {"workload": f"c5: {w['desc']}", "rate_req_s": w["rate"], "tenants": len(tenants),
                    "session_bytes": int(model_bytes)},
         "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
-        "serving": main_run, "rate_sweep": sweep,
+        "serving": main_run, "rate_sweep": sweep, "unpacked_at_same_rate": unpacked,
     }
     for t in tenants:
         t["sess"].close()
