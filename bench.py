@@ -78,15 +78,19 @@ def algorithmic_modmuls(kernel: str, N: int, L: int, G: int, M: int) -> float:
     return float(G) * M * per_pt
 
 
-def kernel_source_digest() -> str:
-    """SHA-256 over the HIP sources; a traffic figure is valid only for the build it was taken on."""
+# The sources that define each profiled kernel's code (its HIP file and the headers it uses).
+KERNEL_SOURCES = {k: ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", "launch.hpp")
+                  for k in ("k_mac", "k_encode_pt", "k_score", "k_finish")}
+
+
+def kernel_source_digest(kernel: str = "k_mac") -> str:
+    """SHA-256 over the sources of `kernel`; a traffic figure is valid only for the code it was taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_00737_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in sorted(KERNEL_SOURCES[kernel]):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
@@ -102,7 +106,7 @@ def recorded_traffic(kernel: str, workload: str):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    if fields.get("source_digest") != kernel_source_digest():
+    if fields.get("source_digest") != kernel_source_digest(kernel):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -478,7 +482,7 @@ def main() -> int:
         ep.ephdc_encode_queries(sess, d_x, d_base, Q, d_hv)
         ep.ephdc_score_encrypted(sess, d_hv, Q, d_out)
 
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):  # at least one run: it is checked below
         step()
     torch.cuda.synchronize()
     # correctness check of this exact launch configuration: decrypted scores of every
