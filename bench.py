@@ -420,6 +420,8 @@ def main() -> int:
                     help="model ciphertexts in the oracle's timed sample (0: the workload's default)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--duration", type=float, default=0.0, help="serving: trace length in seconds")
+    ap.add_argument("--schedule", default="", help="single-request workloads: mode,values_per_thread,limb_group,blocks "
+                                                  "(e.g. split,16,1,512; empty keeps the session's default)")
     ap.add_argument("--rates", default="", help="serving: comma-separated extra arrival rates (req/s)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
@@ -470,6 +472,9 @@ def main() -> int:
     d_gk = torch.from_numpy(gk.view(np.int32)).to(dev) if r > 1 else None
     sess = ep.Session(prm, d_model, d_gk, max_Q=Q)
     del d_model, d_gk, model
+    if args.schedule:
+        mode, vpt, lg, blocks = args.schedule.split(",")
+        sess.tune(int(lg), int(blocks), int(vpt), mode)
     stride = sess.hv_stride(Q)
     G = sess.num_groups(Q)
     d_x = torch.from_numpy(x).to(dev)

@@ -39,11 +39,24 @@ __device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t w
 
 __device__ __forceinline__ uint32_t csub(uint32_t a, uint32_t m) { return a >= m ? a - m : a; }
 
+// Global access at a uniform base plus a 32-bit byte offset: the form the scalar-base,
+// vector-offset addressing mode takes (no 64-bit address arithmetic per lane).
+template <class T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t m, uint32_t mneg_inv) {
+  // (a*b + k*m) / 2^32 with k = (a*b mod 2^32) * (-m^-1): the low word of the sum is zero, so
+  // the high word of one 64-bit multiply-add is the exact result (a*b + k*m < 2^63 whenever
+  // a*b < 2^62).  In [0, 2m) for a*b < m*2^32.
   const uint64_t T = (uint64_t)a * b;
-  const uint32_t lo = (uint32_t)T, hi = (uint32_t)(T >> 32);
-  const uint32_t k = lo * mneg_inv;
-  return hi + __umulhi(k, m) + (lo != 0u ? 1u : 0u);
+  const uint32_t k = (uint32_t)T * mneg_inv;
+  return (uint32_t)(((uint64_t)k * m + T) >> 32);
 }
 
 // Full reduction of a lazy value in [0, 4m) to [0, m).
@@ -193,13 +206,14 @@ __device__ __forceinline__ void load_tw(Tw<LOGN, LE, P>& t, int tid, const uint2
 #pragma unroll
   for (int u = 0; u < k; ++u) {
     const int s = s0 + u;
-    const uint2* base = table + (1 << s) + (xt >> (LOGN - s));
+    const uint32_t lane = ((1u << s) + (uint32_t)(xt >> (LOGN - s))) * (uint32_t)sizeof(uint2);
 #pragma unroll
     for (int e = 0; e < TW::G; ++e)
 #pragma unroll
       for (int v = 0; v < (1 << u); ++v) {
         const int i = (e << k) | (v << (k - u));
-        t.w[TW::off(u) + (e << u) + v] = base[i_part<LOGN, LE, P>(i) >> (LOGN - s)];
+        t.w[TW::off(u) + (e << u) + v] =
+            ld_at(table, lane + (uint32_t)(i_part<LOGN, LE, P>(i) >> (LOGN - s)) * (uint32_t)sizeof(uint2));
       }
   }
 }
@@ -220,37 +234,47 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, 
       const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
       const uint2 w = t.w[TW::off(u) + (e << u) + vb];
       const uint32_t X = csub(v[i], m2);
-      const uint32_t Tm = mul_shoup(v[i + h], w.x, w.y, m);
-      v[i] = X + Tm;
-      v[i + h] = X - Tm + m2;
+      // nT = -(Y*w mod m, in [0, 2m)) mod 2^32: X + T and X - T + 2m each take one operation
+      const uint32_t Y = v[i + h];
+      const uint32_t nT = __umulhi(Y, w.y) * m - Y * w.x;
+      v[i] = X - nT;
+      v[i + h] = X + nT + m2;
     }
   }
 }
 
 // Inverse pass P: Gentleman-Sande butterflies, inputs and outputs in [0, 2m).  With SCALE,
 // the last stage (s = 0) also multiplies by N^-1.
-template <int LOGN, int LE, int P, bool SCALE>
+// TINY (moduli below 2^17, i.e. t = 65537): no reductions between stages.  Inputs are in
+// [0, m); after d stages every value is below 2^d * m, so U + V needs no correction and
+// U - V + m*2^d is non-negative; N * m < 2^32 keeps every value in range, and the Shoup
+// multiplications (any 32-bit input) bring the twiddled half back to [0, 2m).  With SCALE
+// the last stage's multiplications by N^-1 leave every output in [0, 2m).
+template <int LOGN, int LE, int P, bool SCALE, bool TINY = false>
 __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P>& t, const PrimeConst& pc) {
   using S = Shape<LOGN, LE>;
   using TW = Tw<LOGN, LE, P>;
   constexpr int k = TW::k;
   constexpr int s0 = S::s0(P);
+  static_assert(!TINY || SCALE, "the lazy inverse transform ends with the N^-1 scaling stage");
   const uint32_t m = pc.m, m2 = 2 * m;
 #pragma unroll
   for (int u = k - 1; u >= 0; --u) {
     const int h = 1 << (k - 1 - u);
+    const int d = LOGN - 1 - (s0 + u);  // stages already done
+    const uint32_t K = TINY ? (m << d) : m2;
 #pragma unroll
     for (int i = 0; i < S::E; ++i) {
       if (i & h) continue;
       const uint32_t U = v[i], V = v[i + h];
       if (SCALE && s0 + u == 0) {
         v[i] = mul_shoup(U + V, pc.ninv, pc.ninvp, m);
-        v[i + h] = mul_shoup(U - V + m2, pc.ninv_w1, pc.ninv_w1p, m);
+        v[i + h] = mul_shoup(U - V + K, pc.ninv_w1, pc.ninv_w1p, m);
       } else {
         const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
         const uint2 w = t.w[TW::off(u) + (e << u) + vb];
-        v[i] = csub(U + V, m2);
-        v[i + h] = mul_shoup(U - V + m2, w.x, w.y, m);
+        v[i] = TINY ? U + V : csub(U + V, m2);
+        v[i + h] = mul_shoup(U - V + K, w.x, w.y, m);
       }
     }
   }
@@ -337,26 +361,27 @@ __device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, con
   ntt_forward_from<LOGN, LE, 0>(v, t0, tid, table, m, b);
 }
 
-template <int LOGN, int LE, bool SCALE, int P>
+template <int LOGN, int LE, bool SCALE, int P, bool TINY = false>
 __device__ __forceinline__ void ntt_inverse_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P>& tw, int tid,
                                                  const uint2* __restrict__ table, const PrimeConst& pc, LdsBufs& b) {
-  inv_pass<LOGN, LE, P, SCALE>(v, tw, pc);
+  inv_pass<LOGN, LE, P, SCALE, TINY>(v, tw, pc);
   if constexpr (P > 0) {
     Tw<LOGN, LE, P - 1> nt;
     load_tw<LOGN, LE, P - 1>(nt, tid, table);
     exchange<LOGN, LE, P, P - 1>(v, b, tid);
-    ntt_inverse_from<LOGN, LE, SCALE, P - 1>(v, nt, tid, table, pc, b);
+    ntt_inverse_from<LOGN, LE, SCALE, P - 1, TINY>(v, nt, tid, table, pc, b);
   }
 }
 
 // Inverse transform: evaluation layout (tid*E + i) -> coefficient layout (tid + i*T).
-template <int LOGN, int LE, bool SCALE>
+// TINY: lazy form for moduli below 2^17 (see inv_pass); inputs must be in [0, m).
+template <int LOGN, int LE, bool SCALE, bool TINY = false>
 __device__ __forceinline__ void ntt_inverse(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ table,
                                             const PrimeConst& pc, LdsBufs& b) {
   constexpr int PL = Shape<LOGN, LE>::NPASS - 1;
   Tw<LOGN, LE, PL> t0;
   load_tw<LOGN, LE, PL>(t0, tid, table);
-  ntt_inverse_from<LOGN, LE, SCALE, PL>(v, t0, tid, table, pc, b);
+  ntt_inverse_from<LOGN, LE, SCALE, PL, TINY>(v, t0, tid, table, pc, b);
 }
 
 

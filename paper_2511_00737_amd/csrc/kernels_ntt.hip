@@ -121,9 +121,9 @@ struct QuerySrc {
 using TSide = TSideArgs;
 
 // Slot values of query plaintext (g, m) at this thread's evaluation-side positions
-// tid*E + i (the slot feeding each position comes from the scatter table),
-// pre-multiplied by N^-1 mod t so that the inverse transform needs no final scaling; then
-// the inverse transform mod t: mu in [0, t), coefficient layout tid + i*T.
+// tid*E + i (the slot feeding each position comes from the scatter table), then the
+// inverse transform mod t, lazy (t < 2^17) and scaled by N^-1 in its last stage:
+// mu in [0, t), coefficient layout tid + i*T.
 template <int LOGN, int LE>
 __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const QuerySrc& q,
                                              const uint32_t* scatter, const TSide& ts, uint32_t m,
@@ -138,13 +138,12 @@ __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const Query
       const uint32_t j = m * q.r + (e >> 16);
       if (j < q.D) {
         const int h = q.hvg[j * q.hv_stride + (e & 0xFFFFu)];
-        const uint32_t x = h < 0 ? t + (uint32_t)h : (uint32_t)h;
-        val = mul_shoup(x, ts.tninv, ts.tninvp, t);
+        val = h < 0 ? t + (uint32_t)h : (uint32_t)h;
       }
     }
     v[i] = val;
   }
-  ntt_inverse<LOGN, LE, false>(v, tid, ts.inv_t, ts.pct, b);
+  ntt_inverse<LOGN, LE, true, true>(v, tid, ts.inv_t, ts.pct, b);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
 }
@@ -263,47 +262,50 @@ __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __res
                                          int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   constexpr int E = S::E, N = S::N;
+  // per-lane byte offsets inside one polynomial: evaluation layout (tid*E + i) for the model
+  // and the sums, coefficient layout (tid + i*T) for the plaintexts
+  const uint32_t eo = (uint32_t)tid * E * 4u, co = (uint32_t)tid * 4u;
   uint32_t acc[2][LG][E];
 #pragma unroll
   for (int li = 0; li < LG; ++li)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const uint32_t* src = it.slot + ((size_t)c * it.L + it.l0 + li) * N + (size_t)tid * E;
+      const uint32_t* src = it.slot + ((size_t)c * it.L + it.l0 + li) * N;
 #pragma unroll
-      for (int i = 0; i < E; ++i) acc[c][li][i] = accumulate ? src[i] : 0u;
+      for (int i = 0; i < E; ++i) acc[c][li][i] = accumulate ? ld_at(src, eo + 4u * i) : 0u;
     }
 
-  const int32_t* ptt = pt + tid;
   int32_t nxt[E];
   if (PF && it.m0 < it.m1) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) nxt[i] = ptt[i * S::T];
+    for (int i = 0; i < E; ++i) nxt[i] = ld_at(pt, co + 4u * (uint32_t)(i * S::T));
   }
   for (uint32_t m = it.m0; m < it.m1; ++m) {
+    const int32_t* ptm = pt + (size_t)(m - it.m0) * N;  // plaintext (g, m)
     int32_t cur[E];
     if constexpr (PF) {
 #pragma unroll
       for (int i = 0; i < E; ++i) cur[i] = nxt[i];
       if (m + 1 < it.m1) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) nxt[i] = ptt[(size_t)(m + 1 - it.m0) * N + i * S::T];
+        for (int i = 0; i < E; ++i) nxt[i] = ld_at(ptm + N, co + 4u * (uint32_t)(i * S::T));
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < E; ++i) cur[i] = ptt[(size_t)(m - it.m0) * N + i * S::T];
+      for (int i = 0; i < E; ++i) cur[i] = ld_at(ptm, co + 4u * (uint32_t)(i * S::T));
     }
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
       const uint32_t l = it.l0 + li;
       const PrimeConst pc = pcs[l];
-      const uint32_t* ct0 = it.model + (((size_t)m * 2 + 0) * it.L + l) * N + (size_t)tid * E;
-      const uint32_t* ct1 = it.model + (((size_t)m * 2 + 1) * it.L + l) * N + (size_t)tid * E;
+      const uint32_t* ct0 = it.model + (((size_t)m * 2 + 0) * it.L + l) * N;
+      const uint32_t* ct1 = it.model + (((size_t)m * 2 + 1) * it.L + l) * N;
       uint32_t c0[E], c1[E];
       if constexpr (PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-          c0[i] = ct0[i];
-          c1[i] = ct1[i];
+          c0[i] = ld_at(ct0, eo + 4u * i);
+          c1[i] = ld_at(ct1, eo + 4u * i);
         }
       }
       uint32_t p[E];
@@ -313,8 +315,8 @@ __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __res
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-          c0[i] = ct0[i];
-          c1[i] = ct1[i];
+          c0[i] = ld_at(ct0, eo + 4u * i);
+          c1[i] = ld_at(ct1, eo + 4u * i);
         }
       }
       const uint32_t m2 = 2 * pc.m;
