@@ -186,45 +186,48 @@ __host__ __device__ constexpr Pad exchange_pad() {
 // Twiddles of pass P for this thread: for stage u of the pass, group e and sub-block v, the
 // entry table[2^s + block] of the lower butterfly element, s = s0 + u.  Loaded in one go so
 // that the loads can be issued ahead of the exchange that precedes the pass.
-template <int LOGN, int LE, int P>
+template <int LOGN, int LE, int P, class W = uint2>
 struct Tw {
   using S = Shape<LOGN, LE>;
   static constexpr int k = S::k(P);
   static constexpr int G = S::E >> k;                 // groups per thread
   static constexpr int COUNT = G * ((1 << k) - 1);   // sum over stages of G * 2^u
   static constexpr int off(int u) { return G * ((1 << u) - 1); }
-  uint2 w[COUNT];
+  W w[COUNT];
 };
 
-template <int LOGN, int LE, int P>
-__device__ __forceinline__ void load_tw(Tw<LOGN, LE, P>& t, int tid, const uint2* __restrict__ table) {
+template <int LOGN, int LE, int P, class W>
+__device__ __forceinline__ void load_tw(Tw<LOGN, LE, P, W>& t, int tid, const W* __restrict__ table) {
   using S = Shape<LOGN, LE>;
-  using TW = Tw<LOGN, LE, P>;
+  using TW = Tw<LOGN, LE, P, W>;
   constexpr int k = TW::k;
   constexpr int s0 = S::s0(P);
   const int xt = (P == 0) ? 0 : tid_part<LOGN, LE, P>(tid);  // pass 0: blocks at stages < LE are uniform
 #pragma unroll
   for (int u = 0; u < k; ++u) {
     const int s = s0 + u;
-    const uint32_t lane = ((1u << s) + (uint32_t)(xt >> (LOGN - s))) * (uint32_t)sizeof(uint2);
+    const uint32_t lane = ((1u << s) + (uint32_t)(xt >> (LOGN - s))) * (uint32_t)sizeof(W);
 #pragma unroll
     for (int e = 0; e < TW::G; ++e)
 #pragma unroll
       for (int v = 0; v < (1 << u); ++v) {
         const int i = (e << k) | (v << (k - u));
         t.w[TW::off(u) + (e << u) + v] =
-            ld_at(table, lane + (uint32_t)(i_part<LOGN, LE, P>(i) >> (LOGN - s)) * (uint32_t)sizeof(uint2));
+            ld_at(table, lane + (uint32_t)(i_part<LOGN, LE, P>(i) >> (LOGN - s)) * (uint32_t)sizeof(W));
       }
   }
 }
 
-// Forward pass P: Cooley-Tukey butterflies, inputs and outputs in [0, 4m).
+// Forward pass P: Cooley-Tukey butterflies, inputs and outputs in [0, 4m).  Twiddles are
+// in Montgomery form (w * 2^32 mod m), so one table word per twiddle and the product
+// Y * w mod m in [0, 2m) takes two 64-bit multiply-adds and one multiply.
 template <int LOGN, int LE, int P>
-__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P>& t, uint32_t m) {
+__device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P, uint32_t>& t,
+                                         const PrimeConst& pc) {
   using S = Shape<LOGN, LE>;
-  using TW = Tw<LOGN, LE, P>;
+  using TW = Tw<LOGN, LE, P, uint32_t>;
   constexpr int k = TW::k;
-  const uint32_t m2 = 2 * m;
+  const uint32_t m = pc.m, m2 = 2 * m;
 #pragma unroll
   for (int u = 0; u < k; ++u) {
     const int h = 1 << (k - 1 - u);
@@ -232,13 +235,11 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, 
     for (int i = 0; i < S::E; ++i) {
       if (i & h) continue;
       const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
-      const uint2 w = t.w[TW::off(u) + (e << u) + vb];
+      const uint32_t w = t.w[TW::off(u) + (e << u) + vb];
       const uint32_t X = csub(v[i], m2);
-      // nT = -(Y*w mod m, in [0, 2m)) mod 2^32: X + T and X - T + 2m each take one operation
-      const uint32_t Y = v[i + h];
-      const uint32_t nT = __umulhi(Y, w.y) * m - Y * w.x;
-      v[i] = X - nT;
-      v[i + h] = X + nT + m2;
+      const uint32_t T = mont_mul(v[i + h], w, m, pc.mneg_inv);  // Y < 4m, w < m
+      v[i] = X + T;
+      v[i + h] = X - T + m2;
     }
   }
 }
@@ -341,24 +342,26 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
 }
 
 template <int LOGN, int LE, int P = 0>
-__device__ __forceinline__ void ntt_forward_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P>& tw, int tid,
-                                                 const uint2* __restrict__ table, uint32_t m, LdsBufs& b) {
-  fwd_pass<LOGN, LE, P>(v, tw, m);
+__device__ __forceinline__ void ntt_forward_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P, uint32_t>& tw, int tid,
+                                                 const uint32_t* __restrict__ table, const PrimeConst& pc,
+                                                 LdsBufs& b) {
+  fwd_pass<LOGN, LE, P>(v, tw, pc);
   if constexpr (P + 1 < Shape<LOGN, LE>::NPASS) {
-    Tw<LOGN, LE, P + 1> nt;
+    Tw<LOGN, LE, P + 1, uint32_t> nt;
     load_tw<LOGN, LE, P + 1>(nt, tid, table);  // in flight across the exchange
     exchange<LOGN, LE, P, P + 1>(v, b, tid);
-    ntt_forward_from<LOGN, LE, P + 1>(v, nt, tid, table, m, b);
+    ntt_forward_from<LOGN, LE, P + 1>(v, nt, tid, table, pc, b);
   }
 }
 
-// Forward transform: coefficient layout (tid + i*T) -> evaluation layout (tid*E + i).
+// Forward transform: coefficient layout (tid + i*T) -> evaluation layout (tid*E + i); the
+// table holds Montgomery-form twiddles.
 template <int LOGN, int LE>
-__device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ table,
-                                            uint32_t m, LdsBufs& b) {
-  Tw<LOGN, LE, 0> t0;
+__device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, const uint32_t* __restrict__ table,
+                                            const PrimeConst& pc, LdsBufs& b) {
+  Tw<LOGN, LE, 0, uint32_t> t0;
   load_tw<LOGN, LE, 0>(t0, tid, table);
-  ntt_forward_from<LOGN, LE, 0>(v, t0, tid, table, m, b);
+  ntt_forward_from<LOGN, LE, 0>(v, t0, tid, table, pc, b);
 }
 
 template <int LOGN, int LE, bool SCALE, int P, bool TINY = false>

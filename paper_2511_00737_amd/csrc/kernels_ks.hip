@@ -37,7 +37,7 @@ __global__ void k_automorph(const uint32_t* __restrict__ in, uint32_t* __restric
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_modup_ntt(const uint32_t* __restrict__ D,
                                                                   uint32_t* __restrict__ Y, KsConst k,
-                                                                  const uint2* __restrict__ fwd_tw,
+                                                                  const uint32_t* __restrict__ fwd_tw,
                                                                   const PrimeConst* __restrict__ pcs) {
   using S = Shape<LOGN, LE>;
   const uint32_t m = blockIdx.x % k.nmod;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_modup_ntt(const uint32_t*
   }
 #pragma unroll
   for (int e = 0; e < S::E; ++e) v[e] = csub(v[e], pm.m);
-  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)m * S::N, pm.m, b);
+  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)m * S::N, pm, b);
   uint32_t* dst = Y + (((size_t)g * k.dnum + j) * k.nmod + m) * S::N + (size_t)tid * S::E;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) dst[e] = reduce4(v[e], pm.m);
@@ -103,7 +103,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_moddown_ntt(const uint32_
                                                                     const uint32_t* __restrict__ KS,
                                                                     const uint32_t* __restrict__ R,
                                                                     uint32_t* __restrict__ acc, KsConst k,
-                                                                    const uint2* __restrict__ fwd_tw,
+                                                                    const uint32_t* __restrict__ fwd_tw,
                                                                     const PrimeConst* __restrict__ pcs) {
   using S = Shape<LOGN, LE>;
   const uint32_t i = blockIdx.x % k.L;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_moddown_ntt(const uint32_
   }
 #pragma unroll
   for (int e = 0; e < S::E; ++e) v[e] = csub(v[e], pq.m);
-  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)i * S::N, pq.m, b);
+  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)i * S::N, pq, b);
   const size_t off = (size_t)tid * S::E;
   const uint32_t* ks = KS + (((size_t)g * 2 + c) * k.nmod + i) * S::N + off;
   const uint32_t* r0 = R + (((size_t)g * 2 + 0) * k.L + i) * S::N + off;

@@ -29,7 +29,7 @@ struct PolyMap {
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t* __restrict__ in,
                                                                   uint32_t* __restrict__ out,
-                                                                  const uint2* __restrict__ fwd_tw,
+                                                                  const uint32_t* __restrict__ fwd_tw,
                                                                   const PrimeConst* __restrict__ pcs,
                                                                   uint32_t nlimb, uint32_t limb_base, int mont,
                                                                   PolyMap pm) {
@@ -43,7 +43,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t*
   uint32_t v[S::E];
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = src[tid + i * S::T];
-  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)limb * S::N, pc.m, b);
+  ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)limb * S::N, pc, b);
   uint32_t* dst = out + pm.out_off(poly, S::N) + (size_t)tid * S::E;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
@@ -195,7 +195,7 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[2][LG][1 << LE],
 // before its transform so that their latency overlaps the transform.
 template <int LOGN, int LE, int LG>
 __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q, const uint32_t* __restrict__ scatter,
-                                           const TSide& ts, const uint2* __restrict__ fwd_tw,
+                                           const TSide& ts, const uint32_t* __restrict__ fwd_tw,
                                            const PrimeConst* __restrict__ pcs, int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   constexpr int E = S::E, N = S::N;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q,
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = lift(mu[i], t, pc.m);
-      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc.m, b);
+      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc, b);
       const uint32_t m2 = 2 * pc.m;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -258,7 +258,7 @@ __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* s
 // precedes their use (more registers: used where the register budget allows it).
 template <int LOGN, int LE, int LG, bool PF>
 __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
-                                         const uint2* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
+                                         const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   constexpr int E = S::E, N = S::N;
@@ -311,7 +311,7 @@ __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __res
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
-      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc.m, b);
+      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc, b);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -618,7 +618,7 @@ static PolyMap make_map(const BatchMap& m, uint32_t N) {
   return pm;
 }
 
-hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
+hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint32_t* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
                             hipStream_t st, const BatchMap& map) {
   if (npolys == 0) return hipSuccess;

@@ -14,7 +14,7 @@ struct ScoreArgs {
   const int8_t* hv;         // [D][hv_stride] query hypervectors
   uint32_t* partial;        // [G][S][2][L][N] evaluation-domain partial sums
   const uint32_t* scatter;  // [N] slot source of every evaluation-side position
-  const uint2* fwd_tw;      // [L+alpha][N] forward twiddles (w, w')
+  const uint32_t* fwd_tw;   // [L+alpha][N] forward twiddles, Montgomery form
   const uint2* inv_t;       // [N] inverse twiddles mod t
   const PrimeConst* pcs;    // [L+alpha]
   PrimeConst pct;           // constants of t
@@ -87,7 +87,7 @@ struct ListArgs {
   uint32_t nfin;
   int32_t* pt;              // split path: lifted plaintexts of the launch's segments
   uint32_t* partial;        // [slots][2][L][N]
-  const uint2* fwd_tw;
+  const uint32_t* fwd_tw;
   const uint2* inv_tw;
   const PrimeConst* pcs;
   TSideArgs ts;
@@ -115,7 +115,7 @@ struct RotateArgs {
   uint32_t* Y;             // [G][dnum][nmod][N]
   uint32_t* KS;            // [G][2][nmod][N]
   uint32_t* XP;            // [G][2][alpha][N] coefficient domain
-  const uint2* fwd_tw;
+  const uint32_t* fwd_tw;
   const uint2* inv_tw;
   const PrimeConst* pcs;
 };
@@ -148,7 +148,7 @@ XcdMap make_xcd_map(uint32_t n);
 hipError_t prepare_kernels();
 bool supported_logn(int logn);
 
-hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* tw,
+hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint32_t* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
                             hipStream_t st, const BatchMap& map = BatchMap{});
 hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* itw,

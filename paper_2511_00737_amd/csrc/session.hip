@@ -273,13 +273,14 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   s->target_blocks = 512;
 
   const uint32_t N = P.N, nm = P.nmod();
-  std::vector<uint2> fwd((size_t)nm * N), inv((size_t)nm * N), invt(N);
+  std::vector<uint32_t> fwd((size_t)nm * N);
+  std::vector<uint2> inv((size_t)nm * N), invt(N);
   std::vector<PrimeConst> pcs(nm);
   for (uint32_t i = 0; i < nm; ++i) {
     uint32_t m = P.modulus(i);
     HostNtt T(N, m, root_of_unity(2 * N, m));
     for (uint32_t k = 0; k < N; ++k) {
-      fwd[(size_t)i * N + k] = make_uint2(T.fw[k], T.fwp[k]);
+      fwd[(size_t)i * N + k] = (uint32_t)(((uint64_t)T.fw[k] << 32) % m);
       inv[(size_t)i * N + k] = make_uint2(T.iw[k], T.iwp[k]);
     }
     pcs[i] = make_const(T);
@@ -332,7 +333,7 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
 
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-  chk(hipMemcpyAsync(s->d_fwd, fwd.data(), fwd.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_fwd, fwd.data(), fwd.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_inv, inv.data(), inv.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_inv_t, invt.data(), invt.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_pc, pcs.data(), pcs.size() * sizeof(PrimeConst), hipMemcpyHostToDevice, hs));

@@ -25,7 +25,7 @@ struct ephdc_session {
   int32_t* d_pt = nullptr;         // split path: lifted plaintexts of one chunk [G][m_len][N]
   size_t pt_cap = 0;               // plaintexts d_pt holds
   // device memory owned by the session
-  uint2* d_fwd = nullptr;          // [nmod][N]
+  uint32_t* d_fwd = nullptr;       // [nmod][N] forward twiddles, Montgomery form (w * 2^32 mod m)
   uint2* d_inv = nullptr;          // [nmod][N]
   uint2* d_inv_t = nullptr;        // [N]
   ephdc::PrimeConst* d_pc = nullptr;  // [nmod]
