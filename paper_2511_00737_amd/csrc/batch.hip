@@ -243,8 +243,6 @@ ListArgs list_args(const ephdc_batch* b, const Part& pt) {
   a.pcs = s->d_pc;
   a.ts.inv_t = s->d_inv_t;
   a.ts.pct = s->pct;
-  a.ts.tninv = s->tninv;
-  a.ts.tninvp = s->tninvp;
   return a;
 }
 

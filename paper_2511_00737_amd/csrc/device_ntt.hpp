@@ -13,9 +13,11 @@
 // second; the inverse (Gentleman-Sande) maps the second back to the first.
 //
 // Modular arithmetic (all moduli < 2^30, so lazy values below 4m fit in 32 bits):
-//   Shoup multiplication by a constant w with w' = floor(w*2^32/m): 3 integer multiplies,
-//   result in [0, 2m).  Montgomery multiplication of two variables (R = 2^32): 4 multiplies,
-//   result in [0, 2m) whenever a*b < m*2^32.
+//   Montgomery multiplication (R = 2^32): two 64-bit multiply-adds and one multiply, result
+//   in [0, 2m) whenever a*b < m*2^32.  Twiddle tables and the N^-1 constants are stored in
+//   Montgomery form (w*R mod m), so multiplying by them yields plain residues.
+//   Shoup multiplication by a constant w with w' = floor(w*2^32/m): 3 multiplies and a
+//   subtraction, result in [0, 2m) for any 32-bit input (used by the base conversions).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,9 +29,9 @@ struct PrimeConst {
   uint32_t m;         // modulus
   uint32_t mneg_inv;  // -m^-1 mod 2^32 (Montgomery)
   uint32_t r2;        // 2^64 mod m (to enter Montgomery form)
-  uint32_t ninv, ninvp;        // N^-1 mod m and Shoup companion
-  uint32_t ninv_w1, ninv_w1p;  // N^-1 * (first inverse twiddle) and companion
-  uint32_t pad;
+  uint32_t ninv_r;     // N^-1 * 2^32 mod m (Montgomery form)
+  uint32_t ninv_w1_r;  // N^-1 * (first inverse twiddle) * 2^32 mod m
+  uint32_t pad[3];
 };
 
 __device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wp, uint32_t m) {
@@ -186,7 +188,7 @@ __host__ __device__ constexpr Pad exchange_pad() {
 // Twiddles of pass P for this thread: for stage u of the pass, group e and sub-block v, the
 // entry table[2^s + block] of the lower butterfly element, s = s0 + u.  Loaded in one go so
 // that the loads can be issued ahead of the exchange that precedes the pass.
-template <int LOGN, int LE, int P, class W = uint2>
+template <int LOGN, int LE, int P, class W = uint32_t>
 struct Tw {
   using S = Shape<LOGN, LE>;
   static constexpr int k = S::k(P);
@@ -252,9 +254,10 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, 
 // multiplications (any 32-bit input) bring the twiddled half back to [0, 2m).  With SCALE
 // the last stage's multiplications by N^-1 leave every output in [0, 2m).
 template <int LOGN, int LE, int P, bool SCALE, bool TINY = false>
-__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P>& t, const PrimeConst& pc) {
+__device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P, uint32_t>& t,
+                                         const PrimeConst& pc) {
   using S = Shape<LOGN, LE>;
-  using TW = Tw<LOGN, LE, P>;
+  using TW = Tw<LOGN, LE, P, uint32_t>;
   constexpr int k = TW::k;
   constexpr int s0 = S::s0(P);
   static_assert(!TINY || SCALE, "the lazy inverse transform ends with the N^-1 scaling stage");
@@ -269,13 +272,13 @@ __device__ __forceinline__ void inv_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, 
       if (i & h) continue;
       const uint32_t U = v[i], V = v[i + h];
       if (SCALE && s0 + u == 0) {
-        v[i] = mul_shoup(U + V, pc.ninv, pc.ninvp, m);
-        v[i + h] = mul_shoup(U - V + K, pc.ninv_w1, pc.ninv_w1p, m);
+        v[i] = mont_mul(U + V, pc.ninv_r, m, pc.mneg_inv);
+        v[i + h] = mont_mul(U - V + K, pc.ninv_w1_r, m, pc.mneg_inv);
       } else {
         const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
-        const uint2 w = t.w[TW::off(u) + (e << u) + vb];
+        const uint32_t w = t.w[TW::off(u) + (e << u) + vb];
         v[i] = TINY ? U + V : csub(U + V, m2);
-        v[i + h] = mul_shoup(U - V + K, w.x, w.y, m);
+        v[i + h] = mont_mul(U - V + K, w, m, pc.mneg_inv);
       }
     }
   }
@@ -365,11 +368,12 @@ __device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, con
 }
 
 template <int LOGN, int LE, bool SCALE, int P, bool TINY = false>
-__device__ __forceinline__ void ntt_inverse_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P>& tw, int tid,
-                                                 const uint2* __restrict__ table, const PrimeConst& pc, LdsBufs& b) {
+__device__ __forceinline__ void ntt_inverse_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P, uint32_t>& tw, int tid,
+                                                 const uint32_t* __restrict__ table, const PrimeConst& pc,
+                                                 LdsBufs& b) {
   inv_pass<LOGN, LE, P, SCALE, TINY>(v, tw, pc);
   if constexpr (P > 0) {
-    Tw<LOGN, LE, P - 1> nt;
+    Tw<LOGN, LE, P - 1, uint32_t> nt;
     load_tw<LOGN, LE, P - 1>(nt, tid, table);
     exchange<LOGN, LE, P, P - 1>(v, b, tid);
     ntt_inverse_from<LOGN, LE, SCALE, P - 1, TINY>(v, nt, tid, table, pc, b);
@@ -379,10 +383,10 @@ __device__ __forceinline__ void ntt_inverse_from(uint32_t (&v)[1 << LE], Tw<LOGN
 // Inverse transform: evaluation layout (tid*E + i) -> coefficient layout (tid + i*T).
 // TINY: lazy form for moduli below 2^17 (see inv_pass); inputs must be in [0, m).
 template <int LOGN, int LE, bool SCALE, bool TINY = false>
-__device__ __forceinline__ void ntt_inverse(uint32_t (&v)[1 << LE], int tid, const uint2* __restrict__ table,
+__device__ __forceinline__ void ntt_inverse(uint32_t (&v)[1 << LE], int tid, const uint32_t* __restrict__ table,
                                             const PrimeConst& pc, LdsBufs& b) {
   constexpr int PL = Shape<LOGN, LE>::NPASS - 1;
-  Tw<LOGN, LE, PL> t0;
+  Tw<LOGN, LE, PL, uint32_t> t0;
   load_tw<LOGN, LE, PL>(t0, tid, table);
   ntt_inverse_from<LOGN, LE, SCALE, PL, TINY>(v, t0, tid, table, pc, b);
 }

@@ -56,7 +56,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t*
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_inv_batch(const uint32_t* __restrict__ in,
                                                                   uint32_t* __restrict__ out,
-                                                                  const uint2* __restrict__ inv_tw,
+                                                                  const uint32_t* __restrict__ inv_tw,
                                                                   const PrimeConst* __restrict__ pcs,
                                                                   uint32_t nlimb, uint32_t limb_base, PolyMap pm) {
   using S = Shape<LOGN, LE>;
@@ -332,7 +332,7 @@ __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __res
 
 // ------------------------------------------------------------------ single-request kernels
 // Work item w of a launch: limb group w % NLG, then group g, then split of the model range.
-__device__ __forceinline__ TSide tside(const ScoreArgs& a) { return TSide{a.inv_t, a.pct, a.tninv, a.tninvp}; }
+__device__ __forceinline__ TSide tside(const ScoreArgs& a) { return TSide{a.inv_t, a.pct}; }
 
 __device__ __forceinline__ QuerySrc query_src(const ScoreArgs& a, uint32_t g) {
   return QuerySrc{a.hv + (size_t)g * a.B, a.D, a.r, a.hv_stride};
@@ -502,7 +502,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish_list(ListArgs a) {
 template <int LOGN, int LE, bool INVERT>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish(const uint32_t* __restrict__ partial,
                                                                uint32_t* __restrict__ out, uint32_t S_,
-                                                               uint32_t L, const uint2* __restrict__ inv_tw,
+                                                               uint32_t L, const uint32_t* __restrict__ inv_tw,
                                                                const PrimeConst* __restrict__ pcs) {
   using S = Shape<LOGN, LE>;
   const int tid = threadIdx.x;
@@ -631,7 +631,7 @@ hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t 
   });
 }
 
-hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* itw,
+hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint32_t* itw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st,
                             const BatchMap& map) {
   if (npolys == 0) return hipSuccess;
@@ -711,7 +711,7 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
 }
 
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S_,
-                         uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st) {
+                         uint32_t L, const uint32_t* itw, const PrimeConst* pcs, hipStream_t st) {
   if (G == 0) return hipSuccess;
   return dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;

@@ -15,10 +15,9 @@ struct ScoreArgs {
   uint32_t* partial;        // [G][S][2][L][N] evaluation-domain partial sums
   const uint32_t* scatter;  // [N] slot source of every evaluation-side position
   const uint32_t* fwd_tw;   // [L+alpha][N] forward twiddles, Montgomery form
-  const uint2* inv_t;       // [N] inverse twiddles mod t
+  const uint32_t* inv_t;    // [N] inverse twiddles mod t, Montgomery form
   const PrimeConst* pcs;    // [L+alpha]
   PrimeConst pct;           // constants of t
-  uint32_t tninv, tninvp;   // N^-1 mod t and Shoup companion
   uint32_t L, M, D, r, hv_stride, B, G, S, mchunk, NLG;
   // work covers model ciphertexts [m_base, m_base + m_len); splits cut that range
   uint32_t m_base, m_len;
@@ -73,9 +72,8 @@ struct FinishItem {
 };
 
 struct TSideArgs {
-  const uint2* inv_t;
+  const uint32_t* inv_t;
   PrimeConst pct;
-  uint32_t tninv, tninvp;
 };
 
 struct ListArgs {
@@ -88,7 +86,7 @@ struct ListArgs {
   int32_t* pt;              // split path: lifted plaintexts of the launch's segments
   uint32_t* partial;        // [slots][2][L][N]
   const uint32_t* fwd_tw;
-  const uint2* inv_tw;
+  const uint32_t* inv_tw;
   const PrimeConst* pcs;
   TSideArgs ts;
 };
@@ -116,7 +114,7 @@ struct RotateArgs {
   uint32_t* KS;            // [G][2][nmod][N]
   uint32_t* XP;            // [G][2][alpha][N] coefficient domain
   const uint32_t* fwd_tw;
-  const uint2* inv_tw;
+  const uint32_t* inv_tw;
   const PrimeConst* pcs;
 };
 
@@ -151,7 +149,7 @@ bool supported_logn(int logn);
 hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint32_t* tw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, bool mont,
                             hipStream_t st, const BatchMap& map = BatchMap{});
-hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint2* itw,
+hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t npolys, const uint32_t* itw,
                             const PrimeConst* pcs, uint32_t nlimb, uint32_t limb_base, hipStream_t st,
                             const BatchMap& map = BatchMap{});
 hipError_t launch_pointwise_mont(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n, uint32_t N,
@@ -162,7 +160,7 @@ hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nbloc
 hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 bool supported_shape(int logn, int le);
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S,
-                         uint32_t L, const uint2* itw, const PrimeConst* pcs, hipStream_t st);
+                         uint32_t L, const uint32_t* itw, const PrimeConst* pcs, hipStream_t st);
 hipError_t launch_debug_plaintext(int logn, const ScoreArgs& a, uint32_t g, uint32_t m, uint32_t* out,
                                   hipStream_t st);
 

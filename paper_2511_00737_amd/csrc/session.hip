@@ -57,10 +57,8 @@ PrimeConst make_const(const HostNtt& T) {
   pc.m = m;
   pc.mneg_inv = (uint32_t)(0u - inv);
   pc.r2 = (uint32_t)(((unsigned __int128)1 << 64) % m);
-  pc.ninv = T.ninv;
-  pc.ninvp = T.ninvp;
-  pc.ninv_w1 = (uint32_t)((uint64_t)T.ninv * T.iw[1] % m);
-  pc.ninv_w1p = T.shoup(pc.ninv_w1);
+  pc.ninv_r = (uint32_t)(((uint64_t)T.ninv << 32) % m);
+  pc.ninv_w1_r = (uint32_t)(((((uint64_t)T.ninv * T.iw[1]) % m) << 32) % m);
   return pc;
 }
 
@@ -93,8 +91,6 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   a.inv_t = s->d_inv_t;
   a.pcs = s->d_pc;
   a.pct = s->pct;
-  a.tninv = s->tninv;
-  a.tninvp = s->tninvp;
   a.L = P.L;
   a.M = P.M();
   a.D = P.D;
@@ -273,25 +269,22 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   s->target_blocks = 512;
 
   const uint32_t N = P.N, nm = P.nmod();
-  std::vector<uint32_t> fwd((size_t)nm * N);
-  std::vector<uint2> inv((size_t)nm * N), invt(N);
+  std::vector<uint32_t> fwd((size_t)nm * N), inv((size_t)nm * N), invt(N);
   std::vector<PrimeConst> pcs(nm);
   for (uint32_t i = 0; i < nm; ++i) {
     uint32_t m = P.modulus(i);
     HostNtt T(N, m, root_of_unity(2 * N, m));
     for (uint32_t k = 0; k < N; ++k) {
       fwd[(size_t)i * N + k] = (uint32_t)(((uint64_t)T.fw[k] << 32) % m);
-      inv[(size_t)i * N + k] = make_uint2(T.iw[k], T.iwp[k]);
+      inv[(size_t)i * N + k] = (uint32_t)(((uint64_t)T.iw[k] << 32) % m);
     }
     pcs[i] = make_const(T);
   }
   {
     uint32_t zeta = (uint32_t)powmod64(3, (P.t - 1) / (2 * N), P.t);
     HostNtt Tt(N, P.t, zeta);
-    for (uint32_t k = 0; k < N; ++k) invt[k] = make_uint2(Tt.iw[k], Tt.iwp[k]);
+    for (uint32_t k = 0; k < N; ++k) invt[k] = (uint32_t)(((uint64_t)Tt.iw[k] << 32) % P.t);
     s->pct = make_const(Tt);
-    s->tninv = Tt.ninv;
-    s->tninvp = Tt.ninvp;
   }
   std::vector<uint32_t> scatter = query_scatter_table(P);
 
@@ -334,8 +327,8 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   chk(hipMemcpyAsync(s->d_fwd, fwd.data(), fwd.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
-  chk(hipMemcpyAsync(s->d_inv, inv.data(), inv.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
-  chk(hipMemcpyAsync(s->d_inv_t, invt.data(), invt.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_inv, inv.data(), inv.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
+  chk(hipMemcpyAsync(s->d_inv_t, invt.data(), invt.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_pc, pcs.data(), pcs.size() * sizeof(PrimeConst), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_scatter, scatter.data(), scatter.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
   if (P.r > 1) {

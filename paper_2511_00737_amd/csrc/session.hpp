@@ -26,8 +26,8 @@ struct ephdc_session {
   size_t pt_cap = 0;               // plaintexts d_pt holds
   // device memory owned by the session
   uint32_t* d_fwd = nullptr;       // [nmod][N] forward twiddles, Montgomery form (w * 2^32 mod m)
-  uint2* d_inv = nullptr;          // [nmod][N]
-  uint2* d_inv_t = nullptr;        // [N]
+  uint32_t* d_inv = nullptr;       // [nmod][N] inverse twiddles, Montgomery form
+  uint32_t* d_inv_t = nullptr;     // [N] inverse twiddles mod t, Montgomery form
   ephdc::PrimeConst* d_pc = nullptr;  // [nmod]
   uint32_t* d_scatter = nullptr;   // [N]
   uint32_t* d_model = nullptr;     // [M][2][L][N] evaluation domain, Montgomery form
@@ -40,7 +40,6 @@ struct ephdc_session {
   uint32_t* d_rot = nullptr;       // workspace: acc, R, D, Y, KS, XP sized for G(max_Q)
   ephdc::KsConst ks{};
   ephdc::PrimeConst pct{};
-  uint32_t tninv = 0, tninvp = 0;
   size_t device_bytes = 0;
   // kernel timing: pairs of events per stage, resolved when read
   bool profile = false;
