@@ -153,6 +153,8 @@ typedef struct ephdc_session ephdc_session;
  * device-resident evaluation-domain copy owned by the session, and likewise the Galois
  * keys (device pointer, layout of ephdc_keygen, gk_words entries; required when r > 1,
  * else may be NULL).  A buffer shorter than its layout needs gives EPHDC_ERR_BUFFER.
+ * The device kernels take ciphertext primes q_l in [2^29, 2^30) (EPHDC_ERR_UNSUPPORTED
+ * otherwise); the default primes are the largest below 2^30.
  * max_Q bounds the batch size of later calls; it sizes the scratch space of
  * ephdc_score_encrypted, which is allocated on that call's first use (batches and the
  * serving loop bring their own).  The call is synchronous with respect to `stream`.
@@ -220,6 +222,14 @@ ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const ui
  */
 ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks,
                                 uint32_t values_per_thread, uint32_t mode);
+
+/*
+ * Bound (bytes) on the split path's plaintext buffer (0: 512 MiB).  The model range is
+ * scored in chunks whose plaintexts fit it, each chunk's MAC adding into the sums of the
+ * previous ones; the buffer always holds at least one plaintext per query group of max_Q.
+ * Frees the current buffer (after waiting for the device); results do not depend on it.
+ */
+ephdc_status ephdc_session_set_chunk_bytes(ephdc_session* s, size_t bytes);
 
 /*
  * Kernel timing (diagnostics for benchmarks).  While enabled, every kernel launched by the

@@ -79,6 +79,7 @@ def lib() -> C.CDLL:
             "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                               C.c_void_p]),
             "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
+            "ephdc_session_set_chunk_bytes": (C.c_int, [C.c_void_p, C.c_size_t]),
             "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
             "ephdc_session_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), u64p]),
             "ephdc_batch_create": (C.c_int, [C.POINTER(_CRequest), C.c_uint32, C.POINTER(C.c_void_p)]),
@@ -304,6 +305,10 @@ class Session:
         """Schedule of the scoring kernel (see ephdc_session_tune); 0 / None keeps a setting."""
         m = {None: 0, "fused": 1, "split": 2}[mode]
         _check(lib().ephdc_session_tune(self.handle, limb_group, blocks, values_per_thread, m))
+
+    def set_chunk_bytes(self, nbytes: int) -> None:
+        """Bound on the split path's plaintext buffer (see ephdc_session_set_chunk_bytes)."""
+        _check(lib().ephdc_session_set_chunk_bytes(self.handle, nbytes))
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every kernel launch with HIP events on its stream (see ephdc_session_profile)."""

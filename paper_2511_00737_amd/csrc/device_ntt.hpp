@@ -31,7 +31,8 @@ struct PrimeConst {
   uint32_t r2;        // 2^64 mod m (to enter Montgomery form)
   uint32_t ninv_r;     // N^-1 * 2^32 mod m (Montgomery form)
   uint32_t ninv_w1_r;  // N^-1 * (first inverse twiddle) * 2^32 mod m
-  uint32_t pad[3];
+  uint32_t r1;         // 2^32 mod m (folds the high word of a 64-bit sum)
+  uint32_t pad[2];
 };
 
 __device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wp, uint32_t m) {
@@ -63,6 +64,20 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t m,
 
 // Full reduction of a lazy value in [0, 4m) to [0, m).
 __device__ __forceinline__ uint32_t reduce4(uint32_t a, uint32_t m) { return csub(csub(a, 2 * m), m); }
+
+// Lazy 64-bit multiply-accumulate for sums of products a*b with a < m, b < 4m (each below
+// 2^62).  fold64 keeps the residue mod m and brings any sum below 2^64 back under
+// 2^62 + 2^32 (hi * (2^32 mod m) + lo), so two products may be added between folds.
+// redc64 ends the sum: for sums of Montgomery-form a (a*2^32 mod m) it returns the plain
+// residue of sum a*b in [0, m).
+__device__ __forceinline__ uint64_t fold64(uint64_t x, uint32_t r1) {
+  return (uint64_t)(uint32_t)(x >> 32) * r1 + (uint32_t)x;
+}
+__device__ __forceinline__ uint32_t redc64(uint64_t x, uint32_t m, uint32_t mneg_inv) {
+  // x < 2^62 + 2^32 after a fold: (x + k*m) / 2^32 < 2^31 + 2 < 4m, then two corrections
+  const uint32_t k = (uint32_t)x * mneg_inv;
+  return reduce4((uint32_t)(((uint64_t)k * m + x) >> 32), m);
+}
 
 template <int LOGN, int LE>
 struct Shape {

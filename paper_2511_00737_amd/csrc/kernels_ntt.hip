@@ -257,7 +257,7 @@ __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* s
 // plaintext and each limb's model values are requested ahead of the transform that
 // precedes their use (more registers: used where the register budget allows it).
 template <int LOGN, int LE, int LG, bool PF>
-__device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
+__device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
@@ -328,6 +328,115 @@ __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __res
     }
   }
   store_acc<LOGN, LE, LG>(acc, it, pcs, tid);
+}
+
+template <int LOGN, int LE, int LG, bool PF>
+__device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
+                                         const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
+                                         int tid, LdsBufs& b) {
+  using S = Shape<LOGN, LE>;
+  constexpr int E = S::E, N = S::N;
+  // per-lane byte offsets inside one polynomial: evaluation layout (tid*E + i) for the model
+  // and the sums, coefficient layout (tid + i*T) for the plaintexts
+  const uint32_t eo = (uint32_t)tid * E * 4u, co = (uint32_t)tid * 4u;
+  // Sums of (model in Montgomery form) x (plaintext, lazy in [0, 4m)) in 64 bits, folded
+  // every second plaintext and reduced once at the end (fold64 / redc64); a stored partial
+  // sum s re-enters as its Montgomery form s*2^32 mod m.
+  uint64_t acc[2][LG][E];
+#pragma unroll
+  for (int li = 0; li < LG; ++li) {
+    const PrimeConst pc = pcs[it.l0 + li];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t* src = it.slot + ((size_t)c * it.L + it.l0 + li) * N;
+#pragma unroll
+      for (int i = 0; i < E; ++i)
+        acc[c][li][i] = accumulate ? mont_mul(ld_at(src, eo + 4u * i), pc.r2, pc.m, pc.mneg_inv) : 0u;
+    }
+  }
+
+  int32_t nxt[E];
+  if (PF && it.m0 < it.m1) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) nxt[i] = ld_at(pt, co + 4u * (uint32_t)(i * S::T));
+  }
+  for (uint32_t m = it.m0; m < it.m1; ++m) {
+    const int32_t* ptm = pt + (size_t)(m - it.m0) * N;  // plaintext (g, m)
+    int32_t cur[E];
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cur[i] = nxt[i];
+      if (m + 1 < it.m1) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) nxt[i] = ld_at(ptm + N, co + 4u * (uint32_t)(i * S::T));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cur[i] = ld_at(ptm, co + 4u * (uint32_t)(i * S::T));
+    }
+    const bool fold = ((m - it.m0) & 1u) != 0u;
+#pragma unroll
+    for (int li = 0; li < LG; ++li) {
+      const uint32_t l = it.l0 + li;
+      const PrimeConst pc = pcs[l];
+      const uint32_t* ct0 = it.model + (((size_t)m * 2 + 0) * it.L + l) * N;
+      const uint32_t* ct1 = it.model + (((size_t)m * 2 + 1) * it.L + l) * N;
+      uint32_t c0[E], c1[E];
+      if constexpr (PF) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          c0[i] = ld_at(ct0, eo + 4u * i);
+          c1[i] = ld_at(ct1, eo + 4u * i);
+        }
+      }
+      uint32_t p[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
+      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      if constexpr (!PF) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          c0[i] = ld_at(ct0, eo + 4u * i);
+          c1[i] = ld_at(ct1, eo + 4u * i);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        acc[0][li][i] += (uint64_t)c0[i] * p[i];
+        acc[1][li][i] += (uint64_t)c1[i] * p[i];
+      }
+      if (fold) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          acc[0][li][i] = fold64(acc[0][li][i], pc.r1);
+          acc[1][li][i] = fold64(acc[1][li][i], pc.r1);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int li = 0; li < LG; ++li) {
+    const uint32_t l = it.l0 + li;
+    const PrimeConst pc = pcs[l];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t* dst = it.slot + ((size_t)c * it.L + l) * N;
+#pragma unroll
+      for (int i = 0; i < E; ++i) st_at(dst, eo + 4u * i, redc64(fold64(acc[c][li][i], pc.r1), pc.m, pc.mneg_inv));
+    }
+  }
+}
+
+// MAC alone: 64-bit lazy sums where 8 values per thread leave the registers for them,
+// 32-bit sums of Montgomery products otherwise.
+template <int LOGN, int LE, int LG, bool PF>
+__device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
+                                         const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
+                                         int tid, LdsBufs& b) {
+  if constexpr (LE <= 3)
+    mac_item64<LOGN, LE, LG, PF>(it, pt, accumulate, fwd_tw, pcs, tid, b);
+  else
+    mac_item32<LOGN, LE, LG, PF>(it, pt, accumulate, fwd_tw, pcs, tid, b);
 }
 
 // ------------------------------------------------------------------ single-request kernels

@@ -57,6 +57,7 @@ PrimeConst make_const(const HostNtt& T) {
   pc.m = m;
   pc.mneg_inv = (uint32_t)(0u - inv);
   pc.r2 = (uint32_t)(((unsigned __int128)1 << 64) % m);
+  pc.r1 = (uint32_t)((1ull << 32) % m);
   pc.ninv_r = (uint32_t)(((uint64_t)T.ninv << 32) % m);
   pc.ninv_w1_r = (uint32_t)(((((uint64_t)T.ninv * T.iw[1]) % m) << 32) % m);
   return pc;
@@ -108,7 +109,7 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   return a;
 }
 
-constexpr size_t kPtBytes = (size_t)512 << 20;  // bound on the split path's plaintext buffer
+constexpr size_t kPtBytes = (size_t)512 << 20;  // default bound on the split path's plaintext buffer
 
 // Split path: the model range is processed in chunks of m_len ciphertexts so that the
 // lifted plaintexts of a chunk (G x m_len x N int32) fit the session's buffer; the MAC
@@ -248,6 +249,8 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   if (st != EPHDC_OK) return st;
   if (!d_model_ct) return fail(EPHDC_ERR_ARG, "model is NULL");
   if (!supported_logn(P.logn)) return fail(EPHDC_ERR_UNSUPPORTED, "kernels implement N in {4096, 8192, 16384}");
+  for (uint32_t qi : P.q)
+    if (qi < (1u << 29)) return fail(EPHDC_ERR_UNSUPPORTED, "the device kernels take ciphertext primes in [2^29, 2^30)");
   if (P.r > 1 && !d_galois_keys) return fail(EPHDC_ERR_NOKEY, "r > 1 needs Galois keys");
   if (max_Q == 0) return fail(EPHDC_ERR_ARG, "max_Q must be positive");
   if (model_words < (size_t)P.M() * 2 * P.L * P.N) return fail(EPHDC_ERR_BUFFER, "model buffer shorter than [M][2][L][N]");
@@ -396,7 +399,8 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
   if (s->split) {
     if (!s->d_pt) {
       // at least one plaintext per group of the largest batch (max_Q) per chunk
-      const size_t cap = std::max<size_t>(P.G(s->max_Q), kPtBytes / (4 * (size_t)P.N));
+      const size_t bytes = s->pt_bytes ? s->pt_bytes : kPtBytes;
+      const size_t cap = std::max<size_t>(P.G(s->max_Q), bytes / (4 * (size_t)P.N));
       ephdc_status st2 = dev_alloc(s, &s->d_pt, cap * P.N, "split-path plaintexts");
       if (st2 != EPHDC_OK) return st2;
       s->pt_cap = cap;
@@ -451,6 +455,19 @@ ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t 
     if (blocks > kMaxBlocks) return fail(EPHDC_ERR_ARG, "blocks must be <= 1024");
     s->target_blocks = blocks;
   }
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_session_set_chunk_bytes(ephdc_session* s, size_t bytes) {
+  if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
+  (void)hipDeviceSynchronize();  // no launch may still use the buffer
+  if (s->d_pt) {
+    (void)hipFree(s->d_pt);
+    s->device_bytes -= s->pt_cap * s->P.N * 4;
+    s->d_pt = nullptr;
+    s->pt_cap = 0;
+  }
+  s->pt_bytes = bytes;
   return EPHDC_OK;
 }
 

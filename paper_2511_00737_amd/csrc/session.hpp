@@ -24,6 +24,7 @@ struct ephdc_session {
   bool split = false;              // batch-encode and MAC as two kernels (else one fused kernel)
   int32_t* d_pt = nullptr;         // split path: lifted plaintexts of one chunk [G][m_len][N]
   size_t pt_cap = 0;               // plaintexts d_pt holds
+  size_t pt_bytes = 0;             // bound on d_pt in bytes (0: the default, 512 MiB)
   // device memory owned by the session
   uint32_t* d_fwd = nullptr;       // [nmod][N] forward twiddles, Montgomery form (w * 2^32 mod m)
   uint32_t* d_inv = nullptr;       // [nmod][N] inverse twiddles, Montgomery form

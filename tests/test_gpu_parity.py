@@ -198,3 +198,30 @@ def test_rotations_at_large_parameters():
     assert np.array_equal(got[G - 1].astype(np.int64), want[0])
     scores, _ = pipeline.decrypt_scores(o, s, got.astype(np.int64), Q)
     assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
+
+
+@pytest.mark.parametrize("N,L,K,D,Q,vpt", [(8192, 4, 7, 40, 2500, 8), (8192, 4, 7, 40, 2500, 16),
+                                           (4096, 3, 2, 37, 3000, 8), (16384, 2, 26, 12, 1000, 16)])
+def test_chunked_model_ranges_accumulate_exactly(N, L, K, D, Q, vpt):
+    """A tiny plaintext buffer cuts the model range into many chunks whose MAC launches add
+    into the stored sums (both the 64-bit and the 32-bit accumulation forms); the score
+    ciphertexts still match the oracle bit for bit."""
+    torch = torch_cuda()
+    o, e = make(N, L, D=D, K=K)
+    rng = np.random.default_rng(N + Q)
+    C = synth.class_hypervectors(9, K, D)
+    model = bfv.encrypt_model(o, bfv.secret_key(o, 9), C, 9)
+    h = rng.choice(np.array([-1, 1], dtype=np.int8), (Q, D))
+    want = pipeline.score_ciphertexts(o, model, h)
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=Q)
+    try:
+        G = s.num_groups(Q)
+        s.tune(1, 256, vpt, "split")
+        s.set_chunk_bytes(3 * G * N * 4)  # three plaintexts per group and chunk
+        d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
+        d_out = torch.empty(want.shape, dtype=torch.int32, device="cuda")
+        ep.ephdc_score_encrypted(s, d_hv, Q, d_out)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(d_out).astype(np.int64), want)
+    finally:
+        s.close()
