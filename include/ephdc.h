@@ -368,8 +368,8 @@ ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout
 /* Counters: [0] submitted [1] completed [2] rejected [3] waiting [4] batches in flight
  * [5] batches launched [6] mean requests per batch [7] p50 latency ms [8] p99 latency ms
  * (submit to done, completed requests) [9] peak device bytes in use [10] budget bytes
- * [11] seconds since creation. */
-ephdc_status ephdc_server_stats(ephdc_server* sv, double out[12]);
+ * [11] seconds since creation [12] failed (a launch or the device reported an error). */
+ephdc_status ephdc_server_stats(ephdc_server* sv, double out[13]);
 
 /*
  * Packing (set before the first request): the requests of one tenant in a batch share

@@ -471,7 +471,7 @@ class Server:
     """Owns an ephdc_server: tenants, a request queue and a native scheduler thread."""
 
     STATS = ("submitted", "completed", "rejected", "waiting", "in_flight", "batches", "mean_batch",
-             "p50_ms", "p99_ms", "peak_bytes", "budget_bytes", "uptime_s")
+             "p50_ms", "p99_ms", "peak_bytes", "budget_bytes", "uptime_s", "failed")
 
     def __init__(self, budget_bytes: int, streams: int = 2, max_batch: int = 0):
         h = C.c_void_p()
@@ -523,7 +523,7 @@ class Server:
         _check(lib().ephdc_server_wait(self.handle, ticket, timeout_s))
 
     def stats(self) -> dict:
-        out = (C.c_double * 12)()
+        out = (C.c_double * 13)()
         _check(lib().ephdc_server_stats(self.handle, out))
         return {k: out[i] for i, k in enumerate(self.STATS)}
 

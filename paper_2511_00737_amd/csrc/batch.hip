@@ -49,6 +49,15 @@ struct ephdc_batch {
   bool packed = false;
   std::vector<ephdc_request> orig;  // packing: the caller's requests
   std::vector<uint32_t> vreq, qoff;  // packing: virtual request and first query of each
+  // HDC encoding of every request with features, and (packing) the copies of each request's
+  // ciphertexts: one launch each
+  std::vector<HdcReq> hdc;
+  std::vector<HdcTile> tiles;
+  std::vector<CopyRange> copies;
+  size_t copy_words = 0;
+  HdcReq* d_hdc = nullptr;
+  HdcTile* d_tiles = nullptr;
+  CopyRange* d_copies = nullptr;
   std::vector<Part> parts;
   std::vector<uint32_t*> rot_ws;  // per request: rotation workspace (r > 1), else nullptr
   int device = 0;
@@ -153,6 +162,58 @@ void build_part(const ephdc_batch* b, Part& pt) {
   if (begin < pt.segs.size()) pt.chunks.emplace_back(begin, (uint32_t)pt.segs.size());
 }
 
+// HDC work and output copies.  Only the counts are needed to place the arrays; the
+// pointers are filled once the batch's block is placed.  With packing, each request writes
+// exactly its own columns [off, off + Q) of its session's buffer (the session's last request
+// also zeroes the padding up to the end of the rows), so the tiles of all requests can run
+// in one launch without overlapping writes.
+void build_aux(ephdc_batch* b) {
+  b->hdc.clear();
+  b->tiles.clear();
+  b->copies.clear();
+  b->copy_words = 0;
+  auto add = [&](const ephdc_request& rq, int8_t* hv, uint32_t stride, uint32_t ncols) {
+    const ParamSet& P = rq.session->P;
+    HdcReq h{};
+    h.x = rq.d_x;
+    h.base = rq.d_base;
+    h.hv = hv;
+    h.Q = rq.Q;
+    h.F = P.F;
+    h.D = P.D;
+    h.stride = stride;
+    h.ncols = ncols;
+    h.qbits = P.qbits;
+    h.qshift = P.qshift;
+    const uint32_t ri = (uint32_t)b->hdc.size();
+    b->hdc.push_back(h);
+    for (uint32_t j0 = 0; j0 < P.D; j0 += 64)
+      for (uint32_t q0 = 0; q0 < ncols; q0 += 64) b->tiles.push_back(HdcTile{ri, j0, q0, 0});
+  };
+  if (b->packed) {
+    for (uint32_t i = 0; i < b->orig.size(); ++i) {
+      const ephdc_request& rq = b->orig[i];
+      const ephdc_request& v = b->reqs[b->vreq[i]];
+      const ParamSet& P = rq.session->P;
+      const uint32_t stride = P.G(v.Q) * P.B(), off = b->qoff[i];
+      const bool last = off + rq.Q == v.Q;
+      add(rq, v.d_hv ? v.d_hv + off : nullptr, stride, last ? stride - off : rq.Q);
+      const uint32_t g0 = off / P.B(), g1 = (off + rq.Q - 1) / P.B();
+      const size_t ct_words = (size_t)2 * P.L * P.N;
+      CopyRange c{v.d_score_ct ? v.d_score_ct + g0 * ct_words : nullptr, rq.d_score_ct, (g1 - g0 + 1) * ct_words};
+      b->copies.push_back(c);
+      b->copy_words += c.words;
+    }
+  } else {
+    for (const ephdc_request& rq : b->reqs) {
+      if (!rq.d_x) continue;
+      const ParamSet& P = rq.session->P;
+      const uint32_t stride = P.G(rq.Q) * P.B();
+      add(rq, rq.d_hv, stride, stride);
+    }
+  }
+}
+
 // Places every device array of the batch in one block starting at `base` (nullptr: only
 // measures); returns the bytes needed.
 size_t carve(ephdc_batch* b, char* base) {
@@ -184,6 +245,9 @@ size_t carve(ephdc_batch* b, char* base) {
     const ParamSet& P = rq.session->P;
     if (P.r > 1) b->rot_ws[i] = (uint32_t*)take(rotate_words(P, P.G(rq.Q)) * 4);
   }
+  b->d_hdc = (HdcReq*)take(b->hdc.size() * sizeof(HdcReq));
+  b->d_tiles = (HdcTile*)take(b->tiles.size() * sizeof(HdcTile));
+  b->d_copies = (CopyRange*)take(b->copies.size() * sizeof(CopyRange));
   return off;
 }
 
@@ -192,6 +256,7 @@ size_t carve(ephdc_batch* b, char* base) {
 ephdc_status plan(ephdc_batch* b, hipStream_t hs) {
   drop_graph(b);
   for (Part& pt : b->parts) build_part(b, pt);
+  build_aux(b);  // counts only: the packed buffers are not placed yet
   const size_t need = carve(b, nullptr);
   if (need > b->mem_bytes) {
     if (!b->owned && b->mem) return fail(EPHDC_ERR_BUFFER, "batch memory block too small for this schedule");
@@ -223,6 +288,14 @@ ephdc_status plan(ephdc_batch* b, hipStream_t hs) {
       e = hipMemcpyAsync(pt.d_fin, pt.fin.data(), pt.fin.size() * sizeof(FinishItem), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "work list upload");
   }
+  build_aux(b);  // now with the placed buffers
+  hipError_t e = hipSuccess;
+  if (!b->hdc.empty()) e = hipMemcpyAsync(b->d_hdc, b->hdc.data(), b->hdc.size() * sizeof(HdcReq), hipMemcpyHostToDevice, hs);
+  if (e == hipSuccess && !b->tiles.empty())
+    e = hipMemcpyAsync(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(HdcTile), hipMemcpyHostToDevice, hs);
+  if (e == hipSuccess && !b->copies.empty())
+    e = hipMemcpyAsync(b->d_copies, b->copies.data(), b->copies.size() * sizeof(CopyRange), hipMemcpyHostToDevice, hs);
+  if (e != hipSuccess) return hip_fail(e, "work list upload");
   return EPHDC_OK;
 }
 
@@ -251,27 +324,9 @@ ListArgs list_args(const ephdc_batch* b, const Part& pt) {
 namespace ephdc {
 
 hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
-  hipError_t e = hipSuccess;
-  for (const ephdc_request& rq : b->reqs) {
-    if (!rq.d_x) continue;
-    const ParamSet& P = rq.session->P;
-    e = launch_hdc_encode(rq.d_x, rq.d_base, rq.d_hv, rq.Q, P.F, P.D, P.G(rq.Q) * P.B(), P.qbits, P.qshift, hs);
-    if (e != hipSuccess) return e;
-  }
-  // packing: each request's queries are encoded into its columns of the session's packed
-  // buffer, in request order; an encode may zero a few columns past its own (up to its last
-  // 64-query tile), which the next request of the session overwrites, and the session's last
-  // request zeroes the padding up to the end of the rows
-  for (uint32_t i = 0; i < b->orig.size(); ++i) {
-    const ephdc_request& rq = b->orig[i];
-    const ephdc_request& v = b->reqs[b->vreq[i]];
-    const ParamSet& P = rq.session->P;
-    const uint32_t stride = P.G(v.Q) * P.B(), off = b->qoff[i];
-    const bool last = off + rq.Q == v.Q;
-    const uint32_t ncols = last ? stride - off : std::min(stride - off, (rq.Q + 63u) & ~63u);
-    e = launch_hdc_encode(rq.d_x, rq.d_base, v.d_hv + off, rq.Q, P.F, P.D, stride, P.qbits, P.qshift, hs, ncols);
-    if (e != hipSuccess) return e;
-  }
+  // HDC encoding of every request that brings features, in one launch
+  hipError_t e = launch_hdc_encode_list(b->d_hdc, b->d_tiles, (uint32_t)b->tiles.size(), hs);
+  if (e != hipSuccess) return e;
   for (const Part& pt : b->parts) {
     const int le = batch_le(b, pt.logn);
     ListArgs a = list_args(b, pt);
@@ -306,16 +361,9 @@ hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
     }
   }
   // packing: every request receives the ciphertexts of its session's sequence that hold
-  // its queries
-  for (uint32_t i = 0; i < b->orig.size() && e == hipSuccess; ++i) {
-    const ephdc_request& rq = b->orig[i];
-    const ephdc_request& v = b->reqs[b->vreq[i]];
-    const ParamSet& P = rq.session->P;
-    const uint32_t g0 = b->qoff[i] / P.B(), g1 = (b->qoff[i] + rq.Q - 1) / P.B();
-    const size_t ct_words = (size_t)2 * P.L * P.N;
-    e = hipMemcpyAsync(rq.d_score_ct, v.d_score_ct + g0 * ct_words, (g1 - g0 + 1) * ct_words * 4,
-                       hipMemcpyDeviceToDevice, hs);
-  }
+  // its queries, all copies in one launch
+  if (e == hipSuccess) e = launch_copy_list(b->d_copies, (uint32_t)b->copies.size(), b->copy_words, hs);
+  if (e != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -422,6 +470,7 @@ size_t batch_bytes(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, u
                    bool packed) {
   ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len, packed);
   for (Part& pt : b->parts) build_part(b, pt);
+  build_aux(b);
   const size_t need = carve(b, nullptr);
   delete b;
   return need;

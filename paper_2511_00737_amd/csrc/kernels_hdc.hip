@@ -12,6 +12,8 @@
 // 2 x 2 MFMA tiles of 16 x 16.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace ephdc_dev {
@@ -22,14 +24,15 @@ constexpr int HT = 64;      // tile edge
 constexpr int HK = 64;      // contraction chunk
 constexpr int PITCH = 80;   // LDS row pitch in bytes
 
-__global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
-                                                    int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
-                                                    uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift) {
+// One 64 x 64 output tile (dimensions j0.., queries q0..).
+__device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
+                                         int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
+                                         uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift,
+                                         uint32_t j0, uint32_t q0) {
   __shared__ __attribute__((aligned(16))) uint8_t a_lds[HT * PITCH];  // [j][f]
   __shared__ __attribute__((aligned(16))) uint8_t b_lds[HT * PITCH];  // [q][f]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const uint32_t j0 = blockIdx.x * HT, q0 = blockIdx.y * HT;
   const int wj = (wave >> 1) * 32, wq = (wave & 1) * 32;
 
   v4i acc[2][2];
@@ -101,9 +104,49 @@ __global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ 
     }
 }
 
+__global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
+                                                    int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
+                                                    uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift) {
+  hdc_tile(x, base, hv, Q, F, D, stride, ncols, qbits, qshift, blockIdx.x * HT, blockIdx.y * HT);
+}
+
+// Many requests in one launch: workgroup w encodes tile tiles[w] of request reqs[tile.req].
+__global__ __launch_bounds__(256) void k_hdc_encode_list(const HdcReq* __restrict__ reqs,
+                                                         const HdcTile* __restrict__ tiles) {
+  const HdcTile t = tiles[blockIdx.x];
+  const HdcReq r = reqs[t.req];
+  hdc_tile(r.x, r.base, r.hv, r.Q, r.F, r.D, r.stride, r.ncols, r.qbits, r.qshift, t.j0, t.q0);
+}
+
+// Copies of many word ranges in one launch (16-byte moves; every range is a multiple of
+// 4 words and 16-byte aligned): workgroups stride over the ranges' 16-byte units.
+__global__ __launch_bounds__(256) void k_copy_list(const CopyRange* __restrict__ ranges, uint32_t n) {
+  for (uint32_t k = 0; k < n; ++k) {
+    const CopyRange c = ranges[k];
+    const uint4* src = reinterpret_cast<const uint4*>(c.src);
+    uint4* dst = reinterpret_cast<uint4*>(c.dst);
+    const size_t units = c.words / 4;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < units; i += (size_t)gridDim.x * blockDim.x)
+      dst[i] = src[i];
+  }
+}
+
 }  // namespace ephdc_dev
 
 namespace ephdc {
+
+hipError_t launch_hdc_encode_list(const HdcReq* reqs, const HdcTile* tiles, uint32_t ntiles, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  ephdc_dev::k_hdc_encode_list<<<dim3(ntiles), dim3(256), 0, st>>>(reqs, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_list(const CopyRange* ranges, uint32_t n, size_t total_words, hipStream_t st) {
+  if (n == 0 || total_words == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(1, total_words / 4 / 256 / (size_t)n), 1024);
+  ephdc_dev::k_copy_list<<<dim3(grid), dim3(256), 0, st>>>(ranges, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_hdc_encode(const uint8_t* x, const int8_t* base, int8_t* hv, uint32_t Q, uint32_t F, uint32_t D,
                              uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st, uint32_t ncols) {

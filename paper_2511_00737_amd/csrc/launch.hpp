@@ -91,6 +91,25 @@ struct ListArgs {
   TSideArgs ts;
 };
 
+// HDC encoding of many requests in one launch: per request its operands and layout, per
+// 64 x 64 output tile its request and origin.
+struct HdcReq {
+  const uint8_t* x;
+  const int8_t* base;
+  int8_t* hv;  // first column of the request (rows of pitch `stride`)
+  uint32_t Q, F, D, stride, ncols, qbits, qshift, pad;
+};
+struct HdcTile {
+  uint32_t req, j0, q0, pad;
+};
+
+// One device-to-device copy of `words` 32-bit words (a multiple of 4, 16-byte aligned ends).
+struct CopyRange {
+  const uint32_t* src;
+  uint32_t* dst;
+  size_t words;
+};
+
 // Constants of hybrid key switching (Shoup pairs (w, floor(w*2^32/m)) for the modulus
 // each multiplication is taken in).
 struct KsConst {
@@ -122,7 +141,10 @@ struct RotateArgs {
 
 namespace ephdc {
 
+using ephdc_dev::CopyRange;
 using ephdc_dev::FinishItem;
+using ephdc_dev::HdcReq;
+using ephdc_dev::HdcTile;
 using ephdc_dev::KsConst;
 using ephdc_dev::ListArgs;
 using ephdc_dev::ReqDesc;
@@ -172,6 +194,10 @@ hipError_t launch_finish_list(int logn, const ListArgs& a, hipStream_t st);
 
 // One rotate-and-sum step (Galois element of step `step`): acc <- acc + KeySwitch(sigma(acc)).
 hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipStream_t st);
+
+// HDC encoding of many requests (one workgroup per tile) and copies of many ranges.
+hipError_t launch_hdc_encode_list(const HdcReq* reqs, const HdcTile* tiles, uint32_t ntiles, hipStream_t st);
+hipError_t launch_copy_list(const CopyRange* ranges, uint32_t n, size_t total_words, hipStream_t st);
 
 // HDC projection: hv[j][q] = quantise(sum_f (x[q][f]-128) * base[f][j]) for q < Q, 0 for
 // Q <= q < ncols (rows of pitch `stride`; ncols = 0 means the whole row).  Columns past

@@ -128,7 +128,7 @@ struct ephdc_server {
   std::string worker_error;
   // statistics
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-  uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batched_requests = 0;
+  uint64_t submitted = 0, completed = 0, rejected = 0, failed = 0, batches = 0, batched_requests = 0;
   size_t peak_bytes = 0;
   std::vector<double> latencies;  // seconds, completed requests
 };
@@ -162,6 +162,7 @@ bool reap(ephdc_server* sv, std::unique_lock<std::mutex>&) {
       } else {
         r.state = -EPHDC_ERR_HIP;
         r.t_done = t;
+        ++sv->failed;
       }
     }
     batch_free(it->batch);
@@ -264,6 +265,7 @@ bool admit(ephdc_server* sv, int si) {
     for (uint64_t tk : take) {
       sv->reqs[tk].state = st != EPHDC_OK ? -(int)st : -EPHDC_ERR_HIP;
       sv->reqs[tk].t_done = t;
+      ++sv->failed;
     }
     sv->done_cv.notify_all();
     return true;
@@ -446,7 +448,7 @@ ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout
   return EPHDC_OK;
 }
 
-ephdc_status ephdc_server_stats(ephdc_server* sv, double out[12]) {
+ephdc_status ephdc_server_stats(ephdc_server* sv, double out[13]) {
   if (!sv || !out) return fail(EPHDC_ERR_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(sv->mu);
   std::vector<double> l = sv->latencies;
@@ -468,6 +470,7 @@ ephdc_status ephdc_server_stats(ephdc_server* sv, double out[12]) {
   out[9] = (double)sv->peak_bytes;
   out[10] = (double)sv->budget;
   out[11] = now_s(sv);
+  out[12] = (double)sv->failed;
   return EPHDC_OK;
 }
 

@@ -67,7 +67,7 @@ def test_results_are_the_same_alone_and_in_the_mix(tenants):
                 time.sleep(0.002)  # later requests arrive while earlier batches run
         sv.wait(0, timeout_s=120)
         stats = sv.stats()
-        assert stats["completed"] == 40 and stats["rejected"] == 0
+        assert stats["failed"] == 0 and stats["completed"] == 40 and stats["rejected"] == 0
         assert stats["batches"] >= 2 and stats["p99_ms"] >= stats["p50_ms"] > 0
         for tk, ti, Q, x, d_x, out in jobs:
             state, (ts, ta, td) = sv.query(tk)

@@ -34,10 +34,11 @@ def test_empty_server_errors_and_stats():
         assert ep.lib().ephdc_server_query(h, 12345, C.byref(state), None) == ep.ERR_ARG
         assert ep.lib().ephdc_server_wait(h, 0, 1.0) == ep.OK  # nothing waits or runs
         assert ep.lib().ephdc_server_wait(h, 7, 1.0) == ep.ERR_ARG  # unknown ticket
-        out = (C.c_double * 12)()
+        out = (C.c_double * 13)()
         assert ep.lib().ephdc_server_stats(h, out) == ep.OK
         stats = dict(zip(ep.Server.STATS, out))
         assert stats["submitted"] == 0 and stats["completed"] == 0 and stats["batches"] == 0
+        assert stats["failed"] == 0
         assert stats["budget_bytes"] == 1 << 30
     finally:
         assert ep.lib().ephdc_server_destroy(h) == ep.OK
