@@ -232,6 +232,9 @@ def bench_batched(args, w) -> int:
         t_ptune = time.perf_counter() - t0
         print(f"[bench] c3 packed: autotuned {psched} ({ptuned_ms:.2f} ms/run) in {t_ptune:.1f}s",
               file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            pbatch.run(stream)
+        eager_wall, eager_lat = timed(lambda: pbatch.run(stream), max(1, args.steps // 2))
         pbatch.capture(stream)
         for _ in range(args.warmup):
             pbatch.run(stream)
@@ -278,6 +281,9 @@ def bench_batched(args, w) -> int:
         "batched_unpacked": {"value": round(unpacked_value, 1), "unit": "inferences/s",
                              "ms_per_step": round(unpacked_wall * 1e3 / len(unpacked_lat), 4), "schedule": sched,
                              "form": "one graph replay of persistent launches, each request in its own ciphertexts"},
+        "packed_eager": {"value": round(total_q * len(eager_lat) / eager_wall, 1), "unit": "inferences/s",
+                         "ms_per_step": round(eager_wall * 1e3 / len(eager_lat), 4),
+                         "form": "the packed batch enqueued launch by launch instead of replayed as a graph"},
         "speedup_vs_plain": round(value / plain_value, 3),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4)},
         "roofline": {"bound": "alu", "kernel": "whole batched path (batch-encode + MAC dominate)",

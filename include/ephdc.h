@@ -291,8 +291,9 @@ ephdc_status ephdc_batch_schedule(const ephdc_batch* b, uint32_t schedule[5]);
 
 /*
  * Autotuner: times candidate schedules of this batch on `stream` (coordinate descent over
- * the five settings, each candidate run once to warm up and timed over `reps` runs with
- * HIP events) and keeps the fastest.  Writes its schedule and mean time per run.
+ * the five settings; each candidate is run once to warm up and timed over `reps` runs with
+ * HIP events, right after the incumbent is timed the same way, and replaces it only when
+ * at least 2 % faster) and keeps the fastest.  Writes its schedule and mean time per run.
  */
 ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, uint32_t schedule[5],
                                   double* best_ms);

@@ -650,29 +650,35 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
     if (ok) lgs.push_back(g);
   }
   const std::vector<uint32_t> cand[5] = {{2, 1}, vpts, lgs, {64, 128, 256, 512}, {256, 512, 1024, 2048}};
-  const int order[] = {3, 4, 2, 1, 0, 3, 4};
+  const int order[] = {1, 4, 3, 2, 0, 1, 4};  // values per thread first: it matters most
+  // Paired comparisons: the incumbent is timed again right before each candidate, so that
+  // clock and thermal drift during the search do not decide between them.
   for (int k : order) {
     for (uint32_t v : cand[k]) {
       if (v == cur[k]) continue;
+      double inc = 0, ms = 0;
+      st = measure(inc);
+      if (st != EPHDC_OK) return cleanup(st);
       uint32_t trial[5] = {0, 0, 0, 0, 0};
       trial[k] = v;
       if (apply_schedule(b, trial, hs) != EPHDC_OK) {
         apply_schedule(b, cur, hs);
         continue;
       }
-      double ms = 0;
       st = measure(ms);
       if (st != EPHDC_OK) {
         apply_schedule(b, cur, hs);
         return cleanup(st);
       }
-      if (ms < best) {
+      if (ms < 0.98 * inc) {  // a clear win only
         best = ms;
         cur[k] = v;
+      } else {
+        best = inc;
+        st = apply_schedule(b, cur, hs);
+        if (st != EPHDC_OK) return cleanup(st);
       }
     }
-    st = apply_schedule(b, cur, hs);
-    if (st != EPHDC_OK) return cleanup(st);
   }
   HIP_TRY(hipStreamSynchronize(hs), "autotune sync");
   if (schedule) read_schedule(b, schedule);
