@@ -173,7 +173,8 @@ size_t ephdc_session_device_bytes(const ephdc_session* s);
  *   d_hv    out, int8 [D][ephdc_hv_stride(Q)] query hypervectors, dimension-major;
  *           entry [j][q] = sign or Q-bit quantisation of sum_f (x[q][f]-128)*base[f][j],
  *           and 0 for the padding queries q >= Q.
- * Requires F % 16 == 0 and D % 64 == 0 (else EPHDC_ERR_UNSUPPORTED).  int8 MFMA on gfx950.
+ * Requires F % 16 == 0, D % 64 == 0, F * D < 2^31 and Q * F < 2^31 (else
+ * EPHDC_ERR_UNSUPPORTED).  int8 MFMA on gfx950.
  */
 ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const int8_t* d_base,
                                   uint32_t Q, int8_t* d_hv, void* stream);

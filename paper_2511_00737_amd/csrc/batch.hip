@@ -187,8 +187,8 @@ void build_aux(ephdc_batch* b) {
     h.qshift = P.qshift;
     const uint32_t ri = (uint32_t)b->hdc.size();
     b->hdc.push_back(h);
-    for (uint32_t j0 = 0; j0 < P.D; j0 += 64)
-      for (uint32_t q0 = 0; q0 < ncols; q0 += 64) b->tiles.push_back(HdcTile{ri, j0, q0, 0});
+    for (uint32_t j0 = 0; j0 < P.D; j0 += 128)  // the encoder's 128 x 128 tiles
+      for (uint32_t q0 = 0; q0 < ncols; q0 += 128) b->tiles.push_back(HdcTile{ri, j0, q0, 0});
   };
   if (b->packed) {
     for (uint32_t i = 0; i < b->orig.size(); ++i) {
@@ -429,6 +429,8 @@ ephdc_status check_requests(const ephdc_request* reqs, uint32_t n_req, bool pack
     if (r.d_x) {
       if (!r.d_base) return fail(EPHDC_ERR_ARG, "d_x without d_base");
       if (P.F % 16 != 0 || P.D % 64 != 0) return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F % 16 == 0 and D % 64 == 0");
+      if ((uint64_t)P.F * P.D >= (1ull << 31) || (uint64_t)r.Q * P.F >= (1ull << 31))
+        return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F * D and Q * F below 2^31");
       if (((uintptr_t)r.d_x & 15) || ((uintptr_t)r.d_base & 3))
         return fail(EPHDC_ERR_ARG, "x must be 16-byte and base 4-byte aligned");
     }

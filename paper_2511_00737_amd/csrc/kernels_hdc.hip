@@ -5,11 +5,18 @@
 // base^T (D x F) * (x - 128)^T (F x Q) with v_mfma_i32_16x16x64_i8, and written
 // dimension-major so that the batch-encoding step reads one contiguous row per dimension.
 //
-// Tiling: a workgroup of 4 waves owns a 64 (dimensions) x 64 (queries) output tile and
+// Tiling: a workgroup of 4 waves owns a 128 (dimensions) x 128 (queries) output tile and
 // walks F in chunks of 64.  Both operands are staged in LDS with the contraction index
-// contiguous (rows padded to 80 bytes); the base tile is transposed on the way in with
-// 4x4 byte-block transposes in registers.  Each wave computes a 32 x 32 sub-tile as
-// 2 x 2 MFMA tiles of 16 x 16.
+// contiguous, in 64-byte rows whose four 16-byte runs are XOR-swizzled by bits 2-3 of the
+// row, so that the matrix-operand reads (16 rows, one run each) and the stores below touch
+// 64 distinct banks.  The base tile is transposed on the way in with 4 x 4 byte-block
+// transposes (v_perm) and placed at row 32*b + m for dimension 4*m + b, which spreads a
+// wave's transposed stores over all banks too.  Global loads go through buffer resources
+// whose range check returns zero past the end: features past F read zero base rows, so no
+// load needs a branch, and whatever a row past D or Q holds only reaches outputs that are
+// discarded or written as zero.  The next chunk's loads are issued before the current
+// chunk's matrix work and consumed only at the next stage.  Each wave computes a 64 x 64
+// quarter as 4 x 4 MFMA tiles of 16 x 16.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,98 +27,155 @@ namespace ephdc_dev {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int HT = 64;      // tile edge
-constexpr int HK = 64;      // contraction chunk
-constexpr int PITCH = 80;   // LDS row pitch in bytes
+constexpr int HT = 128;     // tile edge (dimensions and queries)
+constexpr int HK = 64;      // contraction chunk (bytes per LDS row)
+constexpr int NT = 256;     // threads: 4 waves, each a 64 x 64 quarter of the tile
+constexpr int SUB = HT / 2 / 16;  // 16 x 16 MFMA tiles per wave edge
+constexpr uint32_t RSRC_WORD3 = 0x00020000u;  // raw (untyped) buffer access on gfx9-family parts
 
-// One 64 x 64 output tile (dimensions j0.., queries q0..).
+// byte offset of 16-byte run c of LDS row r
+__device__ __forceinline__ int lds_at(int r, int c) { return r * HK + 16 * (c ^ ((r >> 2) & 3)); }
+
+// Global operands of one contraction chunk, held in registers so that the next chunk's
+// loads are in flight while the current chunk runs on the matrix cores.
+struct HdcStage {
+  uint32_t d[2][4];  // base: two 4 x 4 byte blocks (4 features x 4 dimensions)
+  uint4 xv[2];       // features: two 16-byte runs (raw bytes; the offset is applied at the store)
+};
+
+struct HdcSrc {
+  __amdgpu_buffer_rsrc_t x, base;  // x from row q0 on; base whole (F * D bytes)
+  uint32_t F, D, j0;
+};
+
+__device__ __forceinline__ void hdc_load(HdcStage& st, const HdcSrc& src, uint32_t f0, int tid) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int blk = tid + NT * k;
+    // 32 dimension quads x 16 feature quads; 16 dimension quads per feature row across lanes
+    const int jq = (blk & 15) + 16 * k, fq = (blk >> 4) & 15;
+    const uint32_t j = src.j0 + 4 * jq;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      st.d[k][a] = __builtin_amdgcn_raw_buffer_load_b32(src.base, (f0 + 4 * fq + a) * src.D + j, 0, 0);
+    const int row = blk >> 2, ch = blk & 3;  // 128 queries x 4 runs of 16 features
+    const v4i v = __builtin_amdgcn_raw_buffer_load_b128(src.x, row * src.F + f0 + 16 * ch, 0, 0);
+    st.xv[k] = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// base rows [f][j] -> a_lds[32 * (j % 4) + j / 4][f] (4 x 4 byte-block transposes);
+// features -> b_lds[q][f] as x - 128 (x ^ 0x80 on each byte)
+__device__ __forceinline__ void hdc_store(const HdcStage& st, uint8_t* a_lds, uint8_t* b_lds, int tid) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int blk = tid + NT * k;
+    const int jq = (blk & 15) + 16 * k, fq = (blk >> 4) & 15;
+    const uint32_t* d = st.d[k];
+    const uint32_t lo01 = __builtin_amdgcn_perm(d[1], d[0], 0x05010400u);
+    const uint32_t hi01 = __builtin_amdgcn_perm(d[1], d[0], 0x07030602u);
+    const uint32_t lo23 = __builtin_amdgcn_perm(d[3], d[2], 0x05010400u);
+    const uint32_t hi23 = __builtin_amdgcn_perm(d[3], d[2], 0x07030602u);
+    const uint32_t col[4] = {__builtin_amdgcn_perm(lo23, lo01, 0x05040100u),
+                             __builtin_amdgcn_perm(lo23, lo01, 0x07060302u),
+                             __builtin_amdgcn_perm(hi23, hi01, 0x05040100u),
+                             __builtin_amdgcn_perm(hi23, hi01, 0x07060302u)};
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const int r = 32 * bb + jq;
+      *reinterpret_cast<uint32_t*>(a_lds + lds_at(r, fq >> 2) + 4 * (fq & 3)) = col[bb];
+    }
+    const int row = blk >> 2, ch = blk & 3;
+    uint4 v = st.xv[k];
+    v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+    *reinterpret_cast<uint4*>(b_lds + lds_at(row, ch)) = v;
+  }
+}
+
+// One 128 x 128 output tile (dimensions j0.., queries q0..).
 __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
                                          int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
                                          uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift,
                                          uint32_t j0, uint32_t q0) {
-  __shared__ __attribute__((aligned(16))) uint8_t a_lds[HT * PITCH];  // [j][f]
-  __shared__ __attribute__((aligned(16))) uint8_t b_lds[HT * PITCH];  // [q][f]
+  __shared__ __attribute__((aligned(16))) uint8_t a_lds[HT * HK];  // [32 * (j % 4) + j / 4][f]
+  __shared__ __attribute__((aligned(16))) uint8_t b_lds[HT * HK];  // [q][f]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wj = (wave >> 1) * 32, wq = (wave & 1) * 32;
+  const int wj = (wave >> 1) * (HT / 2), wq = (wave & 1) * (HT / 2);
 
-  v4i acc[2][2];
+  HdcSrc src;
+  // the resources must live in scalar registers: the row base and its length are uniform
+  const uint64_t xa = reinterpret_cast<uint64_t>(x) + (uint64_t)q0 * F;
+  const uint32_t xlo = __builtin_amdgcn_readfirstlane((uint32_t)xa), xhi = __builtin_amdgcn_readfirstlane((uint32_t)(xa >> 32));
+  const uint32_t xbytes = __builtin_amdgcn_readfirstlane(q0 < Q ? (Q - q0) * F : 0u);
+  src.x = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)xhi << 32) | xlo), 0, (int)xbytes, RSRC_WORD3);
+  src.base = __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(base), 0, (int)(F * D), RSRC_WORD3);
+  src.F = F; src.D = D; src.j0 = j0;
+
+  v4i acc[SUB][SUB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < SUB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    for (int b = 0; b < SUB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
 
-  const int jq = tid & 15, fq = tid >> 4;   // base tile: 4 dims x 4 features per thread
-  const int xrow = tid >> 2, xch = tid & 3;  // feature tile: 16 bytes per thread
-
+  HdcStage st;
+  hdc_load(st, src, 0, tid);
   for (uint32_t f0 = 0; f0 < F; f0 += HK) {
-    // base[f0+4fq+a][j0+4jq .. +3] -> a_lds[j][f], transposing the 4x4 byte block
-    uint32_t d[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const uint32_t f = f0 + 4 * fq + a;
-      d[a] = f < F ? *reinterpret_cast<const uint32_t*>(base + (size_t)f * D + j0 + 4 * jq) : 0u;
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const uint32_t col = ((d[0] >> (8 * b)) & 0xFFu) | (((d[1] >> (8 * b)) & 0xFFu) << 8) |
-                           (((d[2] >> (8 * b)) & 0xFFu) << 16) | (((d[3] >> (8 * b)) & 0xFFu) << 24);
-      *reinterpret_cast<uint32_t*>(a_lds + (4 * jq + b) * PITCH + 4 * fq) = col;
-    }
-    // (x - 128) as int8 is x ^ 0x80
-    {
-      const uint32_t q = q0 + xrow, f = f0 + 16 * xch;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (q < Q && f < F) {
-        v = *reinterpret_cast<const uint4*>(x + (size_t)q * F + f);
-        v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-      }
-      *reinterpret_cast<uint4*>(b_lds + xrow * PITCH + 16 * xch) = v;
-    }
+    hdc_store(st, a_lds, b_lds, tid);
     __syncthreads();
-    v4i av[2], bv[2];
+    if (f0 + HK < F) hdc_load(st, src, f0 + HK, tid);  // in flight meanwhile
+    v4i av[SUB], bv[SUB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-      av[a] = *reinterpret_cast<const v4i*>(a_lds + (wj + 16 * a + (lane & 15)) * PITCH + 16 * (lane >> 4));
+    for (int a = 0; a < SUB; ++a)
+      av[a] = *reinterpret_cast<const v4i*>(a_lds + lds_at(wj + 16 * a + (lane & 15), lane >> 4));
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-      bv[b] = *reinterpret_cast<const v4i*>(b_lds + (wq + 16 * b + (lane & 15)) * PITCH + 16 * (lane >> 4));
+    for (int b = 0; b < SUB; ++b)
+      bv[b] = *reinterpret_cast<const v4i*>(b_lds + lds_at(wq + 16 * b + (lane & 15), lane >> 4));
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < SUB; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[a], bv[b], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < SUB; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv[b], av[a], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
 
-  // lane holds rows 4*(lane/16)+i (dimensions) of column lane%16 (queries) of each 16x16 tile
+  // The product is (x - 128) * base^T, so a lane holds queries 4*(lane/16) + i, i = 0..3, of
+  // one base row (LDS row lane%16, i.e. dimension 4*(row % 32) + row / 32) in each 16 x 16
+  // tile: four consecutive bytes of one hv row, stored as one word where aligned.
   const int lo = -(1 << (qbits - 1)), hi = (1 << (qbits - 1)) - 1;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < SUB; ++a) {
+    const int r = wj + 16 * a + (lane & 15);
+    const uint32_t j = j0 + 4 * (r & 31) + (r >> 5);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const uint32_t q = q0 + wq + 16 * b + (lane & 15);
-      if (q >= ncols) continue;
+    for (int b = 0; b < SUB; ++b) {
+      const uint32_t q = q0 + wq + 16 * b + 4 * (lane >> 4);
+      if (j >= D || q >= ncols) continue;
+      uint32_t w = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint32_t j = j0 + wj + 16 * a + 4 * (lane >> 4) + i;
         const int H = acc[a][b][i];
-        int h;
-        if (q >= Q) h = 0;
-        else if (qbits == 1) h = H >= 0 ? 1 : -1;
-        else h = min(max(H >> qshift, lo), hi);
-        hv[(size_t)j * stride + q] = (int8_t)h;
+        int h = qbits == 1 ? ((H >> 31) | 1) : min(max(H >> qshift, lo), hi);
+        if (q + i >= Q) h = 0;
+        w |= (uint32_t)(h & 0xFF) << (8 * i);
+      }
+      int8_t* dst = hv + (size_t)j * stride + q;
+      if (q + 4 <= ncols && (reinterpret_cast<uintptr_t>(dst) & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(dst) = w;
+      } else {
+        for (int i = 0; i < 4 && q + i < ncols; ++i) dst[i] = (int8_t)(w >> (8 * i));
       }
     }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
                                                     int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
                                                     uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift) {
   hdc_tile(x, base, hv, Q, F, D, stride, ncols, qbits, qshift, blockIdx.x * HT, blockIdx.y * HT);
 }
 
 // Many requests in one launch: workgroup w encodes tile tiles[w] of request reqs[tile.req].
-__global__ __launch_bounds__(256) void k_hdc_encode_list(const HdcReq* __restrict__ reqs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_hdc_encode_list(const HdcReq* __restrict__ reqs,
                                                          const HdcTile* __restrict__ tiles) {
   const HdcTile t = tiles[blockIdx.x];
   const HdcReq r = reqs[t.req];
@@ -152,7 +216,7 @@ hipError_t launch_hdc_encode(const uint8_t* x, const int8_t* base, int8_t* hv, u
                              uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st, uint32_t ncols) {
   if (ncols == 0 || ncols > stride) ncols = stride;
   if (ncols == 0) return hipSuccess;
-  dim3 grid(D / ephdc_dev::HT, (ncols + ephdc_dev::HT - 1) / ephdc_dev::HT);
+  dim3 grid((D + ephdc_dev::HT - 1) / ephdc_dev::HT, (ncols + ephdc_dev::HT - 1) / ephdc_dev::HT);
   ephdc_dev::k_hdc_encode<<<grid, dim3(256), 0, st>>>(x, base, hv, Q, F, D, stride, ncols, qbits, qshift);
   return hipGetLastError();
 }

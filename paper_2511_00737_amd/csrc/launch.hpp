@@ -92,7 +92,7 @@ struct ListArgs {
 };
 
 // HDC encoding of many requests in one launch: per request its operands and layout, per
-// 64 x 64 output tile its request and origin.
+// 128 x 128 output tile its request and origin.
 struct HdcReq {
   const uint8_t* x;
   const int8_t* base;

@@ -395,6 +395,8 @@ ephdc_status ephdc_server_submit(ephdc_server* sv, uint32_t tenant, const uint8_
   const ParamSet& P = t.s->P;
   if (Q == 0 || Q > t.s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, the tenant session's max_Q]");
   if (P.F % 16 != 0 || P.D % 64 != 0) return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F % 16 == 0 and D % 64 == 0");
+  if ((uint64_t)P.F * P.D >= (1ull << 31) || (uint64_t)Q * P.F >= (1ull << 31))
+    return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F * D and Q * F below 2^31");
   if ((uintptr_t)d_x & 15) return fail(EPHDC_ERR_ARG, "x must be 16-byte aligned");
   Req r;
   r.ticket = sv->next_ticket++;

@@ -366,6 +366,8 @@ ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const in
   const ParamSet& P = s->P;
   if (Q == 0 || Q > s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, max_Q]");
   if (P.F % 16 != 0 || P.D % 64 != 0) return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F % 16 == 0 and D % 64 == 0");
+  if ((uint64_t)P.F * P.D >= (1ull << 31) || (uint64_t)Q * P.F >= (1ull << 31))
+    return fail(EPHDC_ERR_UNSUPPORTED, "encoding needs F * D and Q * F below 2^31");
   if (((uintptr_t)d_x & 15) || ((uintptr_t)d_base & 3)) return fail(EPHDC_ERR_ARG, "x must be 16-byte and base 4-byte aligned");
   if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
   hipStream_t hs = (hipStream_t)stream;
