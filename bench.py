@@ -61,6 +61,7 @@ WORKLOADS = {
 # x 2.4 GHz = 39.3 T 32-bit multiplies/s; a Shoup modular multiplication needs 3 of them.
 MUL32_PEAK = 256 * 64 * 2.4e9
 MODMUL_PEAK = MUL32_PEAK / 3
+INT8_PEAK = 5.0e15  # dense int8 MFMA operations/s of MI355X
 
 
 def transform_mults(N: int) -> int:
@@ -81,6 +82,7 @@ def algorithmic_modmuls(kernel: str, N: int, L: int, G: int, M: int) -> float:
 # The sources that define each profiled kernel's code (its HIP file and the headers it uses).
 KERNEL_SOURCES = {k: ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", "launch.hpp")
                   for k in ("k_mac", "k_encode_pt", "k_score", "k_finish")}
+KERNEL_SOURCES["k_hdc_encode"] = ("kernels_hdc.hip", "launch.hpp")
 
 
 def kernel_source_digest(kernel: str = "k_mac") -> str:
@@ -568,6 +570,15 @@ def main() -> int:
                                         "achieved": round(e_ops / (e_ms * 1e-3) / 1e12, 4),
                                         "frac": round(e_ops / (e_ms * 1e-3) / MODMUL_PEAK, 4),
                                         "avg_launch_ms": round(e_ms, 4)}
+    if prof["encode"][1]:
+        # the HDC projection: 2*F*D int8 operations per query, against the dense int8 MFMA peak
+        h_ms = prof["encode"][0] / prof["encode"][1]
+        h_ops = 2.0 * Q * w["F"] * w["D"]
+        result["roofline_hdc"] = {"bound": "mfma", "kernel": "k_hdc_encode",
+                                  "achieved": round(h_ops / (h_ms * 1e-3) / 1e12, 2), "peak": INT8_PEAK / 1e12,
+                                  "unit": "TOP/s", "frac": round(h_ops / (h_ms * 1e-3) / INT8_PEAK, 4),
+                                  "traffic": recorded_traffic("k_hdc_encode", args.workload),
+                                  "avg_launch_ms": round(h_ms, 4)}
     sess.close()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m or w.get("cpu_sample_m", 256))
