@@ -87,7 +87,7 @@ struct Shape {
   static constexpr int NFULL = LOGN / LE;
   static constexpr int REM = LOGN % LE;
   static constexpr int NPASS = NFULL + (REM ? 1 : 0);
-  static constexpr int PADN = N + (N >> 4);  // LDS words per exchange buffer (padding <= 1/16)
+  static constexpr int PADN = N + T;  // LDS words per exchange buffer: 64*E + 64 per wave
   static constexpr int s0(int p) { return p * LE; }
   static constexpr int k(int p) { return p < NFULL ? LE : REM; }
 };
@@ -142,64 +142,94 @@ __host__ __device__ constexpr bool wave_local() {
   }
 }
 
-// LDS padding of an exchange: position x is stored at x + c*(x >> a).  Shifts distribute
-// over the disjoint tid / register parts of x, so the padded address is still a per-thread
-// base plus a compile-time offset.  Each exchange takes the (a, c) whose write layout and
-// read layout have the fewest bank conflicts (simulated at compile time for 32 banks per
-// half-wave and 64 banks per wave), with overhead c/2^a at most 1/16.
+// LDS placement of an exchange.  A wave's block of positions is [64E*w, 64E*(w+1)), so
+// position x splits into the wave part x >> B and the bits below B = 6 + LE.  Position x is
+// stored at R*(x >> B) + sum over b < B of bit_b(x) * w[b], with R = 64E + 64 words per
+// wave and per-bit weights w[b] chosen for the exchange.  The map is additive over bits,
+// so it distributes over the disjoint tid / register parts of a position: the address is a
+// per-thread base plus a compile-time offset.
+//
+// The LDS of gfx950 serves a wave's 32-bit accesses from 64 banks of 4 bytes.  For one
+// register, the 64 lanes of a layout vary exactly six position bits (the lane bits), and
+// the lanes hit 64 distinct banks when the six weights of those bits have distinct 2-adic
+// valuations 0..5 mod 64.  The weights are found at compile time by a depth-first search
+// over bits in increasing order: each weight is the smallest number above the sum of the
+// previous ones (which keeps the map one-to-one) whose valuation is still free in the
+// write layout and in the read layout it belongs to, and the sum must stay below R.  Every
+// wave's image then lies in its own range [R*w, R*(w+1)) under every exchange's
+// placement, which wave-local exchanges (no workgroup barrier) rely on.
+constexpr int kMaxPadBits = 12;
 struct Pad {
-  int a, c;
+  int w[kMaxPadBits];
 };
-
-__host__ __device__ constexpr int padx(Pad p, int x) { return x + p.c * (x >> p.a); }
-
-// Sum over registers of the worst bank multiplicity of one wave's access.
+template <int LOGN, int LE>
+__host__ __device__ constexpr int padx(const Pad& p, int x) {
+  constexpr int B = 6 + LE, R = 64 * (1 << LE) + 64;
+  int a = R * (x >> B);
+  for (int b = 0; b < B; ++b) a += ((x >> b) & 1) * p.w[b];
+  return a;
+}
+// The position bits that the 64 lanes of a wave vary in the layout of pass P.
 template <int LOGN, int LE, int P>
-__host__ __device__ constexpr int layout_conflicts(Pad p) {
+__host__ __device__ constexpr int lane_bits() {
+  int m = 0;
+  for (int l = 0; l < 6; ++l) m |= tid_part<LOGN, LE, P>(1 << l);
+  return m;
+}
+__host__ __device__ constexpr bool pad_search(int B, int R, int inW, int inR, int b, int pre, int usedW, int usedR,
+                                              Pad& p) {
+  if (b == B) return pre < R;
+  const int lo = (1 << b) > pre + 1 ? (1 << b) : pre + 1;
+  const bool bw = (inW >> b) & 1, br = (inR >> b) & 1;
+  if (!bw && !br) {
+    p.w[b] = lo;
+    return pad_search(B, R, inW, inR, b + 1, pre + lo, usedW, usedR, p);
+  }
+  int tried = 0;
+  for (int n = 0; n < 6; ++n) {  // free valuations, smallest resulting weight first
+    int bv = -1, bwt = 0;
+    for (int v = 0; v < 6; ++v) {
+      if (((tried >> v) & 1) || (bw && ((usedW >> v) & 1)) || (br && ((usedR >> v) & 1))) continue;
+      int m = (lo + (1 << v) - 1) >> v;
+      if (!(m & 1)) ++m;
+      if (bv < 0 || (m << v) < bwt) {
+        bv = v;
+        bwt = m << v;
+      }
+    }
+    if (bv < 0) break;
+    tried |= 1 << bv;
+    p.w[b] = bwt;
+    if (pad_search(B, R, inW, inR, b + 1, pre + bwt, bw ? usedW | (1 << bv) : usedW, br ? usedR | (1 << bv) : usedR,
+                   p))
+      return true;
+  }
+  return false;
+}
+template <int LOGN, int LE, int PF, int PT>
+__host__ __device__ constexpr Pad exchange_pad() {
+  Pad p{};
+  constexpr int B = 6 + LE, R = 64 * (1 << LE) + 64;
+  static_assert(B <= kMaxPadBits, "LDS placement has room for 12 position bits");
+  const bool ok = pad_search(B, R, lane_bits<LOGN, LE, PF>(), lane_bits<LOGN, LE, PT>(), 0, 0, 0, 0, p);
+  if (!ok) p.w[0] = -1;  // caught by the static_assert in exchange()
+  return p;
+}
+// Bank-conflict excess of the layout of pass P under placement p: for each register, the
+// number of lanes beyond one per bank (64 banks of 4 bytes, one wave).
+template <int LOGN, int LE, int P>
+__host__ __device__ constexpr int layout_conflicts(const Pad& p) {
   using S = Shape<LOGN, LE>;
   int total = 0;
   for (int i = 0; i < S::E; ++i) {
-    int c32a[32] = {}, c32b[32] = {}, c64[64] = {};
-    int worst32 = 0, worst64 = 0;
+    int c64[64] = {};
     for (int lane = 0; lane < 64; ++lane) {
-      const int addr = padx(p, tid_part<LOGN, LE, P>(lane) | i_part<LOGN, LE, P>(i));
-      int& h = lane < 32 ? c32a[addr & 31] : c32b[addr & 31];
-      ++h;
-      if (h > worst32) worst32 = h;
-      if (++c64[addr & 63] > worst64) worst64 = c64[addr & 63];
+      const int addr = padx<LOGN, LE>(p, tid_part<LOGN, LE, P>(lane) | i_part<LOGN, LE, P>(i));
+      if (++c64[addr & 63] > 1) ++total;
     }
-    total += worst32 + worst64;
   }
   return total;
 }
-
-//
-// Wave-local exchanges run without a workgroup barrier, so the LDS range a wave writes
-// must never overlap the range another wave may still be reading under a different
-// exchange's padding.  They therefore only use paddings of overhead exactly 1/16
-// ((a, c) = (4, 1) or (5, 2)): both map wave w's positions [64*E*w, 64*E*(w+1)) into the
-// same private range [68*E*w, 68*E*(w+1)).
-template <int LOGN, int LE, int PF, int PT>
-__host__ __device__ constexpr Pad exchange_pad() {
-  constexpr bool local = wave_local<LOGN, LE, PF>() && wave_local<LOGN, LE, PT>();
-  Pad best{4, 1};
-  int best_cost = 1 << 30, best_over = 1 << 30;
-  for (int a = 4; a <= 10; ++a)
-    for (int c = 1; c <= 2; ++c) {
-      if ((c << 4) > (1 << a)) continue;  // overhead c/2^a must stay <= 1/16
-      if (local && (c << 4) != (1 << a)) continue;
-      const Pad p{a, c};
-      const int cost = layout_conflicts<LOGN, LE, PF>(p) + layout_conflicts<LOGN, LE, PT>(p);
-      const int over = (c << 10) >> a;
-      if (cost < best_cost || (cost == best_cost && over < best_over)) {
-        best = p;
-        best_cost = cost;
-        best_over = over;
-      }
-    }
-  return best;
-}
-
 // Twiddles of pass P for this thread: for stage u of the pass, group e and sub-block v, the
 // entry table[2^s + block] of the lower butterfly element, s = s0 + u.  Loaded in one go so
 // that the loads can be issued ahead of the exchange that precedes the pass.
@@ -339,6 +369,9 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
   constexpr int P = S::PADN;
   constexpr bool local = wave_local<LOGN, LE, PF>() && wave_local<LOGN, LE, PT>();
   constexpr Pad pd = exchange_pad<LOGN, LE, PF, PT>();
+  static_assert(pd.w[0] > 0, "no conflict-free LDS placement within 64E + 64 words per wave");
+  static_assert(layout_conflicts<LOGN, LE, PF>(pd) == 0 && layout_conflicts<LOGN, LE, PT>(pd) == 0,
+                "exchange layouts must hit 64 distinct banks per register");
   int off;
   if constexpr (local) {
     off = LdsPlan<LOGN, LE>::three ? 2 * P : P;
@@ -349,14 +382,14 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
     off = 0;
     lds_barrier();  // every wave has finished reading the previous contents
   }
-  uint32_t* wb = ephdc_lds + off + padx(pd, tid_part<LOGN, LE, PF>(tid));
+  uint32_t* wb = ephdc_lds + off + padx<LOGN, LE>(pd, tid_part<LOGN, LE, PF>(tid));
 #pragma unroll
-  for (int i = 0; i < S::E; ++i) wb[padx(pd, i_part<LOGN, LE, PF>(i))] = v[i];
+  for (int i = 0; i < S::E; ++i) wb[padx<LOGN, LE>(pd, i_part<LOGN, LE, PF>(i))] = v[i];
   if constexpr (local) lds_wave_sync();
   else lds_barrier();
-  const uint32_t* rb = ephdc_lds + off + padx(pd, tid_part<LOGN, LE, PT>(tid));
+  const uint32_t* rb = ephdc_lds + off + padx<LOGN, LE>(pd, tid_part<LOGN, LE, PT>(tid));
 #pragma unroll
-  for (int i = 0; i < S::E; ++i) v[i] = rb[padx(pd, i_part<LOGN, LE, PT>(i))];
+  for (int i = 0; i < S::E; ++i) v[i] = rb[padx<LOGN, LE>(pd, i_part<LOGN, LE, PT>(i))];
 }
 
 template <int LOGN, int LE, int P = 0>
