@@ -230,6 +230,27 @@ __host__ __device__ constexpr int layout_conflicts(const Pad& p) {
   }
   return total;
 }
+// LDS plan of one workgroup.  Exchanges between two wave-local layouts stay inside one
+// wave and use the wave's own region of the `local` buffer, with no workgroup barrier.
+// When three buffers (and the scatter table) fit in the 160 KB of LDS, cross-wave
+// exchanges alternate between g[0] and g[1] over all calls: a buffer is rewritten only
+// after the barrier of the following cross-wave exchange has retired every read of its
+// previous contents.  Otherwise they all use g[0] behind an extra leading barrier.
+// Cross-wave and wave-local exchanges never share a buffer.
+template <int LOGN, int LE>
+struct LdsPlan {
+  static constexpr int PADN = Shape<LOGN, LE>::PADN;
+  static constexpr int N = Shape<LOGN, LE>::N;
+  static constexpr bool three = (3 * PADN + N) * 4 <= 160 * 1024;
+  static constexpr int exchange_words = three ? 3 * PADN : 2 * PADN;
+  static constexpr bool table_in_lds = three;
+  static constexpr int words = exchange_words + (table_in_lds ? N : 0);
+};
+
+// The dynamic LDS of every kernel.  Buffers are addressed as this symbol plus an integer
+// offset so that every access compiles to an LDS (ds_*) instruction.
+extern __shared__ uint32_t ephdc_lds[];
+
 // Twiddles of pass P for this thread: for stage u of the pass, group e and sub-block v, the
 // entry table[2^s + block] of the lower butterfly element, s = s0 + u.  Loaded in one go so
 // that the loads can be issued ahead of the exchange that precedes the pass.
@@ -243,7 +264,9 @@ struct Tw {
   W w[COUNT];
 };
 
-template <int LOGN, int LE, int P, class W>
+// TL: the table of this transform sits in LDS after the exchange buffers (staged by the
+// caller); otherwise it is read from global memory.
+template <int LOGN, int LE, int P, class W, bool TL = false>
 __device__ __forceinline__ void load_tw(Tw<LOGN, LE, P, W>& t, int tid, const W* __restrict__ table) {
   using S = Shape<LOGN, LE>;
   using TW = Tw<LOGN, LE, P, W>;
@@ -259,8 +282,14 @@ __device__ __forceinline__ void load_tw(Tw<LOGN, LE, P, W>& t, int tid, const W*
 #pragma unroll
       for (int v = 0; v < (1 << u); ++v) {
         const int i = (e << k) | (v << (k - u));
-        t.w[TW::off(u) + (e << u) + v] =
-            ld_at(table, lane + (uint32_t)(i_part<LOGN, LE, P>(i) >> (LOGN - s)) * (uint32_t)sizeof(W));
+        if constexpr (TL) {
+          static_assert(sizeof(W) == 4 && LdsPlan<LOGN, LE>::table_in_lds, "LDS twiddles need the table slot");
+          t.w[TW::off(u) + (e << u) + v] = ephdc_lds[LdsPlan<LOGN, LE>::exchange_words + lane / 4u +
+                                                      (uint32_t)(i_part<LOGN, LE, P>(i) >> (LOGN - s))];
+        } else {
+          t.w[TW::off(u) + (e << u) + v] =
+              ld_at(table, lane + (uint32_t)(i_part<LOGN, LE, P>(i) >> (LOGN - s)) * (uint32_t)sizeof(W));
+        }
       }
   }
 }
@@ -336,27 +365,6 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // Completion of this wave's own LDS operations (orders a wave-private write -> read).
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// LDS plan of one workgroup.  Exchanges between two wave-local layouts stay inside one
-// wave and use the wave's own region of the `local` buffer, with no workgroup barrier.
-// When three buffers (and the scatter table) fit in the 160 KB of LDS, cross-wave
-// exchanges alternate between g[0] and g[1] over all calls: a buffer is rewritten only
-// after the barrier of the following cross-wave exchange has retired every read of its
-// previous contents.  Otherwise they all use g[0] behind an extra leading barrier.
-// Cross-wave and wave-local exchanges never share a buffer.
-template <int LOGN, int LE>
-struct LdsPlan {
-  static constexpr int PADN = Shape<LOGN, LE>::PADN;
-  static constexpr int N = Shape<LOGN, LE>::N;
-  static constexpr bool three = (3 * PADN + N) * 4 <= 160 * 1024;
-  static constexpr int exchange_words = three ? 3 * PADN : 2 * PADN;
-  static constexpr bool table_in_lds = three;
-  static constexpr int words = exchange_words + (table_in_lds ? N : 0);
-};
-
-// The dynamic LDS of every kernel.  Buffers are addressed as this symbol plus an integer
-// offset so that every access compiles to an LDS (ds_*) instruction.
-extern __shared__ uint32_t ephdc_lds[];
-
 // Which cross-wave buffer the next cross-wave exchange uses (alternates in the
 // three-buffer plan).
 struct LdsBufs {
@@ -392,27 +400,39 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
   for (int i = 0; i < S::E; ++i) v[i] = rb[padx<LOGN, LE>(pd, i_part<LOGN, LE, PT>(i))];
 }
 
-template <int LOGN, int LE, int P = 0>
+template <int LOGN, int LE, int P = 0, bool TL = false>
 __device__ __forceinline__ void ntt_forward_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P, uint32_t>& tw, int tid,
                                                  const uint32_t* __restrict__ table, const PrimeConst& pc,
                                                  LdsBufs& b) {
   fwd_pass<LOGN, LE, P>(v, tw, pc);
   if constexpr (P + 1 < Shape<LOGN, LE>::NPASS) {
     Tw<LOGN, LE, P + 1, uint32_t> nt;
-    load_tw<LOGN, LE, P + 1>(nt, tid, table);  // in flight across the exchange
+    load_tw<LOGN, LE, P + 1, uint32_t, TL>(nt, tid, table);  // in flight across the exchange
     exchange<LOGN, LE, P, P + 1>(v, b, tid);
-    ntt_forward_from<LOGN, LE, P + 1>(v, nt, tid, table, pc, b);
+    ntt_forward_from<LOGN, LE, P + 1, TL>(v, nt, tid, table, pc, b);
   }
 }
 
 // Forward transform: coefficient layout (tid + i*T) -> evaluation layout (tid*E + i); the
 // table holds Montgomery-form twiddles.
-template <int LOGN, int LE>
+template <int LOGN, int LE, bool TL = false>
 __device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, const uint32_t* __restrict__ table,
                                             const PrimeConst& pc, LdsBufs& b) {
   Tw<LOGN, LE, 0, uint32_t> t0;
-  load_tw<LOGN, LE, 0>(t0, tid, table);
-  ntt_forward_from<LOGN, LE, 0>(v, t0, tid, table, pc, b);
+  load_tw<LOGN, LE, 0, uint32_t, TL>(t0, tid, table);
+  ntt_forward_from<LOGN, LE, 0, TL>(v, t0, tid, table, pc, b);
+}
+
+// Copies one transform's twiddle table (N words) into the LDS table slot; the caller
+// brackets it with barriers (no wave may still read the previous table, and every wave
+// must see the new one).
+template <int LOGN, int LE>
+__device__ __forceinline__ void stage_twiddles(const uint32_t* __restrict__ table, int tid) {
+  using S = Shape<LOGN, LE>;
+  static_assert(LdsPlan<LOGN, LE>::table_in_lds, "LDS twiddles need the table slot");
+  uint32_t* dst = ephdc_lds + LdsPlan<LOGN, LE>::exchange_words;
+#pragma unroll
+  for (int i = 0; i < S::E; ++i) dst[i * S::T + tid] = ld_at(table, (uint32_t)(i * S::T + tid) * 4u);
 }
 
 template <int LOGN, int LE, bool SCALE, int P, bool TINY = false>

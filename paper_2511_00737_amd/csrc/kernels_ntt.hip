@@ -256,7 +256,7 @@ __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* s
 // accumulate set the item adds to the sums already in its slot.  With PF, the next
 // plaintext and each limb's model values are requested ahead of the transform that
 // precedes their use (more registers: used where the register budget allows it).
-template <int LOGN, int LE, int LG, bool PF>
+template <int LOGN, int LE, int LG, bool PF, bool TL = false>
 __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
@@ -311,7 +311,7 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
-      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      ntt_forward<LOGN, LE, TL>(p, tid, fwd_tw + (size_t)l * N, pc, b);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -330,7 +330,7 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
   store_acc<LOGN, LE, LG>(acc, it, pcs, tid);
 }
 
-template <int LOGN, int LE, int LG, bool PF>
+template <int LOGN, int LE, int LG, bool PF, bool TL = false>
 __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
@@ -392,7 +392,7 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
       uint32_t p[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
-      ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      ntt_forward<LOGN, LE, TL>(p, tid, fwd_tw + (size_t)l * N, pc, b);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -429,14 +429,14 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
 
 // MAC alone: 64-bit lazy sums where 8 values per thread leave the registers for them,
 // 32-bit sums of Montgomery products otherwise.
-template <int LOGN, int LE, int LG, bool PF>
+template <int LOGN, int LE, int LG, bool PF, bool TL = false>
 __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
   if constexpr (LE <= 3)
-    mac_item64<LOGN, LE, LG, PF>(it, pt, accumulate, fwd_tw, pcs, tid, b);
+    mac_item64<LOGN, LE, LG, PF, TL>(it, pt, accumulate, fwd_tw, pcs, tid, b);
   else
-    mac_item32<LOGN, LE, LG, PF>(it, pt, accumulate, fwd_tw, pcs, tid, b);
+    mac_item32<LOGN, LE, LG, PF, TL>(it, pt, accumulate, fwd_tw, pcs, tid, b);
 }
 
 // ------------------------------------------------------------------ single-request kernels
@@ -490,6 +490,13 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
 }
 
 // Split path, MAC: work item (split, g, limb group) over the split's range of the chunk.
+// A MAC item of one limb keeps that limb's forward twiddles in the LDS table slot (unused
+// by the MAC kernels) for all of its plaintexts.
+template <int LOGN, int LE, int LG>
+constexpr bool mac_lds_twiddles() {
+  return LG == 1 && LdsPlan<LOGN, LE>::table_in_lds;
+}
+
 template <int LOGN, int LE, int LG, bool PF>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
   const uint32_t w = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
@@ -499,7 +506,13 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
   uint32_t g, split;
   const MacItem it = single_item<LOGN, LG>(a, w, g, split);
   const int32_t* pt = a.pt + ((size_t)g * a.m_len + (it.m0 - a.m_base)) * ((size_t)1 << LOGN);
-  mac_item<LOGN, LE, LG, PF>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
+  if constexpr (mac_lds_twiddles<LOGN, LE, LG>()) {
+    stage_twiddles<LOGN, LE>(a.fwd_tw + (size_t)it.l0 * ((size_t)1 << LOGN), tid);
+    lds_barrier();
+    mac_item<LOGN, LE, LG, PF, true>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
+  } else {
+    mac_item<LOGN, LE, LG, PF>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
+  }
 }
 
 // Prefetching fits the register budget except for the 1024-thread shape of N = 16384.
@@ -564,13 +577,24 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
   LdsBufs b{0};
   const int tid = threadIdx.x;
   const uint32_t nd = a.xm.slots();
+  uint32_t staged_l = 0xFFFFFFFFu;  // limb whose twiddles the LDS table slot holds
   for (uint32_t d = blockIdx.x; d < nd; d += gridDim.x) {
     const uint32_t w = a.xm.item(d);
     if (w == 0xFFFFFFFFu) continue;
     const Segment sg = a.segs[w / a.NLG];
     const ReqDesc r = a.reqs[sg.req];
     const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG};
-    mac_item<LOGN, LE, LG, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+    if constexpr (mac_lds_twiddles<LOGN, LE, LG>()) {
+      if (it.l0 != staged_l) {  // every request of a list shares the moduli and their tables
+        lds_barrier();          // every wave is done with the previous limb's table
+        stage_twiddles<LOGN, LE>(a.fwd_tw + (size_t)it.l0 * S::N, tid);
+        lds_barrier();
+        staged_l = it.l0;
+      }
+      mac_item<LOGN, LE, LG, PF, true>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+    } else {
+      mac_item<LOGN, LE, LG, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+    }
   }
 }
 
