@@ -435,28 +435,28 @@ __device__ __forceinline__ void stage_twiddles(const uint32_t* __restrict__ tabl
   for (int i = 0; i < S::E; ++i) dst[i * S::T + tid] = ld_at(table, (uint32_t)(i * S::T + tid) * 4u);
 }
 
-template <int LOGN, int LE, bool SCALE, int P, bool TINY = false>
+template <int LOGN, int LE, bool SCALE, int P, bool TINY = false, bool TL = false>
 __device__ __forceinline__ void ntt_inverse_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P, uint32_t>& tw, int tid,
                                                  const uint32_t* __restrict__ table, const PrimeConst& pc,
                                                  LdsBufs& b) {
   inv_pass<LOGN, LE, P, SCALE, TINY>(v, tw, pc);
   if constexpr (P > 0) {
     Tw<LOGN, LE, P - 1, uint32_t> nt;
-    load_tw<LOGN, LE, P - 1>(nt, tid, table);
+    load_tw<LOGN, LE, P - 1, uint32_t, TL>(nt, tid, table);
     exchange<LOGN, LE, P, P - 1>(v, b, tid);
-    ntt_inverse_from<LOGN, LE, SCALE, P - 1, TINY>(v, nt, tid, table, pc, b);
+    ntt_inverse_from<LOGN, LE, SCALE, P - 1, TINY, TL>(v, nt, tid, table, pc, b);
   }
 }
 
 // Inverse transform: evaluation layout (tid*E + i) -> coefficient layout (tid + i*T).
 // TINY: lazy form for moduli below 2^17 (see inv_pass); inputs must be in [0, m).
-template <int LOGN, int LE, bool SCALE, bool TINY = false>
+template <int LOGN, int LE, bool SCALE, bool TINY = false, bool TL = false>
 __device__ __forceinline__ void ntt_inverse(uint32_t (&v)[1 << LE], int tid, const uint32_t* __restrict__ table,
                                             const PrimeConst& pc, LdsBufs& b) {
   constexpr int PL = Shape<LOGN, LE>::NPASS - 1;
   Tw<LOGN, LE, PL, uint32_t> t0;
-  load_tw<LOGN, LE, PL>(t0, tid, table);
-  ntt_inverse_from<LOGN, LE, SCALE, PL, TINY>(v, t0, tid, table, pc, b);
+  load_tw<LOGN, LE, PL, uint32_t, TL>(t0, tid, table);
+  ntt_inverse_from<LOGN, LE, SCALE, PL, TINY, TL>(v, t0, tid, table, pc, b);
 }
 
 

@@ -124,16 +124,16 @@ using TSide = TSideArgs;
 // tid*E + i (the slot feeding each position comes from the scatter table), then the
 // inverse transform mod t, lazy (t < 2^17) and scaled by N^-1 in its last stage:
 // mu in [0, t), coefficient layout tid + i*T.
-template <int LOGN, int LE>
+template <int LOGN, int LE, bool TL = false>
 __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const QuerySrc& q,
-                                             const uint32_t* scatter, const TSide& ts, uint32_t m,
+                                             const uint32_t (&ent)[1 << LE], const TSide& ts, uint32_t m,
                                              int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   const uint32_t t = ts.pct.m;
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
     uint32_t val = 0;
-    const uint32_t e = table_entry<LOGN, LE>(scatter, tid, i);
+    const uint32_t e = ent[i];
     if (e != 0xFFFFFFFFu) {
       const uint32_t j = m * q.r + (e >> 16);
       if (j < q.D) {
@@ -143,9 +143,17 @@ __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const Query
     }
     v[i] = val;
   }
-  ntt_inverse<LOGN, LE, true, true>(v, tid, ts.inv_t, ts.pct, b);
+  ntt_inverse<LOGN, LE, true, true, TL>(v, tid, ts.inv_t, ts.pct, b);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
+}
+
+// This thread's scatter-table entries (from the staged LDS copy when there is one).
+template <int LOGN, int LE>
+__device__ __forceinline__ void table_entries(uint32_t (&ent)[1 << LE], const uint32_t* __restrict__ scatter,
+                                              int tid) {
+#pragma unroll
+  for (int i = 0; i < (1 << LE); ++i) ent[i] = table_entry<LOGN, LE>(scatter, tid, i);
 }
 
 // Centred lift of mu in [0, t) into Z_m: mu if mu <= t/2, else m - (t - mu).
@@ -203,8 +211,9 @@ __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q,
   zero_acc(acc);
   const uint32_t t = ts.pct.m;
   for (uint32_t m = it.m0; m < it.m1; ++m) {
-    uint32_t mu[E];
-    encode_query<LOGN, LE>(mu, q, scatter, ts, m, tid, b);
+    uint32_t mu[E], ent[E];
+    table_entries<LOGN, LE>(ent, scatter, tid);
+    encode_query<LOGN, LE>(mu, q, ent, ts, m, tid, b);
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
       const uint32_t l = it.l0 + li;
@@ -236,15 +245,23 @@ __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q,
 // (int32 in (-t/2, t/2]), coefficient order, at dst + (m - m0) * N.  The table and output
 // pointers are deliberately not __restrict__: that would let the compiler keep a global
 // scatter table in registers across the loop and spill at 1024 threads.
-template <int LOGN, int LE>
+// TL: the scatter entries stay in registers for the whole item and the LDS table slot
+// holds the inverse twiddles mod t (staged by the caller) instead of the scatter table.
+template <int LOGN, int LE, bool TL = false>
 __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* scatter, const TSide& ts,
                                             uint32_t m0, uint32_t m1, int32_t* dst, int tid,
                                             LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   const uint32_t t = ts.pct.m;
+  uint32_t ent[S::E];
+  if constexpr (TL) {
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) ent[i] = ld_at(scatter, (uint32_t)(tid * S::E + i) * 4u);
+  }
   for (uint32_t m = m0; m < m1; ++m) {
     uint32_t mu[S::E];
-    encode_query<LOGN, LE>(mu, q, scatter, ts, m, tid, b);
+    if constexpr (!TL) table_entries<LOGN, LE>(ent, scatter, tid);
+    encode_query<LOGN, LE, TL>(mu, q, ent, ts, m, tid, b);
     int32_t* d = dst + (size_t)(m - m0) * S::N;
 #pragma unroll
     for (int i = 0; i < S::E; ++i) d[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
@@ -481,12 +498,17 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_pt(ScoreArgs a) {
   using S = Shape<LOGN, LE>;
   LdsBufs b{0};
   const int tid = threadIdx.x;
-  stage_table<LOGN, LE>(a.scatter, tid);
   const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
   const uint32_t m0 = a.m_base + split * a.mchunk;
   const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
   int32_t* dst = a.pt + ((size_t)g * a.m_len + (m0 - a.m_base)) * S::N;
-  encode_item<LOGN, LE>(query_src(a, g), a.scatter, tside(a), m0, m1, dst, tid, b);
+  if constexpr (LdsPlan<LOGN, LE>::table_in_lds) {
+    stage_twiddles<LOGN, LE>(a.inv_t, tid);
+    lds_barrier();
+    encode_item<LOGN, LE, true>(query_src(a, g), a.scatter, tside(a), m0, m1, dst, tid, b);
+  } else {
+    encode_item<LOGN, LE>(query_src(a, g), a.scatter, tside(a), m0, m1, dst, tid, b);
+  }
 }
 
 // Split path, MAC: work item (split, g, limb group) over the split's range of the chunk.
@@ -563,11 +585,20 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_list(ListArgs a) {
   LdsBufs b{0};
   const int tid = threadIdx.x;
   const uint32_t* staged = nullptr;
+  if constexpr (LdsPlan<LOGN, LE>::table_in_lds) {  // one inverse table mod t for every request
+    stage_twiddles<LOGN, LE>(a.ts.inv_t, tid);
+    lds_barrier();
+  }
   for (uint32_t w = blockIdx.x; w < a.nseg; w += gridDim.x) {
     const Segment sg = a.segs[w];
     const ReqDesc r = a.reqs[sg.req];
-    restage<LOGN, LE>(r.scatter, staged, tid);
-    encode_item<LOGN, LE>(query_src(r, sg.g), r.scatter, a.ts, sg.m0, sg.m1, a.pt + (size_t)sg.pt * S::N, tid, b);
+    int32_t* dst = a.pt + (size_t)sg.pt * S::N;
+    if constexpr (LdsPlan<LOGN, LE>::table_in_lds) {
+      encode_item<LOGN, LE, true>(query_src(r, sg.g), r.scatter, a.ts, sg.m0, sg.m1, dst, tid, b);
+    } else {
+      restage<LOGN, LE>(r.scatter, staged, tid);
+      encode_item<LOGN, LE>(query_src(r, sg.g), r.scatter, a.ts, sg.m0, sg.m1, dst, tid, b);
+    }
   }
 }
 
@@ -672,8 +703,9 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_debug_plaintext(ScoreArgs
   LdsBufs b{0};
   const int tid = threadIdx.x;
   stage_table<LOGN, LE>(a.scatter, tid);
-  uint32_t mu[S::E];
-  encode_query<LOGN, LE>(mu, query_src(a, g), a.scatter, tside(a), m, tid, b);
+  uint32_t mu[S::E], ent[S::E];
+  table_entries<LOGN, LE>(ent, a.scatter, tid);
+  encode_query<LOGN, LE>(mu, query_src(a, g), ent, tside(a), m, tid, b);
   for (uint32_t l = 0; l < a.L; ++l) {
     const uint32_t qm = a.pcs[l].m;
 #pragma unroll
