@@ -264,12 +264,13 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   s->max_Q = max_Q;
   (void)hipGetDevice(&s->device);
   // default schedule (measured on MI355X at N = 8192, L = 4, 4096 queries): split path,
-  // 8 values per thread, one limb per MAC work item, 512 workgroups
+  // 8 values per thread, one limb per MAC work item; one MAC workgroup per compute unit
+  // (256) from N = 8192 up, whose transform kernels hold one workgroup per CU, 512 below
   s->split = true;
   s->le = P.logn == 13 ? 3 : 0;
   s->lg = 1;
   s->nlg = P.L;
-  s->target_blocks = 512;
+  s->target_blocks = P.logn >= 13 ? 256 : 512;
 
   const uint32_t N = P.N, nm = P.nmod();
   std::vector<uint32_t> fwd((size_t)nm * N), inv((size_t)nm * N), invt(N);
