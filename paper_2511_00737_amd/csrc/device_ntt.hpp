@@ -297,7 +297,8 @@ __device__ __forceinline__ void load_tw(Tw<LOGN, LE, P, W>& t, int tid, const W*
 // Forward pass P: Cooley-Tukey butterflies, inputs and outputs in [0, 4m).  Twiddles are
 // in Montgomery form (w * 2^32 mod m), so one table word per twiddle and the product
 // Y * w mod m in [0, 2m) takes two 64-bit multiply-adds and one multiply.
-template <int LOGN, int LE, int P>
+// IN2M: the pass's inputs are already below 2m (the first stage needs no correction).
+template <int LOGN, int LE, int P, bool IN2M = false>
 __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, LE, P, uint32_t>& t,
                                          const PrimeConst& pc) {
   using S = Shape<LOGN, LE>;
@@ -312,7 +313,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&v)[1 << LE], const Tw<LOGN, 
       if (i & h) continue;
       const int e = i >> k, vb = (i & ((1 << k) - 1)) >> (k - u);
       const uint32_t w = t.w[TW::off(u) + (e << u) + vb];
-      const uint32_t X = csub(v[i], m2);
+      const uint32_t X = (IN2M && u == 0) ? v[i] : csub(v[i], m2);
       const uint32_t T = mont_mul(v[i + h], w, m, pc.mneg_inv);  // Y < 4m, w < m
       v[i] = X + T;
       v[i + h] = X - T + m2;
@@ -400,11 +401,11 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
   for (int i = 0; i < S::E; ++i) v[i] = rb[padx<LOGN, LE>(pd, i_part<LOGN, LE, PT>(i))];
 }
 
-template <int LOGN, int LE, int P = 0, bool TL = false>
+template <int LOGN, int LE, int P = 0, bool TL = false, bool IN2M = false>
 __device__ __forceinline__ void ntt_forward_from(uint32_t (&v)[1 << LE], Tw<LOGN, LE, P, uint32_t>& tw, int tid,
                                                  const uint32_t* __restrict__ table, const PrimeConst& pc,
                                                  LdsBufs& b) {
-  fwd_pass<LOGN, LE, P>(v, tw, pc);
+  fwd_pass<LOGN, LE, P, IN2M && P == 0>(v, tw, pc);
   if constexpr (P + 1 < Shape<LOGN, LE>::NPASS) {
     Tw<LOGN, LE, P + 1, uint32_t> nt;
     load_tw<LOGN, LE, P + 1, uint32_t, TL>(nt, tid, table);  // in flight across the exchange
@@ -415,12 +416,13 @@ __device__ __forceinline__ void ntt_forward_from(uint32_t (&v)[1 << LE], Tw<LOGN
 
 // Forward transform: coefficient layout (tid + i*T) -> evaluation layout (tid*E + i); the
 // table holds Montgomery-form twiddles.
-template <int LOGN, int LE, bool TL = false>
+// IN2M: every input is below 2m (otherwise below 4m).
+template <int LOGN, int LE, bool TL = false, bool IN2M = false>
 __device__ __forceinline__ void ntt_forward(uint32_t (&v)[1 << LE], int tid, const uint32_t* __restrict__ table,
                                             const PrimeConst& pc, LdsBufs& b) {
   Tw<LOGN, LE, 0, uint32_t> t0;
   load_tw<LOGN, LE, 0, uint32_t, TL>(t0, tid, table);
-  ntt_forward_from<LOGN, LE, 0, TL>(v, t0, tid, table, pc, b);
+  ntt_forward_from<LOGN, LE, 0, TL, IN2M>(v, t0, tid, table, pc, b);
 }
 
 // Copies one transform's twiddle table (N words) into the LDS table slot; the caller

@@ -327,8 +327,8 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
       }
       uint32_t p[E];
 #pragma unroll
-      for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
-      ntt_forward<LOGN, LE, TL>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      for (int i = 0; i < E; ++i) p[i] = pc.m + (uint32_t)cur[i];  // |cur| <= t/2: in [0, 2m), = cur mod m
+      ntt_forward<LOGN, LE, TL, true>(p, tid, fwd_tw + (size_t)l * N, pc, b);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -408,8 +408,8 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
       }
       uint32_t p[E];
 #pragma unroll
-      for (int i = 0; i < E; ++i) p[i] = cur[i] < 0 ? pc.m + (uint32_t)cur[i] : (uint32_t)cur[i];
-      ntt_forward<LOGN, LE, TL>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      for (int i = 0; i < E; ++i) p[i] = pc.m + (uint32_t)cur[i];  // |cur| <= t/2: in [0, 2m), = cur mod m
+      ntt_forward<LOGN, LE, TL, true>(p, tid, fwd_tw + (size_t)l * N, pc, b);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
