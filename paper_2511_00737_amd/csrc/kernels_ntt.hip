@@ -124,7 +124,7 @@ using TSide = TSideArgs;
 // tid*E + i (the slot feeding each position comes from the scatter table), then the
 // inverse transform mod t, lazy (t < 2^17) and scaled by N^-1 in its last stage:
 // mu in [0, t), coefficient layout tid + i*T.
-template <int LOGN, int LE, bool TL = false>
+template <int LOGN, int LE>
 __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const QuerySrc& q,
                                              const uint32_t (&ent)[1 << LE], const TSide& ts, uint32_t m,
                                              int tid, LdsBufs& b) {
@@ -143,7 +143,7 @@ __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const Query
     }
     v[i] = val;
   }
-  ntt_inverse<LOGN, LE, true, true, TL>(v, tid, ts.inv_t, ts.pct, b);
+  ntt_inverse<LOGN, LE, true, true>(v, tid, ts.inv_t, ts.pct, b);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
 }
@@ -253,18 +253,46 @@ __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* s
                                             LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   const uint32_t t = ts.pct.m;
-  uint32_t ent[S::E];
   if constexpr (TL) {
+    // Per position, from the scatter entry: the byte offset of its hv entry inside the
+    // group's block at m = 0 and its dimension offset u (all ones for an unused slot).
+    // Every plaintext then takes one uniform base and bound and no branch per value.
+    uint32_t off[S::E], du[S::E];
 #pragma unroll
-    for (int i = 0; i < S::E; ++i) ent[i] = ld_at(scatter, (uint32_t)(tid * S::E + i) * 4u);
-  }
-  for (uint32_t m = m0; m < m1; ++m) {
-    uint32_t mu[S::E];
-    if constexpr (!TL) table_entries<LOGN, LE>(ent, scatter, tid);
-    encode_query<LOGN, LE, TL>(mu, q, ent, ts, m, tid, b);
-    int32_t* d = dst + (size_t)(m - m0) * S::N;
+    for (int i = 0; i < S::E; ++i) {
+      const uint32_t e = ld_at(scatter, (uint32_t)(tid * S::E + i) * 4u);
+      du[i] = e == 0xFFFFFFFFu ? 0xFFFFFFFFu : e >> 16;
+      off[i] = e == 0xFFFFFFFFu ? 0u : (e >> 16) * q.hv_stride + (e & 0xFFFFu);
+    }
+    for (uint32_t m = m0; m < m1; ++m) {
+      const uint32_t base = m * q.r * q.hv_stride, lim = q.D - m * q.r;  // m * r < D
+      uint32_t mu[S::E];
 #pragma unroll
-    for (int i = 0; i < S::E; ++i) d[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
+      for (int i = 0; i < S::E; ++i) {
+        const bool ok = du[i] < lim;  // dimension m * r + u exists (and the slot is used)
+        const int h = ld_at(q.hvg, ok ? base + off[i] : 0u);
+        const uint32_t val = (uint32_t)h + (t & (uint32_t)(h >> 31));  // h mod t
+        mu[i] = ok ? val : 0u;
+      }
+      ntt_inverse<LOGN, LE, true, true, true>(mu, tid, ts.inv_t, ts.pct, b);
+      int32_t* d = dst + (size_t)(m - m0) * S::N;
+#pragma unroll
+      for (int i = 0; i < S::E; ++i) {
+        const uint32_t c = csub(mu[i], t);
+        d[tid + i * S::T] = c > (t >> 1) ? (int32_t)c - (int32_t)t : (int32_t)c;
+      }
+    }
+  } else {
+    uint32_t ent[S::E];
+    for (uint32_t m = m0; m < m1; ++m) {
+      uint32_t mu[S::E];
+      table_entries<LOGN, LE>(ent, scatter, tid);
+      encode_query<LOGN, LE>(mu, q, ent, ts, m, tid, b);
+      int32_t* d = dst + (size_t)(m - m0) * S::N;
+#pragma unroll
+      for (int i = 0; i < S::E; ++i)
+        d[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
+    }
   }
 }
 
