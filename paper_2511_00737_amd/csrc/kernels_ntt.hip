@@ -120,30 +120,40 @@ struct QuerySrc {
 // Constants of the plaintext side (mod t).
 using TSide = TSideArgs;
 
-// Slot values of query plaintext (g, m) at this thread's evaluation-side positions
-// tid*E + i (the slot feeding each position comes from the scatter table), then the
-// inverse transform mod t, lazy (t < 2^17) and scaled by N^-1 in its last stage:
-// mu in [0, t), coefficient layout tid + i*T.
+// Per position, from its scatter-table entry: the dimension offset u of the slot feeding it
+// (all ones for an unused slot) and the byte offset of that slot's hv entry inside the
+// group's block at m = 0.
 template <int LOGN, int LE>
+__device__ __forceinline__ void scatter_offsets(uint32_t (&du)[1 << LE], uint32_t (&off)[1 << LE],
+                                                const uint32_t (&ent)[1 << LE], const QuerySrc& q) {
+#pragma unroll
+  for (int i = 0; i < (1 << LE); ++i) {
+    const uint32_t e = ent[i];
+    du[i] = e == 0xFFFFFFFFu ? 0xFFFFFFFFu : e >> 16;
+    off[i] = e == 0xFFFFFFFFu ? 0u : (e >> 16) * q.hv_stride + (e & 0xFFFFu);
+  }
+}
+
+// Slot values of query plaintext (g, m) at this thread's evaluation-side positions
+// tid*E + i (hv entry of dimension m*r + u, or 0 where that dimension or the slot does not
+// exist; one uniform base and bound, no branch per value), then the inverse transform mod
+// t, lazy (t < 2^17) and scaled by N^-1 in its last stage: mu in [0, t), coefficient
+// layout tid + i*T.  TL: the inverse twiddles mod t are in the LDS table slot.
+template <int LOGN, int LE, bool TL = false>
 __device__ __forceinline__ void encode_query(uint32_t (&v)[1 << LE], const QuerySrc& q,
-                                             const uint32_t (&ent)[1 << LE], const TSide& ts, uint32_t m,
-                                             int tid, LdsBufs& b) {
+                                             const uint32_t (&du)[1 << LE], const uint32_t (&off)[1 << LE],
+                                             const TSide& ts, uint32_t m, int tid, LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   const uint32_t t = ts.pct.m;
+  const uint32_t base = m * q.r * q.hv_stride, lim = q.D - m * q.r;  // m * r < D
 #pragma unroll
   for (int i = 0; i < S::E; ++i) {
-    uint32_t val = 0;
-    const uint32_t e = ent[i];
-    if (e != 0xFFFFFFFFu) {
-      const uint32_t j = m * q.r + (e >> 16);
-      if (j < q.D) {
-        const int h = q.hvg[j * q.hv_stride + (e & 0xFFFFu)];
-        val = h < 0 ? t + (uint32_t)h : (uint32_t)h;
-      }
-    }
-    v[i] = val;
+    const bool ok = du[i] < lim;
+    const int h = ld_at(q.hvg, ok ? base + off[i] : 0u);
+    const uint32_t val = (uint32_t)h + (t & (uint32_t)(h >> 31));  // h mod t
+    v[i] = ok ? val : 0u;
   }
-  ntt_inverse<LOGN, LE, true, true>(v, tid, ts.inv_t, ts.pct, b);
+  ntt_inverse<LOGN, LE, true, true, TL>(v, tid, ts.inv_t, ts.pct, b);
 #pragma unroll
   for (int i = 0; i < S::E; ++i) v[i] = csub(v[i], t);
 }
@@ -211,9 +221,10 @@ __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q,
   zero_acc(acc);
   const uint32_t t = ts.pct.m;
   for (uint32_t m = it.m0; m < it.m1; ++m) {
-    uint32_t mu[E], ent[E];
+    uint32_t mu[E], ent[E], du[E], off[E];
     table_entries<LOGN, LE>(ent, scatter, tid);
-    encode_query<LOGN, LE>(mu, q, ent, ts, m, tid, b);
+    scatter_offsets<LOGN, LE>(du, off, ent, q);
+    encode_query<LOGN, LE>(mu, q, du, off, ts, m, tid, b);
 #pragma unroll
     for (int li = 0; li < LG; ++li) {
       const uint32_t l = it.l0 + li;
@@ -245,54 +256,29 @@ __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q,
 // (int32 in (-t/2, t/2]), coefficient order, at dst + (m - m0) * N.  The table and output
 // pointers are deliberately not __restrict__: that would let the compiler keep a global
 // scatter table in registers across the loop and spill at 1024 threads.
-// TL: the scatter entries stay in registers for the whole item and the LDS table slot
-// holds the inverse twiddles mod t (staged by the caller) instead of the scatter table.
+// TL: the LDS table slot holds the inverse twiddles mod t (staged by the caller) instead
+// of the scatter table, whose entries are then read from global memory.
 template <int LOGN, int LE, bool TL = false>
 __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* scatter, const TSide& ts,
                                             uint32_t m0, uint32_t m1, int32_t* dst, int tid,
                                             LdsBufs& b) {
   using S = Shape<LOGN, LE>;
   const uint32_t t = ts.pct.m;
+  // the item's scatter offsets, in registers for all of its plaintexts
+  uint32_t ent[S::E], du[S::E], off[S::E];
   if constexpr (TL) {
-    // Per position, from the scatter entry: the byte offset of its hv entry inside the
-    // group's block at m = 0 and its dimension offset u (all ones for an unused slot).
-    // Every plaintext then takes one uniform base and bound and no branch per value.
-    uint32_t off[S::E], du[S::E];
 #pragma unroll
-    for (int i = 0; i < S::E; ++i) {
-      const uint32_t e = ld_at(scatter, (uint32_t)(tid * S::E + i) * 4u);
-      du[i] = e == 0xFFFFFFFFu ? 0xFFFFFFFFu : e >> 16;
-      off[i] = e == 0xFFFFFFFFu ? 0u : (e >> 16) * q.hv_stride + (e & 0xFFFFu);
-    }
-    for (uint32_t m = m0; m < m1; ++m) {
-      const uint32_t base = m * q.r * q.hv_stride, lim = q.D - m * q.r;  // m * r < D
-      uint32_t mu[S::E];
-#pragma unroll
-      for (int i = 0; i < S::E; ++i) {
-        const bool ok = du[i] < lim;  // dimension m * r + u exists (and the slot is used)
-        const int h = ld_at(q.hvg, ok ? base + off[i] : 0u);
-        const uint32_t val = (uint32_t)h + (t & (uint32_t)(h >> 31));  // h mod t
-        mu[i] = ok ? val : 0u;
-      }
-      ntt_inverse<LOGN, LE, true, true, true>(mu, tid, ts.inv_t, ts.pct, b);
-      int32_t* d = dst + (size_t)(m - m0) * S::N;
-#pragma unroll
-      for (int i = 0; i < S::E; ++i) {
-        const uint32_t c = csub(mu[i], t);
-        d[tid + i * S::T] = c > (t >> 1) ? (int32_t)c - (int32_t)t : (int32_t)c;
-      }
-    }
+    for (int i = 0; i < S::E; ++i) ent[i] = ld_at(scatter, (uint32_t)(tid * S::E + i) * 4u);
   } else {
-    uint32_t ent[S::E];
-    for (uint32_t m = m0; m < m1; ++m) {
-      uint32_t mu[S::E];
-      table_entries<LOGN, LE>(ent, scatter, tid);
-      encode_query<LOGN, LE>(mu, q, ent, ts, m, tid, b);
-      int32_t* d = dst + (size_t)(m - m0) * S::N;
+    table_entries<LOGN, LE>(ent, scatter, tid);
+  }
+  scatter_offsets<LOGN, LE>(du, off, ent, q);
+  for (uint32_t m = m0; m < m1; ++m) {
+    uint32_t mu[S::E];
+    encode_query<LOGN, LE, TL>(mu, q, du, off, ts, m, tid, b);
+    int32_t* d = dst + (size_t)(m - m0) * S::N;
 #pragma unroll
-      for (int i = 0; i < S::E; ++i)
-        d[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
-    }
+    for (int i = 0; i < S::E; ++i) d[tid + i * S::T] = mu[i] > (t >> 1) ? (int32_t)mu[i] - (int32_t)t : (int32_t)mu[i];
   }
 }
 
@@ -731,9 +717,11 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_debug_plaintext(ScoreArgs
   LdsBufs b{0};
   const int tid = threadIdx.x;
   stage_table<LOGN, LE>(a.scatter, tid);
-  uint32_t mu[S::E], ent[S::E];
+  uint32_t mu[S::E], ent[S::E], du[S::E], off[S::E];
+  const QuerySrc q = query_src(a, g);
   table_entries<LOGN, LE>(ent, a.scatter, tid);
-  encode_query<LOGN, LE>(mu, query_src(a, g), ent, tside(a), m, tid, b);
+  scatter_offsets<LOGN, LE>(du, off, ent, q);
+  encode_query<LOGN, LE>(mu, q, du, off, tside(a), m, tid, b);
   for (uint32_t l = 0; l < a.L; ++l) {
     const uint32_t qm = a.pcs[l].m;
 #pragma unroll
