@@ -71,3 +71,52 @@ def test_plain_workload_at_full_size_sampled():
     # every query of every group decrypts to its exact score
     scores, _ = pipeline.decrypt_scores(o, sk.astype(np.int64), cts, Q)
     assert np.array_equal(scores, hdc.scores_mod_t(h, C, o.t))
+
+
+def test_rotation_workload_at_full_size_sampled():
+    """The rotation workload at its full size (N = 16384, 8 limbs + 2 special primes,
+    dnum = 4, r = 8, F = 2304, D = 10240, K = 26, 16384 queries: 211 groups, three
+    rotate-and-sum steps each) in the benchmark's launch configuration: sampled
+    hypervectors against the oracle's encoding, sampled groups decrypted by the oracle,
+    and every query's scores equal to the exact integer scores mod t."""
+    torch = torch_cuda()
+    N, L, alpha, dnum, r, F, D, K, Q = 16384, 8, 2, 4, 8, 2304, 10240, 26, 16384
+    primes = default_primes(N, L + alpha)
+    kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum)
+    o, e = OParams(**kw), ep.Params(**kw)
+    sk, gk = ep.ephdc_keygen(e, 0)
+    C = synth.class_hypervectors(0, K, D)
+    model = ep.ephdc_encrypt_model(e, sk, C, 0)
+    x = synth.blob_images(0, Q)
+    base = synth.base_hypervectors(0, F, D)
+
+    s = ep.Session(e, to_dev(model), to_dev(gk), max_Q=Q)  # the benchmark's default schedule
+    try:
+        stride, G = s.hv_stride(Q), s.num_groups(Q)
+        d_hv = torch.empty((D, stride), dtype=torch.int8, device="cuda")
+        d_out = torch.empty((G, 2, L, N), dtype=torch.int32, device="cuda")
+        ep.ephdc_encode_queries(s, to_dev(x), to_dev(base), Q, d_hv)
+        ep.ephdc_score_encrypted(s, d_hv, Q, d_out)
+        torch.cuda.synchronize()
+        h = d_hv.cpu().numpy()[:, :Q].T.copy()
+        cts = to_host_u32(d_out)
+    finally:
+        s.close()
+    del d_hv, d_out
+
+    rng = np.random.default_rng(16384)
+    qs = np.sort(rng.choice(Q, 32, replace=False))
+    assert np.array_equal(h[qs], hdc.encode(x[qs], base))
+
+    want = hdc.scores_mod_t(h, C, o.t)
+    # the oracle's decryption of sampled groups (first, last and four others)
+    gs = sorted({0, G - 1, *rng.choice(G, 4, replace=False).tolist()})
+    sko = sk.astype(np.int64)
+    for g in gs:
+        sc, _ = pipeline.decrypt_scores(o, sko, cts[g:g + 1].astype(np.int64), Q, groups=[g])
+        lo, hi = g * o.B, min(Q, (g + 1) * o.B)
+        assert np.array_equal(sc[lo:hi], want[lo:hi]), g
+    # every group through the library's decryption
+    scores, argmax = ep.ephdc_decrypt_scores(e, sk, cts, Q)
+    assert np.array_equal(scores, want)
+    assert np.array_equal(argmax, hdc.argmax(want))
