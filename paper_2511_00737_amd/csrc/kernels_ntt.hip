@@ -286,8 +286,9 @@ __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* s
 // into each limb of the group, transform it and accumulate ct_m[c][l] * pt[l]; with
 // accumulate set the item adds to the sums already in its slot.  With PF, the next
 // plaintext and each limb's model values are requested ahead of the transform that
-// precedes their use (more registers: used where the register budget allows it).
-template <int LOGN, int LE, int LG, bool PF, bool TL = false>
+// precedes their use (more registers: used where the register budget allows it); the
+// 32-bit form can request the next plaintext alone (PTPF).
+template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool PTPF = true>
 __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
@@ -306,15 +307,17 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
       for (int i = 0; i < E; ++i) acc[c][li][i] = accumulate ? ld_at(src, eo + 4u * i) : 0u;
     }
 
+  // PTPF: the next plaintext is requested a whole iteration ahead (it fits the registers of
+  // every shape of the single-request kernel); the model values only with PF
   int32_t nxt[E];
-  if (PF && it.m0 < it.m1) {
+  if (PTPF && it.m0 < it.m1) {
 #pragma unroll
     for (int i = 0; i < E; ++i) nxt[i] = ld_at(pt, co + 4u * (uint32_t)(i * S::T));
   }
   for (uint32_t m = it.m0; m < it.m1; ++m) {
     const int32_t* ptm = pt + (size_t)(m - it.m0) * N;  // plaintext (g, m)
     int32_t cur[E];
-    if constexpr (PF) {
+    if constexpr (PTPF) {
 #pragma unroll
       for (int i = 0; i < E; ++i) cur[i] = nxt[i];
       if (m + 1 < it.m1) {
@@ -460,14 +463,14 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
 
 // MAC alone: 64-bit lazy sums where 8 values per thread leave the registers for them,
 // 32-bit sums of Montgomery products otherwise.
-template <int LOGN, int LE, int LG, bool PF, bool TL = false>
+template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool PTPF = true>
 __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
   if constexpr (LE <= 3)
     mac_item64<LOGN, LE, LG, PF, TL>(it, pt, accumulate, fwd_tw, pcs, tid, b);
   else
-    mac_item32<LOGN, LE, LG, PF, TL>(it, pt, accumulate, fwd_tw, pcs, tid, b);
+    mac_item32<LOGN, LE, LG, PF, TL, PTPF>(it, pt, accumulate, fwd_tw, pcs, tid, b);
 }
 
 // ------------------------------------------------------------------ single-request kernels
@@ -636,9 +639,9 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
         lds_barrier();
         staged_l = it.l0;
       }
-      mac_item<LOGN, LE, LG, PF, true>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+      mac_item<LOGN, LE, LG, PF, true, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
     } else {
-      mac_item<LOGN, LE, LG, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+      mac_item<LOGN, LE, LG, PF, false, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
     }
   }
 }
