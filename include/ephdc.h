@@ -2,7 +2,7 @@
  * ephdc.h - C ABI of the EP-HDC client-side encrypted hyperdimensional inference path
  * on AMD Instinct MI355X (gfx950).
  *
- * The method (EP-HDC, "client-side HE"): the server encrypts its class hypervectors
+ * The method (EP-HDC, client-side HE): the server encrypts its class hypervectors
  * once with BFV and ships them; the client encodes its plaintext queries into
  * hypervectors, batch-encodes every query element into its own plaintext (each value
  * repeated once per class), multiplies those plaintexts into the encrypted model and
