@@ -120,3 +120,83 @@ def test_rotation_workload_at_full_size_sampled():
     scores, argmax = ep.ephdc_decrypt_scores(e, sk, cts, Q)
     assert np.array_equal(scores, want)
     assert np.array_equal(argmax, hdc.argmax(want))
+
+
+def test_batching_workload_at_full_size_sampled():
+    """The batching workload at its full size (256 requests of log-uniform sizes on six
+    models, K in {2, 7} x D in {2048, 4096, 10240}, N = 8192, 4 limbs), in the launch
+    configuration the benchmark times: autotuned, graph-captured batches, unpacked and
+    packed. The unpacked batch reproduces every request's single-request ciphertexts bit
+    for bit; every request decrypts (unpacked, and packed at its offset) to the exact
+    scores of its hypervectors, which match the oracle's encoding on sampled requests; the
+    oracle decrypts sampled requests itself."""
+    torch = torch_cuda()
+    N, L, F, nreq = 8192, 4, 2304, 256
+    models = [(K, D) for K in (2, 7) for D in (2048, 4096, 10240)]
+    primes = default_primes(N, L)
+    sizes, midx = synth.batch_mix(0, nreq, len(models))
+    pool = synth.blob_images(0, 4096)
+    d_pool = to_dev(pool)
+    tenants = []
+    for k, (K, D) in enumerate(models):
+        e = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K)
+        sk, _ = ep.ephdc_keygen(e, k)
+        C = synth.class_hypervectors(k, K, D)
+        sess = ep.Session(e, to_dev(ep.ephdc_encrypt_model(e, sk, C, k)), max_Q=4096)
+        base = synth.base_hypervectors(0, F, D)
+        tenants.append(dict(e=e, o=OParams(N=N, q=tuple(primes), F=F, D=D, K=K), sk=sk, C=C, s=sess,
+                            base=base, d_base=to_dev(base)))
+    try:
+        reqs, offs = [], []
+        for i in range(nreq):
+            t, Q = tenants[int(midx[i])], int(sizes[i])
+            off = (i * 977) % (4096 - Q + 1)
+            d_hv = torch.empty((t["e"].D, t["s"].hv_stride(Q)), dtype=torch.int8, device="cuda")
+            d_out = torch.empty((t["s"].num_groups(Q), 2, L, N), dtype=torch.int32, device="cuda")
+            reqs.append(ep.Request(t["s"], d_hv, Q, d_out, d_x=d_pool[off:off + Q], d_base=t["d_base"]))
+            offs.append(off)
+        # single-request results first
+        alone = []
+        for r in reqs:
+            ep.ephdc_encode_queries(r.session, r.d_x, r.d_base, r.Q, r.d_hv)
+            ep.ephdc_score_encrypted(r.session, r.d_hv, r.Q, r.d_score_ct)
+            alone.append(r.d_score_ct.clone())
+        torch.cuda.synchronize()
+        for r in reqs:
+            r.d_score_ct.zero_()
+        outs_p = [torch.zeros((r.d_score_ct.shape[0] + 1,) + tuple(r.d_score_ct.shape[1:]), dtype=torch.int32,
+                              device="cuda") for r in reqs]
+        torch.cuda.synchronize()
+        stream = torch.cuda.Stream()
+        batch = ep.Batch(reqs)
+        batch.autotune(reps=1, stream=stream)
+        batch.capture(stream)
+        batch.run(stream)
+        pbatch = ep.Batch([ep.Request(r.session, None, r.Q, o, d_x=r.d_x, d_base=r.d_base)
+                           for r, o in zip(reqs, outs_p)], packed=True)
+        pbatch.autotune(reps=1, stream=stream)
+        pbatch.capture(stream)
+        pbatch.run(stream)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(256)
+        sampled = set(rng.choice(nreq, 6, replace=False).tolist())
+        for i, (r, a) in enumerate(zip(reqs, alone)):
+            assert torch.equal(r.d_score_ct, a), i
+            t = tenants[int(midx[i])]
+            h = r.d_hv.cpu().numpy()[:, :r.Q].T.copy()
+            want = hdc.scores_mod_t(h, t["C"], 65537)
+            cts = to_host_u32(r.d_score_ct)
+            scores, _ = ep.ephdc_decrypt_scores(t["e"], t["sk"], cts, r.Q)
+            assert np.array_equal(scores, want), i
+            _, qf, nct = pbatch.packing(i)
+            pscores, _ = ep.ephdc_decrypt_scores_at(t["e"], t["sk"], to_host_u32(outs_p[i])[:nct], qf, r.Q)
+            assert np.array_equal(pscores, want), i
+            if i in sampled:
+                x = pool[offs[i]:offs[i] + r.Q]
+                qs = np.unique(np.linspace(0, r.Q - 1, 8).astype(int))
+                assert np.array_equal(h[qs], hdc.encode(x[qs], t["base"])), i
+                osc, _ = pipeline.decrypt_scores(t["o"], t["sk"].astype(np.int64), cts.astype(np.int64), r.Q)
+                assert np.array_equal(osc, want), i
+    finally:
+        for t in tenants:
+            t["s"].close()
