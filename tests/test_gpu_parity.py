@@ -67,11 +67,14 @@ def test_batch_encoded_plaintexts_match_oracle(N, K, D, r, Q):
         s.close()
 
 
-@pytest.mark.parametrize("F,D,Q,qbits,qshift", [(64, 128, 100, 1, 0), (512, 2048, 64, 1, 0),
-                                                 (2304, 256, 333, 1, 0), (160, 192, 70, 4, 9)])
-def test_hdc_encoding_matches_oracle(F, D, Q, qbits, qshift):
+# K = 5 gives B = 818 queries per ciphertext: hv rows of 818 bytes, so every other row
+# starts off a 4-byte boundary (byte stores), with a ragged last query tile
+@pytest.mark.parametrize("F,D,Q,qbits,qshift,K", [(64, 128, 100, 1, 0, 2), (512, 2048, 64, 1, 0, 2),
+                                                   (2304, 256, 333, 1, 0, 2), (160, 192, 70, 4, 9, 2),
+                                                   (96, 320, 800, 1, 0, 5), (208, 64, 811, 3, 8, 5)])
+def test_hdc_encoding_matches_oracle(F, D, Q, qbits, qshift, K):
     torch = torch_cuda()
-    o, e = make(4096, 1, D=D, K=2, F=F, qbits=qbits, qshift=qshift)
+    o, e = make(4096, 1, D=D, K=K, F=F, qbits=qbits, qshift=qshift)
     x = synth.uniform_features(F + Q, Q, F)
     base = synth.base_hypervectors(F + Q, F, D)
     want = hdc.encode(x, base, qbits, qshift)
