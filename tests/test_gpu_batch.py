@@ -248,3 +248,71 @@ def test_packed_batch_matches_oracle():
     finally:
         for s in sessions:
             s.close()
+
+
+def test_batch_at_n16384_with_rotations():
+    """A batch whose parameter set is N = 16384 (the 1024-thread transform shape without an
+    LDS table slot): two models, one folded (r = 4, two rotate-and-sum steps with key
+    switching), requests with and without HDC encoding inside the batch. Unpacked, every
+    request equals the single-request path bit for bit and the oracle on its groups;
+    packed, every request decrypts at its offset to its exact scores."""
+    torch = torch_cuda()
+    specs = [(16384, 3, 5, 64, 4, 1, 3), (16384, 3, 2, 64, 1, 0, 0)]
+    reqspec = [(0, 1, True), (0, 600, False), (1, 300, True), (1, 2000, False), (0, 150, True)]
+    tenants = [Tenant(90 + i, *t) for i, t in enumerate(specs)]
+    sessions = [ep.Session(t.e, to_dev(t.model.astype(np.uint32)),
+                           to_dev(t.gk.astype(np.uint32)) if t.gk is not None else None, max_Q=2000)
+                for t in tenants]
+    try:
+        reqs, hs = [], []
+        for k, (ti, Q, enc) in enumerate(reqspec):
+            t, s = tenants[ti], sessions[ti]
+            out = torch.zeros((s.num_groups(Q), 2, t.o.L, t.o.N), dtype=torch.int32, device="cuda")
+            if enc:
+                x = synth.uniform_features(170 + k, Q, F)
+                hs.append(hdc.encode(x, t.base))
+                d_hv = torch.full((t.o.D, s.hv_stride(Q)), 99, dtype=torch.int8, device="cuda")
+                reqs.append(ep.Request(s, d_hv, Q, out, d_x=to_dev(x), d_base=to_dev(t.base)))
+            else:
+                hs.append(np.random.default_rng(k).choice(np.array([-1, 1], dtype=np.int8), (Q, t.o.D)))
+                reqs.append(ep.Request(s, to_dev(hv_layout(hs[-1], s.hv_stride(Q))), Q, out))
+        b = ep.Batch(reqs)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+        for k, ((ti, Q, enc), r, h) in enumerate(zip(reqspec, reqs, hs)):
+            t, s = tenants[ti], sessions[ti]
+            got = to_host_u32(r.d_score_ct).astype(np.int64)
+            if enc:
+                assert np.array_equal(r.d_hv.cpu().numpy()[:, :Q], h.T), k
+            one = torch.empty_like(r.d_score_ct)
+            ep.ephdc_score_encrypted(s, r.d_hv, Q, one)
+            torch.cuda.synchronize()
+            assert np.array_equal(to_host_u32(one).astype(np.int64), got), k
+            G = t.o.groups(Q)
+            want = pipeline.score_ciphertexts(t.o, t.model, h, t.gk, groups=[G - 1])
+            assert np.array_equal(got[G - 1], want[0]), k
+            scores, _ = pipeline.decrypt_scores(t.o, t.sk, got, Q)
+            assert np.array_equal(scores, hdc.scores_mod_t(h, t.C, 65537)), k
+        # packed (the requests with features): requests of a model share ciphertexts
+        enc = [k for k, (_, _, e) in enumerate(reqspec) if e]
+        outs = [torch.zeros((reqs[k].d_score_ct.shape[0] + 1,) + tuple(reqs[k].d_score_ct.shape[1:]),
+                            dtype=torch.int32, device="cuda") for k in enc]
+        pb = ep.Batch([ep.Request(reqs[k].session, None, reqs[k].Q, o, d_x=reqs[k].d_x, d_base=reqs[k].d_base)
+                       for k, o in zip(enc, outs)], packed=True)
+        try:
+            pb.run()
+            torch.cuda.synchronize()
+            for i, k in enumerate(enc):
+                (ti, Q, _), h, t = reqspec[k], hs[k], tenants[reqspec[k][0]]
+                _, qf, nct = pb.packing(i)
+                got = to_host_u32(outs[i])[:nct]
+                scores, _ = ep.ephdc_decrypt_scores_at(t.e, t.sk.astype(np.int8), got, qf, Q)
+                assert np.array_equal(scores, hdc.scores_mod_t(h, t.C, 65537)), k
+        finally:
+            pb.close()
+    finally:
+        for s in sessions:
+            s.close()
