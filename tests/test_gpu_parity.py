@@ -124,7 +124,7 @@ def test_qbit_queries_score_exactly():
     assert np.array_equal(scores, hdc.scores_mod_t(h, C, 65537))
 
 
-@pytest.mark.parametrize("N,L,K,D,Q", [(8192, 4, 7, 24, 2500), (4096, 3, 2, 30, 3000)])
+@pytest.mark.parametrize("N,L,K,D,Q", [(8192, 4, 7, 24, 2500), (4096, 3, 2, 30, 3000), (16384, 2, 26, 12, 1000)])
 def test_every_schedule_gives_the_same_bits(N, L, K, D, Q):
     """Schedule invariance (and a race canary): every shape, limb grouping and grid size
     of the scoring kernel reproduces the oracle's score ciphertexts exactly."""
@@ -139,7 +139,7 @@ def test_every_schedule_gives_the_same_bits(N, L, K, D, Q):
     try:
         d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
         d_out = torch.empty(want.shape, dtype=torch.int32, device="cuda")
-        shapes = [16, 8] if N == 8192 else [8]
+        shapes = {4096: [8], 8192: [16, 8], 16384: [16, 32]}[N]
         for mode in ("fused", "split"):
             for vpt in shapes:
                 lgs = [g for g in (1, 2, 4) if L % g == 0] + ([3] if L % 3 == 0 and mode == "fused" else [])
