@@ -257,7 +257,7 @@ def test_batch_at_n16384_with_rotations():
     request equals the single-request path bit for bit and the oracle on its groups;
     packed, every request decrypts at its offset to its exact scores."""
     torch = torch_cuda()
-    specs = [(16384, 3, 5, 64, 4, 1, 3), (16384, 3, 2, 64, 1, 0, 0)]
+    specs = [(16384, 4, 5, 64, 4, 1, 2), (16384, 4, 2, 64, 1, 0, 0)]
     reqspec = [(0, 1, True), (0, 600, False), (1, 300, True), (1, 2000, False), (0, 150, True)]
     tenants = [Tenant(90 + i, *t) for i, t in enumerate(specs)]
     sessions = [ep.Session(t.e, to_dev(t.model.astype(np.uint32)),
@@ -280,6 +280,17 @@ def test_batch_at_n16384_with_rotations():
         try:
             b.run()
             torch.cuda.synchronize()
+            first = [r.d_score_ct.clone() for r in reqs]
+            # the other shapes and paths of the list kernels give the same bits
+            for mode, vpt, lg in (("split", 32, 1), ("fused", 16, 1), ("fused", 32, 2), ("split", 16, 2),
+                                  ("split", 16, 4)):
+                for r in reqs:
+                    r.d_score_ct.fill_(0)
+                b.tune(mode=mode, values_per_thread=vpt, limb_group=lg, seg_len=8, grid=300)
+                b.run()
+                torch.cuda.synchronize()
+                for k, (r, f) in enumerate(zip(reqs, first)):
+                    assert torch.equal(r.d_score_ct, f), (mode, vpt, lg, k)
         finally:
             b.close()
         for k, ((ti, Q, enc), r, h) in enumerate(zip(reqspec, reqs, hs)):
