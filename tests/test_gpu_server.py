@@ -16,8 +16,10 @@ from gpu_helpers import to_dev, to_host_u32, torch_cuda
 pytestmark = pytest.mark.gpu
 
 F = 64
-# (N, L, K, D, r, alpha, dnum)
-TENANTS = [(4096, 3, 2, 64, 1, 0, 0), (4096, 3, 3, 128, 2, 1, 3), (8192, 4, 7, 64, 1, 0, 0)]
+# (N, L, K, D, r, alpha, dnum): two parameter sets with a folded model at N = 4096, one at
+# N = 8192 and a folded model at N = 16384 (the 1024-thread transform shape)
+TENANTS = [(4096, 3, 2, 64, 1, 0, 0), (4096, 3, 3, 128, 2, 1, 3), (8192, 4, 7, 64, 1, 0, 0),
+           (16384, 3, 5, 64, 4, 1, 3)]
 
 
 class Tenant:
