@@ -273,6 +273,32 @@ __device__ __forceinline__ void load_tw(Tw<LOGN, LE, P, W>& t, int tid, const W*
   constexpr int k = TW::k;
   constexpr int s0 = S::s0(P);
   const int xt = (P == 0) ? 0 : tid_part<LOGN, LE, P>(tid);  // pass 0: blocks at stages < LE are uniform
+  if constexpr (TL && P == S::NPASS - 1 && (TW::G << (k - 1)) >= 4) {
+    // Last pass (x = tid*E + i): at stage u the thread's twiddles are the run of
+    // R = G * 2^u consecutive words starting at 2^s + tid * R, read as 16-byte vectors, so
+    // that a wave's lanes cover consecutive LDS bytes (no bank conflicts for R = 4).
+#pragma unroll
+    for (int u = 0; u < k; ++u) {
+      const int s = s0 + u;
+      constexpr int R0 = TW::G;
+      const int R = R0 << u;
+      const uint32_t w0 = LdsPlan<LOGN, LE>::exchange_words + (1u << s) + (uint32_t)tid * (uint32_t)R;
+      if (R >= 4) {
+#pragma unroll
+        for (int j = 0; j < R; j += 4) {
+          const uint4 q = *static_cast<const uint4*>(__builtin_assume_aligned(ephdc_lds + w0 + j, 16));
+          t.w[TW::off(u) + j] = q.x;
+          t.w[TW::off(u) + j + 1] = q.y;
+          t.w[TW::off(u) + j + 2] = q.z;
+          t.w[TW::off(u) + j + 3] = q.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) t.w[TW::off(u) + j] = ephdc_lds[w0 + j];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < k; ++u) {
     const int s = s0 + u;
