@@ -1,6 +1,8 @@
 """Pins of the oracle's BFV: definitions written out with schoolbook products, decryption
 identities, the exact integer score closed form, base-conversion identities with big
 integers, and rotation by Galois automorphism + key switching."""
+import math
+
 import numpy as np
 import pytest
 
@@ -196,3 +198,30 @@ def test_batched_model_encryption_equals_per_ciphertext():
     batched = bfv.encrypt_model(P, s, C, 15, ms=[0, 3, 6], chunk=2)
     for i, m in enumerate([0, 3, 6]):
         assert np.array_equal(batched[i], bfv.encrypt(P, s, bfv.model_plaintext(P, C, m), 15, m))
+
+
+def test_noise_budget_decides_correctness():
+    """The invariant noise is real: with two 19-bit primes (Q about 2^38, Delta about 2^22)
+    a fresh ciphertext still decrypts, but after the ct x pt products of a dot product the
+    noise exceeds Delta/2 and the scores come out wrong; with the default 30-bit primes the
+    same computation keeps the noise far below Delta/2 and decrypts to the exact scores. A
+    dropped error term or a wrong scaling in the oracle would fail one of the two halves."""
+    N, D, K = 32, 12, 3
+    rng = np.random.default_rng(11)
+    C = rng.integers(-128, 128, (K, D)).astype(np.int8)
+    h = rng.choice([-1, 1], (5, D)).astype(np.int8)
+    want = hdc.scores_mod_t(h, C, T)
+    small = Params(N=N, q=tuple(default_primes(N, 2, bound=1 << 19)), D=D, K=K, F=8)
+    big = tiny(N=N, L=2, D=D, K=K)
+    for P, ok in ((small, False), (big, True)):
+        s = bfv.secret_key(P, 5)
+        mu = np.random.default_rng(5).integers(0, T, P.N)
+        fresh = bfv.encrypt(P, s, mu, 5, 0)
+        assert np.array_equal(bfv.decrypt(P, s, fresh), mu)  # fresh noise |e| <= 19 < Delta/2
+        model = bfv.encrypt_model(P, s, C, 5)
+        cts = pipeline.score_ciphertexts(P, model, h)
+        scores, _ = pipeline.decrypt_scores(P, s, cts, h.shape[0])
+        assert np.array_equal(scores, want) == ok, P.q
+        if ok:  # the distance to the nearest codeword is the true noise when decryption is right
+            noise = max(bfv.noise_bits(P, s, ct) for ct in cts)
+            assert noise < math.log2(P.Delta) - 1 - 5, (noise, math.log2(P.Delta))
