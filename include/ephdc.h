@@ -213,13 +213,16 @@ ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const ui
  *   limb_group         limbs per work item, a divisor of L in 1..4
  *   blocks             target workgroups per launch (<= 1024): the model ciphertexts are
  *                      split into ranges until groups x ranges x limb groups reaches it
- *   values_per_thread  transform values held per thread (8 or 16 at N = 8192; the
- *                      workgroup has N / values_per_thread threads)
+ *   values_per_thread  transform values held per thread (8 at N = 4096, 8 or 16 at
+ *                      N = 8192, 16 or 32 at N = 16384; the workgroup has
+ *                      N / values_per_thread threads)
  *   mode               1: one fused kernel batch-encodes and multiplies (the batch
  *                      encoding is repeated per limb group); 2: split path, a batch-encode
  *                      kernel writes each lifted plaintext once (into a session buffer of
  *                      at most 512 MiB, allocated on first use) and a MAC kernel reads it
- * Results do not depend on the schedule.
+ * Results do not depend on the schedule.  Defaults: split path, one limb per work item,
+ * 8 values per thread (16 at N = 16384), 256 workgroups from N = 8192 up (one per compute
+ * unit of an MI355X) and 512 below.
  */
 ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks,
                                 uint32_t values_per_thread, uint32_t mode);
