@@ -18,6 +18,12 @@ Modules, each citing the passage of the paper it restates:
   bfv       BFV key generation, encryption, decryption, ct x pt MAC,
             Galois automorphisms and hybrid key switching
   pipeline  the whole client-side path: queries -> encrypted score ciphertexts
+  dmax      findDmax of the design-space exploration (Algorithm 1): the
+            largest dimension whose encrypted dot product still decrypts
+
+Variants (BGV/BFV-aware quantisation and the noise study): any prime plaintext
+modulus t = 1 (mod 2N); the schemes BFV, BFV with rounded scaling, and BGV; and
+the scaling op (multiply by (2^s)^-1 mod t after every g accumulations).
 
 Parity status: every function is pinned by tests under tests/ against
 closed forms, brute force on tiny inputs, invariants or published values.
@@ -25,5 +31,5 @@ The key-switching output bits are pinned only through decryption
 (a rotated, correctly decrypting ciphertext) and the stated formulas; there
 is no published worked example of them.
 """
-from . import arith, prng, ntt, slots, hdc, layout, bfv, pipeline  # noqa: F401
+from . import arith, prng, ntt, slots, hdc, layout, bfv, pipeline, dmax  # noqa: F401
 from .params import Params, default_primes  # noqa: F401

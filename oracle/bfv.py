@@ -17,6 +17,19 @@ readings are:
 * Plaintext of a query slot vector: mu = Encode(v), lifted to integers by the
   centred representative in (-t/2, t/2] and reduced into every limb.
 * Decryption: x = [c0 + c1*s]_Q by exact CRT, mu = floor((2t*x + Q) / (2Q)) mod t.
+* BFV with rounded scaling ("bfv-r"): the message term is round(Q*mu/t)
+  instead of Delta*mu (the scaling many BFV libraries use); everything else,
+  decryption included, is as in BFV.  Under Delta*mu a ct x pt product carries
+  the extra error (Q mod t) * floor(mu*p/t), which the rounded scaling avoids.
+* BGV (the noise study's comparison scheme; the paper keeps BFV): the message
+  sits in the low bits and the error is scaled by t instead:
+  ct = ([-a*s + t*e + mu~]_Q, a) with mu~ the centred representative of mu,
+  and decryption is mu = ([c0 + c1*s]_Q, centred) mod t.  The ct x pt product,
+  the accumulation and the scaling op are the same ring operations as in BFV.
+* HE-aware scaling (BGV/BFV-aware quantisation): with g = scale_every > 0,
+  after every g additions of the MAC the accumulator is multiplied by the
+  plaintext scalar c = centred (2^s)^-1 mod t, so the plaintext becomes
+  m * (2^s)^-1 mod t: the exact quotient m / 2^s whenever 2^s divides m.
 * Rotations (fold factor r > 1 only; the paper's own packing needs none):
   the Galois automorphism X -> X^g, then hybrid key switching with dnum digits
   over the extended basis PQ (fast base conversion up, inner product with the
@@ -53,13 +66,24 @@ def encrypt(P: Params, s: np.ndarray, mu: np.ndarray, seed: int, index: int) -> 
     """Ciphertext int64 [2][L][N] of plaintext mu, using the draws reserved for ciphertext `index`."""
     L, N = P.L, P.N
     a, e = _mask_and_error(P, P.q, seed, prng.TAG_ENCRYPT, index * (L + 1) * N)
-    Delta = P.Delta
     ct = np.empty((2, L, N), dtype=np.int64)
     for l, q in enumerate(P.q):
         as_ = ntt.polymul(a[l], s % q, q)
-        ct[0, l] = (-as_ + e + (Delta % q) * mu) % q
+        ct[0, l] = (-as_ + _message_term(P, e, mu, q)) % q
         ct[1, l] = a[l]
     return ct
+
+
+def _message_term(P: Params, e: np.ndarray, mu: np.ndarray, q: int) -> np.ndarray:
+    """e + Delta*mu (BFV), e + round(Q*mu/t) (BFV with rounded scaling) or t*e + centred(mu)
+    (BGV), reduced mod q.  round(Q*mu/t) = Delta*mu + floor((2*r*mu + t) / (2t)), r = Q mod t."""
+    if P.scheme == "bgv":
+        return (P.t * e + slots.centered(mu, P.t)) % q
+    out = (e + (P.Delta % q) * mu) % q
+    if P.scheme == "bfv-r":
+        r = P.Qmod % P.t
+        out = (out + (2 * r * mu + P.t) // (2 * P.t)) % q
+    return out
 
 
 def model_plaintext(P: Params, C: np.ndarray, m: int) -> np.ndarray:
@@ -86,22 +110,53 @@ def encrypt_model(P: Params, s: np.ndarray, C: np.ndarray, seed: int, ms=None,
         for l, q in enumerate(P.q):
             a = prng.uniform_mod(u[:, l], q)
             as_ = ntt.polymul(a, (s % q)[None, :], q)
-            out[i0:i0 + len(sel), 0, l] = (-as_ + e + (P.Delta % q) * mu) % q
+            out[i0:i0 + len(sel), 0, l] = (-as_ + _message_term(P, e, mu, q)) % q
             out[i0:i0 + len(sel), 1, l] = a
     return out
 
 
-def decrypt(P: Params, s: np.ndarray, ct: np.ndarray) -> np.ndarray:
-    """mu in [0, t) of a ciphertext int64 [2][L][N]."""
-    Qm, t = P.Qmod, P.t
+def phase(P: Params, s: np.ndarray, ct: np.ndarray) -> np.ndarray:
+    """x = [c0 + c1*s]_Q in [0, Q) as Python integers (exact CRT), object [N]."""
+    Qm = P.Qmod
     x = [(ct[0, l] + ntt.polymul(ct[1, l], s % q, q)) % q for l, q in enumerate(P.q)]
     acc = np.zeros(P.N, dtype=object)
     for l, q in enumerate(P.q):
         Qhat = Qm // q
         acc = acc + x[l].astype(object) * ((Qhat * inv(Qhat, q)) % Qm)
-    acc = acc % Qm
+    return acc % Qm
+
+
+def decrypt(P: Params, s: np.ndarray, ct: np.ndarray) -> np.ndarray:
+    """mu in [0, t) of a ciphertext int64 [2][L][N]."""
+    Qm, t = P.Qmod, P.t
+    acc = phase(P, s, ct)
+    if P.scheme == "bgv":
+        mu = np.array([(int(v) - Qm if int(v) > Qm // 2 else int(v)) % t for v in acc], dtype=np.int64)
+        return mu
     mu = (2 * t * acc + Qm) // (2 * Qm) % t
     return mu.astype(np.int64)
+
+
+def noise_margin_bits(P: Params, s: np.ndarray, ct: np.ndarray, mu: np.ndarray) -> float:
+    """Bits left before decryption of ct would stop returning mu (the plaintext it should hold).
+
+    BFV: log2(Delta/2) - log2 max |x - Delta*mu| (centred mod Q).  BGV: log2(Q/2) - log2 max |x|
+    (centred mod Q), which measures the integer phase only while it has not wrapped, so a
+    ciphertext that no longer decrypts to mu gets -inf.  x = [c0 + c1*s]_Q.
+    """
+    Qm = P.Qmod
+    acc = phase(P, s, ct)
+    if P.scheme == "bgv":
+        err = [int(v) - Qm if int(v) > Qm // 2 else int(v) for v in acc]
+        if any((e - int(m)) % P.t for e, m in zip(err, mu)):
+            return -math.inf
+        bound = Qm / 2
+    else:
+        err = [(int(v) - int(m) * P.Delta) % Qm for v, m in zip(acc, mu)]
+        err = [v - Qm if v > Qm // 2 else v for v in err]
+        bound = P.Delta / 2
+    mx = max(abs(v) for v in err)
+    return math.log2(bound) - (math.log2(mx) if mx else 0.0)
 
 
 def noise_bits(P: Params, s: np.ndarray, ct: np.ndarray) -> float:
@@ -140,23 +195,40 @@ def mul_plain(P: Params, ct: np.ndarray, p: np.ndarray, moduli=None) -> np.ndarr
     return out
 
 
+def mul_scalar(P: Params, ct: np.ndarray, c: int) -> np.ndarray:
+    """ct * c for an integer plaintext scalar c (each residue times c mod q_l)."""
+    out = np.empty_like(ct)
+    for l, q in enumerate(P.q):
+        out[:, l] = ct[:, l] * (c % q) % q
+    return out
+
+
 def mac(P: Params, model_ct: np.ndarray, h: np.ndarray, g: int, chunk: int = 256) -> np.ndarray:
     """acc_g = sum_m ct_m * p_(g,m) over all M model ciphertexts, int64 [2][L][N].
 
     Products are taken in the evaluation domain of each limb (ntt.forward) and
-    summed there; the sum is exact, so the order of m does not matter.
+    summed there; within a run of additions the order of m does not matter (the
+    sums are exact).  With scale_every = g_s > 0 the additions come in blocks of
+    g_s model ciphertexts, and after every complete block the accumulator is
+    multiplied by the scaling scalar (the multiplication commutes with the
+    transform, so it is applied in the evaluation domain).
     """
     L, N, t = P.L, P.N, P.t
     acc = np.zeros((2, L, N), dtype=np.int64)
-    for m0 in range(0, P.M, chunk):
-        ms = range(m0, min(P.M, m0 + chunk))
-        v = np.stack([query_slots(P, h, g, m) for m in ms])
-        pt = lift_centered(slots.encode(v, t), t)
-        for l, q in enumerate(P.q):
-            ptf = ntt.forward(pt % q, q)
-            for c in range(2):
-                ctf = ntt.forward(model_ct[m0:m0 + len(ms), c, l], q)
-                acc[c, l] = (acc[c, l] + (ctf * ptf % q).sum(axis=0)) % q
+    blk = P.scale_every if P.scale_every else P.M
+    for b0 in range(0, P.M, blk):
+        b1 = min(P.M, b0 + blk)
+        for m0 in range(b0, b1, chunk):
+            ms = range(m0, min(b1, m0 + chunk))
+            v = np.stack([query_slots(P, h, g, m) for m in ms])
+            pt = lift_centered(slots.encode(v, t), t)
+            for l, q in enumerate(P.q):
+                ptf = ntt.forward(pt % q, q)
+                for c in range(2):
+                    ctf = ntt.forward(model_ct[m0:m0 + len(ms), c, l], q)
+                    acc[c, l] = (acc[c, l] + (ctf * ptf % q).sum(axis=0)) % q
+        if P.scale_every and b1 - b0 == P.scale_every:
+            acc = mul_scalar(P, acc, P.scale_const)
     out = np.empty_like(acc)
     for l, q in enumerate(P.q):
         for c in range(2):

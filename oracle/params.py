@@ -13,6 +13,14 @@ queries and D model ciphertexts are needed (Analysis / proposed method).
 The fold factor r generalises this: r consecutive dimensions share one
 ciphertext in r blocks of W = N/(2r) slots per row, and log2(r)
 rotate-and-sum steps fold the blocks together.  r = 1 is the paper's packing.
+
+The plaintext modulus t is any prime with t = 1 (mod 2N) (the paper sweeps
+log2 t; its optimised settings use log2 t = 16 and 17, optimisation table).
+The scheme is BFV (the paper's choice) or BGV (its comparison in the noise
+study).  HE-aware quantisation (BGV/BFV-aware quantisation): with
+scale_every = g > 0 the accumulator is multiplied by the inverse of
+2^scale_shift mod t after every g ciphertext additions, which divides the
+plaintext by 2^scale_shift whenever it is divisible.
 """
 from __future__ import annotations
 
@@ -49,6 +57,9 @@ class Params:
     dnum: int = 0
     qbits: int = 1          # 1: binarise; 2..8: clamp(H >> qshift) to qbits signed bits
     qshift: int = 0
+    scheme: str = "bfv"     # "bfv", "bfv-r" (rounded scaling) or "bgv"
+    scale_every: int = 0    # g: scale after every g accumulations (0: never)
+    scale_shift: int = 0    # s: the scale is the inverse of 2^s mod t
 
     # ---- derived sizes
     @property
@@ -95,6 +106,12 @@ class Params:
         return self.Qmod // self.t
 
     @property
+    def scale_const(self) -> int:
+        """Centred representative of (2^s)^-1 mod t: the plaintext scalar of the scaling op."""
+        c = pow(2, -self.scale_shift, self.t)
+        return c - self.t if c > self.t // 2 else c
+
+    @property
     def log2r(self) -> int:
         return self.r.bit_length() - 1
 
@@ -111,6 +128,9 @@ class Params:
         N = self.N
         assert N >= 8 and N & (N - 1) == 0
         assert is_prime(self.t) and self.t % (2 * N) == 1
+        assert self.scheme in ("bfv", "bfv-r", "bgv")
+        assert self.scheme != "bgv" or self.r == 1  # BGV key switching is not implemented
+        assert self.scale_every >= 0 and 0 <= self.scale_shift < 32
         allp = list(self.q) + list(self.p)
         assert len(set(allp)) == len(allp)
         for x in allp:

@@ -6,7 +6,8 @@ slot (Preliminary: HE, packing).  The paper does not fix which slot is which;
 the reading used here puts slot s at an evaluation point chosen so that the
 Galois automorphism X -> X^(3^k) rotates each half of the vector by k:
 
-  zeta = 3^((t-1)/(2N)) mod t   (3 generates Z_65537^*, so zeta has order 2N)
+  zeta = g^((t-1)/(2N)) mod t   (g the smallest generator of Z_t^*, so zeta has
+                                 order 2N; g = 3 for t = 65537)
   slot s < N/2      <->  point zeta^(3^s mod 2N)
   slot N/2 + s      <->  point zeta^(-3^s mod 2N)
 
@@ -20,10 +21,12 @@ from functools import lru_cache
 import numpy as np
 
 from . import ntt
+from .arith import smallest_generator
 
 
+@lru_cache(maxsize=None)
 def zeta(N: int, t: int) -> int:
-    return pow(3, (t - 1) // (2 * N), t)
+    return pow(smallest_generator(t), (t - 1) // (2 * N), t)
 
 
 @lru_cache(maxsize=None)
