@@ -326,7 +326,7 @@ def bench_serving(args, w) -> int:
         model = ep.ephdc_encrypt_model(prm, sk, C, seed + 100 + k)
         d_model = torch.from_numpy(model.view(np.int32)).to(dev)
         d_gk = torch.from_numpy(gk.view(np.int32)).to(dev) if gk is not None else None
-        sess = ep.Session(prm, d_model, d_gk, max_Q=w["qmax"])
+        sess = ep.Session(prm, d_model, d_gk, max_Q=w["qmax"], workspace=None)  # served only: no workspace
         del d_model, d_gk, model
         if D not in bases:
             bases[D] = torch.from_numpy(synth.base_hypervectors(seed, F, D)).to(dev)

@@ -47,21 +47,40 @@ typedef enum {
   EPHDC_ERR_UNSUPPORTED = 7  /* valid parameters outside what the kernels implement */
 } ephdc_status;
 
+/* Homomorphic scheme of the model ciphertexts (Preliminary: HE; noise results). */
+enum {
+  EPHDC_BFV = 0,          /* BFV, message term Delta*mu with Delta = floor(Q/t) (the paper's scheme) */
+  EPHDC_BFV_ROUNDED = 1,  /* BFV, message term round(Q*mu/t) */
+  EPHDC_BGV = 2           /* BGV: ([-a*s + t*e + mu]_Q, a), mu centred; decryption [c0 + c1*s]_Q mod t */
+};
+
 /*
- * BFV + HDC parameters (symbols of the paper's table of symbols: N polynomial degree,
+ * BFV / BGV + HDC parameters (symbols of the paper's table of symbols: N polynomial degree,
  * log2 t message bits, D hypervector dimension, K = k classes).
  *
- *   N      ring degree; the kernels implement N in {4096, 8192, 16384}
+ *   N      ring degree; the device kernels implement N in {2048, 4096, 8192, 16384}
  *   L      number of ciphertext primes q[0..L-1], 1 <= L <= 16
  *   alpha  number of special primes p[0..alpha-1] used only by key switching
  *   dnum   key-switching digits (limb groups of ceil(L/dnum) primes); 0 when r == 1
  *   q, p   the primes: distinct, prime, < 2^30, and = 1 (mod 2N)
- *   t      plaintext modulus; must be 65537
+ *   t      plaintext modulus: a prime = 1 (mod 2N) with 257 <= t and N * t < 2^32 (the
+ *          device's inverse transform mod t runs without reductions under that bound);
+ *          t = 65537 is the default.  The slot map uses zeta = g^((t-1)/2N), g the smallest
+ *          generator of Z_t^*.
  *   F      features per query; D hypervector dimension; K classes
  *   r      fold factor (power of two): r consecutive dimensions share one ciphertext,
  *          in r blocks of W = N/(2r) slots per row; log2(r) rotate-and-sum steps fold
- *          them (r = 1 is the paper's packing and needs no rotation)
+ *          them (r = 1 is the paper's packing and needs no rotation; BGV takes r = 1 only)
  *   qbits  1: binarised queries (+1 / -1); 2..8: clamp(H >> qshift) to qbits signed bits
+ *   scheme EPHDC_BFV, EPHDC_BFV_ROUNDED or EPHDC_BGV (server-side encryption and
+ *          decryption; the client's ct x pt arithmetic is the same ring arithmetic for all)
+ *   scale_every, scale_shift
+ *          HE-aware quantisation (EP-HDC design space exploration, BGV/BFV-aware
+ *          quantisation): with g = scale_every > 0, after every g ciphertext additions of
+ *          the multiply-accumulate (model ciphertexts m = 0..M-1 in order) the accumulator
+ *          is multiplied by the plaintext scalar c = centred (2^scale_shift)^-1 mod t, which
+ *          divides the plaintext by 2^scale_shift wherever it is divisible.  A trailing
+ *          block of fewer than g additions is not scaled.  0 <= scale_shift < 32.
  *
  * Derived: Bq = floor(W/K) queries per row, B = 2*Bq queries per ciphertext,
  * M = ceil(D/r) model ciphertexts, G = ceil(Q/B) score ciphertexts for Q queries.
@@ -72,7 +91,10 @@ typedef struct {
   const uint32_t* p;
   uint32_t t;
   uint32_t F, D, K, r;
-  uint32_t qbits, qshift;
+  int32_t qbits;
+  uint32_t qshift;
+  uint32_t scheme;
+  uint32_t scale_every, scale_shift;
 } ephdc_params;
 
 /* Message describing the last failure on this thread ("" if none). */
@@ -148,22 +170,39 @@ ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, 
 typedef struct ephdc_session ephdc_session;
 
 /*
- * Creates a client session on the current HIP device: copies the encrypted model
- * (device pointer, uint32 [M][2][L][N], coefficient domain, model_words entries) into a
- * device-resident evaluation-domain copy owned by the session, and likewise the Galois
- * keys (device pointer, layout of ephdc_keygen, gk_words entries; required when r > 1,
- * else may be NULL).  A buffer shorter than its layout needs gives EPHDC_ERR_BUFFER.
- * The device kernels take ciphertext primes q_l in [2^29, 2^30) (EPHDC_ERR_UNSUPPORTED
- * otherwise); the default primes are the largest below 2^30.
- * max_Q bounds the batch size of later calls; it sizes the scratch space of
- * ephdc_score_encrypted, which is allocated on that call's first use (batches and the
- * serving loop bring their own).  The call is synchronous with respect to `stream`.
+ * Device workspace of ephdc_score_encrypted for batches of up to max_Q queries, in bytes
+ * (0 on invalid parameters): the work items' partial sums (sized for every schedule of
+ * ephdc_session_tune), the rotation workspace when r > 1, and the split path's plaintext
+ * chunk (the lifted plaintexts of all groups of max_Q queries, at most 512 MiB, at least one
+ * plaintext per group).  Any buffer of at least the size without the 512 MiB chunk (one
+ * plaintext per group of max_Q) is accepted; a larger chunk scores the model in fewer chunks.
+ * Client side, homomorphic scoring (proposed method: client-side HE).
+ */
+size_t ephdc_workspace_bytes(const ephdc_params* prm, uint32_t max_Q);
+
+/*
+ * Creates a client session on the current HIP device (proposed method, client-side HE: the
+ * client receives the encrypted model once and keeps it for many batches).  The session
+ * holds the encrypted model as a device-resident evaluation-domain copy (Montgomery form;
+ * it owns that copy and its transform tables):
+ *   d_model_ct     device, uint32 [M][2][L][N], coefficient domain, model_words entries;
+ *                  read during the call only
+ *   d_galois_keys  device, layout of ephdc_keygen, gk_words entries (r > 1; else NULL)
+ *   max_Q          largest batch of later calls
+ *   d_workspace    device, ws_bytes bytes, 256-byte aligned, caller-owned and borrowed until
+ *                  destroy (see ephdc_workspace_bytes); NULL for a session used only through
+ *                  batches, the serving loop and ephdc_score_encrypted_static
+ * Errors: EPHDC_ERR_BUFFER (a buffer shorter than its layout), EPHDC_ERR_UNSUPPORTED
+ * (ciphertext primes outside [2^29, 2^30), N outside the device shapes), EPHDC_ERR_OOM.
+ * The call is synchronous with respect to `stream`.
  */
 ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
-                                  const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q, void* stream,
-                                  ephdc_session** out);
+                                  const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q,
+                                  void* d_workspace, size_t ws_bytes, void* stream, ephdc_session** out);
+/* Waits for the session's last scoring call and frees it.  Batches and servers that use the
+ * session must be destroyed first. */
 ephdc_status ephdc_session_destroy(ephdc_session* s);
-/* Device bytes the session holds (model, keys, tables, scratch). */
+/* Device bytes the session owns (model copy, keys, tables; not the caller's workspace). */
 size_t ephdc_session_device_bytes(const ephdc_session* s);
 
 /*
@@ -181,13 +220,18 @@ ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const in
 
 /*
  * Homomorphic scoring of Q query hypervectors (d_hv as written by ephdc_encode_queries,
- * stride ephdc_hv_stride(Q)) against the encrypted model: for every group g of B queries
- * and every model ciphertext m, batch-encode the query plaintext (slot scatter and
- * inverse transform mod t, centred lift), multiply it into ciphertext m and accumulate;
- * when r > 1, fold the r blocks with log2(r) rotate-and-sum steps (Galois automorphism
- * and hybrid key switching).
- *   d_score_ct  out, uint32 [G][2][L][N], coefficient domain: the client -> server message.
- * Q must be <= the session's max_Q.  Asynchronous on `stream`.
+ * stride ephdc_hv_stride(Q)) against the encrypted model (proposed method, client-side HE:
+ * batch encoding of every query element into its own plaintext, D ct x pt products per
+ * batch): for every group g of B queries and every model ciphertext m, batch-encode the
+ * query plaintext (slot scatter and inverse transform mod t, centred lift), multiply it
+ * into ciphertext m and accumulate (with the scaling op of the parameters); when r > 1,
+ * fold the r blocks with log2(r) rotate-and-sum steps (Galois automorphism and hybrid key
+ * switching).
+ *   d_score_ct  out, device, uint32 [G][2][L][N], coefficient domain: the client -> server
+ *               message.
+ * Q must be <= the session's max_Q.  Asynchronous on `stream`; the scratch comes from the
+ * session's workspace, so a call on another stream than the session's previous call first
+ * waits (on the device) for that call.  EPHDC_ERR_BUFFER when the session has no workspace.
  */
 ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_t Q,
                                    uint32_t* d_score_ct, void* stream);
@@ -228,10 +272,10 @@ ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t 
                                 uint32_t values_per_thread, uint32_t mode);
 
 /*
- * Bound (bytes) on the split path's plaintext buffer (0: 512 MiB).  The model range is
- * scored in chunks whose plaintexts fit it, each chunk's MAC adding into the sums of the
- * previous ones; the buffer always holds at least one plaintext per query group of max_Q.
- * Frees the current buffer (after waiting for the device); results do not depend on it.
+ * Bound (bytes) on the split path's plaintext chunk inside the workspace (0: all of it).
+ * The model range is scored in chunks whose plaintexts fit it, each chunk's MAC adding into
+ * the sums of the previous ones; a chunk always holds at least one plaintext per query
+ * group of max_Q.  Results do not depend on it.
  */
 ephdc_status ephdc_session_set_chunk_bytes(ephdc_session* s, size_t bytes);
 

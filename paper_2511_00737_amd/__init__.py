@@ -32,7 +32,11 @@ class _CParams(C.Structure):
     _fields_ = [("N", C.c_uint32), ("L", C.c_uint32), ("alpha", C.c_uint32), ("dnum", C.c_uint32),
                 ("q", C.POINTER(C.c_uint32)), ("p", C.POINTER(C.c_uint32)), ("t", C.c_uint32),
                 ("F", C.c_uint32), ("D", C.c_uint32), ("K", C.c_uint32), ("r", C.c_uint32),
-                ("qbits", C.c_uint32), ("qshift", C.c_uint32)]
+                ("qbits", C.c_int32), ("qshift", C.c_uint32), ("scheme", C.c_uint32),
+                ("scale_every", C.c_uint32), ("scale_shift", C.c_uint32)]
+
+
+SCHEMES = {"bfv": 0, "bfv-r": 1, "bgv": 2}
 
 
 class _CRequest(C.Structure):
@@ -67,8 +71,9 @@ def lib() -> C.CDLL:
             "ephdc_encrypt_model": (C.c_int, [P, i8p, i8p, C.c_uint64, u32p]),
             "ephdc_decrypt_scores": (C.c_int, [P, i8p, u32p, C.c_uint32, i32p, i32p]),
             "ephdc_decrypt_scores_at": (C.c_int, [P, i8p, u32p, C.c_uint32, C.c_uint32, i32p, i32p]),
+            "ephdc_workspace_bytes": (C.c_size_t, [P, C.c_uint32]),
             "ephdc_session_create": (C.c_int, [P, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_uint32,
-                                               C.c_void_p, C.POINTER(C.c_void_p)]),
+                                               C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
             "ephdc_session_destroy": (C.c_int, [C.c_void_p]),
             "ephdc_session_device_bytes": (C.c_size_t, [C.c_void_p]),
             "ephdc_encode_queries": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
@@ -137,6 +142,9 @@ class Params:
     t: int = T_PLAIN
     qbits: int = 1
     qshift: int = 0
+    scheme: str = "bfv"     # "bfv", "bfv-r" (rounded scaling) or "bgv"
+    scale_every: int = 0    # HE-aware scaling after every g accumulations (0: never)
+    scale_shift: int = 0    # ... by the inverse of 2^scale_shift mod t
     _keep: list = field(default_factory=list, repr=False, compare=False)
 
     @property
@@ -152,7 +160,7 @@ class Params:
         pa = (C.c_uint32 * max(1, len(self.p)))(*self.p)
         self._keep[:] = [qa, pa]
         return _CParams(self.N, len(self.q), len(self.p), self.dnum, qa, pa, self.t, self.F, self.D, self.K,
-                        self.r, self.qbits, self.qshift)
+                        self.r, self.qbits, self.qshift, SCHEMES[self.scheme], self.scale_every, self.scale_shift)
 
 
 def default_primes(N: int, count: int, skip: int = 0) -> list[int]:
@@ -189,6 +197,11 @@ def ephdc_hv_stride(prm: Params, Q: int) -> int:
 def ephdc_galois_key_words(prm: Params) -> int:
     c = prm.c()
     return lib().ephdc_galois_key_words(C.byref(c))
+
+
+def ephdc_workspace_bytes(prm: Params, max_Q: int) -> int:
+    c = prm.c()
+    return lib().ephdc_workspace_bytes(C.byref(c), max_Q)
 
 
 def ephdc_gaussian_cdt() -> list[int]:
@@ -273,16 +286,31 @@ def _words(t) -> int:
 
 
 class Session:
-    """Owns an ephdc_session: device-resident evaluation-domain model and keys."""
+    """Owns an ephdc_session: device-resident evaluation-domain model and keys.
 
-    def __init__(self, prm: Params, d_model_ct, d_galois_keys=None, max_Q: int = 4096, stream=None):
+    workspace: True allocates a device tensor of ephdc_workspace_bytes(prm, max_Q) bytes
+    (kept alive here and lent to the session); a uint8 device tensor is lent as given;
+    None creates a session without one (batches, serving and the static-scratch entry
+    point bring their own scratch)."""
+
+    def __init__(self, prm: Params, d_model_ct, d_galois_keys=None, max_Q: int = 4096, stream=None,
+                 workspace=True):
+        import torch
         self.prm = prm
         self._c = prm.c()
         h = C.c_void_p()
         gk_ptr = _dptr(d_galois_keys) if d_galois_keys is not None else None
         gk_words = _words(d_galois_keys) if d_galois_keys is not None else 0
+        if workspace is True:
+            nbytes = lib().ephdc_workspace_bytes(C.byref(self._c), max_Q)
+            if nbytes == 0:
+                _check(lib().ephdc_check_params(C.byref(self._c)) or ERR_ARG)
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.workspace = workspace if workspace is not None and workspace is not False else None
+        ws_ptr = _dptr(self.workspace) if self.workspace is not None else None
+        ws_bytes = self.workspace.numel() * self.workspace.element_size() if self.workspace is not None else 0
         _check(lib().ephdc_session_create(C.byref(self._c), _dptr(d_model_ct), _words(d_model_ct), gk_ptr,
-                                          gk_words, max_Q, _stream(stream), C.byref(h)))
+                                          gk_words, max_Q, ws_ptr, ws_bytes, _stream(stream), C.byref(h)))
         self.handle = h
         self.max_Q = max_Q
 
@@ -329,8 +357,9 @@ class Session:
         return lib().ephdc_num_groups(C.byref(self._c), Q)
 
 
-def ephdc_session_create(prm: Params, d_model_ct, d_galois_keys=None, max_Q: int = 4096, stream=None) -> Session:
-    return Session(prm, d_model_ct, d_galois_keys, max_Q, stream)
+def ephdc_session_create(prm: Params, d_model_ct, d_galois_keys=None, max_Q: int = 4096, stream=None,
+                         workspace=True) -> Session:
+    return Session(prm, d_model_ct, d_galois_keys, max_Q, stream, workspace)
 
 
 def ephdc_session_destroy(s: Session) -> None:

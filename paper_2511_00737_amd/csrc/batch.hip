@@ -85,7 +85,8 @@ void drop_graph(ephdc_batch* b) {
 // N = 16384 and 16 there (the shapes measured fastest for the split path).
 int batch_le(const ephdc_batch* b, int logn) { return b->vpt ? ilog2(b->vpt) : (logn >= 14 ? 4 : 3); }
 
-bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q; }
+// Requests of one list share N, the ciphertext primes and t (their transform tables).
+bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q && a.t == b.t; }
 
 // Splits the requests into parameter sets.
 void group_parts(ephdc_batch* b) {
@@ -130,6 +131,7 @@ void build_part(const ephdc_batch* b, Part& pt) {
     d.r = P.r;
     d.B = P.B();
     d.hv_stride = G * P.B();
+    d.scale = scale_op(rq.session);
     pt.rd.push_back(d);
     // S near-equal ranges of at most seg_len ciphertexts, none of them empty
     const uint32_t n = (M + b->seg_len - 1) / b->seg_len;

@@ -27,14 +27,20 @@ ephdc_status fail(ephdc_status st, const std::string& msg) {
 ephdc_status ParamSet::load(const ephdc_params* prm) {
   if (!prm) return fail(EPHDC_ERR_ARG, "params is NULL");
   N = prm->N; L = prm->L; alpha = prm->alpha; dnum = prm->dnum; t = prm->t;
-  F = prm->F; D = prm->D; K = prm->K; r = prm->r; qbits = prm->qbits; qshift = prm->qshift;
+  F = prm->F; D = prm->D; K = prm->K; r = prm->r; qshift = prm->qshift;
+  scheme = prm->scheme; scale_every = prm->scale_every; scale_shift = prm->scale_shift;
+  if (prm->qbits < 1 || prm->qbits > 8) return fail(EPHDC_ERR_PARAMS, "qbits must be in [1, 8]");
+  qbits = (uint32_t)prm->qbits;
   if (N < 8 || N > 32768 || (N & (N - 1))) return fail(EPHDC_ERR_PARAMS, "N must be a power of two in [8, 32768]");
   logn = ilog2(N);
   if (L < 1 || L > 16) return fail(EPHDC_ERR_PARAMS, "L must be in [1, 16]");
   if (alpha > 4) return fail(EPHDC_ERR_PARAMS, "alpha must be <= 4");
   if (!prm->q || (alpha && !prm->p)) return fail(EPHDC_ERR_ARG, "prime list is NULL");
-  if (t != 65537) return fail(EPHDC_ERR_PARAMS, "t must be 65537");
+  if (t < 257 || !is_prime_u64(t)) return fail(EPHDC_ERR_PARAMS, "t must be a prime >= 257");
   if (t % (2 * N) != 1) return fail(EPHDC_ERR_PARAMS, "t must be 1 mod 2N");
+  if ((uint64_t)N * t >= (1ull << 32)) return fail(EPHDC_ERR_PARAMS, "N * t must be below 2^32");
+  if (scheme > EPHDC_BGV) return fail(EPHDC_ERR_PARAMS, "scheme must be EPHDC_BFV, EPHDC_BFV_ROUNDED or EPHDC_BGV");
+  if (scale_shift > 31) return fail(EPHDC_ERR_PARAMS, "scale_shift must be < 32");
   q.assign(prm->q, prm->q + L);
   p.assign(alpha ? prm->p : prm->q, alpha ? prm->p + alpha : prm->q);
   std::vector<uint32_t> all(q);
@@ -51,10 +57,10 @@ ephdc_status ParamSet::load(const ephdc_params* prm) {
   if (K < 1 || D < 1 || F < 1) return fail(EPHDC_ERR_PARAMS, "F, D, K must be positive");
   if (r < 1 || (r & (r - 1))) return fail(EPHDC_ERR_PARAMS, "r must be a power of two");
   if (N / (2 * r) < K) return fail(EPHDC_ERR_PARAMS, "N/(2r) must be >= K (at least one query per row)");
-  if (qbits < 1 || qbits > 8) return fail(EPHDC_ERR_PARAMS, "qbits must be in [1, 8]");
   if (qshift > 31) return fail(EPHDC_ERR_PARAMS, "qshift must be <= 31");
   if (r > 1) {
     if (alpha < 1 || dnum < 1 || dnum > L) return fail(EPHDC_ERR_PARAMS, "r > 1 needs alpha >= 1 and 1 <= dnum <= L");
+    if (scheme == EPHDC_BGV) return fail(EPHDC_ERR_PARAMS, "BGV takes r = 1 (no key switching)");
   }
   return EPHDC_OK;
 }
@@ -118,8 +124,7 @@ struct HostTables {
       uint32_t m = P.modulus(i);
       mod.emplace_back(P.N, m, root_of_unity(2 * P.N, m));
     }
-    uint32_t zeta = (uint32_t)powmod64(3, (P.t - 1) / (2 * P.N), P.t);
-    tt = HostNtt(P.N, P.t, zeta);
+    tt = HostNtt(P.N, P.t, root_of_unity(2 * P.N, P.t));
     pos = slot_positions(P.N);
   }
 };
@@ -165,6 +170,11 @@ struct Big {
       r.w.push_back((uint32_t)v);
     }
     r.trim(); return r;
+  }
+  uint32_t mod(uint32_t m) const {
+    uint64_t r = 0;
+    for (size_t i = w.size(); i-- > 0;) r = ((r << 32) | w[i]) % m;
+    return (uint32_t)r;
   }
   int cmp(const Big& o) const {
     if (w.size() != o.w.size()) return w.size() < o.w.size() ? -1 : 1;
@@ -300,6 +310,8 @@ ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, cons
   const uint32_t N = P.N, L = P.L, M = P.M();
   const auto cdt = gaussian_cdt();
   std::vector<uint32_t> dl(L);
+  uint64_t rt = 1;  // Q mod t (rounded BFV: round(Q*mu/t) = Delta*mu + floor((2*rt*mu + t) / 2t))
+  for (uint32_t x : P.q) rt = rt * (x % P.t) % P.t;
   std::vector<std::vector<uint32_t>> S(L);  // secret key in each limb's evaluation domain
   for (uint32_t l = 0; l < L; ++l) {
     dl[l] = delta_mod(P, l);
@@ -338,8 +350,16 @@ ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, cons
       uint32_t* c0 = model_ct + (((size_t)m * 2 + 0) * L + l) * N;
       uint32_t* c1 = model_ct + (((size_t)m * 2 + 1) * L + l) * N;
       for (uint32_t k = 0; k < N; ++k) {
-        uint64_t v = (uint64_t)(ql - as[k]) + (e[k] < 0 ? ql + e[k] : e[k]) + (uint64_t)dl[l] * mu[k] % ql;
-        c0[k] = (uint32_t)(v % ql);
+        const uint64_t err = e[k] < 0 ? ql + e[k] : e[k];
+        uint64_t msg;
+        if (P.scheme == EPHDC_BGV) {  // t*e + centred(mu)
+          const uint64_t mc = mu[k] > P.t / 2 ? ql - (P.t - mu[k]) : mu[k];
+          msg = (err * P.t + mc) % ql;
+        } else {  // e + Delta*mu, plus the rounding of Q*mu/t for the rounded variant
+          msg = (err + (uint64_t)dl[l] * mu[k]) % ql;
+          if (P.scheme == EPHDC_BFV_ROUNDED) msg += (2 * rt * mu[k] + P.t) / (2 * (uint64_t)P.t);
+        }
+        c0[k] = (uint32_t)(((uint64_t)(ql - as[k]) + msg) % ql);
         c1[k] = a[k];
       }
     }
@@ -376,6 +396,7 @@ ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, 
     Qhat_inv[l] = inv_mod(r, P.q[l]);
   }
   const Big twoQ = Qbig.mul(2);
+  const uint32_t Qmod_t = Qbig.mod(t);
   std::vector<std::vector<uint32_t>> S(L);
   for (uint32_t l = 0; l < L; ++l) {
     S[l].resize(N);
@@ -400,7 +421,16 @@ ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, 
     // sum_l y_l*t/q_l minus a multiple of t; split y_l*t = a_l*q_l + b_l and round the
     // fraction sum_l b_l*Qhat_l / Q exactly with big integers.
     std::vector<uint32_t> mu(N);
-    for (uint32_t k = 0; k < N; ++k) {
+    for (uint32_t k = 0; k < N && P.scheme == EPHDC_BGV; ++k) {
+      // BGV: x = sum_l y_l * Qhat_l reduced mod Q, centred, then mod t
+      Big X;
+      for (uint32_t l = 0; l < L; ++l)
+        X = X.add(Qhat[l].mul((uint32_t)((uint64_t)x[l][k] * Qhat_inv[l] % P.q[l])));
+      while (X.cmp(Qbig) >= 0) X = X.sub(Qbig);
+      const uint32_t xt = X.mod(t);
+      mu[k] = X.mul(2).cmp(Qbig) > 0 ? (uint32_t)(((uint64_t)xt + t - Qmod_t) % t) : xt;
+    }
+    for (uint32_t k = 0; k < N && P.scheme != EPHDC_BGV; ++k) {
       uint64_t A = 0;
       Big Sf;
       for (uint32_t l = 0; l < L; ++l) {

@@ -23,6 +23,8 @@ template <class F>
 inline hipError_t dispatch(int logn, int le, F&& f) {
   using std::integral_constant;
   switch (logn * 16 + le) {
+    case 11 * 16 + 0:
+    case 11 * 16 + 3: return f(integral_constant<int, 11>{}, integral_constant<int, 3>{});
     case 12 * 16 + 0:
     case 12 * 16 + 3: return f(integral_constant<int, 12>{}, integral_constant<int, 3>{});
     case 13 * 16 + 3: return f(integral_constant<int, 13>{}, integral_constant<int, 3>{});

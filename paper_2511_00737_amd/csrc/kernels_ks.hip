@@ -158,7 +158,7 @@ hipError_t prepare_ks_kernels() {
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_moddown_ntt<LN, LEv>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
   };
-  for (int logn = 12; logn <= 14; ++logn) dispatch(logn, shape);
+  for (int logn = 11; logn <= 14; ++logn) dispatch(logn, shape);
   return e;
 }
 

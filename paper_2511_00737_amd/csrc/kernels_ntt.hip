@@ -178,7 +178,23 @@ struct MacItem {
   const uint32_t* model;  // [M][2][L][N] evaluation domain, Montgomery form
   uint32_t* slot;         // partial sums of this item
   uint32_t L, m0, m1, l0;
+  ScaleOp scale;          // HE-aware scaling (pow == nullptr: none)
 };
+
+// Weight of plaintext m in limb l under the scaling op: the transformed plaintext (values
+// in [0, 4q)) is multiplied by c^e(m), back in [0, 2q).  The weights distribute the
+// accumulator's scalings over its terms, which gives the same residues in any order of
+// the additions and across work items.
+template <int E>
+__device__ __forceinline__ void apply_scale(uint32_t (&p)[E], const ScaleOp& so, uint32_t m, uint32_t l,
+                                            const PrimeConst& pc) {
+  if (so.pow == nullptr) return;
+  const uint32_t e = so.exponent(m);
+  if (e == 0) return;
+  const uint32_t w = so.pow[l * (so.nb + 1) + e];
+#pragma unroll
+  for (int i = 0; i < E; ++i) p[i] = mont_mul(p[i], w, pc.m, pc.mneg_inv);
+}
 
 template <int LG, int E>
 __device__ __forceinline__ void zero_acc(uint32_t (&acc)[2][LG][E]) {
@@ -241,6 +257,7 @@ __device__ __forceinline__ void score_item(const MacItem& it, const QuerySrc& q,
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = lift(mu[i], t, pc.m);
       ntt_forward<LOGN, LE>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      apply_scale(p, it.scale, m, l, pc);
       const uint32_t m2 = 2 * pc.m;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -346,6 +363,7 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = pc.m + (uint32_t)cur[i];  // |cur| <= t/2: in [0, 2m), = cur mod m
       ntt_forward<LOGN, LE, TL, true>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      apply_scale(p, it.scale, m, l, pc);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -427,6 +445,7 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = pc.m + (uint32_t)cur[i];  // |cur| <= t/2: in [0, 2m), = cur mod m
       ntt_forward<LOGN, LE, TL, true>(p, tid, fwd_tw + (size_t)l * N, pc, b);
+      apply_scale(p, it.scale, m, l, pc);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -493,6 +512,7 @@ __device__ __forceinline__ MacItem single_item(const ScoreArgs& a, uint32_t w, u
   it.m0 = a.m_base + split * a.mchunk;
   it.m1 = min(a.m_base + a.m_len, it.m0 + a.mchunk);
   it.l0 = lgi * LG;
+  it.scale = a.scale;
   return it;
 }
 
@@ -591,7 +611,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_score_list(ListArgs a) {
     const Segment sg = a.segs[w / a.NLG];
     const ReqDesc r = a.reqs[sg.req];
     restage<LOGN, LE>(r.scatter, staged, tid);
-    const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG};
+    const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG,
+                      r.scale};
     score_item<LOGN, LE, LG>(it, query_src(r, sg.g), r.scatter, a.ts, a.fwd_tw, a.pcs, tid, b);
   }
 }
@@ -631,7 +652,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
     if (w == 0xFFFFFFFFu) continue;
     const Segment sg = a.segs[w / a.NLG];
     const ReqDesc r = a.reqs[sg.req];
-    const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG};
+    const MacItem it{r.model, a.partial + (size_t)sg.slot * 2 * a.L * S::N, a.L, sg.m0, sg.m1, (w % a.NLG) * LG,
+                      r.scale};
     if constexpr (mac_lds_twiddles<LOGN, LE, LG>()) {
       if (it.l0 != staged_l) {  // every request of a list shares the moduli and their tables
         lds_barrier();          // every wave is done with the previous limb's table
@@ -775,7 +797,8 @@ hipError_t prepare_kernels() {
   static hipError_t once = [] {
     hipError_t ks = prepare_ks_kernels();
     if (ks != hipSuccess) return ks;
-    hipError_t e = prepare_shape<12, 3>();
+    hipError_t e = prepare_shape<11, 3>();
+    if (e == hipSuccess) e = prepare_shape<12, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 4>();
     if (e == hipSuccess) e = prepare_shape<14, 4>();
@@ -786,11 +809,11 @@ hipError_t prepare_kernels() {
 }
 
 bool supported_shape(int logn, int le) {
-  return le == 0 || (logn == 12 && le == 3) || (logn == 13 && (le == 3 || le == 4)) ||
+  return le == 0 || ((logn == 11 || logn == 12) && le == 3) || (logn == 13 && (le == 3 || le == 4)) ||
          (logn == 14 && (le == 4 || le == 5));
 }
 
-bool supported_logn(int logn) { return logn >= 12 && logn <= 14; }
+bool supported_logn(int logn) { return logn >= 11 && logn <= 14; }
 
 
 static PolyMap make_map(const BatchMap& m, uint32_t N) {

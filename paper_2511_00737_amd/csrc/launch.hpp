@@ -8,6 +8,20 @@
 
 namespace ephdc_dev {
 
+// HE-aware scaling of the multiply-accumulate: after every g additions (model ciphertexts
+// in order, nb complete blocks) the accumulator is multiplied by the plaintext scalar c.
+// The product of ciphertext m is therefore weighted by c^e(m), e(m) = nb - floor(m/g) for
+// m in a complete block and 0 in the trailing partial block; pow[l * (nb + 1) + e] holds
+// c^e * 2^32 mod q_l (Montgomery form).  pow == nullptr: no scaling.
+struct ScaleOp {
+  const uint32_t* pow;
+  uint32_t g, nb;
+  __host__ __device__ uint32_t exponent(uint32_t m) const {
+    const uint32_t b = m / g;
+    return b < nb ? nb - b : 0u;
+  }
+};
+
 // Arguments of the fused scoring kernel (and the debug plaintext kernel).
 struct ScoreArgs {
   const uint32_t* model;    // [M][2][L][N] evaluation domain, Montgomery form
@@ -28,6 +42,7 @@ struct ScoreArgs {
   uint32_t accumulate;
   // XCD-aware order of the MAC / fused work items (see XcdMap); xcd = 0: block = item
   uint32_t xcd, nitems;
+  ScaleOp scale;
 };
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin (workgroup d runs on XCD
@@ -58,6 +73,7 @@ struct ReqDesc {
   const uint32_t* scatter;  // [N] slot source table of the request's (K, r)
   uint32_t* out;
   uint32_t D, r, B, hv_stride;
+  ScaleOp scale;
 };
 
 // A segment: model ciphertexts [m0, m1) of group g of request `req`; its plaintexts sit at
@@ -154,6 +170,7 @@ using ephdc_dev::RotateArgs;
 
 using ephdc_dev::PrimeConst;
 using ephdc_dev::ScoreArgs;
+using ephdc_dev::ScaleOp;
 
 // Addressing of batched transforms: polynomial p is read from in + (p / in_per) * in_stride +
 // (p % in_per) * N (likewise written); in_per / out_per = 0 means densely packed.

@@ -18,6 +18,8 @@ ephdc_status fail(ephdc_status st, const std::string& msg);
 struct ParamSet {
   uint32_t N = 0, L = 0, alpha = 0, dnum = 0, t = 0, F = 0, D = 0, K = 0, r = 0;
   uint32_t qbits = 1, qshift = 0;
+  uint32_t scheme = EPHDC_BFV;              // EPHDC_BFV, EPHDC_BFV_ROUNDED or EPHDC_BGV
+  uint32_t scale_every = 0, scale_shift = 0;  // HE-aware scaling: g and s (g = 0: off)
   int logn = 0;
   std::vector<uint32_t> q, p;  // ciphertext primes, special primes
 
@@ -30,6 +32,13 @@ struct ParamSet {
   uint32_t digit_size() const { return dnum ? (L + dnum - 1) / dnum : 0; }
   uint32_t nmod() const { return L + alpha; }
   uint32_t modulus(uint32_t i) const { return i < L ? q[i] : p[i - L]; }
+  // Scaling op: full blocks of scale_every model ciphertexts (each followed by one scaling)
+  // and the plaintext scalar, the centred representative of (2^scale_shift)^-1 mod t.
+  uint32_t scale_blocks() const { return scale_every ? M() / scale_every : 0; }
+  int64_t scale_const() const {
+    const uint64_t c = powmod64(inv_mod(2, t), scale_shift, t);
+    return c > t / 2 ? (int64_t)c - (int64_t)t : (int64_t)c;
+  }
 
   // Validates and fills from the public struct; returns EPHDC_OK or an error (message set).
   ephdc_status load(const ephdc_params* prm);

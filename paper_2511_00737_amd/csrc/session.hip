@@ -12,6 +12,8 @@ using namespace ephdc;
 
 namespace {
 
+using ephdc::scale_op;
+
 void drop_events(ephdc_session* s) {
   for (auto& v : s->ev) {
     for (auto& pr : v) {
@@ -42,10 +44,11 @@ void timed_end(ephdc_session* s, int stage, hipEvent_t start, hipStream_t hs) {
 void free_session(ephdc_session* s) {
   if (!s) return;
   drop_events(s);
-  void* ptrs[] = {s->d_fwd,  s->d_inv,     s->d_inv_t, s->d_pc,   s->d_scatter, s->d_model,
-                  s->d_gk,   s->d_partial, s->d_pt,    s->d_perm, s->d_ksc,     s->d_rot};
+  void* ptrs[] = {s->d_fwd, s->d_inv, s->d_inv_t, s->d_pc,   s->d_scatter,
+                  s->d_model, s->d_gk, s->d_spow,  s->d_perm, s->d_ksc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (s->done) (void)hipEventDestroy(s->done);
   delete s;
 }
 
@@ -81,12 +84,13 @@ Schedule schedule(const ephdc_session* s, uint32_t Q) {
   return sc;
 }
 
-ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, const Schedule& sc) {
+ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, const Schedule& sc,
+                     const Workspace* ws) {
   const ParamSet& P = s->P;
   ScoreArgs a{};
   a.model = s->d_model;
   a.hv = d_hv;
-  a.partial = s->d_partial;
+  a.partial = ws ? ws->partial : nullptr;
   a.scatter = s->d_scatter;
   a.fwd_tw = s->d_fwd;
   a.inv_t = s->d_inv_t;
@@ -104,21 +108,22 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   a.NLG = s->nlg;
   a.m_base = 0;
   a.m_len = P.M();
-  a.pt = s->d_pt;
+  a.pt = ws ? ws->pt : nullptr;
   a.accumulate = 0;
+  a.scale = scale_op(s);
   return a;
 }
 
-constexpr size_t kPtBytes = (size_t)512 << 20;  // default bound on the split path's plaintext buffer
+constexpr size_t kPtBytes = (size_t)512 << 20;  // default plaintext chunk of ephdc_workspace_bytes
 
 // Split path: the model range is processed in chunks of m_len ciphertexts so that the
-// lifted plaintexts of a chunk (G x m_len x N int32) fit the session's buffer; the MAC
+// lifted plaintexts of a chunk (G x m_len x N int32) fit the workspace's buffer; the MAC
 // kernel of every chunk after the first adds into the stored partial sums.
-hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, hipStream_t hs) {
+hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, size_t pt_cap, hipStream_t hs) {
   const ParamSet& P = s->P;
   const uint32_t M = P.M();
-  if (sc.G > s->pt_cap) return hipErrorInvalidValue;  // cannot happen: cap >= G(max_Q) >= G
-  const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, s->pt_cap / sc.G));
+  if (sc.G > pt_cap) return hipErrorInvalidValue;  // cannot happen: cap >= G(max_Q) >= G
+  const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, pt_cap / sc.G));
   const uint32_t blocks_enc = std::max<uint32_t>(1, s->target_blocks);
   for (uint32_t base = 0; base < M; base += mc) {
     const uint32_t len = std::min(mc, M - base);
@@ -207,11 +212,118 @@ std::vector<uint32_t> automorphism_perms(const ParamSet& P) {
 
 namespace ephdc {
 
+size_t score_partial_words(const ephdc_session* s, uint32_t Q) {
+  const Schedule sc = schedule(s, Q);
+  return (size_t)sc.G * sc.S * 2 * s->P.L * s->P.N;
+}
+
+ScaleOp scale_op(const ephdc_session* s) {
+  ScaleOp so{};
+  so.pow = s->d_spow;
+  so.g = s->P.scale_every ? s->P.scale_every : 1;
+  so.nb = s->P.scale_blocks();
+  return so;
+}
+
 // Words of the rotation workspace for G groups: acc, R [G][2][L][N]; D [G][L][N];
 // Y [G][dnum][nmod][N]; KS [G][2][nmod][N]; XP [G][2][alpha][N].
 size_t rotate_words(const ParamSet& P, uint32_t G) {
   const size_t N = P.N;
   return (size_t)G * N * (4 * P.L + P.L + (size_t)P.dnum * P.nmod() + 2 * P.nmod() + 2 * P.alpha);
+}
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsSizes {
+  size_t partial_words, rot_words, gmax;
+};
+
+// G*S <= target/nlg + G for any schedule, so the partial sums cover every target up to
+// kMaxBlocks workgroups.
+WsSizes ws_sizes(const ParamSet& P, uint32_t max_Q) {
+  WsSizes z;
+  z.gmax = P.G(max_Q);
+  z.partial_words = ((size_t)kMaxBlocks + z.gmax) * 2 * P.L * P.N;
+  z.rot_words = P.r > 1 ? rotate_words(P, (uint32_t)z.gmax) : 0;
+  return z;
+}
+
+}  // namespace
+
+size_t workspace_min_bytes(const ParamSet& P, uint32_t max_Q) {
+  const WsSizes z = ws_sizes(P, max_Q);
+  return align256(z.partial_words * 4) + align256(z.rot_words * 4) + z.gmax * P.N * 4;
+}
+
+size_t workspace_default_bytes(const ParamSet& P, uint32_t max_Q) {
+  const WsSizes z = ws_sizes(P, max_Q);
+  const size_t cap = std::max<size_t>(z.gmax, std::min<size_t>(z.gmax * P.M(), kPtBytes / (4 * (size_t)P.N)));
+  return align256(z.partial_words * 4) + align256(z.rot_words * 4) + cap * P.N * 4;
+}
+
+ephdc_status workspace_layout(const ParamSet& P, uint32_t max_Q, void* base, size_t bytes, Workspace* out) {
+  const WsSizes z = ws_sizes(P, max_Q);
+  if ((uintptr_t)base & 255) return fail(EPHDC_ERR_ARG, "the workspace must be 256-byte aligned");
+  if (bytes < workspace_min_bytes(P, max_Q))
+    return fail(EPHDC_ERR_BUFFER, "workspace of " + std::to_string(bytes) + " bytes, needs at least " +
+                                      std::to_string(workspace_min_bytes(P, max_Q)) + " (ephdc_workspace_bytes)");
+  char* p = static_cast<char*>(base);
+  Workspace w;
+  w.partial = reinterpret_cast<uint32_t*>(p);
+  w.partial_words = z.partial_words;
+  p += align256(z.partial_words * 4);
+  w.rot = z.rot_words ? reinterpret_cast<uint32_t*>(p) : nullptr;
+  p += align256(z.rot_words * 4);
+  w.pt = reinterpret_cast<int32_t*>(p);
+  w.pt_cap = (bytes - (size_t)(p - static_cast<char*>(base))) / (4 * (size_t)P.N);
+  *out = w;
+  return EPHDC_OK;
+}
+
+ephdc_status score_with(ephdc_session* s, const Workspace& ws, const int8_t* d_hv, uint32_t Q,
+                        uint32_t* d_score_ct, hipStream_t hs) {
+  const ParamSet& P = s->P;
+  Schedule sc = schedule(s, Q);
+  if ((size_t)sc.G * sc.S * 2 * P.L * P.N > ws.partial_words) return fail(EPHDC_ERR_BUFFER, "scratch too small");
+  if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
+  // a call on another stream than the previous one waits for the previous one, whose
+  // scratch it reuses
+  if (s->done_set && s->done_stream != hs) HIP_TRY(hipStreamWaitEvent(hs, s->done, 0), "stream ordering");
+  ScoreArgs a = score_args(s, d_hv, Q, sc, &ws);
+  if (s->split) {
+    size_t cap = ws.pt_cap;
+    if (s->pt_bytes) cap = std::max<size_t>(sc.G, std::min(cap, s->pt_bytes / (4 * (size_t)P.N)));
+    HIP_TRY(score_split(s, a, sc, cap, hs), "split score launch");
+  } else {
+    hipEvent_t t0 = timed_begin(s, hs);
+    HIP_TRY(launch_score(P.logn, (int)s->le, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
+    timed_end(s, kStFused, t0, hs);
+  }
+  if (P.r == 1) {
+    hipEvent_t t1 = timed_begin(s, hs);
+    HIP_TRY(launch_finish(P.logn, true, ws.partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
+            "finish launch");
+    timed_end(s, kStFinish, t1, hs);
+  } else {
+    // r > 1: sum the partials in the evaluation domain, fold the r blocks of every row with
+    // log2 r rotations, then return to the coefficient domain
+    RotateArgs ra = rotate_args(s, ws.rot, sc.G);
+    hipEvent_t t1 = timed_begin(s, hs);
+    HIP_TRY(launch_finish(P.logn, false, ws.partial, ra.acc, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
+            "finish launch");
+    timed_end(s, kStFinish, t1, hs);
+    hipEvent_t t2 = timed_begin(s, hs);
+    for (uint32_t i = 0; i < P.log2r(); ++i) HIP_TRY(launch_rotate_step(P.logn, ra, i, hs), "rotate launch");
+    HIP_TRY(launch_inv_batch(P.logn, ra.acc, d_score_ct, (size_t)sc.G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs),
+            "output transform launch");
+    timed_end(s, kStRotate, t2, hs);
+  }
+  HIP_TRY(hipEventRecord(s->done, hs), "completion event");
+  s->done_stream = hs;
+  s->done_set = true;
+  return EPHDC_OK;
 }
 
 RotateArgs rotate_args(const ephdc_session* s, uint32_t* workspace, uint32_t G) {
@@ -239,16 +351,22 @@ RotateArgs rotate_args(const ephdc_session* s, uint32_t* workspace, uint32_t G) 
 
 extern "C" {
 
+size_t ephdc_workspace_bytes(const ephdc_params* prm, uint32_t max_Q) {
+  ParamSet P;
+  if (P.load(prm) != EPHDC_OK || max_Q == 0) return 0;
+  return workspace_default_bytes(P, max_Q);
+}
+
 ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
-                                  const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q, void* stream,
-                                  ephdc_session** out) {
+                                  const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q,
+                                  void* d_workspace, size_t ws_bytes, void* stream, ephdc_session** out) {
   if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
   *out = nullptr;
   ParamSet P;
   ephdc_status st = P.load(prm);
   if (st != EPHDC_OK) return st;
   if (!d_model_ct) return fail(EPHDC_ERR_ARG, "model is NULL");
-  if (!supported_logn(P.logn)) return fail(EPHDC_ERR_UNSUPPORTED, "kernels implement N in {4096, 8192, 16384}");
+  if (!supported_logn(P.logn)) return fail(EPHDC_ERR_UNSUPPORTED, "kernels implement N in {2048, 4096, 8192, 16384}");
   for (uint32_t qi : P.q)
     if (qi < (1u << 29)) return fail(EPHDC_ERR_UNSUPPORTED, "the device kernels take ciphertext primes in [2^29, 2^30)");
   if (P.r > 1 && !d_galois_keys) return fail(EPHDC_ERR_NOKEY, "r > 1 needs Galois keys");
@@ -256,12 +374,22 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   if (model_words < (size_t)P.M() * 2 * P.L * P.N) return fail(EPHDC_ERR_BUFFER, "model buffer shorter than [M][2][L][N]");
   if (P.r > 1 && gk_words < (size_t)P.log2r() * P.dnum * 2 * P.nmod() * P.N)
     return fail(EPHDC_ERR_BUFFER, "Galois key buffer shorter than [log2 r][dnum][2][L+alpha][N]");
+  Workspace ws;
+  if (d_workspace && (st = workspace_layout(P, max_Q, d_workspace, ws_bytes, &ws)) != EPHDC_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
   HIP_TRY(prepare_kernels(), "kernel setup");
 
   ephdc_session* s = new ephdc_session();
   s->P = P;
   s->max_Q = max_Q;
+  s->ws = ws;
+  s->has_ws = d_workspace != nullptr;
+  if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    s->done = nullptr;
+    free_session(s);
+    return fail(EPHDC_ERR_HIP, "event creation failed");
+  }
   (void)hipGetDevice(&s->device);
   // default schedule (measured on MI355X at N = 8192, L = 4, 4096 queries): split path,
   // 8 values per thread, one limb per MAC work item; one MAC workgroup per compute unit
@@ -285,8 +413,7 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
     pcs[i] = make_const(T);
   }
   {
-    uint32_t zeta = (uint32_t)powmod64(3, (P.t - 1) / (2 * N), P.t);
-    HostNtt Tt(N, P.t, zeta);
+    HostNtt Tt(N, P.t, root_of_unity(2 * N, P.t));
     for (uint32_t k = 0; k < N; ++k) invt[k] = (uint32_t)(((uint64_t)Tt.iw[k] << 32) % P.t);
     s->pct = make_const(Tt);
   }
@@ -295,9 +422,18 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   const size_t M = P.M();
   const size_t model_copy_words = M * 2 * P.L * N;
   const size_t key_words = P.r > 1 ? (size_t)P.log2r() * P.dnum * 2 * nm * N : 0;
-  const uint32_t Gmax = P.G(max_Q);
-  // G*S <= target/nlg + G for any schedule, so this covers every target up to kMaxBlocks
-  s->partial_words = ((size_t)kMaxBlocks + (size_t)Gmax) * 2 * P.L * N;
+  // scaling op: c^e * 2^32 mod q_l for e = 0 .. scale_blocks
+  std::vector<uint32_t> spow;
+  if (P.scale_every) {
+    const uint32_t nb = P.scale_blocks();
+    const int64_t c = P.scale_const();
+    spow.resize((size_t)P.L * (nb + 1));
+    for (uint32_t l = 0; l < P.L; ++l) {
+      const uint64_t ql = P.q[l], cl = c < 0 ? ql - (uint64_t)(-c) % ql : (uint64_t)c % ql;
+      uint64_t pw = 1;
+      for (uint32_t e = 0; e <= nb; ++e, pw = mulmod64(pw, cl, ql)) spow[(size_t)l * (nb + 1) + e] = (uint32_t)((pw << 32) % ql);
+    }
+  }
 
   auto cleanup = [&](ephdc_status e) { free_session(s); return e; };
   if ((st = dev_alloc(s, &s->d_fwd, fwd.size(), "twiddles")) != EPHDC_OK) return cleanup(st);
@@ -307,6 +443,7 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   if ((st = dev_alloc(s, &s->d_scatter, scatter.size(), "scatter table")) != EPHDC_OK) return cleanup(st);
   if ((st = dev_alloc(s, &s->d_model, model_copy_words, "model")) != EPHDC_OK) return cleanup(st);
   if ((st = dev_alloc(s, &s->d_gk, key_words, "Galois keys")) != EPHDC_OK) return cleanup(st);
+  if ((st = dev_alloc(s, &s->d_spow, spow.size(), "scaling constants")) != EPHDC_OK) return cleanup(st);
   std::vector<uint32_t> perm;
   std::vector<uint2> ksc;
   if (P.r > 1) {
@@ -335,6 +472,8 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   chk(hipMemcpyAsync(s->d_inv_t, invt.data(), invt.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_pc, pcs.data(), pcs.size() * sizeof(PrimeConst), hipMemcpyHostToDevice, hs));
   chk(hipMemcpyAsync(s->d_scatter, scatter.data(), scatter.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
+  if (!spow.empty())
+    chk(hipMemcpyAsync(s->d_spow, spow.data(), spow.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
   if (P.r > 1) {
     chk(hipMemcpyAsync(s->d_perm, perm.data(), perm.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs));
     chk(hipMemcpyAsync(s->d_ksc, ksc.data(), ksc.size() * sizeof(uint2), hipMemcpyHostToDevice, hs));
@@ -354,7 +493,8 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
 
 ephdc_status ephdc_session_destroy(ephdc_session* s) {
   if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
-  (void)hipDeviceSynchronize();
+  // the session's own calls are done once its last scoring call is (setup was synchronous)
+  if (s->done_set) (void)hipEventSynchronize(s->done);
   free_session(s);
   return EPHDC_OK;
 }
@@ -383,58 +523,8 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
                                    void* stream) {
   if (!s || !d_hv || !d_score_ct) return fail(EPHDC_ERR_ARG, "NULL argument");
   if (Q == 0 || Q > s->max_Q) return fail(EPHDC_ERR_ARG, "Q must be in [1, max_Q]");
-  const ParamSet& P = s->P;
-  hipStream_t hs = (hipStream_t)stream;
-  Schedule sc = schedule(s, Q);
-  if ((size_t)sc.G * sc.S * 2 * P.L * P.N > s->partial_words) return fail(EPHDC_ERR_BUFFER, "scratch too small");
-  // the single-request scratch is allocated on first use, so that sessions used only through
-  // batches and the serving loop hold no more than their model, keys and tables
-  if (!s->d_partial) {
-    ephdc_status st2 = dev_alloc(s, &s->d_partial, s->partial_words, "partial sums");
-    if (st2 != EPHDC_OK) return st2;
-  }
-  if (P.r > 1 && !s->d_rot) {
-    ephdc_status st2 = dev_alloc(s, &s->d_rot, rotate_words(P, P.G(s->max_Q)), "rotation workspace");
-    if (st2 != EPHDC_OK) return st2;
-  }
-  if ((uint64_t)P.D * P.G(Q) * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "D * hv stride must be < 2^31");
-  ScoreArgs a = score_args(s, d_hv, Q, sc);
-  if (s->split) {
-    if (!s->d_pt) {
-      // at least one plaintext per group of the largest batch (max_Q) per chunk
-      const size_t bytes = s->pt_bytes ? s->pt_bytes : kPtBytes;
-      const size_t cap = std::max<size_t>(P.G(s->max_Q), bytes / (4 * (size_t)P.N));
-      ephdc_status st2 = dev_alloc(s, &s->d_pt, cap * P.N, "split-path plaintexts");
-      if (st2 != EPHDC_OK) return st2;
-      s->pt_cap = cap;
-    }
-    a.pt = s->d_pt;
-    HIP_TRY(score_split(s, a, sc, hs), "split score launch");
-  } else {
-    hipEvent_t t0 = timed_begin(s, hs);
-    HIP_TRY(launch_score(P.logn, (int)s->le, (int)s->lg, a, sc.G * sc.S * s->nlg, hs), "score launch");
-    timed_end(s, kStFused, t0, hs);
-  }
-  if (P.r == 1) {
-    hipEvent_t t1 = timed_begin(s, hs);
-    HIP_TRY(launch_finish(P.logn, true, s->d_partial, d_score_ct, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
-            "finish launch");
-    timed_end(s, kStFinish, t1, hs);
-    return EPHDC_OK;
-  }
-  // r > 1: sum the partials in the evaluation domain, fold the r blocks of every row with
-  // log2 r rotations, then return to the coefficient domain
-  RotateArgs ra = rotate_args(s, s->d_rot, sc.G);
-  hipEvent_t t1 = timed_begin(s, hs);
-  HIP_TRY(launch_finish(P.logn, false, s->d_partial, ra.acc, sc.G, sc.S, P.L, s->d_inv, s->d_pc, hs),
-          "finish launch");
-  timed_end(s, kStFinish, t1, hs);
-  hipEvent_t t2 = timed_begin(s, hs);
-  for (uint32_t i = 0; i < P.log2r(); ++i) HIP_TRY(launch_rotate_step(P.logn, ra, i, hs), "rotate launch");
-  HIP_TRY(launch_inv_batch(P.logn, ra.acc, d_score_ct, (size_t)sc.G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs),
-          "output transform launch");
-  timed_end(s, kStRotate, t2, hs);
-  return EPHDC_OK;
+  if (!s->has_ws) return fail(EPHDC_ERR_BUFFER, "the session was created without a workspace");
+  return score_with(s, s->ws, d_hv, Q, d_score_ct, (hipStream_t)stream);
 }
 
 ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t blocks, uint32_t values_per_thread,
@@ -463,13 +553,6 @@ ephdc_status ephdc_session_tune(ephdc_session* s, uint32_t limb_group, uint32_t 
 
 ephdc_status ephdc_session_set_chunk_bytes(ephdc_session* s, size_t bytes) {
   if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");
-  (void)hipDeviceSynchronize();  // no launch may still use the buffer
-  if (s->d_pt) {
-    (void)hipFree(s->d_pt);
-    s->device_bytes -= s->pt_cap * s->P.N * 4;
-    s->d_pt = nullptr;
-    s->pt_cap = 0;
-  }
   s->pt_bytes = bytes;
   return EPHDC_OK;
 }
@@ -503,7 +586,7 @@ ephdc_status ephdc_debug_plaintext(ephdc_session* s, const int8_t* d_hv, uint32_
   const ParamSet& P = s->P;
   if (Q == 0 || g >= P.G(Q) || m >= P.M()) return fail(EPHDC_ERR_ARG, "g or m out of range");
   Schedule sc = schedule(s, Q);
-  ScoreArgs a = score_args(s, d_hv, Q, sc);
+  ScoreArgs a = score_args(s, d_hv, Q, sc, nullptr);
   HIP_TRY(launch_debug_plaintext(P.logn, a, g, m, d_out, (hipStream_t)stream), "debug launch");
   return EPHDC_OK;
 }

@@ -14,6 +14,20 @@
 // Profiling stages (see ephdc_session_profile_read).
 enum : int { kStFused = 0, kStFinish = 1, kStHdc = 2, kStRotate = 3, kStEncodePt = 4, kStMac = 5, kStages = 6 };
 
+namespace ephdc {
+
+// Device scratch of one scoring call, carved from a caller-owned buffer: partial sums of
+// the work items, the rotation workspace (r > 1) and the split path's plaintext chunk.
+struct Workspace {
+  uint32_t* partial = nullptr;  // [G][S][2][L][N] partial accumulators
+  size_t partial_words = 0;
+  uint32_t* rot = nullptr;      // acc, R, D, Y, KS, XP for G(max_Q) groups (r > 1)
+  int32_t* pt = nullptr;        // lifted plaintexts of one chunk [G][m_len][N]
+  size_t pt_cap = 0;            // plaintexts the chunk buffer holds (>= G(max_Q))
+};
+
+}  // namespace ephdc
+
 struct ephdc_session {
   ephdc::ParamSet P;
   int device = 0;
@@ -22,9 +36,15 @@ struct ephdc_session {
   uint32_t target_blocks = 256;    // workgroups per scoring launch the schedule aims at
   uint32_t le = 0;                 // log2 values per thread of the scoring kernel (0: default)
   bool split = false;              // batch-encode and MAC as two kernels (else one fused kernel)
-  int32_t* d_pt = nullptr;         // split path: lifted plaintexts of one chunk [G][m_len][N]
-  size_t pt_cap = 0;               // plaintexts d_pt holds
-  size_t pt_bytes = 0;             // bound on d_pt in bytes (0: the default, 512 MiB)
+  size_t pt_bytes = 0;             // bound on the plaintext chunk in bytes (0: all of the workspace's)
+  // the caller's workspace (borrowed; none when the session is used only through batches,
+  // the serving loop or the static-scratch entry point)
+  ephdc::Workspace ws;
+  bool has_ws = false;
+  // the last scoring call's completion, so that a call on another stream waits for it
+  hipEvent_t done = nullptr;
+  hipStream_t done_stream = nullptr;
+  bool done_set = false;
   // device memory owned by the session
   uint32_t* d_fwd = nullptr;       // [nmod][N] forward twiddles, Montgomery form (w * 2^32 mod m)
   uint32_t* d_inv = nullptr;       // [nmod][N] inverse twiddles, Montgomery form
@@ -33,12 +53,10 @@ struct ephdc_session {
   uint32_t* d_scatter = nullptr;   // [N]
   uint32_t* d_model = nullptr;     // [M][2][L][N] evaluation domain, Montgomery form
   uint32_t* d_gk = nullptr;        // [log2r][dnum][2][nmod][N] evaluation domain, Montgomery form
-  uint32_t* d_partial = nullptr;   // scratch: partial accumulators
-  size_t partial_words = 0;
+  uint32_t* d_spow = nullptr;      // scaling op: [L][scale_blocks + 1] powers c^e * 2^32 mod q_l
   // rotate-and-sum (r > 1)
   uint32_t* d_perm = nullptr;      // [log2r][N] automorphism permutations of evaluation points
   uint2* d_ksc = nullptr;          // key-switching constants, pointed into by ks
-  uint32_t* d_rot = nullptr;       // workspace: acc, R, D, Y, KS, XP sized for G(max_Q)
   ephdc::KsConst ks{};
   ephdc::PrimeConst pct{};
   size_t device_bytes = 0;
@@ -74,6 +92,23 @@ inline ephdc_status dev_alloc(ephdc_session* s, T** p, size_t count, const char*
   s->device_bytes += count * sizeof(T);
   return EPHDC_OK;
 }
+
+// Workspace of ephdc_score_encrypted for batches of up to max_Q queries: the layout of a
+// buffer of `bytes` bytes at `base` (EPHDC_ERR_BUFFER when it is too small), and the size
+// ephdc_workspace_bytes reports (the minimum plus a plaintext chunk of up to 512 MiB).
+size_t workspace_min_bytes(const ParamSet& P, uint32_t max_Q);
+size_t workspace_default_bytes(const ParamSet& P, uint32_t max_Q);
+ephdc_status workspace_layout(const ParamSet& P, uint32_t max_Q, void* base, size_t bytes, Workspace* out);
+
+// Words of the partial sums that scoring Q queries takes under the session's schedule.
+size_t score_partial_words(const ephdc_session* s, uint32_t Q);
+
+// The scaling op of a session's parameters (pow == nullptr when scale_every is 0).
+ScaleOp scale_op(const ephdc_session* s);
+
+// The scoring of ephdc_score_encrypted with the scratch of `ws`.
+ephdc_status score_with(ephdc_session* s, const Workspace& ws, const int8_t* d_hv, uint32_t Q,
+                        uint32_t* d_score_ct, hipStream_t hs);
 
 // Rotation workspace and arguments for G groups of a folded (r > 1) session.
 size_t rotate_words(const ParamSet& P, uint32_t G);

@@ -34,12 +34,15 @@ def hv_layout(h: np.ndarray, stride: int) -> np.ndarray:
     return out
 
 
-def score_on_gpu(e: ep.Params, model_ct: np.ndarray, h: np.ndarray, gk=None, max_Q=None):
-    """Score ciphertexts uint32 [G][2][L][N] of query hypervectors h int8 [Q][D]."""
+def score_on_gpu(e: ep.Params, model_ct: np.ndarray, h: np.ndarray, gk=None, max_Q=None, tune=None):
+    """Score ciphertexts uint32 [G][2][L][N] of query hypervectors h int8 [Q][D]; tune: keyword
+    arguments of Session.tune (the kernel schedule)."""
     import torch
     Q = h.shape[0]
     s = ep.Session(e, to_dev(model_ct), to_dev(gk) if gk is not None else None, max_Q=max_Q or Q)
     try:
+        if tune:
+            s.tune(**tune)
         stride = s.hv_stride(Q)
         G = s.num_groups(Q)
         d_hv = to_dev(hv_layout(h, stride))

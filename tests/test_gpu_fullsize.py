@@ -1,7 +1,8 @@
-"""The plain-path workload at its full size (N = 8192, 4 limbs, F = 2304, D = 4096, K = 7,
-4096 queries), in the launch configuration the benchmark times, checked where the oracle
-can follow it: sampled hypervectors, sampled coefficients of the score ciphertexts, and
-the decryption of every group against the exact integer scores.
+"""The workloads at their full sizes, in the launch configuration the benchmark times,
+checked where the oracle can follow them: the tiny workload word for word; the plain-path
+workload (N = 8192, 4 limbs, F = 2304, D = 4096, K = 7, 4096 queries) with sampled
+hypervectors, its whole last group word for word and every group decrypted against the
+exact integer scores; the rotation and batching workloads as stated at their tests.
 
 The encrypted model comes from the library's host-side encryption (bit-exact with the
 oracle's on the CPU tests); every expected value here is computed by the oracle from it.
@@ -51,26 +52,54 @@ def test_plain_workload_at_full_size_sampled():
     qs = np.sort(rng.choice(Q, 48, replace=False))
     assert np.array_equal(h[qs], hdc.encode(x[qs], base))
 
-    # sampled coefficients of the last (ragged) group: c[g][comp][l][i] =
-    # sum_m (ct_m[comp][l] * p_{g,m})[i] mod q_l, the negacyclic product written out for one
-    # output coefficient
+    # the whole last (ragged) group, every word of both components and all limbs, against
+    # the oracle's multiply-accumulate over all 4096 model ciphertexts
     mdl = model.astype(np.int64)
     g = G - 1
-    samples = [(0, 0, 0), (1, L - 1, N - 1), (0, 2, 4321), (1, 1, 77)]
-    acc = [0] * len(samples)
-    j = np.arange(N)
-    for m in range(o.M):
-        p = bfv.query_plaintext(o, h, g, m)
-        for k, (comp, l, i) in enumerate(samples):
-            q = o.q[l]
-            pi = np.where(j <= i, p[(i - j) % N], -p[(i - j) % N]) % q
-            acc[k] = (acc[k] + int(np.sum(mdl[m, comp, l] * pi % q))) % q
-    for k, (comp, l, i) in enumerate(samples):
-        assert cts[g, comp, l, i] == acc[k], (g, comp, l, i)
+    assert np.array_equal(cts[g], bfv.mac(o, mdl, h, g))
 
     # every query of every group decrypts to its exact score
     scores, _ = pipeline.decrypt_scores(o, sk.astype(np.int64), cts, Q)
     assert np.array_equal(scores, hdc.scores_mod_t(h, C, o.t))
+
+
+def test_tiny_workload_at_full_size():
+    """The tiny workload exactly (N = 4096, 3 limbs, F = 512 uniform features, D = 2048,
+    K = 2, 64 queries, every input from seed 0), in the benchmark's launch configuration:
+    every word of the score ciphertext against the oracle's, the oracle's HDC encoding of
+    every query, decryption to h . C mod t and the argmax of the exact integer scores."""
+    torch = torch_cuda()
+    N1, L1, F1, D1, K1, Q1 = 4096, 3, 512, 2048, 2, 64
+    primes = default_primes(N1, L1)
+    o = OParams(N=N1, q=tuple(primes), F=F1, D=D1, K=K1)
+    e = ep.Params(N=N1, q=tuple(primes), F=F1, D=D1, K=K1)
+    x = synth.uniform_features(0, Q1, F1)
+    base = synth.base_hypervectors(0, F1, D1)
+    C = synth.class_hypervectors(0, K1, D1)
+    sk = bfv.secret_key(o, 0)
+    model = bfv.encrypt_model(o, sk, C, 0)
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=Q1)
+    try:
+        stride, G = s.hv_stride(Q1), s.num_groups(Q1)
+        d_hv = torch.empty((D1, stride), dtype=torch.int8, device="cuda")
+        d_out = torch.empty((G, 2, L1, N1), dtype=torch.int32, device="cuda")
+        ep.ephdc_encode_queries(s, to_dev(x), to_dev(base), Q1, d_hv)
+        ep.ephdc_score_encrypted(s, d_hv, Q1, d_out)
+        torch.cuda.synchronize()
+        hv = d_hv.cpu().numpy()
+        cts = to_host_u32(d_out).astype(np.int64)
+    finally:
+        s.close()
+    h = hdc.encode(x, base)
+    assert np.array_equal(hv[:, :Q1].T, h)
+    assert not hv[:, Q1:].any()
+    assert G == 1
+    assert np.array_equal(cts, pipeline.score_ciphertexts(o, model, h))
+    scores, am = pipeline.decrypt_scores(o, sk, cts, Q1)
+    assert np.array_equal(scores, hdc.scores_mod_t(h, C, o.t))
+    assert np.array_equal(am, hdc.argmax(hdc.scores_int(h, C)))
+    sc2, am2 = ep.ephdc_decrypt_scores(e, sk.astype(np.int8), cts.astype(np.uint32), Q1)
+    assert np.array_equal(sc2, scores) and np.array_equal(am2, am)
 
 
 def test_rotation_workload_at_full_size_sampled():

@@ -41,7 +41,11 @@ def test_parameter_validation():
     _, e = _pair(64)
     assert ep.ephdc_check_params(e) == ep.OK
     bad = [
-        dict(t=65521),                         # t must be 65537
+        dict(t=65521),                         # prime, but not 1 mod 2N
+        dict(t=65535),                         # not prime
+        dict(t=193),                           # 1 mod 2N and prime, but below 257
+        dict(scheme=3),                        # no such scheme
+        dict(scale_shift=32),
         dict(N=100),                           # not a power of two
         dict(q=(1073692673 + 2,)),             # not prime
         dict(q=(65537 * 2 + 1,)),              # not 1 mod 2N for N = 64? (131075 composite anyway)
@@ -49,12 +53,32 @@ def test_parameter_validation():
         dict(r=2),                             # rotations without special primes / digits
         dict(K=40),                            # fewer than one query per row
         dict(qbits=9),
+        dict(qbits=0),
+        dict(qbits=-1),                        # signed field: negative values are rejected
     ]
     for kw in bad:
-        p = ep.Params(**{**e.__dict__, "_keep": [], **kw})
+        kw2 = dict(kw)
+        if kw2.get("scheme") == 3:
+            kw2["scheme"] = "bgv"
+            p = ep.Params(**{**e.__dict__, "_keep": [], **kw2})
+            c = p.c()
+            c.scheme = 3
+            assert ep.lib().ephdc_check_params(ctypes.byref(c)) == ep.ERR_PARAMS
+            continue
+        p = ep.Params(**{**e.__dict__, "_keep": [], **kw2})
         assert ep.ephdc_check_params(p) == ep.ERR_PARAMS, kw
     # a prime that is not 1 mod 2N
     assert ep.ephdc_check_params(ep.Params(N=64, q=(1073741789,), F=16, D=16, K=3)) == ep.ERR_PARAMS
+    # other plaintext primes, both BFV variants and BGV, the scaling op
+    for kw in [dict(t=257), dict(t=7681), dict(t=40961), dict(scheme="bfv-r"), dict(scheme="bgv"),
+               dict(scale_every=512, scale_shift=8)]:
+        assert ep.ephdc_check_params(ep.Params(**{**e.__dict__, "_keep": [], **kw})) == ep.OK, kw
+    # N * t must stay below 2^32 (the device's lazy inverse transform mod t)
+    assert ep.ephdc_check_params(ep.Params(N=16384, q=tuple(default_primes(16384, 1)), t=786433, F=16, D=16,
+                                           K=3)) == ep.ERR_PARAMS
+    # BGV has no key switching here
+    o2, e2 = _pair(64, L=4, D=16, K=2, r=4, alpha=2, dnum=2)
+    assert ep.ephdc_check_params(ep.Params(**{**e2.__dict__, "_keep": [], "scheme": "bgv"})) == ep.ERR_PARAMS
 
 
 def test_derived_sizes_match_oracle():
@@ -154,3 +178,53 @@ def test_decrypt_at_an_offset_reads_the_same_rows():
         sc, am = ep.ephdc_decrypt_scores_at(e, sk, cts, q_first, Q)
         assert np.array_equal(sc, run["scores"][q_first:q_first + Q]), (q_first, Q)
         assert np.array_equal(am, run["argmax"][q_first:q_first + Q]), (q_first, Q)
+
+
+def test_workspace_size_formula():
+    """ephdc_workspace_bytes = partial sums for 1024 + G work items of [2][L][N] words, the
+    rotation workspace of G groups (r > 1), and a plaintext chunk of min(G*M, 512 MiB / 4N)
+    plaintexts (at least G), each of the first two regions rounded up to 256 bytes."""
+    def a256(x):
+        return -(-x // 256) * 256
+
+    for N, L, K, D, r, alpha, dnum, Q in [(4096, 3, 2, 2048, 1, 0, 0, 64), (8192, 4, 7, 4096, 1, 0, 0, 4096),
+                                          (16384, 8, 26, 10240, 8, 2, 4, 16384), (2048, 2, 2, 1024, 1, 0, 0, 5000),
+                                          (64, 3, 3, 40, 2, 1, 1, 100)]:
+        primes = default_primes(N, L + alpha)
+        e = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=16, D=D, K=K, r=r, dnum=dnum)
+        o = OParams(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=16, D=D, K=K, r=r, dnum=dnum)
+        G = o.groups(Q)
+        partial = (1024 + G) * 2 * L * N * 4
+        rot = G * N * (5 * L + dnum * (L + alpha) + 2 * (L + alpha) + 2 * alpha) * 4 if r > 1 else 0
+        cap = max(G, min(G * o.M, (512 << 20) // (4 * N)))
+        assert ep.ephdc_workspace_bytes(e, Q) == a256(partial) + a256(rot) + cap * N * 4, (N, Q)
+    assert ep.ephdc_workspace_bytes(ep.Params(N=100, q=(7,), F=16, D=16, K=3), 10) == 0
+
+
+@pytest.mark.parametrize("N,t,scheme", [(64, 257, "bfv"), (64, 7681, "bfv-r"), (32, 65537, "bgv"), (64, 40961, "bgv"),
+                                        (2048, 12289, "bfv"), (2048, 40961, "bfv-r")])
+def test_other_schemes_and_plaintext_primes_match_oracle(N, t, scheme):
+    """Model encryption and decryption under BGV, rounded BFV and plaintext primes other than
+    65537, bit-exact against the oracle (ciphertexts, then the scores of a whole pipeline)."""
+    primes = default_primes(N, 3)
+    D, K, F, Qn = 9, 3, 16, 24
+    o = OParams(N=N, q=tuple(primes), t=t, F=F, D=D, K=K, scheme=scheme)
+    e = ep.Params(N=N, q=tuple(primes), t=t, F=F, D=D, K=K, scheme=scheme)
+    C = synth.class_hypervectors(41, K, D)
+    sk, _ = ep.ephdc_keygen(e, 41)
+    got = ep.ephdc_encrypt_model(e, sk, C, 42)
+    want = bfv.encrypt_model(o, sk.astype(np.int64), C, 42)
+    assert np.array_equal(got.astype(np.int64), want)
+    x = synth.uniform_features(43, Qn, F)
+    base = synth.base_hypervectors(43, F, D)
+    run = pipeline.run(o, x, base, C, seed=43)
+    sc, am = ep.ephdc_decrypt_scores(e, run["s"].astype(np.int8), run["score_ct"].astype(np.uint32), Qn)
+    assert np.array_equal(sc, run["scores"])
+    assert np.array_equal(am, run["argmax"])
+    assert np.array_equal(sc, hdc.scores_mod_t(run["h"], C, t))
+    # arbitrary residues: the decryption rule itself (rounding for BFV, centred phase for BGV)
+    rng = np.random.default_rng(44)
+    junk = np.stack([np.stack([rng.integers(0, q, o.N) for q in o.q]) for _ in range(2)])[None]
+    sc2, _ = ep.ephdc_decrypt_scores(e, run["s"].astype(np.int8), junk.astype(np.uint32), min(Qn, o.B))
+    want2, _ = pipeline.decrypt_scores(o, run["s"], junk, min(Qn, o.B))
+    assert np.array_equal(sc2, want2)
