@@ -237,6 +237,20 @@ ephdc_status ephdc_score_encrypted(ephdc_session* s, const int8_t* d_hv, uint32_
                                    uint32_t* d_score_ct, void* stream);
 
 /*
+ * ephdc_score_encrypted for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same scoring, with its
+ * scratch in a fixed 64 MiB array of the library's device code instead of the session's
+ * workspace (one copy per GPU, held until the process ends; the session needs no
+ * workspace).  Allocates nothing.  EPHDC_ERR_UNSUPPORTED, before any work is queued, when
+ * this call's partial sums (current schedule), rotation workspace and one plaintext per
+ * query group do not fit in 64 MiB (N = 8192, L = 4, default schedule: up to 227 groups).  Every
+ * call on one GPU shares that GPU's array: calls that overlap on the device (from any
+ * session or stream) race, so the caller orders them (one stream, or events).
+ */
+ephdc_status ephdc_score_encrypted_static(ephdc_session* s, const int8_t* d_hv, uint32_t Q,
+                                          uint32_t* d_score_ct, void* stream);
+
+/*
  * Debug: the lifted plaintext of query group g and model index m, reduced into every
  * limb, uint32 [L][N] coefficient domain (the centred representative of
  * Encode(slot vector) in (-t/2, t/2], mod q_l).  Exposes the batch-encoding step alone.

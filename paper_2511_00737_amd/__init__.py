@@ -79,6 +79,8 @@ def lib() -> C.CDLL:
             "ephdc_encode_queries": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                                C.c_void_p]),
             "ephdc_score_encrypted": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+            "ephdc_score_encrypted_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                                       C.c_void_p]),
             "ephdc_debug_plaintext": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
                                                 C.c_void_p, C.c_void_p]),
             "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
@@ -383,6 +385,13 @@ def ephdc_score_encrypted(s: Session, d_hv, Q: int, d_score_ct, stream=None) -> 
     _, hv_bytes, out_bytes = _sizes(s, Q)
     _check(lib().ephdc_score_encrypted(s.handle, _dptr(d_hv, hv_bytes), Q, _dptr(d_score_ct, out_bytes),
                                        _stream(stream)))
+
+
+def ephdc_score_encrypted_static(s: Session, d_hv, Q: int, d_score_ct, stream=None) -> None:
+    """ephdc_score_encrypted with the library's static per-GPU scratch (allocates nothing)."""
+    _, hv_bytes, out_bytes = _sizes(s, Q)
+    _check(lib().ephdc_score_encrypted_static(s.handle, _dptr(d_hv, hv_bytes), Q, _dptr(d_score_ct, out_bytes),
+                                              _stream(stream)))
 
 
 def ephdc_debug_plaintext(s: Session, d_hv, Q: int, g: int, m: int, d_out, stream=None) -> None:
