@@ -62,6 +62,7 @@ WORKLOADS = {
 MUL32_PEAK = 256 * 64 * 2.4e9
 MODMUL_PEAK = MUL32_PEAK / 3
 INT8_PEAK = 5.0e15  # dense int8 MFMA operations/s of MI355X
+HBM_PEAK = 8.0e12  # HBM3E bytes/s of MI355X
 
 
 def transform_mults(N: int) -> int:
@@ -81,7 +82,7 @@ def algorithmic_modmuls(kernel: str, N: int, L: int, G: int, M: int) -> float:
 
 # The sources that define each profiled kernel's code (its HIP file and the headers it uses).
 KERNEL_SOURCES = {k: ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", "launch.hpp")
-                  for k in ("k_mac", "k_encode_pt", "k_score", "k_finish")}
+                  for k in ("k_mac", "k_encode_pt", "k_score", "k_finish", "k_mac_list", "k_encode_list")}
 KERNEL_SOURCES["k_hdc_encode"] = ("kernels_hdc.hip", "launch.hpp")
 
 
@@ -116,6 +117,91 @@ def recorded_traffic(kernel: str, workload: str):
         return None
 
 
+def _oracle_mac_worker(kw, D, C, m0, sample_m, seed, barrier, out):
+    """One process of the all-cores oracle leg: the oracle's MAC of query group 0 over model
+    ciphertexts m0 .. m0 + sample_m - 1 (encrypted here, untimed), timed after a barrier so
+    that every process runs its MAC at the same time."""
+    from oracle import bfv
+    from oracle.params import Params as OParams
+    o = OParams(D=D, **kw)
+    s = bfv.secret_key(o, seed)
+    model = bfv.encrypt_model(o, s, C, seed, ms=range(m0, m0 + sample_m))
+    osub = OParams(D=sample_m * o.r, **kw)
+    h = np.zeros((o.B, sample_m * o.r), dtype=np.int8)
+    h[:16] = 1
+    barrier.wait()
+    t0 = time.time()
+    bfv.mac(osub, model, h, 0)
+    out.put((t0, time.time()))
+
+
+def recorded_valu_issue(kernel: str, workload: str):
+    """Fraction of SIMD cycles issuing a VALU instruction (SQ_INSTS_VALU * 4 / (SIMDs * cycles))
+    recorded for `kernel` in profiles/sq_counters_<workload>.md, or None when missing or taken
+    on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    for line in open(path):
+        if line.startswith("- source_digest:"):
+            digest = line.split(":", 1)[1].strip().strip("`")
+        if line.startswith(f"- valu_issue_{kernel}:"):
+            try:
+                val = float(line.split(":", 1)[1].strip().strip("`"))
+            except ValueError:
+                val = None
+    return val if digest == kernel_source_digest(kernel) else None
+
+
+def cpu_baseline_all_cores(prm: ep.Params, C: np.ndarray, sample_m: int, t_hdc: float, t_rot: float):
+    """The oracle on every host core: one process per core (spawned, single-threaded numpy),
+    each timing the MAC of a different slice of sample_m model ciphertexts at the same time;
+    the slices' plaintexts per second give inferences/s as in the single-core leg."""
+    import multiprocessing as mp
+    from oracle.params import Params as OParams
+    kw = dict(N=prm.N, q=tuple(prm.q), p=tuple(prm.p), F=prm.F, K=prm.K, r=prm.r, dnum=prm.dnum)
+    o = OParams(D=prm.D, **kw)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nproc = max(1, min(cores, 16, o.M // sample_m))
+    ctx = mp.get_context("spawn")
+    barrier, out = ctx.Barrier(nproc), ctx.Queue()
+    env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_keep:
+        os.environ[k] = "1"
+    procs = [ctx.Process(target=_oracle_mac_worker, args=(kw, prm.D, C, i * sample_m, sample_m, 0, barrier, out))
+             for i in range(nproc)]
+    try:
+        for p in procs:
+            p.start()
+        spans = [out.get(timeout=600) for _ in procs]
+        for p in procs:
+            p.join()
+    finally:
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    wall = max(e for _, e in spans) - min(s_ for s_, _ in spans)
+    pt_per_s = nproc * sample_m / wall
+    t_group = o.M / pt_per_s + (t_rot + t_hdc * o.B) / nproc
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": o.B / t_group, "unit": "inferences/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{nproc} processes at once, each the oracle's ct x pt MAC of query group 0 over its own "
+                      f"{sample_m} of the {o.M} model ciphertexts (plaintexts per second over the slowest "
+                      f"process's span, scaled to the full model, HDC encoding and rotations added per core); "
+                      f"host: {cores} usable cores of {os.cpu_count()}, {cpu}",
+            "seconds": round(wall, 2)}
+
+
 def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np.ndarray, sample_m: int):
     """The oracle, timed on the host: HDC encoding of a few queries, the MAC of query group 0
     over the first `sample_m` model ciphertexts (scaled to the whole model) and, for folded
@@ -145,18 +231,32 @@ def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np
         t_rot = time.perf_counter() - t0
     t_group = t_mac * o.M / sample_m + t_rot + t_hdc * o.B
     rot = f" and its rotate-and-sum ({o.log2r} rotations)" if o.r > 1 else ""
-    return {"value": o.B / t_group, "unit": "inferences/s", "cores": 1, "kind": "oracle",
-            "sample": f"HDC encoding of {nq} queries, the ct x pt MAC of query group 0 "
-                      f"({o.B} queries) over model ciphertexts 0..{sample_m - 1} of {o.M} "
-                      f"scaled linearly to the full model{rot}; numpy, single thread "
-                      f"(host has {os.cpu_count()} cores)",
-            "seconds": round(t_mac + t_rot + t_hdc * nq, 2)}
+    one = {"value": o.B / t_group, "unit": "inferences/s", "cores": 1, "kind": "oracle",
+           "sample": f"HDC encoding of {nq} queries, the ct x pt MAC of query group 0 "
+                     f"({o.B} queries) over model ciphertexts 0..{sample_m - 1} of {o.M} "
+                     f"scaled linearly to the full model{rot}; numpy, single thread "
+                     f"(host has {os.cpu_count()} cores)",
+           "seconds": round(t_mac + t_rot + t_hdc * nq, 2)}
+    try:
+        one["all_cores"] = cpu_baseline_all_cores(prm, C, sample_m, t_hdc, t_rot)
+    except Exception as exc:  # the single-core figure stands on its own
+        one["all_cores"] = {"error": repr(exc)}
+    return one
 
 
 def bench_batched(args, w) -> int:
+    res = run_batched(args, w)
+    if res is None:
+        return 3
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def run_batched(args, w):
     """The batching workload: all requests scored by one graph-captured batch (persistent
     launches over a shared work list, schedule from the autotuner) against the plain form,
-    the same requests one after another through the single-request entry points."""
+    the same requests one after another through the single-request entry points.  Returns
+    the result dict (None when a check fails)."""
     import torch
     N, L, F, nreq = w["N"], w["L"], w["F"], w["requests"]
     primes = ep.default_primes(N, L)
@@ -246,7 +346,7 @@ def bench_batched(args, w) -> int:
     for r, p in zip(reqs, plain_out):
         if not torch.equal(r.d_score_ct, p):
             print("[bench] batched ciphertexts differ from the plain form", file=sys.stderr)
-            return 3
+            return None
     for i in range(0, nreq, 16):
         r, t = reqs[i], tenants[int(midx[i])]
         hv = r.d_hv.cpu().numpy()[:, :r.Q].T.astype(np.float64)
@@ -258,47 +358,60 @@ def bench_batched(args, w) -> int:
                                                 qf, r.Q)
         if not (np.array_equal(scores, want) and np.array_equal(pscores, want)):
             print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
-            return 3
+            return None
     total_q = int(sizes.sum())
-    plain_value = total_q * len(plain_lat) / plain_wall
-    unpacked_value = total_q * len(unpacked_lat) / unpacked_wall
-    value = total_q * args.steps / wall
-    modmuls = 0.0  # algorithmic work of the packed batch: one query sequence per model
+    # algorithmic work of a step: plain and unpacked forms score every request in its own
+    # ciphertexts (G_i = ceil(Q_i / B) groups each), the packed form one query sequence per model
+    work_unpacked = 0.0
+    for i in range(nreq):
+        t = tenants[int(midx[i])]
+        work_unpacked += algorithmic_modmuls("k_score", N, L, ep.ephdc_num_groups(t["prm"], int(sizes[i])),
+                                             ep.ephdc_num_model_ct(t["prm"]))
+    work_packed = 0.0
     for k, t in enumerate(tenants):
         Qk = int(sizes[midx == k].sum())
         if Qk:
-            G = ep.ephdc_num_groups(t["prm"], Qk)
-            modmuls += algorithmic_modmuls("k_score", N, L, G, ep.ephdc_num_model_ct(t["prm"]))
-    ms_step = wall * 1e3 / args.steps
-    achieved = modmuls / (ms_step * 1e-3)
+            work_packed += algorithmic_modmuls("k_score", N, L, ep.ephdc_num_groups(t["prm"], Qk),
+                                               ep.ephdc_num_model_ct(t["prm"]))
+
+    def form(wall_s, lat_ms, work, desc, **extra):
+        ms = wall_s * 1e3 / len(lat_ms)
+        ach = work / (ms * 1e-3)
+        return {"value": round(total_q / (ms * 1e-3), 1), "unit": "inferences/s", "ms_per_step": round(ms, 4),
+                "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                               "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+                "roofline": {"bound": "alu", "kernel": "whole path of a step (batch encoding and MAC dominate)",
+                             "achieved": round(ach / 1e12, 4), "peak": round(MODMUL_PEAK / 1e12, 4),
+                             "unit": "Tmodmul/s", "frac": round(ach / MODMUL_PEAK, 4),
+                             "per_step_modmuls": work},
+                "form": desc, **extra}
+
+    plain = form(plain_wall, plain_lat, work_unpacked,
+                 "the requests one after another: an encode and a score call per request, no graph")
+    unpacked = form(unpacked_wall, unpacked_lat, work_unpacked,
+                    "one graph replay of persistent launches, every request in its own ciphertexts",
+                    schedule=sched, autotune_s=round(t_tune, 1))
+    packed = form(wall, lat, work_packed,
+                  "one graph replay, the requests of each model sharing ciphertexts (one query sequence per model)",
+                  schedule=psched, autotune_s=round(t_ptune, 1))
+    packed_eager = form(eager_wall, eager_lat, work_packed, "the packed batch enqueued launch by launch, no graph")
+    mac_traffic = recorded_traffic("k_mac_list", "c3")
+    unpacked["roofline"]["k_mac_list_traffic"] = mac_traffic
     result = {
-        "metric": METRIC, "value": round(value, 1), "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": packed["value"], "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": packed["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {w['desc']}", "requests": nreq, "queries_per_step": total_q,
-                   "form": "packed batch: the requests of each model share ciphertexts; one graph replay",
-                   "schedule": psched, "autotune_s": round(t_ptune, 1)},
-        "plain": {"value": round(plain_value, 1), "unit": "inferences/s", "ms_per_step": round(plain_wall * 1e3 / len(plain_lat), 4),
-                  "form": "the same requests one after another: encode + score call per request, no graph"},
-        "batched_unpacked": {"value": round(unpacked_value, 1), "unit": "inferences/s",
-                             "ms_per_step": round(unpacked_wall * 1e3 / len(unpacked_lat), 4), "schedule": sched,
-                             "form": "one graph replay of persistent launches, each request in its own ciphertexts"},
-        "packed_eager": {"value": round(total_q * len(eager_lat) / eager_wall, 1), "unit": "inferences/s",
-                         "ms_per_step": round(eager_wall * 1e3 / len(eager_lat), 4),
-                         "form": "the packed batch enqueued launch by launch instead of replayed as a graph"},
-        "speedup_vs_plain": round(value / plain_value, 3),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4)},
-        "roofline": {"bound": "alu", "kernel": "whole batched path (batch-encode + MAC dominate)",
-                     "achieved": round(achieved / 1e12, 4), "peak": round(MODMUL_PEAK / 1e12, 4),
-                     "unit": "Tmodmul/s", "frac": round(achieved / MODMUL_PEAK, 4), "traffic": None,
-                     "per_step_modmuls": modmuls},
+        "config": {"workload": f"c3: {w['desc']}", "requests": nreq, "queries_per_step": total_q},
+        "latency_ms": packed["latency_ms"], "roofline": packed["roofline"],
+        "plain": plain, "batched_unpacked": unpacked, "packed": packed, "packed_eager": packed_eager,
+        "speedup_unpacked_vs_plain": round(unpacked["value"] / plain["value"], 3),
+        "speedup_packed_vs_plain": round(packed["value"] / plain["value"], 3),
     }
     batch.close()
     pbatch.close()
     for t in tenants:
         t["sess"].close()
-    print(json.dumps(result), flush=True)
-    return 0
+    return result
 
 
 def bench_serving(args, w) -> int:
@@ -424,6 +537,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="plain workload only: skip the batching workload's plain / batched / packed leg")
     ap.add_argument("--cpu-sample-m", type=int, default=0,
                     help="model ciphertexts in the oracle's timed sample (0: the workload's default)")
     ap.add_argument("--seed", type=int, default=0)
@@ -537,6 +652,12 @@ def main() -> int:
     kern, stage = ("k_mac", "mac") if split else ("k_score", "score")
     modmuls, k_ms = per_launch(kern, stage)
     achieved = modmuls / (k_ms * 1e-3)
+
+    def hbm(traffic, ms):
+        """Achieved HBM bandwidth of a launch moving `traffic` bytes in `ms`, and its fraction of 8 TB/s."""
+        if traffic is None:
+            return {"hbm_gbps": None, "hbm_frac": None}
+        return {"hbm_gbps": round(traffic / (ms * 1e-3) / 1e9, 1), "hbm_frac": round(traffic / (ms * 1e-3) / HBM_PEAK, 4)}
     result = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -562,14 +683,19 @@ def main() -> int:
                      "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
                      "frac": round(achieved / MODMUL_PEAK, 4),
                      "traffic": recorded_traffic(kern, args.workload),
-                     "per_launch_modmuls": modmuls, "avg_launch_ms": round(k_ms, 4)},
+                     "per_launch_modmuls": modmuls, "avg_launch_ms": round(k_ms, 4),
+                     **hbm(recorded_traffic(kern, args.workload), k_ms),
+                     "valu_issue": recorded_valu_issue(kern, args.workload)},
     }
     if split:
         e_ops, e_ms = per_launch("k_encode_pt", "encode_pt")
         result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_pt",
                                         "achieved": round(e_ops / (e_ms * 1e-3) / 1e12, 4),
                                         "frac": round(e_ops / (e_ms * 1e-3) / MODMUL_PEAK, 4),
-                                        "avg_launch_ms": round(e_ms, 4)}
+                                        "avg_launch_ms": round(e_ms, 4),
+                                        "traffic": recorded_traffic("k_encode_pt", args.workload),
+                                        **hbm(recorded_traffic("k_encode_pt", args.workload), e_ms),
+                                        "valu_issue": recorded_valu_issue("k_encode_pt", args.workload)}
     if prof["encode"][1]:
         # the HDC projection: 2*F*D int8 operations per query, against the dense int8 MFMA peak
         h_ms = prof["encode"][0] / prof["encode"][1]
@@ -580,6 +706,15 @@ def main() -> int:
                                   "traffic": recorded_traffic("k_hdc_encode", args.workload),
                                   "avg_launch_ms": round(h_ms, 4)}
     sess.close()
+    del d_x, d_base, d_hv, d_out
+    if args.workload == "c2" and not args.no_batched:
+        # the metric's other half: the batching workload at the same N and limbs, its requests
+        # scored one after another (plain), as one unpacked batch and as one packed batch
+        b = run_batched(args, WORKLOADS["c3"])
+        if b is None:
+            return 3
+        result["batched"] = {k: b[k] for k in ("config", "plain", "batched_unpacked", "packed", "packed_eager",
+                                               "speedup_unpacked_vs_plain", "speedup_packed_vs_plain")}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m or w.get("cpu_sample_m", 256))
     print(json.dumps(result), flush=True)
