@@ -49,6 +49,14 @@ WORKLOADS = {
                     "encrypted models (16 at BFV N=8192 / 4 limbs cycling K in {2, 7} x D in {2048, 4096, 10240}; "
                     "16 at N=16384 / 8+2 limbs, dnum=4, r=4 cycling the same (K, D)), HBM-budget admission, "
                     "continuous batching on 2 streams"),
+    # findDmax sweep (design space exploration): N = 2048, two 24-bit limbs (Q about 2^48),
+    # binary queries and 8-bit classes, K = 2 (the paper's Face task), per scheme and t
+    "dmax": dict(dmax=True, N=2048, L=2, prime_bits=24, K=2, qbits=1, cbits=8, d_cap=4096, trials=8,
+                 sweep={"bfv": [12289, 40961, 65537, 114689, 147457, 270337],
+                        "bfv-r": [114689, 270337, 786433, 1179649, 1597441],
+                        "bgv": [114689, 270337, 786433, 1179649, 1597441]},
+                 desc="findDmax trials at N=2048, 2 x 24-bit primes, K=2, binary queries, 8-bit classes, "
+                      "d_cap=4096: BFV, rounded BFV and BGV over t"),
     # large parameters: 8 ciphertext limbs + 2 special primes, hybrid key switching with 4
     # digits, 8 blocks folded per row (3 rotations per score ciphertext)
     "c4": dict(N=16384, L=8, alpha=2, dnum=4, r=8, F=2304, D=10240, K=26, Q=16384, images=True, cpu_sample_m=24,
@@ -530,6 +538,74 @@ def bench_serving(args, w) -> int:
     return 0
 
 
+def _primes_below(bound: int, N: int, count: int) -> list[int]:
+    """The `count` largest primes below `bound` that are 1 mod 2N (trial division: the
+    bounds used here are small)."""
+    def is_prime(n):
+        if n < 2 or n % 2 == 0:
+            return n == 2
+        f = 3
+        while f * f <= n:
+            if n % f == 0:
+                return False
+            f += 2
+        return True
+    out, k = [], (bound - 2) // (2 * N)
+    while len(out) < count:
+        if is_prime(k * 2 * N + 1):
+            out.append(k * 2 * N + 1)
+        k -= 1
+    return out
+
+
+def bench_dmax(args, w) -> int:
+    """findDmax on the device over schemes and plaintext moduli: mean and spread of D_max per
+    (scheme, t), the device's seconds per trial, and the oracle's seconds per trial on the
+    host for the first setting (a bounded number of its prefixes)."""
+    N, L, K = w["N"], w["L"], w["K"]
+    q = tuple(_primes_below(1 << w["prime_bits"], N, L))
+    rows = []
+    t_all = time.perf_counter()
+    trials = args.steps if args.steps != 20 else w["trials"]
+    for scheme, ts in w["sweep"].items():
+        for t in ts:
+            prm = ep.Params(N=N, q=q, t=t, D=w["d_cap"], K=K, F=16, scheme=scheme, qbits=w["qbits"])
+            t0 = time.perf_counter()
+            d = ep.ephdc_find_dmax(prm, args.seed, trials, w["d_cap"], w["cbits"])
+            dt = time.perf_counter() - t0
+            rows.append({"scheme": scheme, "t": t, "log2_t": round(math.log2(t), 2), "mean": float(np.mean(d)),
+                         "std": round(float(np.std(d)), 2), "min": int(d.min()), "max": int(d.max()),
+                         "capped": int((d >= w["d_cap"]).sum()), "s_per_trial": round(dt / trials, 4)})
+            print(f"[bench] dmax {scheme} t={t}: mean {rows[-1]['mean']:.1f} (min {d.min()}, max {d.max()}), "
+                  f"{dt / trials:.3f} s/trial", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t_all
+    ntr = trials * len(rows)
+    result = {"metric": "findDmax prefix evaluations/s (every D-term sum of a trial encrypted, decrypted and "
+                        "checked; host encryption included)",
+              "value": round(ntr * w["d_cap"] / wall, 1),
+              "unit": "prefixes/s", "n_gpus": 1, "steps": ntr, "warmup": 0, "ms_per_step": round(wall * 1e3 / ntr, 2),
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+              "config": {"workload": f"dmax: {w['desc']}", "primes": list(q), "trials_per_setting": trials},
+              "sweep": rows}
+    if not args.no_cpu_baseline:
+        from oracle import dmax as odmax
+        from oracle.params import Params as OParams
+        r0 = rows[0]
+        cap = 64  # a bounded oracle trial: at most 64 prefixes (encryption of its model untimed)
+        o = OParams(N=N, q=q, t=r0["t"], D=cap, K=K, F=8, scheme=r0["scheme"], qbits=w["qbits"])
+        t0 = time.perf_counter()
+        d0 = odmax.trial(o, args.seed, cap, w["cbits"])
+        t_or = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(min(d0 + 1, cap) / t_or, 3), "unit": "prefixes/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"one oracle trial of the first setting ({r0['scheme']}, t={r0['t']}) "
+                                            f"capped at {cap} prefixes (it evaluated {min(d0 + 1, cap)}; its model "
+                                            f"encryption included); numpy and Python integers, single thread",
+                                  "seconds": round(t_or, 2)}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,6 +647,8 @@ def main() -> int:
         return bench_batched(args, w)
     if w.get("serving"):
         return bench_serving(args, w)
+    if w.get("dmax"):
+        return bench_dmax(args, w)
     N, L, Q = w["N"], w["L"], w["Q"]
     alpha, r = w.get("alpha", 0), w.get("r", 1)
     primes = ep.default_primes(N, L + alpha)

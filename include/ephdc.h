@@ -307,6 +307,27 @@ ephdc_status ephdc_session_set_chunk_bytes(ephdc_session* s, size_t bytes);
 ephdc_status ephdc_session_profile(ephdc_session* s, int enable);
 ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[6], uint64_t count[6]);
 
+/*
+ * findDmax (EP-HDC design space exploration, Exploration Algorithm, procedure findDmax; the
+ * noise study): the largest hypervector dimension whose encrypted ciphertext x plaintext
+ * dot product still decrypts correctly, for `trials` independent trials.
+ * Trial i uses seed + i for every stream: secret key (tag 4), model encryption (tag 5),
+ * class values C [K][d_cap] (tag 8, draw m*K + c) and query values h [B][d_cap] (tag 9,
+ * draw m*B + q); a value of b bits is 2*(u mod 2) - 1 for b = 1, else (u mod 2^b) - 2^(b-1),
+ * with b = cbits for classes and qbits (of prm) for queries.  The class values are encrypted
+ * as d_cap model ciphertexts (the paper's packing, r = 1, prm's scheme), the queries form
+ * query group 0, and the D-term sum_{m<D} ct_m * p_m is correct when it decrypts to the
+ * plaintext of the exact dot products mod t in every slot.  dmax[i] (host, int32 [trials])
+ * is the number of D = 1, 2, ... that decrypt correctly before the first that does not
+ * (d_cap when none fails).  Uses prm's N, L <= 2, q, t, K, qbits and scheme (r must be 1;
+ * F, D and the scaling op are ignored); the primes may be any above t (the noise budget is
+ * set by Q), not only the scoring kernels' [2^29, 2^30).  Key generation and encryption run on the host; the
+ * batch encoding, every prefix sum, its decryption and the comparison on the device, which
+ * the call allocates for itself (about d_cap * N * (8L + 12) bytes).  Synchronous.
+ */
+ephdc_status ephdc_find_dmax(const ephdc_params* prm, uint64_t seed, uint32_t trials, uint32_t d_cap,
+                             uint32_t cbits, int32_t* dmax, void* stream);
+
 /* ---------------------------------------------------------------- request batches
  * Many clients' requests scored together: every kernel stage of the scoring path runs as one
  * persistent launch over the work items (request, query group, model-ciphertext segment,

@@ -85,6 +85,7 @@ def lib() -> C.CDLL:
                                                 C.c_void_p, C.c_void_p]),
             "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                               C.c_void_p]),
+            "ephdc_find_dmax": (C.c_int, [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, i32p, C.c_void_p]),
             "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
             "ephdc_session_set_chunk_bytes": (C.c_int, [C.c_void_p, C.c_size_t]),
             "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
@@ -405,6 +406,14 @@ def ephdc_debug_polymul(s: Session, d_a, d_b, count: int, d_out, stream=None) ->
     nb = count * s.prm.N * 4
     _check(lib().ephdc_debug_polymul(s.handle, _dptr(d_a, nb), _dptr(d_b, nb), count, _dptr(d_out, nb),
                                      _stream(stream)))
+
+
+def ephdc_find_dmax(prm: Params, seed: int, trials: int, d_cap: int, cbits: int = 8, stream=None) -> np.ndarray:
+    """D_i of `trials` findDmax trials (int32 [trials]); see the header."""
+    c = prm.c()
+    out = np.zeros(trials, dtype=np.int32)
+    _check(lib().ephdc_find_dmax(C.byref(c), seed, trials, d_cap, cbits, _ptr(out, C.c_int32), _stream(stream)))
+    return out
 
 
 # ------------------------------------------------------------------ request batches

@@ -306,6 +306,15 @@ ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, cons
   ephdc_status st = P.load(prm);
   if (st != EPHDC_OK) return st;
   if (!sk || !class_hv || !model_ct) return fail(EPHDC_ERR_ARG, "NULL buffer");
+  return encrypt_model_host(P, sk, class_hv, seed, model_ct);
+}
+
+}  // extern "C"
+
+namespace ephdc {
+
+ephdc_status encrypt_model_host(const ParamSet& P, const int8_t* sk, const int8_t* class_hv, uint64_t seed,
+                                uint32_t* model_ct) {
   HostTables H(P);
   const uint32_t N = P.N, L = P.L, M = P.M();
   const auto cdt = gaussian_cdt();
@@ -366,6 +375,10 @@ ephdc_status ephdc_encrypt_model(const ephdc_params* prm, const int8_t* sk, cons
   });
   return EPHDC_OK;
 }
+
+}  // namespace ephdc
+
+extern "C" {
 
 ephdc_status ephdc_decrypt_scores(const ephdc_params* prm, const int8_t* sk, const uint32_t* score_ct,
                                   uint32_t Q, int32_t* scores, int32_t* argmax) {

@@ -61,6 +61,11 @@ inline uint32_t slot_index(const ParamSet& P, uint32_t rho, uint32_t u, uint32_t
   return rho * (P.N / 2) + u * P.W() + ql * P.K + c;
 }
 
+// The model ciphertexts of ephdc_encrypt_model for a validated parameter set: class
+// hypervectors int8 [K][D] -> uint32 [M][2][L][N], coefficient domain.
+ephdc_status encrypt_model_host(const ParamSet& P, const int8_t* sk, const int8_t* class_hv, uint64_t seed,
+                                uint32_t* model_ct);
+
 // Galois element of rotate-and-sum step i: 3^(W * 2^i) mod 2N.
 inline uint32_t galois_element(const ParamSet& P, uint32_t i) {
   return (uint32_t)powmod64(3, (uint64_t)P.W() << i, 2ull * P.N);

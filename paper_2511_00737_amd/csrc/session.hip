@@ -360,6 +360,16 @@ size_t ephdc_workspace_bytes(const ephdc_params* prm, uint32_t max_Q) {
 ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
                                   const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q,
                                   void* d_workspace, size_t ws_bytes, void* stream, ephdc_session** out) {
+  return session_create(prm, d_model_ct, model_words, d_galois_keys, gk_words, max_Q, d_workspace, ws_bytes, stream,
+                        true, out);
+}
+
+}  // extern "C"
+
+ephdc_status ephdc::session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
+                                   const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q,
+                                   void* d_workspace, size_t ws_bytes, void* stream, bool mac_primes,
+                                   ephdc_session** out) {
   if (!out) return fail(EPHDC_ERR_ARG, "out is NULL");
   *out = nullptr;
   ParamSet P;
@@ -367,8 +377,11 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   if (st != EPHDC_OK) return st;
   if (!d_model_ct) return fail(EPHDC_ERR_ARG, "model is NULL");
   if (!supported_logn(P.logn)) return fail(EPHDC_ERR_UNSUPPORTED, "kernels implement N in {2048, 4096, 8192, 16384}");
-  for (uint32_t qi : P.q)
-    if (qi < (1u << 29)) return fail(EPHDC_ERR_UNSUPPORTED, "the device kernels take ciphertext primes in [2^29, 2^30)");
+  for (uint32_t qi : P.q) {
+    if (mac_primes && qi < (1u << 29))
+      return fail(EPHDC_ERR_UNSUPPORTED, "the device kernels take ciphertext primes in [2^29, 2^30)");
+    if (qi <= P.t) return fail(EPHDC_ERR_UNSUPPORTED, "the device kernels take ciphertext primes above t");
+  }
   if (P.r > 1 && !d_galois_keys) return fail(EPHDC_ERR_NOKEY, "r > 1 needs Galois keys");
   if (max_Q == 0) return fail(EPHDC_ERR_ARG, "max_Q must be positive");
   if (model_words < (size_t)P.M() * 2 * P.L * P.N) return fail(EPHDC_ERR_BUFFER, "model buffer shorter than [M][2][L][N]");
@@ -490,6 +503,8 @@ ephdc_status ephdc_session_create(const ephdc_params* prm, const uint32_t* d_mod
   *out = s;
   return EPHDC_OK;
 }
+
+extern "C" {
 
 ephdc_status ephdc_session_destroy(ephdc_session* s) {
   if (!s) return fail(EPHDC_ERR_ARG, "session is NULL");

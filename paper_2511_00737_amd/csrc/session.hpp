@@ -100,6 +100,13 @@ size_t workspace_min_bytes(const ParamSet& P, uint32_t max_Q);
 size_t workspace_default_bytes(const ParamSet& P, uint32_t max_Q);
 ephdc_status workspace_layout(const ParamSet& P, uint32_t max_Q, void* base, size_t bytes, Workspace* out);
 
+// ephdc_session_create; with mac_primes false, ciphertext primes below 2^29 (but above t)
+// are accepted, for callers that use the transforms and the batch encoding but not the
+// multiply-accumulate kernels, whose lazy bounds need primes of at least 2^29.
+ephdc_status session_create(const ephdc_params* prm, const uint32_t* d_model_ct, size_t model_words,
+                            const uint32_t* d_galois_keys, size_t gk_words, uint32_t max_Q, void* d_workspace,
+                            size_t ws_bytes, void* stream, bool mac_primes, ephdc_session** out);
+
 // Words of the partial sums that scoring Q queries takes under the session's schedule.
 size_t score_partial_words(const ephdc_session* s, uint32_t Q);
 
