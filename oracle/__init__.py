@@ -20,6 +20,8 @@ Modules, each citing the passage of the paper it restates:
   pipeline  the whole client-side path: queries -> encrypted score ciphertexts
   dmax      findDmax of the design-space exploration (Algorithm 1): the
             largest dimension whose encrypted dot product still decrypts
+  hog       the detection front end: sliding windows over a frame and each
+            window's HOG feature map (integer reading of Dalal-Triggs HOG)
 
 Variants (BGV/BFV-aware quantisation and the noise study): any prime plaintext
 modulus t = 1 (mod 2N); the schemes BFV, BFV with rounded scaling, and BGV; and
@@ -31,5 +33,5 @@ The key-switching output bits are pinned only through decryption
 (a rotated, correctly decrypting ciphertext) and the stated formulas; there
 is no published worked example of them.
 """
-from . import arith, prng, ntt, slots, hdc, layout, bfv, pipeline, dmax  # noqa: F401
+from . import arith, prng, ntt, slots, hdc, layout, bfv, pipeline, dmax, hog  # noqa: F401
 from .params import Params, default_primes  # noqa: F401
