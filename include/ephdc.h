@@ -328,6 +328,45 @@ ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[6], uint64_t
 ephdc_status ephdc_find_dmax(const ephdc_params* prm, uint64_t seed, uint32_t trials, uint32_t d_cap,
                              uint32_t cbits, int32_t* dmax, void* stream);
 
+/* ---------------------------------------------------------------- detection front end
+ * The paper's driving example (Our Proposed Method, applications: HDC-based object
+ * detection): a window slides over an image frame left to right, row by row, and each
+ * window's HOG feature map is one query of ephdc_encode_queries.  The HOG here is exact
+ * integer arithmetic: central-difference gradients with replicated borders, floor(sqrt)
+ * magnitudes, 9 unsigned orientation bins of 20 degrees (a gradient folded to the upper half
+ * plane is in bin b = the number of k = 1..8 with C_k*gy - S_k*gx >= 0, C_k = round(2^14
+ * cos(20k deg)), S_k = round(2^14 sin(20k deg))), 8 x 8-pixel cells, 2 x 2-cell blocks at a
+ * stride of one cell whose 36 values v are L2-normalised with the clip at 0.2 scaled to byte
+ * 255, min(255, floor(1275 v / n)) with n = floor(sqrt(sum v^2)) (0 when n is 0), and per
+ * window its (w/8 - 1)^2 blocks in row order, padded with 128 (the encoder's zero point) to a
+ * multiple of 16 features.
+ */
+
+/* Features per window (the F of the HDC parameters): (w/8 - 1)^2 * 36 rounded up to a
+ * multiple of 16; 0 unless w is a multiple of 8 and >= 16. */
+uint32_t ephdc_hog_feature_count(uint32_t window);
+
+/* Windows of a frame: ((H - w)/stride + 1) * ((W - w)/stride + 1), 0 for an invalid shape
+ * (w, stride multiples of 8, w >= 16, w <= H, W <= 65536). */
+uint32_t ephdc_hog_window_count(uint32_t H, uint32_t W, uint32_t window, uint32_t stride);
+
+/* Device workspace of ephdc_hog_windows for an H x W frame: cell histograms and blocks. */
+size_t ephdc_hog_workspace_bytes(uint32_t H, uint32_t W);
+
+/*
+ * HOG features of every window of a frame:
+ *   d_frame      device, uint8 [H][W] grey levels, row-major
+ *   window, stride  window side and step in pixels (multiples of 8; window >= 16)
+ *   d_workspace  device, ws_bytes >= ephdc_hog_workspace_bytes(H, W), 256-byte aligned
+ *   d_x          out, device, uint8 [ephdc_hog_window_count][ephdc_hog_feature_count],
+ *                4-byte aligned; window (i, j) (origin (i*stride, j*stride)) is row
+ *                i * ((W - window)/stride + 1) + j
+ * Asynchronous on `stream`.  EPHDC_ERR_ARG for an invalid shape or alignment,
+ * EPHDC_ERR_BUFFER for a short workspace.
+ */
+ephdc_status ephdc_hog_windows(const uint8_t* d_frame, uint32_t H, uint32_t W, uint32_t window, uint32_t stride,
+                               void* d_workspace, size_t ws_bytes, uint8_t* d_x, void* stream);
+
 /* ---------------------------------------------------------------- request batches
  * Many clients' requests scored together: every kernel stage of the scoring path runs as one
  * persistent launch over the work items (request, query group, model-ciphertext segment,

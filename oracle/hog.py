@@ -15,7 +15,8 @@ arithmetic, so that every feature is a plain function of the pixels:
   S_k = round(2^14 sin)) it lies on or past: C_k * gy - S_k * gx >= 0;
 * cells of 8 x 8 pixels; a cell's histogram adds each pixel's magnitude to its bin;
 * blocks of 2 x 2 cells at a stride of one cell; a block's 36 values v (cells in row order,
-  bins within) are L1-normalised to bytes: floor(255 * v / sum) (0 when the sum is 0);
+  bins within) are L2-normalised with the usual clip at 0.2, scaled so that the clip is
+  byte 255: min(255, floor(1275 * v / n)) with n = floor(sqrt(sum v^2)) (0 when n is 0);
 * a window of w x w pixels at (wy, wx), both multiples of 8, covers (w/8 - 1)^2 blocks of
   the frame; its feature vector is their values in block row order, padded with 128 (the
   HDC encoder's zero point) to a multiple of 16 entries;
@@ -85,11 +86,11 @@ def cell_histograms(frame: np.ndarray) -> np.ndarray:
 
 
 def block_features(hist: np.ndarray) -> np.ndarray:
-    """uint8 [hc-1][wc-1][36]: L1-normalised 2 x 2-cell blocks (floor(255 v / sum))."""
+    """uint8 [hc-1][wc-1][36]: 2 x 2-cell blocks, min(255, floor(1275 v / isqrt(sum v^2)))."""
     hc, wc, _ = hist.shape
     v = np.concatenate([hist[:-1, :-1], hist[:-1, 1:], hist[1:, :-1], hist[1:, 1:]], axis=2)
-    s = v.sum(axis=2, keepdims=True)
-    out = np.where(s > 0, (255 * v) // np.maximum(s, 1), 0)
+    n = isqrt((v * v).sum(axis=2, keepdims=True))
+    out = np.where(n > 0, np.minimum(255, (1275 * v) // np.maximum(n, 1)), 0)
     return out.astype(np.uint8)
 
 
@@ -145,7 +146,7 @@ def window_features_naive(frame: np.ndarray, window: int, stride: int) -> np.nda
         for by in range(wy // CELL, wy // CELL + nb):
             for bx in range(wx // CELL, wx // CELL + nb):
                 v = hist[by][bx] + hist[by][bx + 1] + hist[by + 1][bx] + hist[by + 1][bx + 1]
-                s = sum(v)
-                feat += [(255 * a) // s if s else 0 for a in v]
+                n = math.isqrt(sum(a * a for a in v))
+                feat += [min(255, (1275 * a) // n) if n else 0 for a in v]
         rows.append(feat + [PAD_VALUE] * (F - len(feat)))
     return np.array(rows, dtype=np.uint8).reshape(-1, F)

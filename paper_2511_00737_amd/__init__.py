@@ -86,6 +86,11 @@ def lib() -> C.CDLL:
             "ephdc_debug_polymul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                               C.c_void_p]),
             "ephdc_find_dmax": (C.c_int, [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, i32p, C.c_void_p]),
+            "ephdc_hog_feature_count": (C.c_uint32, [C.c_uint32]),
+            "ephdc_hog_window_count": (C.c_uint32, [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
+            "ephdc_hog_workspace_bytes": (C.c_size_t, [C.c_uint32, C.c_uint32]),
+            "ephdc_hog_windows": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
+                                            C.c_size_t, C.c_void_p, C.c_void_p]),
             "ephdc_session_profile": (C.c_int, [C.c_void_p, C.c_int]),
             "ephdc_session_set_chunk_bytes": (C.c_int, [C.c_void_p, C.c_size_t]),
             "ephdc_session_tune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
@@ -414,6 +419,34 @@ def ephdc_find_dmax(prm: Params, seed: int, trials: int, d_cap: int, cbits: int 
     out = np.zeros(trials, dtype=np.int32)
     _check(lib().ephdc_find_dmax(C.byref(c), seed, trials, d_cap, cbits, _ptr(out, C.c_int32), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------ detection front end
+def ephdc_hog_feature_count(window: int) -> int:
+    return lib().ephdc_hog_feature_count(window)
+
+
+def ephdc_hog_window_count(H: int, W: int, window: int, stride: int) -> int:
+    return lib().ephdc_hog_window_count(H, W, window, stride)
+
+
+def ephdc_hog_workspace_bytes(H: int, W: int) -> int:
+    return lib().ephdc_hog_workspace_bytes(H, W)
+
+
+def ephdc_hog_windows(d_frame, window: int, stride: int, d_x, d_workspace=None, stream=None) -> None:
+    """HOG features of every window of the uint8 [H][W] device frame into d_x (uint8
+    [windows][features]); d_workspace: a device tensor of ephdc_hog_workspace_bytes(H, W)
+    bytes, allocated here when None."""
+    import torch
+    H, W = int(d_frame.shape[0]), int(d_frame.shape[1])
+    nws = lib().ephdc_hog_workspace_bytes(H, W)
+    if d_workspace is None:
+        d_workspace = torch.empty(max(nws, 1), dtype=torch.uint8, device=d_frame.device)
+    need = ephdc_hog_window_count(H, W, window, stride) * ephdc_hog_feature_count(window)
+    ws_bytes = d_workspace.numel() * d_workspace.element_size()
+    _check(lib().ephdc_hog_windows(_dptr(d_frame, H * W), H, W, window, stride, _dptr(d_workspace), ws_bytes,
+                                   _dptr(d_x, need), _stream(stream)))
 
 
 # ------------------------------------------------------------------ request batches

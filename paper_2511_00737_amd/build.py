@@ -25,7 +25,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
 HIP_SOURCES = ["kernels_ntt.hip", "kernels_ks.hip", "kernels_hdc.hip", "session.hip", "batch.hip", "server.hip",
-               "static_scratch.hip", "dmax.hip"]
+               "static_scratch.hip", "dmax.hip", "kernels_hog.hip"]
 CXX_SOURCES = ["host_crypto.cpp"]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-fconstexpr-steps=20000000",

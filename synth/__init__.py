@@ -106,6 +106,29 @@ def blob_images(seed: int, Q: int, side: int = 48) -> np.ndarray:
     return out
 
 
+def frame(seed: int, H: int, W: int, n_objects: int = 24) -> np.ndarray:
+    """uint8 [H][W]: one camera frame for the sliding-window detector, a stand-in for the
+    face-detection frames the paper's windows are taken from.  A base of U{0..31} noise, a
+    horizontal illumination ramp of up to 48 levels, and n_objects elliptical Gaussian blobs
+    (centre U over the frame, widths 6 + (u mod 40) and 6 + (u mod 40) pixels, amplitude
+    U{64..223}) whose sum is clipped to [0, 255]; draws from stream (seed, features tag)."""
+    u = draws(seed, TAG_FEATURES, 0, H * W + 5 * n_objects)
+    img = (u[:H * W] % np.uint64(32)).astype(np.float64).reshape(H, W)
+    img += 48.0 * np.arange(W)[None, :] / max(1, W - 1)
+    yy, xx = np.mgrid[0:H, 0:W]
+    for b in range(n_objects):
+        cy, cx, wy, wx, a = (int(v) for v in u[H * W + 5 * b: H * W + 5 * b + 5])
+        cy %= H
+        cx %= W
+        sy, sx = 6 + wy % 40, 6 + wx % 40
+        amp = 64 + a % 160
+        y0, y1 = max(0, cy - 4 * sy), min(H, cy + 4 * sy + 1)
+        x0, x1 = max(0, cx - 4 * sx), min(W, cx + 4 * sx + 1)
+        dy, dx = yy[y0:y1, x0:x1] - cy, xx[y0:y1, x0:x1] - cx
+        img[y0:y1, x0:x1] += amp * np.exp(-(dy * dy) / (2.0 * sy * sy) - (dx * dx) / (2.0 * sx * sx))
+    return np.clip(np.floor(img), 0, 255).astype(np.uint8)
+
+
 # --------------------------------------------------------------------------- request traces
 def loguniform_batch_sizes(seed: int, n: int, hi: int = 4096) -> np.ndarray:
     """n batch sizes floor(exp(U[0, ln hi])), clipped to [1, hi]."""

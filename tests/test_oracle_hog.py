@@ -40,7 +40,9 @@ def test_bins_agree_with_angles_away_from_the_boundaries():
 
 
 def test_integer_square_root_is_exact():
-    n = np.concatenate([np.arange(0, 200000), np.random.default_rng(0).integers(0, 2 * 255 ** 2 + 1, 100000)])
+    n = np.concatenate([np.arange(0, 200000), np.random.default_rng(0).integers(0, 2 * 255 ** 2 + 1, 100000),
+                        np.random.default_rng(1).integers(0, 36 * 23040 ** 2 + 1, 100000),
+                        np.array([k * k - 1 for k in range(1, 150000, 7)] + [k * k for k in range(1, 150000, 7)])])
     assert np.array_equal(hog.isqrt(n), np.array([math.isqrt(int(v)) for v in n]))
 
 
@@ -71,8 +73,13 @@ def test_cell_totals_and_block_normalisation():
     h = hog.cell_histograms(fr)
     assert np.array_equal(h.sum(axis=2), mag.reshape(8, 8, 9, 8).sum(axis=(1, 3)))
     blk = hog.block_features(h).astype(np.int64)
-    s = blk.sum(axis=2)
-    assert np.all((s <= 255) & (s >= 255 - 35))
+    # the largest of a block's values is at least a sixth of its norm: its byte is >= 212
+    assert np.all(blk.max(axis=2) >= 212) and blk.max() == 255
+    # a block of one non-zero value clips to 255; equal values give floor(1275 / 6) = 212
+    one = np.zeros((2, 2, 9), dtype=np.int64)
+    one[0, 0, 3] = 77
+    assert hog.block_features(one)[0, 0, 3] == 255 and hog.block_features(one).sum() == 255
+    assert np.all(hog.block_features(np.full((2, 2, 9), 5, dtype=np.int64)) == 212)
 
 
 def test_interior_windows_depend_only_on_their_neighbourhood():
