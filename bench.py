@@ -469,7 +469,7 @@ def bench_serving(args, w) -> int:
         if pack:
             sv.set_packing(True)
         ids = [sv.add_tenant(t["sess"], t["base"]) for t in tenants]
-        live, check, tickets = {}, [], []
+        live, check, waits = {}, [], []
         torch.cuda.synchronize()
         start = time.perf_counter()
         for i, (ta, ti, Q) in enumerate(trace):
@@ -481,18 +481,22 @@ def bench_serving(args, w) -> int:
                               dtype=torch.int32, device=dev)
             tk = sv.submit(ids[ti], pool[:Q], Q, out)
             live[tk] = (out, Q, ti)
-            tickets.append(tk)
-            if i % 200 == 0:  # release finished outputs now and then; keep a few to check
-                for k in [k for k in live if sv.query(k)[0] == 2]:
+            if i % 200 == 0:  # release finished requests now and then; keep a few to check
+                for k in list(live):
+                    st, (ts, tad, td) = sv.query(k)
+                    if st != 2:
+                        continue
+                    waits.append(tad - ts)
                     item = live.pop(k)
                     if len(check) < 4 and k % 7 == 0:
                         check.append((k, item))
+                    else:
+                        sv.release(k)
         t_submitted = time.perf_counter() - start
         sv.wait(0, timeout_s=600)
         wall = time.perf_counter() - start
         stats = sv.stats()
-        waits = []
-        for tk in tickets:
+        for tk in live:
             st, (ts, tad, td) = sv.query(tk)
             if st == 2:
                 waits.append(tad - ts)

@@ -16,8 +16,9 @@
  *
  * Conventions
  *  - Every buffer is owned by the caller.  A session copies what it keeps (its own
- *    transformed copy of the model and keys) and may be used only from one host
- *    thread at a time.
+ *    transformed copy of the model and keys), borrows the scratch workspace it is given,
+ *    and may be used only from one host thread at a time; its scoring calls on different
+ *    streams are ordered by the session (each waits on the device for the previous one).
  *  - Residues are uint32 in [0, q); polynomials are N coefficients in degree order;
  *    arrays are C-contiguous with the shapes given below.
  *  - Errors: argument and parameter errors are returned before any work is queued.
@@ -44,7 +45,8 @@ typedef enum {
   EPHDC_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
   EPHDC_ERR_NOKEY = 5,       /* rotations needed (r > 1) but no Galois keys were given */
   EPHDC_ERR_OOM = 6,         /* device allocation failed */
-  EPHDC_ERR_UNSUPPORTED = 7  /* valid parameters outside what the kernels implement */
+  EPHDC_ERR_UNSUPPORTED = 7, /* valid parameters outside what the kernels implement */
+  EPHDC_ERR_TIMEOUT = 8      /* a wait ended at its time limit */
 } ephdc_status;
 
 /* Homomorphic scheme of the model ciphertexts (Preliminary: HE; noise results). */
@@ -253,7 +255,9 @@ ephdc_status ephdc_score_encrypted_static(ephdc_session* s, const int8_t* d_hv, 
 /*
  * Debug: the lifted plaintext of query group g and model index m, reduced into every
  * limb, uint32 [L][N] coefficient domain (the centred representative of
- * Encode(slot vector) in (-t/2, t/2], mod q_l).  Exposes the batch-encoding step alone.
+ * Encode(slot vector) in (-t/2, t/2], mod q_l).  Exposes the batch-encoding step alone
+ * (proposed method, client-side HE: every query element in its own plaintext, repeated
+ * once per class; the plaintext encoding the paper times as EncPt).
  */
 ephdc_status ephdc_debug_plaintext(ephdc_session* s, const int8_t* d_hv, uint32_t Q, uint32_t g,
                                    uint32_t m, uint32_t* d_out, void* stream);
@@ -368,7 +372,8 @@ ephdc_status ephdc_hog_windows(const uint8_t* d_frame, uint32_t H, uint32_t W, u
                                void* d_workspace, size_t ws_bytes, uint8_t* d_x, void* stream);
 
 /* ---------------------------------------------------------------- request batches
- * Many clients' requests scored together: every kernel stage of the scoring path runs as one
+ * Many clients' requests scored together (the client-side method's batch inference, which
+ * the paper argues scales to many clients, applied across requests): every kernel stage of the scoring path runs as one
  * persistent launch over the work items (request, query group, model-ciphertext segment,
  * limb group) of all requests, so requests of 1 query and of thousands, and models of
  * different K, D and r, share the GPU in the same launches.  Requests whose sessions have
@@ -444,7 +449,8 @@ ephdc_status ephdc_batch_create_packed(const ephdc_request* reqs, uint32_t n_req
 ephdc_status ephdc_batch_packing(const ephdc_batch* b, uint32_t i, uint32_t* query_offset, uint32_t* q_first,
                                  uint32_t* n_ct);
 
-/* Convenience: plan, run on `stream`, wait for it and free the plan. */
+/* Many requests' homomorphic scoring in one call (ephdc_score_encrypted per request, batched
+ * as above): plan, run on `stream`, wait for it and free the plan. */
 ephdc_status ephdc_score_many(const ephdc_request* reqs, uint32_t n_req, void* stream);
 
 /* ---------------------------------------------------------------- serving loop
@@ -472,27 +478,38 @@ ephdc_status ephdc_server_add_tenant(ephdc_server* sv, ephdc_session* s, const i
 
 /*
  * Queues a request: d_x uint8 [Q][F] features (device, 16-byte aligned, unchanged until the
- * request is done), out d_score_ct uint32 [G][2][L][N].  Returns a ticket at once.
- * Errors (synchronous): EPHDC_ERR_ARG (unknown tenant, Q outside [1, max_Q], NULL),
- * EPHDC_ERR_UNSUPPORTED (encoding constraints).
+ * request is done), out d_score_ct uint32 [G][2][L][N].  The request's kernels run after the
+ * work queued on `stream` before this call (an event recorded there at submission), so d_x
+ * may be written by kernels or copies still in flight on that stream.  Returns a ticket at
+ * once.  Errors (synchronous): EPHDC_ERR_ARG (unknown tenant, Q outside [1, max_Q], NULL),
+ * EPHDC_ERR_UNSUPPORTED (encoding constraints), EPHDC_ERR_HIP (the scheduler could not
+ * start on the tenants' device).
  */
 ephdc_status ephdc_server_submit(ephdc_server* sv, uint32_t tenant, const uint8_t* d_x, uint32_t Q,
-                                 uint32_t* d_score_ct, uint64_t* ticket);
+                                 uint32_t* d_score_ct, void* stream, uint64_t* ticket);
 
 /* State of a ticket: 0 waiting, 1 in flight, 2 done, -status when it failed or was rejected
  * (-EPHDC_ERR_OOM: larger than the budget); times[3] = submit, admit, done in seconds since
- * the server was created (0 when not reached). */
+ * the server was created (0 when not reached).  A finished ticket is kept until released
+ * (ephdc_server_release); beyond 65536 finished tickets the oldest are forgotten, and calls
+ * that name a released or forgotten ticket return EPHDC_ERR_ARG. */
 ephdc_status ephdc_server_query(ephdc_server* sv, uint64_t ticket, int32_t* state, double times[3]);
 
 /* Waits until the ticket is done (ticket 0: until nothing waits or runs); timeout_s <= 0
- * waits without limit.  Returns the request's failure status if it failed. */
+ * waits without limit.  Returns the request's failure status if it failed, and
+ * EPHDC_ERR_TIMEOUT when the time limit passes first. */
 ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout_s);
+
+/* Forgets a finished ticket (done, failed or rejected); EPHDC_ERR_ARG while it waits or runs. */
+ephdc_status ephdc_server_release(ephdc_server* sv, uint64_t ticket);
 
 /* Counters: [0] submitted [1] completed [2] rejected [3] waiting [4] batches in flight
  * [5] batches launched [6] mean requests per batch [7] p50 latency ms [8] p99 latency ms
- * (submit to done, completed requests) [9] peak device bytes in use [10] budget bytes
- * [11] seconds since creation [12] failed (a launch or the device reported an error). */
-ephdc_status ephdc_server_stats(ephdc_server* sv, double out[13]);
+ * (submit to done, completed requests, from a histogram of 1 % wide bins) [9] peak device
+ * bytes in use [10] budget bytes [11] seconds since creation [12] failed (a launch or the
+ * device reported an error) [13] tickets the server holds (waiting, running, finished and
+ * not yet released). */
+ephdc_status ephdc_server_stats(ephdc_server* sv, double out[14]);
 
 /*
  * Packing (set before the first request): the requests of one tenant in a batch share

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libephdc.so")
 
-OK, ERR_ARG, ERR_PARAMS, ERR_BUFFER, ERR_HIP, ERR_NOKEY, ERR_OOM, ERR_UNSUPPORTED = range(8)
+OK, ERR_ARG, ERR_PARAMS, ERR_BUFFER, ERR_HIP, ERR_NOKEY, ERR_OOM, ERR_UNSUPPORTED, ERR_TIMEOUT = range(9)
 T_PLAIN = 65537
 
 
@@ -111,7 +111,8 @@ def lib() -> C.CDLL:
             "ephdc_server_create": (C.c_int, [C.c_size_t, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
             "ephdc_server_add_tenant": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, u32p]),
             "ephdc_server_submit": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
-                                              u64p]),
+                                              C.c_void_p, u64p]),
+            "ephdc_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
             "ephdc_server_query": (C.c_int, [C.c_void_p, C.c_uint64, i32p, C.POINTER(C.c_double)]),
             "ephdc_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double]),
             "ephdc_server_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -551,7 +552,7 @@ class Server:
     """Owns an ephdc_server: tenants, a request queue and a native scheduler thread."""
 
     STATS = ("submitted", "completed", "rejected", "waiting", "in_flight", "batches", "mean_batch",
-             "p50_ms", "p99_ms", "peak_bytes", "budget_bytes", "uptime_s", "failed")
+             "p50_ms", "p99_ms", "peak_bytes", "budget_bytes", "uptime_s", "failed", "tickets")
 
     def __init__(self, budget_bytes: int, streams: int = 2, max_batch: int = 0):
         h = C.c_void_p()
@@ -578,7 +579,9 @@ class Server:
         self._keep[("tenant", t.value)] = (session, d_base)
         return t.value
 
-    def submit(self, tenant: int, d_x, Q: int, d_score_ct) -> int:
+    def submit(self, tenant: int, d_x, Q: int, d_score_ct, stream=None) -> int:
+        """Queue a request; its kernels run after the work queued so far on `stream` (the
+        current stream by default), which may still be writing d_x."""
         session = self._keep[("tenant", tenant)][0] if ("tenant", tenant) in self._keep else None
         if session is None:
             raise EphdcError(ERR_ARG, "unknown tenant")
@@ -588,9 +591,14 @@ class Server:
             out_bytes += 2 * p.L * p.N * 4
         tk = C.c_uint64()
         _check(lib().ephdc_server_submit(self.handle, tenant, _dptr(d_x, Q * p.F), Q, _dptr(d_score_ct, out_bytes),
-                                         C.byref(tk)))
+                                         _stream(stream), C.byref(tk)))
         self._keep[("req", tk.value)] = (d_x, d_score_ct)
         return tk.value
+
+    def release(self, ticket: int) -> None:
+        """Forget a finished ticket (and drop this wrapper's references to its tensors)."""
+        _check(lib().ephdc_server_release(self.handle, ticket))
+        self._keep.pop(("req", ticket), None)
 
     def query(self, ticket: int):
         """(state, (t_submit, t_admit, t_done)); state 0 waiting, 1 in flight, 2 done, <0 failed."""
@@ -603,7 +611,7 @@ class Server:
         _check(lib().ephdc_server_wait(self.handle, ticket, timeout_s))
 
     def stats(self) -> dict:
-        out = (C.c_double * 13)()
+        out = (C.c_double * 14)()
         _check(lib().ephdc_server_stats(self.handle, out))
         return {k: out[i] for i, k in enumerate(self.STATS)}
 

@@ -70,6 +70,10 @@ struct ephdc_batch {
   void* mem = nullptr;
   size_t mem_bytes = 0;
   bool owned = false;
+  // completion of the last run (ephdc_batch_run / autotune), waited for before the work
+  // lists or the block are changed or freed
+  hipEvent_t done = nullptr;
+  bool done_set = false;
 };
 
 namespace {
@@ -513,9 +517,29 @@ void batch_packing(const ephdc_batch* b, uint32_t i, uint32_t* query_offset, uin
   *n_ct = (off + b->orig[i].Q - 1) / B - off / B + 1;
 }
 
+// Waits for the batch's last run on the device (not for other work of the process).
+void wait_done(ephdc_batch* b) {
+  if (b->done_set) (void)hipEventSynchronize(b->done);
+}
+
+// Records the completion of work just enqueued on `hs`.
+hipError_t mark_done(ephdc_batch* b, hipStream_t hs) {
+  if (!b->done) {
+    hipError_t e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      b->done = nullptr;
+      return e;
+    }
+  }
+  hipError_t e = hipEventRecord(b->done, hs);
+  if (e == hipSuccess) b->done_set = true;
+  return e;
+}
+
 void batch_free(ephdc_batch* b) {
   if (!b) return;
   drop_graph(b);
+  if (b->done) (void)hipEventDestroy(b->done);
   if (b->owned && b->mem) (void)hipFree(b->mem);
   delete b;
 }
@@ -545,7 +569,7 @@ ephdc_status ephdc_batch_create(const ephdc_request* reqs, uint32_t n_req, ephdc
 
 ephdc_status ephdc_batch_destroy(ephdc_batch* b) {
   if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
-  (void)hipDeviceSynchronize();
+  wait_done(b);
   batch_free(b);
   return EPHDC_OK;
 }
@@ -554,7 +578,7 @@ size_t ephdc_batch_device_bytes(const ephdc_batch* b) { return b ? b->mem_bytes 
 
 ephdc_status ephdc_batch_tune(ephdc_batch* b, const uint32_t schedule[5]) {
   if (!b || !schedule) return fail(EPHDC_ERR_ARG, "NULL argument");
-  (void)hipDeviceSynchronize();  // no launch of this batch may still read its work lists
+  wait_done(b);  // no launch of this batch may still read its work lists
   ephdc_status st = apply_schedule(b, schedule, nullptr);
   if (st == EPHDC_OK) {
     hipError_t e = hipStreamSynchronize(nullptr);
@@ -574,9 +598,10 @@ ephdc_status ephdc_batch_run(ephdc_batch* b, void* stream) {
   hipStream_t hs = (hipStream_t)stream;
   if (b->exec) {
     HIP_TRY(hipGraphLaunch(b->exec, hs), "graph launch");
-    return EPHDC_OK;
+  } else {
+    HIP_TRY(batch_enqueue(b, hs), "batch launch");
   }
-  HIP_TRY(batch_enqueue(b, hs), "batch launch");
+  HIP_TRY(mark_done(b, hs), "completion event");
   return EPHDC_OK;
 }
 
@@ -584,6 +609,7 @@ ephdc_status ephdc_batch_capture(ephdc_batch* b, void* stream) {
   if (!b) return fail(EPHDC_ERR_ARG, "batch is NULL");
   if (!stream) return fail(EPHDC_ERR_ARG, "capture needs a stream other than the null stream");
   hipStream_t hs = (hipStream_t)stream;
+  wait_done(b);
   drop_graph(b);
   HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeRelaxed), "begin capture");
   hipError_t e = batch_enqueue(b, hs);
@@ -621,7 +647,7 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
     (void)hipEventDestroy(e1);
     return st;
   };
-  (void)hipDeviceSynchronize();
+  wait_done(b);
   drop_graph(b);
   // mean ms per run of the current schedule
   auto measure = [&](double& ms) -> ephdc_status {
@@ -685,6 +711,7 @@ ephdc_status ephdc_batch_autotune(ephdc_batch* b, void* stream, uint32_t reps, u
     }
   }
   HIP_TRY(hipStreamSynchronize(hs), "autotune sync");
+  b->done_set = false;  // every run of the search has completed
   if (schedule) read_schedule(b, schedule);
   if (best_ms) *best_ms = best;
   return cleanup(EPHDC_OK);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -88,10 +89,43 @@ struct Req {
   const uint8_t* d_x;
   uint32_t* d_out;
   size_t hv_bytes;
+  hipEvent_t ready = nullptr;      // recorded on the caller's stream at submission
   uint32_t q_first = 0, n_ct = 0;  // where the request's queries sit in its output
   double t_submit = 0, t_admit = 0, t_done = 0;
   int state = 0;  // 0 waiting, 1 in flight, 2 done, < 0 failed (negated status)
 };
+
+// Submit-to-done latencies in a fixed histogram: bins of 1 % relative width from 1 us to
+// about 1000 s; percentiles are read to within that 1 %.
+class LatencyHist {
+ public:
+  static constexpr double kLo = 1e-6, kRatio = 1.01;
+  static constexpr int kBins = 2100;
+  void add(double s) {
+    int i = s <= kLo ? 0 : (int)(std::log(s / kLo) / std::log(kRatio));
+    bins_[std::min(std::max(i, 0), kBins - 1)] += 1;
+    ++n_;
+  }
+  // seconds at fraction p of the recorded latencies (the geometric centre of its bin)
+  double percentile(double p) const {
+    if (!n_) return 0.0;
+    const uint64_t want = std::min<uint64_t>(n_ - 1, (uint64_t)(p * (double)(n_ - 1) + 0.5));
+    uint64_t run = 0;
+    for (int i = 0; i < kBins; ++i) {
+      run += bins_[i];
+      if (run > want) return kLo * std::pow(kRatio, i + 0.5);
+    }
+    return kLo * std::pow(kRatio, kBins - 0.5);
+  }
+
+ private:
+  uint64_t bins_[kBins] = {};
+  uint64_t n_ = 0;
+};
+
+// Finished tickets (done, failed or rejected) kept for ephdc_server_query / _result until
+// released; past this many, the oldest are forgotten.
+constexpr size_t kKeepFinished = 1 << 16;
 
 struct Inflight {
   ephdc_batch* batch = nullptr;
@@ -126,11 +160,13 @@ struct ephdc_server {
   std::list<Inflight> inflight;
   std::thread worker;
   std::string worker_error;
+  bool broken = false;  // the scheduler could not start: every request fails
+  std::deque<uint64_t> finished;  // finished tickets, oldest first (may hold released ones)
   // statistics
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   uint64_t submitted = 0, completed = 0, rejected = 0, failed = 0, batches = 0, batched_requests = 0;
   size_t peak_bytes = 0;
-  std::vector<double> latencies;  // seconds, completed requests
+  LatencyHist latencies;  // completed requests
 };
 
 namespace {
@@ -142,6 +178,24 @@ double now_s(const ephdc_server* sv) {
 // Device memory of one request outside the batch block: its query hypervectors.
 size_t hv_bytes(const ephdc_session* s, uint32_t Q) { return (size_t)s->P.D * s->P.G(Q) * s->P.B(); }
 
+// A request reaches a final state: its submission event is released, and the oldest
+// finished tickets beyond kKeepFinished are forgotten (callers that never release them
+// keep the server's memory bounded).
+void finish(ephdc_server* sv, Req& r, int state) {
+  r.state = state;
+  r.t_done = now_s(sv);
+  if (r.ready) {
+    (void)hipEventDestroy(r.ready);
+    r.ready = nullptr;
+  }
+  sv->finished.push_back(r.ticket);
+  while (sv->finished.size() > kKeepFinished) {
+    auto it = sv->reqs.find(sv->finished.front());
+    if (it != sv->reqs.end() && (it->second.state == 2 || it->second.state < 0)) sv->reqs.erase(it);
+    sv->finished.pop_front();
+  }
+}
+
 // Completes every in-flight batch whose event has fired; returns whether any did.
 bool reap(ephdc_server* sv, std::unique_lock<std::mutex>&) {
   bool any = false;
@@ -151,17 +205,14 @@ bool reap(ephdc_server* sv, std::unique_lock<std::mutex>&) {
       ++it;
       continue;
     }
-    const double t = now_s(sv);
     for (uint64_t tk : it->tickets) {
       Req& r = sv->reqs[tk];
       if (q == hipSuccess) {
-        r.state = 2;
-        r.t_done = t;
-        sv->latencies.push_back(t - r.t_submit);
+        finish(sv, r, 2);
+        sv->latencies.add(r.t_done - r.t_submit);
         ++sv->completed;
       } else {
-        r.state = -EPHDC_ERR_HIP;
-        r.t_done = t;
+        finish(sv, r, -EPHDC_ERR_HIP);
         ++sv->failed;
       }
     }
@@ -177,11 +228,15 @@ bool reap(ephdc_server* sv, std::unique_lock<std::mutex>&) {
 }
 
 // Forms and launches one batch from the head of the waiting queue on stream `si`: requests
-// are taken in arrival order while the batch's footprint fits the free device memory.
+// are taken in arrival order while the batch's footprint fits the free device memory.  The
+// selection and the memory reservation happen under the lock; planning, uploading the work
+// lists and enqueueing the launches do not, so submissions and queries proceed meanwhile.
 // Returns false when nothing could be admitted.
-bool admit(ephdc_server* sv, int si) {
+bool admit(ephdc_server* sv, int si, std::unique_lock<std::mutex>& lk) {
   std::vector<uint64_t> take;
   std::vector<ephdc_request> rq;
+  std::vector<size_t> hvb;
+  std::vector<hipEvent_t> ready;
   size_t hv_total = 0, need = 0;
   const size_t free_bytes = sv->budget - sv->arena.used();
   // footprint of a candidate list: with packing the batch holds the packed hypervectors
@@ -206,10 +261,9 @@ bool admit(ephdc_server* sv, int si) {
       rq.pop_back();
       if (take.empty() && footprint({e}, hv) > sv->budget) {
         // larger than the whole budget: can never be admitted
-        r.state = -EPHDC_ERR_OOM;
-        r.t_done = now_s(sv);
         ++sv->rejected;
         sv->waiting.pop_front();
+        finish(sv, r, -EPHDC_ERR_OOM);
         sv->done_cv.notify_all();
         continue;
       }
@@ -218,6 +272,8 @@ bool admit(ephdc_server* sv, int si) {
     hv_total += hv;
     need = total;
     take.push_back(r.ticket);
+    hvb.push_back(r.hv_bytes);
+    ready.push_back(r.ready);
     sv->waiting.pop_front();
   }
   if (take.empty()) return false;
@@ -226,53 +282,70 @@ bool admit(ephdc_server* sv, int si) {
     for (auto it = take.rbegin(); it != take.rend(); ++it) sv->waiting.push_front(*it);
     return false;
   }
+  const double t_admit = now_s(sv);
+  for (uint64_t tk : take) {
+    sv->reqs[tk].state = 1;
+    sv->reqs[tk].t_admit = t_admit;
+  }
+  sv->stream_busy[si] = true;
+  sv->peak_bytes = std::max(sv->peak_bytes, sv->arena.used());
+  const bool pack = sv->pack;
+  const size_t pt_bytes = sv->pt_bytes;
+  hipStream_t hs = sv->streams[si];
   char* base = sv->arena.base() + off;
+
+  lk.unlock();  // ---- plan and launch without the lock
   size_t hv_off = 0;
-  if (!sv->pack) {
+  if (!pack) {
     for (size_t i = 0; i < take.size(); ++i) {
       rq[i].d_hv = reinterpret_cast<int8_t*>(base + hv_off);
-      hv_off += align_up(sv->reqs[take[i]].hv_bytes);
+      hv_off += align_up(hvb[i]);
     }
   }
-  hipStream_t hs = sv->streams[si];
-  ephdc_batch* b = nullptr;
-  ephdc_status st = batch_new(rq.data(), (uint32_t)rq.size(), sv->pt_bytes, 2, 128, sv->pack, base + hv_off,
-                              need - hv_off, hs, &b);
-  hipEvent_t ev = nullptr;
   hipError_t e = hipSuccess;
+  for (hipEvent_t ev : ready)  // the requests' inputs are written on the callers' streams
+    if (e == hipSuccess && ev) e = hipStreamWaitEvent(hs, ev, 0);
+  ephdc_batch* b = nullptr;
+  ephdc_status st = e == hipSuccess ? batch_new(rq.data(), (uint32_t)rq.size(), pt_bytes, 2, 128, pack,
+                                                base + hv_off, need - hv_off, hs, &b)
+                                    : EPHDC_ERR_HIP;
   if (st == EPHDC_OK) e = batch_enqueue(b, hs);
+  std::vector<std::pair<uint32_t, uint32_t>> where(take.size());
   if (st == EPHDC_OK) {
     for (size_t i = 0; i < take.size(); ++i) {
-      Req& r = sv->reqs[take[i]];
-      if (sv->pack) {
+      if (pack) {
         uint32_t qoff = 0;
-        batch_packing(b, (uint32_t)i, &qoff, &r.q_first, &r.n_ct);
+        batch_packing(b, (uint32_t)i, &qoff, &where[i].first, &where[i].second);
       } else {
-        r.q_first = 0;
-        r.n_ct = sv->tenants[r.tenant].s->P.G(r.Q);
+        where[i] = {0u, rq[i].session->P.G(rq[i].Q)};
       }
     }
   }
+  hipEvent_t ev = nullptr;
   if (st == EPHDC_OK && e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (st == EPHDC_OK && e == hipSuccess) e = hipEventRecord(ev, hs);
-  const double t = now_s(sv);
-  if (st != EPHDC_OK || e != hipSuccess) {
-    // the launch failed: fail these requests, release their memory once the stream is idle
+  const bool ok = st == EPHDC_OK && e == hipSuccess;
+  if (!ok) {
+    // the launch failed: release the memory once this stream is idle
     (void)hipStreamSynchronize(hs);
     if (b) batch_free(b);
     if (ev) (void)hipEventDestroy(ev);
+  }
+  lk.lock();  // ---- publish
+  if (!ok) {
     sv->arena.put(off, need);
+    sv->stream_busy[si] = false;
     for (uint64_t tk : take) {
-      sv->reqs[tk].state = st != EPHDC_OK ? -(int)st : -EPHDC_ERR_HIP;
-      sv->reqs[tk].t_done = t;
+      finish(sv, sv->reqs[tk], st != EPHDC_OK ? -(int)st : -EPHDC_ERR_HIP);
       ++sv->failed;
     }
     sv->done_cv.notify_all();
     return true;
   }
-  for (uint64_t tk : take) {
-    sv->reqs[tk].state = 1;
-    sv->reqs[tk].t_admit = t;
+  for (size_t i = 0; i < take.size(); ++i) {
+    Req& r = sv->reqs[take[i]];
+    r.q_first = where[i].first;
+    r.n_ct = where[i].second;
   }
   Inflight f;
   f.batch = b;
@@ -281,18 +354,24 @@ bool admit(ephdc_server* sv, int si) {
   f.off = off;
   f.bytes = need;
   f.tickets = std::move(take);
-  sv->stream_busy[si] = true;
   sv->inflight.push_back(std::move(f));
   ++sv->batches;
   sv->batched_requests += sv->inflight.back().tickets.size();
-  sv->peak_bytes = std::max(sv->peak_bytes, sv->arena.used());
   return true;
 }
 
 void worker_main(ephdc_server* sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   if (hipSetDevice(sv->device) != hipSuccess) {
-    sv->worker_error = "hipSetDevice failed";
+    // no scheduler: fail what waits now and (through `broken`) every later submission
+    sv->worker_error = "hipSetDevice failed in the scheduler thread";
+    sv->broken = true;
+    while (!sv->waiting.empty()) {
+      finish(sv, sv->reqs[sv->waiting.front()], -EPHDC_ERR_HIP);
+      ++sv->failed;
+      sv->waiting.pop_front();
+    }
+    sv->done_cv.notify_all();
     return;
   }
   while (true) {
@@ -300,7 +379,7 @@ void worker_main(ephdc_server* sv) {
     if (sv->stop && sv->waiting.empty() && sv->inflight.empty()) break;
     bool progressed = false;
     for (int si = 0; si < (int)sv->streams.size() && !sv->waiting.empty(); ++si)
-      if (!sv->stream_busy[si] && admit(sv, si)) progressed = true;
+      if (!sv->stream_busy[si] && admit(sv, si, lk)) progressed = true;
     if (progressed) continue;
     // wait for a submission, or poll the in-flight batches
     if (sv->inflight.empty())
@@ -385,10 +464,11 @@ ephdc_status ephdc_server_add_tenant(ephdc_server* sv, ephdc_session* s, const i
 }
 
 ephdc_status ephdc_server_submit(ephdc_server* sv, uint32_t tenant, const uint8_t* d_x, uint32_t Q, uint32_t* d_score_ct,
-                                 uint64_t* ticket) {
+                                 void* stream, uint64_t* ticket) {
   if (!sv || !d_x || !d_score_ct || !ticket) return fail(EPHDC_ERR_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stop) return fail(EPHDC_ERR_ARG, "server is shutting down");
+  if (sv->broken) return fail(EPHDC_ERR_HIP, sv->worker_error);
   if (tenant >= sv->tenants.size()) return fail(EPHDC_ERR_ARG, "unknown tenant");
   const Tenant& t = sv->tenants[tenant];
   if (!t.d_base) return fail(EPHDC_ERR_ARG, "tenant has no base hypervectors");
@@ -405,6 +485,12 @@ ephdc_status ephdc_server_submit(ephdc_server* sv, uint32_t tenant, const uint8_
   r.d_x = d_x;
   r.d_out = d_score_ct;
   r.hv_bytes = hv_bytes(t.s, Q);
+  // the batch that takes this request waits for the work the caller queued so far on `stream`
+  HIP_TRY(hipEventCreateWithFlags(&r.ready, hipEventDisableTiming), "submission event");
+  if (hipError_t e = hipEventRecord(r.ready, (hipStream_t)stream); e != hipSuccess) {
+    (void)hipEventDestroy(r.ready);
+    return hip_fail(e, "submission event");
+  }
   r.t_submit = now_s(sv);
   sv->reqs.emplace(r.ticket, r);
   sv->waiting.push_back(r.ticket);
@@ -440,26 +526,31 @@ ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout
   const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
   while (!finished()) {
     if (timeout_s > 0 && std::chrono::steady_clock::now() >= deadline)
-      return fail(EPHDC_ERR_HIP, "wait timed out");
+      return fail(EPHDC_ERR_TIMEOUT, "wait timed out");
     sv->done_cv.wait_for(lk, std::chrono::milliseconds(1));
   }
   if (ticket != 0) {
-    const int st = sv->reqs[ticket].state;
-    if (st < 0) return fail((ephdc_status)(-st), "request failed");
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return fail(EPHDC_ERR_ARG, "ticket released or forgotten");
+    if (it->second.state < 0) return fail((ephdc_status)(-it->second.state), "request failed");
   }
   return EPHDC_OK;
 }
 
-ephdc_status ephdc_server_stats(ephdc_server* sv, double out[13]) {
+ephdc_status ephdc_server_release(ephdc_server* sv, uint64_t ticket) {
+  if (!sv) return fail(EPHDC_ERR_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(EPHDC_ERR_ARG, "unknown ticket");
+  if (it->second.state != 2 && it->second.state >= 0) return fail(EPHDC_ERR_ARG, "request not finished");
+  sv->reqs.erase(it);
+  return EPHDC_OK;
+}
+
+ephdc_status ephdc_server_stats(ephdc_server* sv, double out[14]) {
   if (!sv || !out) return fail(EPHDC_ERR_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(sv->mu);
-  std::vector<double> l = sv->latencies;
-  std::sort(l.begin(), l.end());
-  auto pct = [&](double p) {
-    if (l.empty()) return 0.0;
-    const size_t i = std::min(l.size() - 1, (size_t)(p * (double)(l.size() - 1) + 0.5));
-    return l[i] * 1e3;
-  };
+  auto pct = [&](double p) { return sv->latencies.percentile(p) * 1e3; };
   out[0] = (double)sv->submitted;
   out[1] = (double)sv->completed;
   out[2] = (double)sv->rejected;
@@ -473,6 +564,7 @@ ephdc_status ephdc_server_stats(ephdc_server* sv, double out[13]) {
   out[10] = (double)sv->budget;
   out[11] = now_s(sv);
   out[12] = (double)sv->failed;
+  out[13] = (double)sv->reqs.size();
   return EPHDC_OK;
 }
 
@@ -484,6 +576,8 @@ ephdc_status ephdc_server_destroy(ephdc_server* sv) {
     sv->cv.notify_all();
   }
   if (sv->worker.joinable()) sv->worker.join();
+  for (auto& kv : sv->reqs)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
   if (sv->mem) (void)hipFree(sv->mem);
   delete sv;

@@ -229,3 +229,51 @@ def test_batching_workload_at_full_size_sampled():
     finally:
         for t in tenants:
             t["s"].close()
+
+
+def test_served_tenant_of_the_serving_workload_shape():
+    """One tenant of the serving workload's large half (N = 16384, 8 limbs + 2 special primes,
+    dnum = 4, r = 4: two rotate-and-sum steps; F = 2304 blob images, K = 7, D = 2048) served
+    together with an N = 8192 tenant's requests: its score ciphertext equals the oracle's
+    word for word (multiply-accumulate and rotations), and every query decrypts to h . C mod t."""
+    torch = torch_cuda()
+    N, L, alpha, dnum, r, F5, D5, K5, Q5 = 16384, 8, 2, 4, 4, 2304, 2048, 7, 500
+    primes = default_primes(N, L + alpha)
+    kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F5, D=D5, K=K5, r=r, dnum=dnum)
+    o, e = OParams(**kw), ep.Params(**kw)
+    sk, gk = ep.ephdc_keygen(e, 50)
+    C = synth.class_hypervectors(50, K5, D5)
+    model = ep.ephdc_encrypt_model(e, sk, C, 50)
+    base = synth.base_hypervectors(50, F5, D5)
+    x = synth.blob_images(50, Q5)
+    s = ep.Session(e, to_dev(model), to_dev(gk), max_Q=Q5, workspace=None)
+    p2 = ep.Params(N=8192, q=tuple(default_primes(8192, 4)), F=F5, D=4096, K=7)
+    sk2, _ = ep.ephdc_keygen(p2, 51)
+    s2 = ep.Session(p2, to_dev(ep.ephdc_encrypt_model(p2, sk2, synth.class_hypervectors(51, 7, 4096), 51)),
+                    max_Q=1024, workspace=None)
+    base2 = to_dev(synth.base_hypervectors(51, F5, 4096))
+    sv = ep.Server(8 << 30, streams=2, max_batch=8)
+    try:
+        t_big = sv.add_tenant(s, to_dev(base))
+        t_small = sv.add_tenant(s2, base2)
+        d_x = to_dev(x)
+        out = torch.empty((s.num_groups(Q5), 2, L, N), dtype=torch.int32, device="cuda")
+        others = []
+        for k in range(3):
+            xs = to_dev(synth.blob_images(60 + k, 700))
+            o2 = torch.empty((s2.num_groups(700), 2, 4, 8192), dtype=torch.int32, device="cuda")
+            others.append((sv.submit(t_small, xs, 700, o2), xs, o2))
+        tk = sv.submit(t_big, d_x, Q5, out)
+        sv.wait(0, timeout_s=300)
+        assert sv.stats()["failed"] == 0 and sv.query(tk)[0] == 2
+        cts = to_host_u32(out).astype(np.int64)
+    finally:
+        sv.close()
+        s.close()
+        s2.close()
+    h = hdc.encode(x, base)
+    assert o.groups(Q5) == 1
+    want = pipeline.score_ciphertexts(o, model.astype(np.int64), h, gk.astype(np.int64))
+    assert np.array_equal(cts, want)
+    sc, am = ep.ephdc_decrypt_scores(e, sk, cts.astype(np.uint32), Q5)
+    assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))

@@ -172,3 +172,90 @@ def test_packed_serving_gives_each_request_its_scores(tenants):
         assert shared > 0  # some requests did share a ciphertext with an earlier one
     finally:
         sv.close()
+
+
+def test_submission_waits_for_the_callers_stream(tenants):
+    """The features of each request are written by a kernel on the caller's stream that is
+    still running when the request is submitted: the served result equals the request
+    scored alone from the same features (the server waited for that stream)."""
+    torch = tenants[0].torch
+    t = tenants[2]  # N = 8192
+    side = torch.cuda.Stream()
+    sv = ep.Server(1 << 30, streams=2, max_batch=4)
+    try:
+        tid = sv.add_tenant(t.s, t.d_base)
+        jobs = []
+        for k in range(6):
+            Q = 400 + 97 * k
+            src = to_dev(synth.uniform_features(1300 + k, Q, F))
+            d_x = torch.zeros((Q, F), dtype=torch.uint8, device="cuda")
+            out = t.out(Q)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side):
+                # a long kernel first, then the copy that writes d_x, all on `side`
+                big = torch.randn((4096, 4096), device="cuda")
+                for _ in range(8):
+                    big = big @ big
+                    big = big / big.abs().max()
+                d_x.copy_(src)
+                tk = sv.submit(tid, d_x, Q, out, stream=side)
+            jobs.append((tk, Q, src, out))
+        sv.wait(0, timeout_s=120)
+        assert sv.stats()["failed"] == 0
+    finally:
+        sv.close()
+    for tk, Q, src, out in jobs:
+        d_hv = torch.empty((t.o.D, t.s.hv_stride(Q)), dtype=torch.int8, device="cuda")
+        alone = t.out(Q)
+        ep.ephdc_encode_queries(t.s, src, t.d_base, Q, d_hv)
+        ep.ephdc_score_encrypted(t.s, d_hv, Q, alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(out), to_host_u32(alone))
+
+
+def test_ticket_count_stays_bounded_over_thousands_of_requests(tenants):
+    """3000 small requests, each released once done: the server's tracked tickets stay
+    bounded by what is queued or running, and sampled results equal the request alone."""
+    torch = tenants[0].torch
+    t = tenants[0]  # N = 4096, D = 64
+    sv = ep.Server(1 << 30, streams=2, max_batch=64)
+    pool = to_dev(synth.uniform_features(1400, 64, F))
+    try:
+        tid = sv.add_tenant(t.s, t.d_base)
+        live, peak, checks = [], 0, []
+        for k in range(3000):
+            Q = 1 + k % 37
+            out = t.out(Q)
+            tk = sv.submit(tid, pool[:Q], Q, out)
+            live.append((tk, Q, out))
+            if k % 100 == 99:
+                sv.wait(tk, timeout_s=60)
+                still = []
+                for item in live:
+                    if sv.query(item[0])[0] == 2:
+                        if len(checks) < 5 and item[0] % 7 == 0:
+                            checks.append(item)
+                        sv.release(item[0])
+                    else:
+                        still.append(item)
+                live = still
+                peak = max(peak, int(sv.stats()["tickets"]))
+        sv.wait(0, timeout_s=60)
+        stats = sv.stats()
+        assert stats["completed"] == 3000 and stats["failed"] == 0
+        assert peak <= 200, peak
+        for tk, Q, out in live:
+            if sv.query(tk)[0] == 2:
+                sv.release(tk)
+        assert sv.stats()["tickets"] == 0
+        with pytest.raises(ep.EphdcError):
+            sv.query(checks[0][0])  # released
+    finally:
+        sv.close()
+    for tk, Q, out in checks:
+        d_hv = torch.empty((t.o.D, t.s.hv_stride(Q)), dtype=torch.int8, device="cuda")
+        alone = t.out(Q)
+        ep.ephdc_encode_queries(t.s, pool[:Q], t.d_base, Q, d_hv)
+        ep.ephdc_score_encrypted(t.s, d_hv, Q, alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(out), to_host_u32(alone))

@@ -27,18 +27,19 @@ def test_empty_server_errors_and_stats():
     try:
         tk = C.c_uint64()
         fake = C.c_void_p(0x10000)  # never dereferenced: the tenant check fails first
-        assert ep.lib().ephdc_server_submit(h, 0, fake, 10, fake, C.byref(tk)) == ep.ERR_ARG
+        assert ep.lib().ephdc_server_submit(h, 0, fake, 10, fake, None, C.byref(tk)) == ep.ERR_ARG
         assert b"unknown tenant" in ep.lib().ephdc_last_error()
-        assert ep.lib().ephdc_server_submit(h, 0, None, 10, fake, C.byref(tk)) == ep.ERR_ARG
+        assert ep.lib().ephdc_server_submit(h, 0, None, 10, fake, None, C.byref(tk)) == ep.ERR_ARG
         state = C.c_int32()
         assert ep.lib().ephdc_server_query(h, 12345, C.byref(state), None) == ep.ERR_ARG
         assert ep.lib().ephdc_server_wait(h, 0, 1.0) == ep.OK  # nothing waits or runs
         assert ep.lib().ephdc_server_wait(h, 7, 1.0) == ep.ERR_ARG  # unknown ticket
-        out = (C.c_double * 13)()
+        assert ep.lib().ephdc_server_release(h, 7) == ep.ERR_ARG  # unknown ticket
+        out = (C.c_double * 14)()
         assert ep.lib().ephdc_server_stats(h, out) == ep.OK
         stats = dict(zip(ep.Server.STATS, out))
         assert stats["submitted"] == 0 and stats["completed"] == 0 and stats["batches"] == 0
-        assert stats["failed"] == 0
+        assert stats["failed"] == 0 and stats["tickets"] == 0
         assert stats["budget_bytes"] == 1 << 30
     finally:
         assert ep.lib().ephdc_server_destroy(h) == ep.OK
