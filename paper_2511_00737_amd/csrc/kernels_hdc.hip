@@ -16,7 +16,9 @@
 // load needs a branch, and whatever a row past D or Q holds only reaches outputs that are
 // discarded or written as zero.  The next chunk's loads are issued before the current
 // chunk's matrix work and consumed only at the next stage.  Each wave computes a 64 x 64
-// quarter as 4 x 4 MFMA tiles of 16 x 16.
+// quarter as 4 x 4 MFMA tiles of 16 x 16.  The LDS holds two chunks: chunk k is read from one
+// buffer while chunk k + 1 is written to the other after the chunk's matrix instructions are
+// issued, so each chunk needs one workgroup barrier.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,8 +99,10 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
                                          int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
                                          uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift,
                                          uint32_t j0, uint32_t q0) {
-  __shared__ __attribute__((aligned(16))) uint8_t a_lds[HT * HK];  // [32 * (j % 4) + j / 4][f]
-  __shared__ __attribute__((aligned(16))) uint8_t b_lds[HT * HK];  // [q][f]
+  // two LDS buffers per operand: chunk k is read from buffer k % 2 while chunk k + 1 is stored
+  // into the other, so one barrier per chunk suffices
+  __shared__ __attribute__((aligned(16))) uint8_t a_lds[2][HT * HK];  // [32 * (j % 4) + j / 4][f]
+  __shared__ __attribute__((aligned(16))) uint8_t b_lds[2][HT * HK];  // [q][f]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wj = (wave >> 1) * (HT / 2), wq = (wave & 1) * (HT / 2);
@@ -120,22 +124,31 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
 
   HdcStage st;
   hdc_load(st, src, 0, tid);
+  hdc_store(st, a_lds[0], b_lds[0], tid);
+  if (HK < F) hdc_load(st, src, HK, tid);
+  int cur = 0;
   for (uint32_t f0 = 0; f0 < F; f0 += HK) {
-    hdc_store(st, a_lds, b_lds, tid);
+    // buffer `cur` holds chunk f0 (stored by every wave), and every wave is done reading the
+    // other buffer (chunk f0 - HK)
     __syncthreads();
-    if (f0 + HK < F) hdc_load(st, src, f0 + HK, tid);  // in flight meanwhile
     v4i av[SUB], bv[SUB];
 #pragma unroll
     for (int a = 0; a < SUB; ++a)
-      av[a] = *reinterpret_cast<const v4i*>(a_lds + lds_at(wj + 16 * a + (lane & 15), lane >> 4));
+      av[a] = *reinterpret_cast<const v4i*>(a_lds[cur] + lds_at(wj + 16 * a + (lane & 15), lane >> 4));
 #pragma unroll
     for (int b = 0; b < SUB; ++b)
-      bv[b] = *reinterpret_cast<const v4i*>(b_lds + lds_at(wq + 16 * b + (lane & 15), lane >> 4));
+      bv[b] = *reinterpret_cast<const v4i*>(b_lds[cur] + lds_at(wq + 16 * b + (lane & 15), lane >> 4));
 #pragma unroll
     for (int a = 0; a < SUB; ++a)
 #pragma unroll
       for (int b = 0; b < SUB; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv[b], av[a], acc[a][b], 0, 0, 0);
-    __syncthreads();
+    // while the matrix cores work: chunk f0 + HK (loaded an iteration ago) into the other
+    // buffer, and the loads of chunk f0 + 2 HK
+    if (f0 + HK < F) {
+      hdc_store(st, a_lds[cur ^ 1], b_lds[cur ^ 1], tid);
+      if (f0 + 2 * HK < F) hdc_load(st, src, f0 + 2 * HK, tid);
+    }
+    cur ^= 1;
   }
 
   // The product is (x - 128) * base^T, so a lane holds queries 4*(lane/16) + i, i = 0..3, of

@@ -96,23 +96,24 @@ __global__ __launch_bounds__(256) void k_hog_blocks(const uint32_t* __restrict__
   }
 }
 
-// One thread per output word: window `win`'s row r of nb blocks is the contiguous run of
-// nb * 9 words of block row (by + r) starting at block bx; the words past nb * nb * 9 are
-// the padding (bytes 128).
+// One workgroup per window, one thread per output word: the window's row r of nb blocks is
+// the contiguous run of nb * 9 words of block row (by + r) starting at block bx; the words
+// past nb * nb * 9 are the padding (bytes 128).
 __global__ __launch_bounds__(256) void k_hog_windows(const uint32_t* __restrict__ blocks, uint32_t nbx,
                                                       uint32_t nb, uint32_t fw, uint32_t nwx, uint32_t sc,
-                                                      uint64_t total, uint32_t* __restrict__ x) {
+                                                      uint32_t* __restrict__ x) {
+  const uint32_t win = blockIdx.x;
+  const uint32_t wy = win / nwx, wx = win % nwx;  // window origin in strides
   const uint32_t feat_words = nb * nb * 9, row_words = nb * 9;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t win = (uint32_t)(i / fw), w = (uint32_t)(i % fw);
+  const uint32_t* src = blocks + ((size_t)(wy * sc) * nbx + wx * sc) * 9;
+  uint32_t* dst = x + (size_t)win * fw;
+  for (uint32_t w = threadIdx.x; w < fw; w += blockDim.x) {
     uint32_t out = 0x80808080u;
     if (w < feat_words) {
-      const uint32_t wy = win / nwx, wx = win % nwx;  // window origin in strides
-      const uint32_t r = w / row_words, j = w % row_words;
-      out = blocks[((size_t)(wy * sc + r) * nbx + wx * sc) * 9 + j];
+      const uint32_t r = w / row_words, j = w - r * row_words;
+      out = src[(size_t)r * nbx * 9 + j];
     }
-    x[i] = out;
+    dst[w] = out;
   }
 }
 
@@ -183,10 +184,8 @@ ephdc_status ephdc_hog_windows(const uint8_t* d_frame, uint32_t H, uint32_t W, u
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    const uint64_t total = nwin * (F / 4);
-    const uint32_t grid = (uint32_t)std::min<uint64_t>((total + 255) / 256, 1u << 20);
-    k_hog_windows<<<dim3(grid), dim3(256), 0, hs>>>(blocks, wc - 1, nb, F / 4, nwx, stride / 8, total,
-                                                    reinterpret_cast<uint32_t*>(d_x));
+    k_hog_windows<<<dim3((uint32_t)nwin), dim3(256), 0, hs>>>(blocks, wc - 1, nb, F / 4, nwx, stride / 8,
+                                                              reinterpret_cast<uint32_t*>(d_x));
     e = hipGetLastError();
   }
   if (e != hipSuccess) return fail(EPHDC_ERR_HIP, std::string("HOG launch: ") + hipGetErrorString(e));

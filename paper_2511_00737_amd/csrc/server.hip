@@ -161,6 +161,7 @@ struct ephdc_server {
   std::thread worker;
   std::string worker_error;
   bool broken = false;  // the scheduler could not start: every request fails
+  uint32_t planning = 0;  // batches taken from the queue and being planned outside the lock
   std::deque<uint64_t> finished;  // finished tickets, oldest first (may hold released ones)
   // statistics
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -289,6 +290,7 @@ bool admit(ephdc_server* sv, int si, std::unique_lock<std::mutex>& lk) {
   }
   sv->stream_busy[si] = true;
   sv->peak_bytes = std::max(sv->peak_bytes, sv->arena.used());
+  ++sv->planning;  // neither waiting nor in flight until published: waits must still see it
   const bool pack = sv->pack;
   const size_t pt_bytes = sv->pt_bytes;
   hipStream_t hs = sv->streams[si];
@@ -332,6 +334,7 @@ bool admit(ephdc_server* sv, int si, std::unique_lock<std::mutex>& lk) {
     if (ev) (void)hipEventDestroy(ev);
   }
   lk.lock();  // ---- publish
+  --sv->planning;
   if (!ok) {
     sv->arena.put(off, need);
     sv->stream_busy[si] = false;
@@ -518,7 +521,7 @@ ephdc_status ephdc_server_wait(ephdc_server* sv, uint64_t ticket, double timeout
   if (!sv) return fail(EPHDC_ERR_ARG, "server is NULL");
   std::unique_lock<std::mutex> lk(sv->mu);
   auto finished = [&] {
-    if (ticket == 0) return sv->waiting.empty() && sv->inflight.empty();
+    if (ticket == 0) return sv->waiting.empty() && sv->inflight.empty() && sv->planning == 0;
     auto it = sv->reqs.find(ticket);
     return it == sv->reqs.end() || it->second.state >= 2 || it->second.state < 0;
   };
@@ -555,7 +558,7 @@ ephdc_status ephdc_server_stats(ephdc_server* sv, double out[14]) {
   out[1] = (double)sv->completed;
   out[2] = (double)sv->rejected;
   out[3] = (double)sv->waiting.size();
-  out[4] = (double)sv->inflight.size();
+  out[4] = (double)(sv->inflight.size() + sv->planning);
   out[5] = (double)sv->batches;
   out[6] = sv->batches ? (double)sv->batched_requests / (double)sv->batches : 0.0;
   out[7] = pct(0.50);
