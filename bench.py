@@ -97,6 +97,8 @@ def algorithmic_modmuls(kernel: str, N: int, L: int, G: int, M: int) -> float:
 # The sources that define each profiled kernel's code (its HIP file and the headers it uses).
 KERNEL_SOURCES = {k: ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", "launch.hpp")
                   for k in ("k_mac", "k_encode_pt", "k_score", "k_finish", "k_mac_list", "k_encode_list")}
+KERNEL_SOURCES["batch_unpacked"] = ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", "launch.hpp",
+                                    "kernels_hdc.hip", "batch.hip")
 KERNEL_SOURCES["k_hdc_encode"] = ("kernels_hdc.hip", "launch.hpp")
 
 
@@ -266,6 +268,48 @@ def bench_batched(args, w) -> int:
     return 0
 
 
+def profile_unpacked(args, w) -> int:
+    """For counter runs: the batching workload's unpacked batch alone, enqueued launch by launch
+    (no graph, no autotuner: the default schedule, which the autotuner keeps at this size),
+    `--steps` runs after `--warmup`; prints ms per run."""
+    import torch
+    N, L, F, nreq = w["N"], w["L"], w["F"], w["requests"]
+    primes = ep.default_primes(N, L)
+    sizes, midx = synth.batch_mix(args.seed, nreq, len(w["models"]))
+    dev = torch.device("cuda")
+    d_pool = torch.from_numpy(synth.blob_images(args.seed, 4096)).to(dev)
+    sessions, bases = [], []
+    for k, (K, D) in enumerate(w["models"]):
+        prm = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K)
+        sk, _ = ep.ephdc_keygen(prm, args.seed + k)
+        model = ep.ephdc_encrypt_model(prm, sk, synth.class_hypervectors(args.seed + k, K, D), args.seed + k)
+        sessions.append(ep.Session(prm, torch.from_numpy(model.view(np.int32)).to(dev), max_Q=4096, workspace=None))
+        bases.append(torch.from_numpy(synth.base_hypervectors(args.seed, F, D)).to(dev))
+    reqs = []
+    for i in range(nreq):
+        s, Q = sessions[int(midx[i])], int(sizes[i])
+        off = (i * 977) % (4096 - Q + 1)
+        d_hv = torch.empty((s.prm.D, s.hv_stride(Q)), dtype=torch.int8, device=dev)
+        d_out = torch.empty((s.num_groups(Q), 2, L, N), dtype=torch.int32, device=dev)
+        reqs.append(ep.Request(s, d_hv, Q, d_out, d_x=d_pool[off:off + Q], d_base=bases[int(midx[i])]))
+    batch = ep.Batch(reqs)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        batch.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+    print(json.dumps({"form": "unpacked batch, eager", "runs": args.steps, "warmup": args.warmup,
+                      "ms_per_run": round(ms, 4), "schedule": batch.schedule()}), flush=True)
+    batch.close()
+    for s in sessions:
+        s.close()
+    return 0
+
+
 def run_batched(args, w):
     """The batching workload: all requests scored by one graph-captured batch (persistent
     launches over a shared work list, schedule from the autotuner) against the plain form,
@@ -409,8 +453,13 @@ def run_batched(args, w):
                   "one graph replay, the requests of each model sharing ciphertexts (one query sequence per model)",
                   schedule=psched, autotune_s=round(t_ptune, 1))
     packed_eager = form(eager_wall, eager_lat, work_packed, "the packed batch enqueued launch by launch, no graph")
-    mac_traffic = recorded_traffic("k_mac_list", "c3")
-    unpacked["roofline"]["k_mac_list_traffic"] = mac_traffic
+    # HBM bytes of one unpacked run, recorded by counter runs of --profile-unpacked
+    run_traffic = recorded_traffic("batch_unpacked", "c3")
+    unpacked["roofline"]["traffic"] = run_traffic
+    if run_traffic is not None:
+        gbps = run_traffic / (unpacked["ms_per_step"] * 1e-3)
+        unpacked["roofline"]["hbm_gbps"] = round(gbps / 1e9, 1)
+        unpacked["roofline"]["hbm_frac"] = round(gbps / HBM_PEAK, 4)
     result = {
         "metric": METRIC, "value": packed["value"], "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": packed["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -733,6 +782,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-unpacked", action="store_true",
+                    help="batching workload: only its unpacked batch, eager, default schedule (for counter runs)")
     ap.add_argument("--no-batched", action="store_true",
                     help="plain workload only: skip the batching workload's plain / batched / packed leg")
     ap.add_argument("--cpu-sample-m", type=int, default=0,
@@ -764,7 +815,7 @@ def main() -> int:
         return 0
     w = WORKLOADS[args.workload]
     if "requests" in w:
-        return bench_batched(args, w)
+        return profile_unpacked(args, w) if args.profile_unpacked else bench_batched(args, w)
     if w.get("serving"):
         return bench_serving(args, w)
     if w.get("dmax"):

@@ -113,8 +113,9 @@ void group_parts(ephdc_batch* b) {
 }
 
 // Host work lists of one parameter set under the batch's schedule:
-//   segment order: request, then model range, then group -- the groups of a request that
-//   read the same model ciphertexts run side by side, so the model tile is shared in L2;
+//   segment order: model, then model range, then request, then group -- every group of every
+//   request that reads the same model ciphertexts runs side by side, so the model tile is
+//   shared in L2;
 //   slot numbering: request, then group, then range -- the slots of one output are adjacent.
 void build_part(const ephdc_batch* b, Part& pt) {
   pt.rd.clear();
@@ -150,6 +151,26 @@ void build_part(const ephdc_batch* b, Part& pt) {
     total += (size_t)G * M;
   }
   pt.nslot = slot;
+  // requests of one model (session) read the same model ciphertexts: order the segments by
+  // model, then range, then request and group, so that the work items of all of a model's
+  // requests that read one range are neighbours in item order (one XCD, at the same time)
+  // and share that range in L2 instead of each reading it from memory
+  {
+    std::vector<uint32_t> model_of(pt.reqs.size());
+    std::vector<const ephdc_session*> seen;
+    for (uint32_t li = 0; li < pt.reqs.size(); ++li) {
+      const ephdc_session* s = b->reqs[pt.reqs[li]].session;
+      auto it = std::find(seen.begin(), seen.end(), s);
+      model_of[li] = (uint32_t)(it - seen.begin());
+      if (it == seen.end()) seen.push_back(s);
+    }
+    std::stable_sort(pt.segs.begin(), pt.segs.end(), [&](const Segment& a, const Segment& c) {
+      if (model_of[a.req] != model_of[c.req]) return model_of[a.req] < model_of[c.req];
+      if (a.m0 != c.m0) return a.m0 < c.m0;
+      if (a.req != c.req) return a.req < c.req;
+      return a.g < c.g;
+    });
+  }
   // split path: consecutive segments fill the plaintext buffer chunk by chunk
   pt.pt_cap = std::min<size_t>(total, std::max<size_t>(kMaxSegLen, b->pt_bytes / (4 * (size_t)pt.N)));
   pt.chunks.clear();
@@ -322,6 +343,8 @@ ListArgs list_args(const ephdc_batch* b, const Part& pt) {
   a.pcs = s->d_pc;
   a.ts.inv_t = s->d_inv_t;
   a.ts.pct = s->pct;
+  a.scaled = 0;
+  for (const ReqDesc& d : pt.rd) a.scaled |= d.scale.pow != nullptr ? 1u : 0u;
   return a;
 }
 

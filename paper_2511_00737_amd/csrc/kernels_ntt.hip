@@ -305,7 +305,7 @@ __device__ __forceinline__ void encode_item(const QuerySrc& q, const uint32_t* s
 // plaintext and each limb's model values are requested ahead of the transform that
 // precedes their use (more registers: used where the register budget allows it); the
 // 32-bit form can request the next plaintext alone (PTPF).
-template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool PTPF = true>
+template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool PTPF = true, bool SC = false>
 __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
@@ -363,7 +363,7 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = pc.m + (uint32_t)cur[i];  // |cur| <= t/2: in [0, 2m), = cur mod m
       ntt_forward<LOGN, LE, TL, true>(p, tid, fwd_tw + (size_t)l * N, pc, b);
-      apply_scale(p, it.scale, m, l, pc);
+      if constexpr (SC) apply_scale(p, it.scale, m, l, pc);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -382,7 +382,7 @@ __device__ __forceinline__ void mac_item32(const MacItem& it, const int32_t* __r
   store_acc<LOGN, LE, LG>(acc, it, pcs, tid);
 }
 
-template <int LOGN, int LE, int LG, bool PF, bool TL = false>
+template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool SC = false>
 __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
@@ -445,7 +445,7 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
 #pragma unroll
       for (int i = 0; i < E; ++i) p[i] = pc.m + (uint32_t)cur[i];  // |cur| <= t/2: in [0, 2m), = cur mod m
       ntt_forward<LOGN, LE, TL, true>(p, tid, fwd_tw + (size_t)l * N, pc, b);
-      apply_scale(p, it.scale, m, l, pc);
+      if constexpr (SC) apply_scale(p, it.scale, m, l, pc);
       if constexpr (!PF) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -482,14 +482,15 @@ __device__ __forceinline__ void mac_item64(const MacItem& it, const int32_t* __r
 
 // MAC alone: 64-bit lazy sums where 8 values per thread leave the registers for them,
 // 32-bit sums of Montgomery products otherwise.
-template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool PTPF = true>
+// SC: the work items may carry the scaling op (kernels without it keep their registers).
+template <int LOGN, int LE, int LG, bool PF, bool TL = false, bool PTPF = true, bool SC = false>
 __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __restrict__ pt, bool accumulate,
                                          const uint32_t* __restrict__ fwd_tw, const PrimeConst* __restrict__ pcs,
                                          int tid, LdsBufs& b) {
   if constexpr (LE <= 3)
-    mac_item64<LOGN, LE, LG, PF, TL>(it, pt, accumulate, fwd_tw, pcs, tid, b);
+    mac_item64<LOGN, LE, LG, PF, TL, SC>(it, pt, accumulate, fwd_tw, pcs, tid, b);
   else
-    mac_item32<LOGN, LE, LG, PF, TL, PTPF>(it, pt, accumulate, fwd_tw, pcs, tid, b);
+    mac_item32<LOGN, LE, LG, PF, TL, PTPF, SC>(it, pt, accumulate, fwd_tw, pcs, tid, b);
 }
 
 // ------------------------------------------------------------------ single-request kernels
@@ -556,7 +557,7 @@ constexpr bool mac_lds_twiddles() {
   return LG == 1 && LdsPlan<LOGN, LE>::table_in_lds;
 }
 
-template <int LOGN, int LE, int LG, bool PF>
+template <int LOGN, int LE, int LG, bool PF, bool SC = false>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
   const uint32_t w = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
   if (w == 0xFFFFFFFFu) return;  // a slot past the last item: the whole workgroup leaves
@@ -568,9 +569,9 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac(ScoreArgs a) {
   if constexpr (mac_lds_twiddles<LOGN, LE, LG>()) {
     stage_twiddles<LOGN, LE>(a.fwd_tw + (size_t)it.l0 * ((size_t)1 << LOGN), tid);
     lds_barrier();
-    mac_item<LOGN, LE, LG, PF, true>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
+    mac_item<LOGN, LE, LG, PF, true, true, SC>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
   } else {
-    mac_item<LOGN, LE, LG, PF>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
+    mac_item<LOGN, LE, LG, PF, false, true, SC>(it, pt, a.accumulate != 0, a.fwd_tw, a.pcs, tid, b);
   }
 }
 
@@ -640,7 +641,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_encode_list(ListArgs a) {
   }
 }
 
-template <int LOGN, int LE, int LG, bool PF>
+template <int LOGN, int LE, int LG, bool PF, bool SC = false>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
   using S = Shape<LOGN, LE>;
   LdsBufs b{0};
@@ -661,9 +662,9 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_mac_list(ListArgs a) {
         lds_barrier();
         staged_l = it.l0;
       }
-      mac_item<LOGN, LE, LG, PF, true, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+      mac_item<LOGN, LE, LG, PF, true, PF, SC>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
     } else {
-      mac_item<LOGN, LE, LG, PF, false, PF>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
+      mac_item<LOGN, LE, LG, PF, false, PF, SC>(it, a.pt + (size_t)sg.pt * S::N, false, a.fwd_tw, a.pcs, tid, b);
     }
   }
 }
@@ -779,6 +780,9 @@ static hipError_t prepare_shape() {
   set((const void*)k_mac<LOGN, LE, 1, mac_prefetch<LOGN, LE>()>);
   set((const void*)k_mac<LOGN, LE, 2, mac_prefetch<LOGN, LE>()>);
   set((const void*)k_mac<LOGN, LE, 4, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_mac<LOGN, LE, 1, mac_prefetch<LOGN, LE>(), true>);
+  set((const void*)k_mac<LOGN, LE, 2, mac_prefetch<LOGN, LE>(), true>);
+  set((const void*)k_mac<LOGN, LE, 4, mac_prefetch<LOGN, LE>(), true>);
   set((const void*)k_finish<LOGN, LE, true>);
   set((const void*)k_finish<LOGN, LE, false>);
   set((const void*)k_debug_plaintext<LOGN, LE>);
@@ -789,6 +793,9 @@ static hipError_t prepare_shape() {
   set((const void*)k_mac_list<LOGN, LE, 1, mac_prefetch<LOGN, LE>()>);
   set((const void*)k_mac_list<LOGN, LE, 2, mac_prefetch<LOGN, LE>()>);
   set((const void*)k_mac_list<LOGN, LE, 4, mac_prefetch<LOGN, LE>()>);
+  set((const void*)k_mac_list<LOGN, LE, 1, mac_prefetch<LOGN, LE>(), true>);
+  set((const void*)k_mac_list<LOGN, LE, 2, mac_prefetch<LOGN, LE>(), true>);
+  set((const void*)k_mac_list<LOGN, LE, 4, mac_prefetch<LOGN, LE>(), true>);
   set((const void*)k_finish_list<LOGN, LE>);
   return e;
 }
@@ -907,10 +914,15 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const dim3 grid(xm.slots()), block(Shape<LN, LEv>::T);
     const size_t sh = lds_bytes<LN, LEv>();
-    switch (lg) {
-      case 1: k_mac<LN, LEv, 1, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
-      case 2: k_mac<LN, LEv, 2, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
-      case 4: k_mac<LN, LEv, 4, mac_prefetch<LN, LEv>()><<<grid, block, sh, st>>>(a); break;
+    constexpr bool P = mac_prefetch<LN, LEv>();
+    const bool sc = a.scale.pow != nullptr;
+    switch (lg * 2 + (sc ? 1 : 0)) {
+      case 2: k_mac<LN, LEv, 1, P><<<grid, block, sh, st>>>(a); break;
+      case 3: k_mac<LN, LEv, 1, P, true><<<grid, block, sh, st>>>(a); break;
+      case 4: k_mac<LN, LEv, 2, P><<<grid, block, sh, st>>>(a); break;
+      case 5: k_mac<LN, LEv, 2, P, true><<<grid, block, sh, st>>>(a); break;
+      case 8: k_mac<LN, LEv, 4, P><<<grid, block, sh, st>>>(a); break;
+      case 9: k_mac<LN, LEv, 4, P, true><<<grid, block, sh, st>>>(a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -976,10 +988,14 @@ hipError_t launch_mac_list(int logn, int le, int lg, const ListArgs& a0, uint32_
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const dim3 g(grid), block(Shape<LN, LEv>::T);
     const size_t sh = lds_bytes<LN, LEv>();
-    switch (lg) {
-      case 1: k_mac_list<LN, LEv, 1, mac_prefetch<LN, LEv>()><<<g, block, sh, st>>>(a); break;
-      case 2: k_mac_list<LN, LEv, 2, mac_prefetch<LN, LEv>()><<<g, block, sh, st>>>(a); break;
-      case 4: k_mac_list<LN, LEv, 4, mac_prefetch<LN, LEv>()><<<g, block, sh, st>>>(a); break;
+    constexpr bool P = mac_prefetch<LN, LEv>();
+    switch (lg * 2 + (a.scaled ? 1 : 0)) {
+      case 2: k_mac_list<LN, LEv, 1, P><<<g, block, sh, st>>>(a); break;
+      case 3: k_mac_list<LN, LEv, 1, P, true><<<g, block, sh, st>>>(a); break;
+      case 4: k_mac_list<LN, LEv, 2, P><<<g, block, sh, st>>>(a); break;
+      case 5: k_mac_list<LN, LEv, 2, P, true><<<g, block, sh, st>>>(a); break;
+      case 8: k_mac_list<LN, LEv, 4, P><<<g, block, sh, st>>>(a); break;
+      case 9: k_mac_list<LN, LEv, 4, P, true><<<g, block, sh, st>>>(a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -105,6 +105,7 @@ struct ListArgs {
   const uint32_t* inv_tw;
   const PrimeConst* pcs;
   TSideArgs ts;
+  uint32_t scaled;          // some request of the list carries the scaling op
 };
 
 // HDC encoding of many requests in one launch: per request its operands and layout, per
