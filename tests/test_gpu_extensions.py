@@ -176,3 +176,77 @@ def test_session_without_workspace_rejects_single_request_scoring():
     assert ei.value.status == ep.ERR_BUFFER
     ws = torch.empty(minimum, dtype=torch.uint8, device="cuda")
     ep.Session(e, to_dev(model), max_Q=10, workspace=ws).close()
+
+
+
+def test_scaling_op_in_batches():
+    """Batches whose requests mix scaled and unscaled models (one list launch serves both),
+    Q-bit queries encoded inside the batch, segment lengths shorter and longer than a
+    scaling block, split and fused, unpacked and packed: every request equals the oracle's
+    ciphertexts of its own query sequence (unpacked) or of its model's sequence (packed)."""
+    import synth
+    torch = torch_cuda()
+    # (N, L, t, D, K, scale_every, scale_shift, Q bits, qshift)
+    specs = [(4096, 3, 65537, 192, 3, 64, 12, 8, 4), (4096, 3, 65537, 128, 2, 0, 0, 1, 0),
+             (8192, 4, 114689, 128, 2, 24, 5, 6, 6)]
+    reqs_spec = [(0, 300), (1, 40), (2, 700), (0, 5), (2, 1), (1, 1200), (0, 900)]
+    tenants, sessions = [], []
+    for i, (N, L, t, D, K, g, s_, qb, qs) in enumerate(specs):
+        o, e = make(N, L, D, K=K, t=t, scale_every=g, scale_shift=s_, qbits=qb, qshift=qs)
+        C = values(np.random.default_rng(70 + i), 8, (K, D))
+        sk = bfv.secret_key(o, 71 + i)
+        model = bfv.encrypt_model(o, sk, C, 72 + i)
+        base = synth.base_hypervectors(73 + i, o.F, D)
+        tenants.append((o, model, base))
+        mq = max(Q for ti, Q in reqs_spec if ti == i)
+        sessions.append(ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=mq))
+    try:
+        xs, hs = [], []
+        for k, (ti, Q) in enumerate(reqs_spec):
+            o, _, base = tenants[ti]
+            xs.append(synth.uniform_features(200 + k, Q, o.F))
+            hs.append(hdc.encode(xs[k], base, o.qbits, o.qshift))
+
+        def requests(packed):
+            out = []
+            for k, (ti, Q) in enumerate(reqs_spec):
+                o, _, base = tenants[ti]
+                s = sessions[ti]
+                d_out = torch.zeros((s.num_groups(Q) + (1 if packed else 0), 2, o.L, o.N), dtype=torch.int32,
+                                    device="cuda")
+                d_hv = None if packed else torch.empty((o.D, s.hv_stride(Q)), dtype=torch.int8, device="cuda")
+                out.append(ep.Request(s, d_hv, Q, d_out, d_x=to_dev(xs[k]), d_base=to_dev(base)))
+            return out
+
+        reqs = requests(False)
+        want = [pipeline.score_ciphertexts(tenants[ti][0], tenants[ti][1], hs[k])
+                for k, (ti, _) in enumerate(reqs_spec)]
+        b = ep.Batch(reqs)
+        try:
+            for mode, seg_len in (("split", 16), ("split", 1024), ("fused", 40)):
+                b.tune(mode=mode, seg_len=seg_len, grid=300)
+                for r in reqs:
+                    r.d_score_ct.fill_(0)
+                b.run()
+                torch.cuda.synchronize()
+                for k, r in enumerate(reqs):
+                    assert np.array_equal(to_host_u32(r.d_score_ct).astype(np.int64), want[k]), (mode, seg_len, k)
+        finally:
+            b.close()
+        preqs = requests(True)
+        b = ep.Batch(preqs, packed=True)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+            for k, ((ti, Q), r) in enumerate(zip(reqs_spec, preqs)):
+                o, model, _ = tenants[ti]
+                seq = np.concatenate([hs[j] for j, (tj, _) in enumerate(reqs_spec) if tj == ti])
+                off, qf, nct = b.packing(k)
+                got = to_host_u32(r.d_score_ct)[:nct].astype(np.int64)
+                grp = list(range(off // o.B, off // o.B + nct))
+                assert np.array_equal(got, pipeline.score_ciphertexts(o, model, seq, groups=grp)), ("packed", k)
+        finally:
+            b.close()
+    finally:
+        for s in sessions:
+            s.close()
