@@ -15,16 +15,57 @@ paper's packing):
 * model ciphertext m holds C[c][m*r + u] at every (rho, u, ql, c);
 * query plaintext (g, m) holds h[g*B + rho*Bq + ql][m*r + u];
 * a missing query (index >= Q) or dimension (index >= D) contributes 0.
+
+Subring layout (P.layout == "subring", r = 1), with K' = P.Kp and B = N/K':
+
+* the slot exponents (odd residues e mod 2N, slots.slot_exponents) fall into the
+  orbits {e * h : h = 1 (mod 2B)} = {e + 2B*c : c < K'} of the subgroup of Z_2N^*
+  of order K'; query ql < B of a ciphertext takes the orbit of exponent
+  e_ql = 2*brev(ql) + 1 (brev: bit reversal over log2 B bits) and class c < K' the
+  slot of exponent e_ql + 2B*c mod 2N;
+* query index inside group g is g*B + ql;
+* model ciphertext m holds C[c][m] at class c < K and 0 at the K' - K extra classes;
+* query plaintext (g, m) holds h[g*B + ql][m] at all K' slots of the orbit, so its
+  slot vector is constant on every orbit and the plaintext is a polynomial in X^K'.
 """
 from __future__ import annotations
 
+from functools import lru_cache
+
 import numpy as np
 
+from . import slots
 from .params import Params
 
 
 def slot_index(P: Params, rho, u, ql, c):
     return rho * (P.N // 2) + u * P.W + ql * P.K + c
+
+
+def _brev(x: np.ndarray, bits: int) -> np.ndarray:
+    out = np.zeros_like(x)
+    for b in range(bits):
+        out |= ((x >> b) & 1) << (bits - 1 - b)
+    return out
+
+
+def subring_slot(P: Params, ql, c):
+    """Slot of (query ql, class c) in the subring layout (module docstring)."""
+    B = P.B
+    e = (2 * _brev(np.asarray(ql, dtype=np.int64), B.bit_length() - 1) + 1 + 2 * B * np.asarray(c)) % (2 * P.N)
+    return _exponent_to_slot(P.N)[e]
+
+
+@lru_cache(maxsize=None)
+def _exponent_to_slot(N: int) -> np.ndarray:
+    inv = np.full(2 * N, -1, dtype=np.int64)
+    inv[slots.slot_exponents(N)] = np.arange(N)
+    return inv
+
+
+def _subring_grid(P: Params):
+    ql, c = np.meshgrid(np.arange(P.B), np.arange(P.Kp), indexing="ij")
+    return ql.ravel(), c.ravel()
 
 
 def _grid(P: Params):
@@ -36,6 +77,11 @@ def _grid(P: Params):
 def model_slots(P: Params, C: np.ndarray, m: int) -> np.ndarray:
     """Slot vector (int64 [N], values in [-128, 127] or 0) of model ciphertext m."""
     v = np.zeros(P.N, dtype=np.int64)
+    if P.layout == "subring":
+        ql, c = _subring_grid(P)
+        ok = (c < P.K) & (m < P.D)
+        v[subring_slot(P, ql[ok], c[ok])] = C[c[ok], m]
+        return v
     rho, u, ql, c = _grid(P)
     j = m * P.r + u
     ok = j < P.D
@@ -47,6 +93,12 @@ def query_slots(P: Params, h: np.ndarray, g: int, m: int) -> np.ndarray:
     """Slot vector (int64 [N]) of query plaintext (g, m); h is int8 [Q][D]."""
     Qn = h.shape[0]
     v = np.zeros(P.N, dtype=np.int64)
+    if P.layout == "subring":
+        ql, c = _subring_grid(P)
+        q = g * P.B + ql
+        ok = (q < Qn) & (m < P.D)
+        v[subring_slot(P, ql[ok], c[ok])] = h[q[ok], m]
+        return v
     rho, u, ql, c = _grid(P)
     q = g * P.B + rho * P.Bq + ql
     j = m * P.r + u
@@ -58,6 +110,11 @@ def query_slots(P: Params, h: np.ndarray, g: int, m: int) -> np.ndarray:
 def read_scores(P: Params, slots: np.ndarray, g: int, Qn: int) -> tuple[np.ndarray, np.ndarray]:
     """Query indices and their K scores from the decoded slot vector of group g (block u = 0)."""
     qi = np.arange(P.B)
+    if P.layout == "subring":
+        q = g * P.B + qi
+        ok = q < Qn
+        idx = subring_slot(P, qi[:, None], np.arange(P.K)[None, :])
+        return q[ok], slots[idx[ok]]
     rho, ql = qi // P.Bq, qi % P.Bq
     q = g * P.B + qi
     ok = q < Qn

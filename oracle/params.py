@@ -14,6 +14,14 @@ The fold factor r generalises this: r consecutive dimensions share one
 ciphertext in r blocks of W = N/(2r) slots per row, and log2(r)
 rotate-and-sum steps fold the blocks together.  r = 1 is the paper's packing.
 
+Slot layout (the paper never fixes which slots a query occupies): "contiguous"
+puts the K copies of a query in K consecutive slots of a row (B = floor(N/k),
+the paper's batch size); "subring" puts them on one orbit of the subgroup
+{h = 1 (mod 2N/K')} of Z_2N^* acting on the slot exponents, K' the power of two
+at or above K, so that every query plaintext lies in Z_t[X^K'] (the K' - K extra
+slots of an orbit carry the query value against zero model classes) and one
+ciphertext holds B = N/K' queries (r = 1 only).
+
 The plaintext modulus t is any prime with t = 1 (mod 2N) (the paper sweeps
 log2 t; its optimised settings use log2 t = 16 and 17, optimisation table).
 The scheme is BFV (the paper's choice) or BGV (its comparison in the noise
@@ -60,6 +68,7 @@ class Params:
     scheme: str = "bfv"     # "bfv", "bfv-r" (rounded scaling) or "bgv"
     scale_every: int = 0    # g: scale after every g accumulations (0: never)
     scale_shift: int = 0    # s: the scale is the inverse of 2^s mod t
+    layout: str = "contiguous"  # "contiguous" or "subring" (see the module docstring)
 
     # ---- derived sizes
     @property
@@ -76,13 +85,22 @@ class Params:
         return self.N // (2 * self.r)
 
     @property
+    def Kp(self) -> int:
+        """Class slots per query: K (contiguous) or the power of two at or above K (subring)."""
+        if self.layout == "subring":
+            return 1 << (self.K - 1).bit_length()
+        return self.K
+
+    @property
     def Bq(self) -> int:
-        """Queries per row of one ciphertext."""
+        """Queries per row of one ciphertext (contiguous layout)."""
         return self.W // self.K
 
     @property
     def B(self) -> int:
-        """Queries per ciphertext (two rows)."""
+        """Queries per ciphertext (two rows of Bq, or N/K' orbits)."""
+        if self.layout == "subring":
+            return self.N // self.Kp
         return 2 * self.Bq
 
     @property
@@ -136,6 +154,8 @@ class Params:
         for x in allp:
             assert x < (1 << 30) and x % (2 * N) == 1 and is_prime(x)
         assert self.r >= 1 and self.r & (self.r - 1) == 0
+        assert self.layout in ("contiguous", "subring")
+        assert self.layout == "contiguous" or (self.r == 1 and self.Kp <= N // 2)
         assert self.Bq >= 1
         if self.r > 1:
             assert self.dnum >= 1 and self.alpha >= 1
