@@ -14,7 +14,7 @@
 // wave's transposed stores over all banks too.  Global loads go through buffer resources
 // whose range check returns zero past the end: features past F read zero base rows, so no
 // load needs a branch, and whatever a row past D or Q holds only reaches outputs that are
-// discarded or written as zero.  The next chunk's loads are issued before the current
+// discarded or written as zero (tiles lying wholly past Q skip the contraction).  The next chunk's loads are issued before the current
 // chunk's matrix work and consumed only at the next stage.  Each wave computes a 64 x 64
 // quarter as 4 x 4 MFMA tiles of 16 x 16.  The LDS holds two chunks: chunk k is read from one
 // buffer while chunk k + 1 is written to the other after the chunk's matrix instructions are
@@ -122,12 +122,17 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
 #pragma unroll
     for (int b = 0; b < SUB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
 
+  // a tile whose queries all lie past Q (padding columns of the last query group) holds
+  // zeros only: it skips the contraction and goes straight to the stores
+  const uint32_t F_run = q0 < Q ? F : 0u;
   HdcStage st;
-  hdc_load(st, src, 0, tid);
-  hdc_store(st, a_lds[0], b_lds[0], tid);
-  if (HK < F) hdc_load(st, src, HK, tid);
+  if (F_run) {
+    hdc_load(st, src, 0, tid);
+    hdc_store(st, a_lds[0], b_lds[0], tid);
+    if (HK < F) hdc_load(st, src, HK, tid);
+  }
   int cur = 0;
-  for (uint32_t f0 = 0; f0 < F; f0 += HK) {
+  for (uint32_t f0 = 0; f0 < F_run; f0 += HK) {
     // buffer `cur` holds chunk f0 (stored by every wave), and every wave is done reading the
     // other buffer (chunk f0 - HK)
     __syncthreads();
