@@ -793,6 +793,8 @@ def main() -> int:
     ap.add_argument("--schedule", default="", help="single-request workloads: mode,values_per_thread,limb_group,blocks "
                                                   "(e.g. split,16,1,512; empty keeps the session's default)")
     ap.add_argument("--rates", default="", help="serving: comma-separated extra arrival rates (req/s)")
+    ap.add_argument("--layout", default="contiguous", choices=["contiguous", "subring"],
+                    help="single-request workloads with r = 1: slot layout of the queries")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -826,7 +828,7 @@ def main() -> int:
     alpha, r = w.get("alpha", 0), w.get("r", 1)
     primes = ep.default_primes(N, L + alpha)
     prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=w["F"], D=w["D"], K=w["K"], r=r,
-                    dnum=w.get("dnum", 0))
+                    dnum=w.get("dnum", 0), layout=args.layout)
     M = ep.ephdc_num_model_ct(prm)
     seed = args.seed
     t0 = time.perf_counter()

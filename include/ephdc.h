@@ -56,6 +56,14 @@ enum {
   EPHDC_BGV = 2           /* BGV: ([-a*s + t*e + mu]_Q, a), mu centred; decryption [c0 + c1*s]_Q mod t */
 };
 
+/* Slot layouts (ephdc_params.layout); the paper does not fix which slots a query occupies. */
+enum {
+  EPHDC_LAYOUT_CONTIGUOUS = 0, /* the K copies of a query in K consecutive slots of a row; B = 2 floor(N/(2rK)) */
+  EPHDC_LAYOUT_SUBRING = 1     /* the K' copies of a query (K' the power of two >= K) on one orbit of
+                                  {h = 1 mod 2N/K'} acting on the slot exponents: every query plaintext
+                                  is a polynomial in X^K'; B = N/K'; r = 1 only */
+};
+
 /*
  * BFV / BGV + HDC parameters (symbols of the paper's table of symbols: N polynomial degree,
  * log2 t message bits, D hypervector dimension, K = k classes).
@@ -83,9 +91,17 @@ enum {
  *          is multiplied by the plaintext scalar c = centred (2^scale_shift)^-1 mod t, which
  *          divides the plaintext by 2^scale_shift wherever it is divisible.  A trailing
  *          block of fewer than g additions is not scaled.  0 <= scale_shift < 32.
+ *   layout EPHDC_LAYOUT_CONTIGUOUS (the default) or EPHDC_LAYOUT_SUBRING.  Subring layout:
+ *          query ql < B = N/K' of a ciphertext takes the slots of exponents
+ *          2*brev(ql) + 1 + 2B*c mod 2N (brev over log2 B bits), class c < K' (slot s < N/2
+ *          is the exponent 3^s mod 2N, slot N/2 + s its negation); the model holds class c's
+ *          value at c < K and 0 at K <= c < K', the query plaintext the query's value at all
+ *          K' slots.  Its plaintexts are polynomials in X^K', so their transforms are
+ *          N/K'-point transforms (scoring runs that shorter transform where the kernels
+ *          implement it).  Needs r = 1 and K' <= N/2.
  *
- * Derived: Bq = floor(W/K) queries per row, B = 2*Bq queries per ciphertext,
- * M = ceil(D/r) model ciphertexts, G = ceil(Q/B) score ciphertexts for Q queries.
+ * Derived: Bq = floor(W/K) queries per row, B = 2*Bq queries per ciphertext (subring: B =
+ * N/K'), M = ceil(D/r) model ciphertexts, G = ceil(Q/B) score ciphertexts for Q queries.
  */
 typedef struct {
   uint32_t N, L, alpha, dnum;
@@ -97,6 +113,7 @@ typedef struct {
   uint32_t qshift;
   uint32_t scheme;
   uint32_t scale_every, scale_shift;
+  uint32_t layout;
 } ephdc_params;
 
 /* Message describing the last failure on this thread ("" if none). */
@@ -323,7 +340,7 @@ ephdc_status ephdc_session_profile_read(ephdc_session* s, double ms[6], uint64_t
  * query group 0, and the D-term sum_{m<D} ct_m * p_m is correct when it decrypts to the
  * plaintext of the exact dot products mod t in every slot.  dmax[i] (host, int32 [trials])
  * is the number of D = 1, 2, ... that decrypt correctly before the first that does not
- * (d_cap when none fails).  Uses prm's N, L <= 2, q, t, K, qbits and scheme (r must be 1;
+ * (d_cap when none fails).  Uses prm's N, L <= 2, q, t, K, qbits and scheme (r must be 1 and the layout contiguous;
  * F, D and the scaling op are ignored); the primes may be any above t (the noise budget is
  * set by Q), not only the scoring kernels' [2^29, 2^30).  Key generation and encryption run on the host; the
  * batch encoding, every prefix sum, its decryption and the comparison on the device, which

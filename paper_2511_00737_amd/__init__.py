@@ -33,10 +33,11 @@ class _CParams(C.Structure):
                 ("q", C.POINTER(C.c_uint32)), ("p", C.POINTER(C.c_uint32)), ("t", C.c_uint32),
                 ("F", C.c_uint32), ("D", C.c_uint32), ("K", C.c_uint32), ("r", C.c_uint32),
                 ("qbits", C.c_int32), ("qshift", C.c_uint32), ("scheme", C.c_uint32),
-                ("scale_every", C.c_uint32), ("scale_shift", C.c_uint32)]
+                ("scale_every", C.c_uint32), ("scale_shift", C.c_uint32), ("layout", C.c_uint32)]
 
 
 SCHEMES = {"bfv": 0, "bfv-r": 1, "bgv": 2}
+LAYOUTS = {"contiguous": 0, "subring": 1}
 
 
 class _CRequest(C.Structure):
@@ -154,6 +155,7 @@ class Params:
     scheme: str = "bfv"     # "bfv", "bfv-r" (rounded scaling) or "bgv"
     scale_every: int = 0    # HE-aware scaling after every g accumulations (0: never)
     scale_shift: int = 0    # ... by the inverse of 2^scale_shift mod t
+    layout: str = "contiguous"  # slot layout: "contiguous" or "subring"
     _keep: list = field(default_factory=list, repr=False, compare=False)
 
     @property
@@ -169,7 +171,8 @@ class Params:
         pa = (C.c_uint32 * max(1, len(self.p)))(*self.p)
         self._keep[:] = [qa, pa]
         return _CParams(self.N, len(self.q), len(self.p), self.dnum, qa, pa, self.t, self.F, self.D, self.K,
-                        self.r, self.qbits, self.qshift, SCHEMES[self.scheme], self.scale_every, self.scale_shift)
+                        self.r, self.qbits, self.qshift, SCHEMES[self.scheme], self.scale_every, self.scale_shift,
+                        LAYOUTS[self.layout])
 
 
 def default_primes(N: int, count: int, skip: int = 0) -> list[int]:

@@ -396,6 +396,7 @@ __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcn
 // three-buffer plan).
 struct LdsBufs {
   int sel;
+  int base = 0;  // word offset added to every exchange buffer (several transforms per workgroup)
 };
 
 template <int LOGN, int LE, int PF, int PT>
@@ -417,6 +418,7 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
     off = 0;
     lds_barrier();  // every wave has finished reading the previous contents
   }
+  off += b.base;
   uint32_t* wb = ephdc_lds + off + padx<LOGN, LE>(pd, tid_part<LOGN, LE, PF>(tid));
 #pragma unroll
   for (int i = 0; i < S::E; ++i) wb[padx<LOGN, LE>(pd, i_part<LOGN, LE, PF>(i))] = v[i];

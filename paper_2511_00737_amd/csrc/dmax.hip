@@ -247,7 +247,8 @@ ephdc_status ephdc_find_dmax(const ephdc_params* prm, uint64_t seed, uint32_t tr
   ParamSet P;
   ephdc_status st = P.load(&pp);
   if (st != EPHDC_OK) return st;
-  if (P.r != 1) return fail(EPHDC_ERR_UNSUPPORTED, "findDmax uses the paper's packing (r = 1)");
+  if (P.r != 1 || P.subring())
+    return fail(EPHDC_ERR_UNSUPPORTED, "findDmax uses the paper's packing (r = 1, contiguous layout)");
   if (P.L > 2) return fail(EPHDC_ERR_UNSUPPORTED, "findDmax decrypts on the device with L <= 2 limbs");
   if (P.K > 255) return fail(EPHDC_ERR_UNSUPPORTED, "findDmax takes K <= 255");
   if ((uint64_t)d_cap * P.B() >= (1ull << 31)) return fail(EPHDC_ERR_UNSUPPORTED, "d_cap * B must be < 2^31");

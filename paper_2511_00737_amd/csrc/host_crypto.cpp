@@ -9,6 +9,7 @@
 #include <atomic>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <thread>
 
 #include "params.hpp"
@@ -29,6 +30,7 @@ ephdc_status ParamSet::load(const ephdc_params* prm) {
   N = prm->N; L = prm->L; alpha = prm->alpha; dnum = prm->dnum; t = prm->t;
   F = prm->F; D = prm->D; K = prm->K; r = prm->r; qshift = prm->qshift;
   scheme = prm->scheme; scale_every = prm->scale_every; scale_shift = prm->scale_shift;
+  layout = prm->layout;
   if (prm->qbits < 1 || prm->qbits > 8) return fail(EPHDC_ERR_PARAMS, "qbits must be in [1, 8]");
   qbits = (uint32_t)prm->qbits;
   if (N < 8 || N > 32768 || (N & (N - 1))) return fail(EPHDC_ERR_PARAMS, "N must be a power of two in [8, 32768]");
@@ -58,6 +60,9 @@ ephdc_status ParamSet::load(const ephdc_params* prm) {
   if (r < 1 || (r & (r - 1))) return fail(EPHDC_ERR_PARAMS, "r must be a power of two");
   if (N / (2 * r) < K) return fail(EPHDC_ERR_PARAMS, "N/(2r) must be >= K (at least one query per row)");
   if (qshift > 31) return fail(EPHDC_ERR_PARAMS, "qshift must be <= 31");
+  if (layout > EPHDC_LAYOUT_SUBRING) return fail(EPHDC_ERR_PARAMS, "layout must be contiguous or subring");
+  if (subring() && (r != 1 || Kp() > N / 2))
+    return fail(EPHDC_ERR_PARAMS, "the subring layout needs r = 1 and K' <= N/2");
   if (r > 1) {
     if (alpha < 1 || dnum < 1 || dnum > L) return fail(EPHDC_ERR_PARAMS, "r > 1 needs alpha >= 1 and 1 <= dnum <= L");
     if (scheme == EPHDC_BGV) return fail(EPHDC_ERR_PARAMS, "BGV takes r = 1 (no key switching)");
@@ -83,9 +88,20 @@ std::vector<uint32_t> slot_positions(uint32_t N) {
   return pos;
 }
 
+SubringSlots::SubringSlots(const ParamSet& P) : of_exp(2 * P.N, 0), N(P.N), B(P.B()), logb(ilog2(P.B())) {
+  const std::vector<uint32_t> e = slot_exponents(P.N);
+  for (uint32_t s = 0; s < P.N; ++s) of_exp[e[s]] = s;
+}
+
 std::vector<uint32_t> query_scatter_table(const ParamSet& P) {
   std::vector<uint32_t> pos = slot_positions(P.N);
   std::vector<uint32_t> tab(P.N, 0xFFFFFFFFu);
+  if (P.subring()) {  // every slot of query ql's orbit carries its value
+    const SubringSlots ss(P);
+    for (uint32_t ql = 0; ql < P.B(); ++ql)
+      for (uint32_t c = 0; c < P.Kp(); ++c) tab[pos[ss.slot_of(ql, c)]] = ql;
+    return tab;
+  }
   for (uint32_t rho = 0; rho < 2; ++rho)
     for (uint32_t u = 0; u < P.r; ++u)
       for (uint32_t ql = 0; ql < P.Bq(); ++ql)
@@ -329,11 +345,19 @@ ephdc_status encrypt_model_host(const ParamSet& P, const int8_t* sk, const int8_
     H.mod[l].forward(S[l].data());
   }
   Stream enc(seed, TAG_ENCRYPT);
+  std::unique_ptr<SubringSlots> subring(P.subring() ? new SubringSlots(P) : nullptr);
   parallel_for(M, [&](size_t mi) {
     const uint32_t m = (uint32_t)mi;
     // slot vector of ciphertext m, placed at transform positions, then mu = Encode(v)
     std::vector<uint32_t> mu(N, 0);
-    for (uint32_t rho = 0; rho < 2; ++rho)
+    if (subring) {
+      for (uint32_t ql = 0; ql < P.B(); ++ql)
+        for (uint32_t c = 0; c < P.K; ++c) {
+          int v = class_hv[(size_t)c * P.D + m];
+          mu[H.pos[subring->slot_of(ql, c)]] = v < 0 ? (uint32_t)(P.t + v) : (uint32_t)v;
+        }
+    }
+    for (uint32_t rho = 0; rho < 2 && !subring; ++rho)
       for (uint32_t u = 0; u < P.r; ++u) {
         uint32_t j = m * P.r + u;
         if (j >= P.D) continue;
@@ -416,6 +440,7 @@ ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, 
     for (uint32_t k = 0; k < N; ++k) S[l][k] = sk[k] < 0 ? P.q[l] - 1 : (uint32_t)sk[k];
     H.mod[l].forward(S[l].data());
   }
+  std::unique_ptr<SubringSlots> subring(P.subring() ? new SubringSlots(P) : nullptr);
   parallel_for(G, [&](size_t gi) {
     const uint32_t g = g_first + (uint32_t)gi;
     std::vector<std::vector<uint32_t>> x(L, std::vector<uint32_t>(N));
@@ -467,7 +492,7 @@ ephdc_status ephdc_decrypt_scores_at(const ephdc_params* prm, const int8_t* sk, 
       uint32_t rho = qi / Bq, ql = qi % Bq;
       int32_t best = 0;
       for (uint32_t c = 0; c < P.K; ++c) {
-        uint32_t v = mu[H.pos[slot_index(P, rho, 0, ql, c)]];
+        uint32_t v = mu[H.pos[subring ? subring->slot_of(qi, c) : slot_index(P, rho, 0, ql, c)]];
         int32_t sc = v > t / 2 ? (int32_t)v - (int32_t)t : (int32_t)v;
         scores[(size_t)qq * P.K + c] = sc;
         if (c == 0 || sc > scores[(size_t)qq * P.K + best]) best = (int32_t)c;

@@ -581,6 +581,168 @@ constexpr bool mac_prefetch() {
   return Shape<LOGN, LE>::T <= 512 || LE <= 3;
 }
 
+// ------------------------------------------------------------------ subring layout
+// In the subring layout every query plaintext is p(X) = p~(X^K'), K' = N/n, so
+//  * its batch encoding is the n-point inverse transform (root zeta^K') of its n orbit
+//    values, and query ql of the group sits at n-point evaluation position ql: a lane's
+//    inputs are E consecutive bytes of the group's hypervector row;
+//  * its transform mod q_l is the n-point forward transform of p~ (root psi^K'), and the
+//    value at N-point evaluation position x is the n-point output at position x >> log2 K'.
+// The n-point twiddle tables are the first n entries of the N-point ones (the bit reversal
+// over log2 N bits of k < n is K' times the one over log2 n bits), and only the n^-1
+// constants differ (pct_sub).  One wave runs one n-point transform (n = 64 E), all of its
+// exchanges inside the wave's own LDS region.
+
+// LDS offset of the wave-local exchange buffer inside an exchange plan (see exchange()).
+template <int LOGN, int LE>
+constexpr int local_exchange_offset() {
+  return LdsPlan<LOGN, LE>::three ? 2 * Shape<LOGN, LE>::PADN : Shape<LOGN, LE>::PADN;
+}
+
+// Batch encoding: work item (split, g); wave w of the workgroup encodes plaintexts
+// m0 + w, m0 + w + waves, ... of the split into a.pt[g][m - m_base][0 .. n).
+template <int LOGn, int LEs>
+__global__ __launch_bounds__(256) void k_encode_sub(ScoreArgs a) {
+  using S = Shape<LOGn, LEs>;
+  static_assert(S::T == 64, "one wave per transform");
+  constexpr int E = S::E, n = S::N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  LdsBufs b{0, wave * S::PADN - local_exchange_offset<LOGn, LEs>()};
+  const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
+  const uint32_t m0 = a.m_base + split * a.mchunk;
+  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
+  const uint32_t t = a.pct_sub.m;
+  const int8_t* hvg = a.hv + (size_t)g * a.B + (uint32_t)lane * E;  // queries g*B + lane*E + i
+  int32_t* dst = a.pt + ((size_t)g * a.m_len + (m0 - a.m_base)) * n;
+  for (uint32_t m = m0 + wave; m < m1; m += nwave) {
+    uint32_t w[E / 4];
+    const int8_t* src = hvg + (size_t)m * a.hv_stride;
+    if constexpr (E == 16) {
+      const uint4 q = *reinterpret_cast<const uint4*>(src);
+      w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+    } else if constexpr (E == 8) {
+      const uint2 q = *reinterpret_cast<const uint2*>(src);
+      w[0] = q.x; w[1] = q.y;
+    } else {
+      w[0] = *reinterpret_cast<const uint32_t*>(src);
+    }
+    uint32_t v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int h = (int)(w[i >> 2] << (24 - 8 * (i & 3))) >> 24;  // signed byte i
+      v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));                 // h mod t
+    }
+    ntt_inverse<LOGn, LEs, true, true>(v, lane, a.inv_t, a.pct_sub, b);
+    int32_t* d = dst + (size_t)(m - m0) * n;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t mu = csub(v[i], t);
+      d[lane + i * 64] = mu > (t >> 1) ? (int32_t)mu - (int32_t)t : (int32_t)mu;
+    }
+  }
+}
+
+// Word of n-point output y in a wave's LDS region (one pad word per 16 spreads the banks).
+__device__ __forceinline__ uint32_t sub_slot(uint32_t y) { return y + (y >> 4); }
+
+// MAC: work item (split, g, limb) as in k_mac with one limb per item; the workgroup's
+// threads own 8 consecutive evaluation positions each.  Per round, wave w transforms
+// plaintext r0 + w into its LDS region; after a barrier every thread accumulates the round's
+// plaintexts at its positions (64-bit lazy sums as in mac_item64); a second barrier frees
+// the regions for the next round.
+template <int LOGN, int LOGn, int LEs, bool SC>
+__global__ __launch_bounds__((1 << LOGN) >> 3) void k_mac_sub(ScoreArgs a) {
+  using Ss = Shape<LOGn, LEs>;
+  static_assert(Ss::T == 64, "one wave per transform");
+  constexpr int N = 1 << LOGN, E = 8, T = N / E, NW = T / 64, Es = Ss::E, n = Ss::N;
+  constexpr int LOGKP = LOGN - LOGn;
+  constexpr int NY = LOGKP >= 3 ? 1 : (E >> LOGKP);  // distinct n-point outputs per thread
+  const uint32_t wi = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
+  if (wi == 0xFFFFFFFFu) return;  // a slot past the last item: the whole workgroup leaves
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  LdsBufs b{0, wave * Ss::PADN - local_exchange_offset<LOGn, LEs>()};
+  uint32_t g, split;
+  const MacItem it = single_item<LOGN, 1>(a, wi, g, split);
+  const uint32_t l = it.l0;
+  const PrimeConst pc = a.pcs[l];
+  const int32_t* pt = a.pt + ((size_t)g * a.m_len + (it.m0 - a.m_base)) * n;
+  const uint32_t* tw = a.fwd_tw + (size_t)l * N;
+  const uint32_t eo = (uint32_t)tid * E * 4u;
+  const size_t cstride = (size_t)it.L * N;  // words from c0 to c1 of one ciphertext
+
+  uint64_t acc[2][E];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const uint32_t* src = it.slot + ((size_t)c * it.L + l) * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      acc[c][i] = a.accumulate ? mont_mul(ld_at(src, eo + 4u * i), pc.r2, pc.m, pc.mneg_inv) : 0u;
+  }
+  // model values of the next plaintext, requested one plaintext ahead
+  uint32_t n0[E], n1[E];
+  auto load_model = [&](uint32_t m) {
+    const uint32_t* ct0 = it.model + ((size_t)m * 2 * it.L + l) * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      n0[i] = ld_at(ct0, eo + 4u * i);
+      n1[i] = ld_at(ct0 + cstride, eo + 4u * i);
+    }
+  };
+  if (it.m0 < it.m1) load_model(it.m0);
+  uint32_t since_fold = 0;
+  for (uint32_t r0 = it.m0; r0 < it.m1; r0 += NW) {
+    const uint32_t m = r0 + wave;
+    if (m < it.m1) {
+      const int32_t* ptm = pt + (size_t)(m - it.m0) * n;
+      uint32_t v[Es];
+#pragma unroll
+      for (int i = 0; i < Es; ++i) v[i] = pc.m + (uint32_t)ld_at(ptm, 4u * (uint32_t)(lane + i * 64));
+      ntt_forward<LOGn, LEs, false, true>(v, lane, tw, pc, b);
+      if constexpr (SC) apply_scale(v, it.scale, m, l, pc);
+      uint32_t* region = ephdc_lds + wave * Ss::PADN;
+#pragma unroll
+      for (int i = 0; i < Es; ++i) region[sub_slot((uint32_t)lane * Es + i)] = v[i];
+    }
+    lds_barrier();
+    const uint32_t nr = min((uint32_t)NW, it.m1 - r0);
+    for (uint32_t j = 0; j < nr; ++j) {
+      const uint32_t mm = r0 + j;
+      uint32_t c0[E], c1[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        c0[i] = n0[i];
+        c1[i] = n1[i];
+      }
+      if (mm + 1 < it.m1) load_model(mm + 1);
+      const uint32_t* region = ephdc_lds + j * Ss::PADN;
+      uint32_t p[NY];
+#pragma unroll
+      for (int k = 0; k < NY; ++k) p[k] = region[sub_slot(((uint32_t)tid * E + (uint32_t)k * (E / NY)) >> LOGKP)];
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t pv = p[i / (E / NY)];
+        acc[0][i] += (uint64_t)c0[i] * pv;
+        acc[1][i] += (uint64_t)c1[i] * pv;
+      }
+      if (++since_fold == 2) {
+        since_fold = 0;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          acc[0][i] = fold64(acc[0][i], pc.r1);
+          acc[1][i] = fold64(acc[1][i], pc.r1);
+        }
+      }
+    }
+    lds_barrier();
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    uint32_t* dst = it.slot + ((size_t)c * it.L + l) * N;
+#pragma unroll
+    for (int i = 0; i < E; ++i) st_at(dst, eo + 4u * i, redc64(fold64(acc[c][i], pc.r1), pc.m, pc.mneg_inv));
+  }
+}
+
 // ------------------------------------------------------------------ request-list kernels
 // Persistent kernels over the segments of many requests (one launch for all of them):
 // workgroup w takes items w, w + gridDim.x, ...  Every request of a list shares N and the
@@ -800,11 +962,40 @@ static hipError_t prepare_shape() {
   return e;
 }
 
+// The subring kernels: n-point shapes (one wave per transform) under each N of the MAC.
+template <int LN, int LS>
+static hipError_t prepare_sub_mac() {
+  if constexpr (LS < LN) {
+    const int bytes = (int)(((1 << LN) / 8 / 64) * Shape<LS, LS - 6>::PADN * sizeof(uint32_t));
+    hipError_t e = hipFuncSetAttribute((const void*)k_mac_sub<LN, LS, LS - 6, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_mac_sub<LN, LS, LS - 6, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              bytes);
+    return e;
+  } else {
+    return hipSuccess;
+  }
+}
+
+template <int LS>
+static hipError_t prepare_sub() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_encode_sub<LS, LS - 6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(4 * Shape<LS, LS - 6>::PADN * sizeof(uint32_t)));
+  if (e == hipSuccess) e = prepare_sub_mac<11, LS>();
+  if (e == hipSuccess) e = prepare_sub_mac<12, LS>();
+  if (e == hipSuccess) e = prepare_sub_mac<13, LS>();
+  return e;
+}
+
 hipError_t prepare_kernels() {
   static hipError_t once = [] {
     hipError_t ks = prepare_ks_kernels();
     if (ks != hipSuccess) return ks;
-    hipError_t e = prepare_shape<11, 3>();
+    hipError_t e = prepare_sub<8>();
+    if (e == hipSuccess) e = prepare_sub<9>();
+    if (e == hipSuccess) e = prepare_sub<10>();
+    if (e == hipSuccess) e = prepare_shape<11, 3>();
     if (e == hipSuccess) e = prepare_shape<12, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 4>();
@@ -926,6 +1117,62 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+  });
+}
+
+bool subring_kernels(int logn, int sub_logn) {
+  return logn >= 11 && logn <= 13 && sub_logn >= 8 && sub_logn <= 10 && sub_logn < logn;
+}
+
+template <class F>
+hipError_t dispatch_sub(int sub_logn, F&& f) {
+  switch (sub_logn) {
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 9: return f(std::integral_constant<int, 9>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  return dispatch_sub(sub_logn, [&](auto lc) {
+    constexpr int LS = decltype(lc)::value;
+    using S = Shape<LS, LS - 6>;
+    k_encode_sub<LS, LS - 6><<<dim3(nblocks), dim3(256), 4 * S::PADN * sizeof(uint32_t), st>>>(a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  if (!subring_kernels(logn, sub_logn)) return hipErrorInvalidValue;
+  ScoreArgs a = a0;
+  const XcdMap xm = make_xcd_map(nblocks);
+  a.xcd = xm.on;
+  a.nitems = nblocks;
+  const bool sc = a.scale.pow != nullptr;
+  return dispatch_sub(sub_logn, [&](auto lc) -> hipError_t {
+    constexpr int LS = decltype(lc)::value;
+    using S = Shape<LS, LS - 6>;
+    auto go = [&](auto lnc) -> hipError_t {
+      constexpr int LN = decltype(lnc)::value;
+      if constexpr (LS < LN) {
+        constexpr int T = (1 << LN) / 8;
+        const size_t sh = (size_t)(T / 64) * S::PADN * sizeof(uint32_t);
+        if (sc) k_mac_sub<LN, LS, LS - 6, true><<<dim3(xm.slots()), dim3(T), sh, st>>>(a);
+        else k_mac_sub<LN, LS, LS - 6, false><<<dim3(xm.slots()), dim3(T), sh, st>>>(a);
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
+    };
+    switch (logn) {
+      case 11: return go(std::integral_constant<int, 11>{});
+      case 12: return go(std::integral_constant<int, 12>{});
+      case 13: return go(std::integral_constant<int, 13>{});
+      default: return hipErrorInvalidValue;
+    }
   });
 }
 

@@ -43,6 +43,10 @@ struct ScoreArgs {
   // XCD-aware order of the MAC / fused work items (see XcdMap); xcd = 0: block = item
   uint32_t xcd, nitems;
   ScaleOp scale;
+  // subring layout (sub_logn > 0): plaintexts are n = 2^sub_logn coefficients p~ of
+  // p(X) = p~(X^(N/n)), stored [G][m_len][n]; pct_sub holds the n-point constants of t
+  uint32_t sub_logn;
+  PrimeConst pct_sub;
 };
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin (workgroup d runs on XCD
@@ -198,6 +202,10 @@ hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t n
 // split path: batch-encode every (g, m) plaintext of the launch into a.pt, then MAC
 hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+// subring layout: n-point batch encoding (G x splits items) and MAC (G x S x L items)
+bool subring_kernels(int logn, int sub_logn);
+hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 bool supported_shape(int logn, int le);
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S,
                          uint32_t L, const uint32_t* itw, const PrimeConst* pcs, hipStream_t st);

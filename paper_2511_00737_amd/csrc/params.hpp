@@ -20,12 +20,15 @@ struct ParamSet {
   uint32_t qbits = 1, qshift = 0;
   uint32_t scheme = EPHDC_BFV;              // EPHDC_BFV, EPHDC_BFV_ROUNDED or EPHDC_BGV
   uint32_t scale_every = 0, scale_shift = 0;  // HE-aware scaling: g and s (g = 0: off)
+  uint32_t layout = EPHDC_LAYOUT_CONTIGUOUS;
   int logn = 0;
   std::vector<uint32_t> q, p;  // ciphertext primes, special primes
 
   uint32_t W() const { return N / (2 * r); }           // block width per row
-  uint32_t Bq() const { return W() / K; }              // queries per row
-  uint32_t B() const { return 2 * Bq(); }              // queries per ciphertext
+  bool subring() const { return layout == EPHDC_LAYOUT_SUBRING; }
+  uint32_t Kp() const { return subring() ? 1u << ilog2(K) : K; }  // class slots per query (ilog2 rounds up)
+  uint32_t Bq() const { return W() / K; }              // queries per row (contiguous layout)
+  uint32_t B() const { return subring() ? N / Kp() : 2 * Bq(); }  // queries per ciphertext
   uint32_t M() const { return (D + r - 1) / r; }       // model ciphertexts
   uint32_t G(uint32_t Q) const { return (Q + B() - 1) / B(); }
   uint32_t log2r() const { return (uint32_t)ilog2(r); }
@@ -60,6 +63,19 @@ std::vector<uint32_t> query_scatter_table(const ParamSet& P);
 inline uint32_t slot_index(const ParamSet& P, uint32_t rho, uint32_t u, uint32_t ql, uint32_t c) {
   return rho * (P.N / 2) + u * P.W() + ql * P.K + c;
 }
+
+// Slots of the subring layout: slot_of(ql, c) is the slot of exponent
+// 2*brev(ql) + 1 + 2B*c mod 2N (query ql < B, class c < K').
+struct SubringSlots {
+  std::vector<uint32_t> of_exp;  // odd exponent -> slot
+  uint32_t N = 0, B = 0;
+  int logb = 0;
+  explicit SubringSlots(const ParamSet& P);
+  uint32_t slot_of(uint32_t ql, uint32_t c) const {
+    const uint64_t e = (2ull * bitrev(ql, logb) + 1 + 2ull * B * c) % (2ull * N);
+    return of_exp[e];
+  }
+};
 
 // The model ciphertexts of ephdc_encrypt_model for a validated parameter set: class
 // hypervectors int8 [K][D] -> uint32 [M][2][L][N], coefficient domain.

@@ -111,6 +111,8 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   a.pt = ws ? ws->pt : nullptr;
   a.accumulate = 0;
   a.scale = scale_op(s);
+  a.sub_logn = s->sub_logn;
+  a.pct_sub = s->pct_sub;
   return a;
 }
 
@@ -144,6 +146,44 @@ hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, size_t
     c.mchunk = (len + sc.S - 1) / sc.S;
     t0 = timed_begin(s, hs);
     e = launch_mac(P.logn, (int)s->le, (int)s->lg, c, sc.G * sc.S * s->nlg, hs);
+    if (e != hipSuccess) return e;
+    timed_end(s, kStMac, t0, hs);
+  }
+  return hipSuccess;
+}
+
+// Subring layout with n-point kernels: the same chunking as score_split with plaintexts of
+// n words (a workspace that holds c N-word plaintexts holds c*N/n of them) and MAC items
+// of one limb each.
+hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_cap, Schedule& sc, hipStream_t hs) {
+  const ParamSet& P = s->P;
+  const uint32_t M = P.M(), n = 1u << s->sub_logn;
+  sc.G = P.G(Q);
+  const uint32_t per = sc.G * P.L;
+  sc.S = std::min(M, std::max<uint32_t>(1, (s->target_blocks + per - 1) / per));
+  sc.mchunk = (M + sc.S - 1) / sc.S;
+  sc.S = (M + sc.mchunk - 1) / sc.mchunk;
+  a.S = sc.S;
+  a.NLG = P.L;
+  const size_t cap = pt_cap * (P.N / n);
+  const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, cap / sc.G));
+  constexpr uint32_t kEncodeBlocks = 2048;  // 4 waves each: 8 per SIMD across the chip
+  for (uint32_t base = 0; base < M; base += mc) {
+    const uint32_t len = std::min(mc, M - base);
+    ScoreArgs c = a;
+    c.m_base = base;
+    c.m_len = len;
+    c.accumulate = base > 0;
+    uint32_t Se = std::max<uint32_t>(1, std::min(len, (kEncodeBlocks + sc.G - 1) / sc.G));
+    c.mchunk = (len + Se - 1) / Se;
+    Se = (len + c.mchunk - 1) / c.mchunk;
+    hipEvent_t t0 = timed_begin(s, hs);
+    hipError_t e = launch_encode_sub((int)s->sub_logn, c, sc.G * Se, hs);
+    if (e != hipSuccess) return e;
+    timed_end(s, kStEncodePt, t0, hs);
+    c.mchunk = (len + sc.S - 1) / sc.S;
+    t0 = timed_begin(s, hs);
+    e = launch_mac_sub(P.logn, (int)s->sub_logn, c, sc.G * sc.S * P.L, hs);
     if (e != hipSuccess) return e;
     timed_end(s, kStMac, t0, hs);
   }
@@ -292,7 +332,13 @@ ephdc_status score_with(ephdc_session* s, const Workspace& ws, const int8_t* d_h
   // scratch it reuses
   if (s->done_set && s->done_stream != hs) HIP_TRY(hipStreamWaitEvent(hs, s->done, 0), "stream ordering");
   ScoreArgs a = score_args(s, d_hv, Q, sc, &ws);
-  if (s->split) {
+  // the n-point kernels read each lane's queries as one aligned vector of E bytes
+  const bool sub = s->sub_logn && ((uintptr_t)d_hv & 15) == 0;
+  if (sub) {
+    size_t cap = ws.pt_cap;
+    if (s->pt_bytes) cap = std::max<size_t>(sc.G, std::min(cap, s->pt_bytes / (4 * (size_t)P.N)));
+    HIP_TRY(score_split_sub(s, a, Q, cap, sc, hs), "subring score launch");
+  } else if (s->split) {
     size_t cap = ws.pt_cap;
     if (s->pt_bytes) cap = std::max<size_t>(sc.G, std::min(cap, s->pt_bytes / (4 * (size_t)P.N)));
     HIP_TRY(score_split(s, a, sc, cap, hs), "split score launch");
@@ -429,6 +475,18 @@ ephdc_status ephdc::session_create(const ephdc_params* prm, const uint32_t* d_mo
     HostNtt Tt(N, P.t, root_of_unity(2 * N, P.t));
     for (uint32_t k = 0; k < N; ++k) invt[k] = (uint32_t)(((uint64_t)Tt.iw[k] << 32) % P.t);
     s->pct = make_const(Tt);
+    if (P.subring()) {
+      // n-point transforms of p~ in p(X) = p~(X^K'): the same tables (their first n words),
+      // with n^-1 in the scaling stage of the inverse
+      const uint32_t n = N / P.Kp();
+      if (subring_kernels(P.logn, ilog2(n))) {
+        s->sub_logn = (uint32_t)ilog2(n);
+        s->pct_sub = s->pct;
+        const uint64_t ninv = inv_mod(n, P.t);
+        s->pct_sub.ninv_r = (uint32_t)((ninv << 32) % P.t);
+        s->pct_sub.ninv_w1_r = (uint32_t)((((ninv * Tt.iw[1]) % P.t) << 32) % P.t);
+      }
+    }
   }
   std::vector<uint32_t> scatter = query_scatter_table(P);
 

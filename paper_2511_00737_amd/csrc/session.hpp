@@ -59,6 +59,10 @@ struct ephdc_session {
   uint2* d_ksc = nullptr;          // key-switching constants, pointed into by ks
   ephdc::KsConst ks{};
   ephdc::PrimeConst pct{};
+  // subring layout with n-point kernels: log2 n (0: the N-point kernels) and the n-point
+  // constants of t
+  uint32_t sub_logn = 0;
+  ephdc::PrimeConst pct_sub{};
   size_t device_bytes = 0;
   // kernel timing: pairs of events per stage, resolved when read
   bool profile = false;

@@ -1,0 +1,163 @@
+"""Subring slot layout through the C ABI (needs a gfx950 GPU): the n-point batch-encoding and
+MAC kernels (n = N/K') against the oracle word for word, against the N-point kernels of the
+same session, with the scaling op, with the plaintext chunk split, with queries encoded on
+the device, and in batches (whose list kernels run the N-point transforms)."""
+import numpy as np
+import pytest
+
+import paper_2511_00737_amd as ep
+import synth
+from oracle import bfv, hdc, pipeline
+from oracle.params import Params as OParams, default_primes
+
+from gpu_helpers import hv_layout, to_dev, to_host_u32, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def make(N, L, D, K, F=64, **kw):
+    args = dict(N=N, q=tuple(default_primes(N, L)), F=F, D=D, K=K, layout="subring", **kw)
+    o = OParams(**args)
+    o.validate()
+    return o, ep.Params(**args)
+
+
+def values(rng, bits, shape):
+    if bits == 1:
+        return rng.choice(np.array([-1, 1], dtype=np.int8), shape)
+    return rng.integers(-(1 << (bits - 1)), 1 << (bits - 1), shape).astype(np.int8)
+
+
+def score(e, model, h, stride_offset=0, chunk_bytes=0):
+    """Score ciphertexts of h through ephdc_score_encrypted; stride_offset > 0 places the
+    hypervectors at a byte offset (not 16-byte aligned), which takes the N-point kernels."""
+    torch = torch_cuda()
+    Q = h.shape[0]
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=Q)
+    try:
+        if chunk_bytes:
+            s.set_chunk_bytes(chunk_bytes)
+        stride = s.hv_stride(Q)
+        lay = hv_layout(h, stride).reshape(-1)
+        buf = torch.zeros(lay.size + 64, dtype=torch.int8, device="cuda")
+        buf[stride_offset:stride_offset + lay.size] = to_dev(lay)
+        d_hv = buf[stride_offset:stride_offset + lay.size]
+        out = torch.empty((s.num_groups(Q), 2, e.L, e.N), dtype=torch.int32, device="cuda")
+        ep.ephdc_score_encrypted(s, d_hv, Q, out)
+        torch.cuda.synchronize()
+        return to_host_u32(out).astype(np.int64)
+    finally:
+        s.close()
+
+
+# (N, L, K, D, Q): n = N/K' of 1024, 512 and 256 under N = 2048, 4096 and 8192; ragged
+# last groups
+CASES = [(8192, 4, 7, 70, 2500), (8192, 4, 12, 33, 1100), (8192, 4, 26, 21, 300), (4096, 3, 3, 64, 1500),
+         (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100), (2048, 2, 5, 31, 600)]
+
+
+@pytest.mark.parametrize("N,L,K,D,Q", CASES)
+def test_subring_scores_match_oracle(N, L, K, D, Q):
+    o, e = make(N, L, D, K)
+    rng = np.random.default_rng(N + K + D)
+    C = values(rng, 8, (K, D))
+    h = values(rng, 1, (Q, D))
+    sk = bfv.secret_key(o, 3)
+    model = bfv.encrypt_model(o, sk, C, 3)
+    got = score(e, model, h)
+    want = pipeline.score_ciphertexts(o, model, h)
+    assert np.array_equal(got, want)
+    sc, am = ep.ephdc_decrypt_scores(e, sk.astype(np.int8), got.astype(np.uint32), Q)
+    assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))
+
+
+@pytest.mark.parametrize("N,L,K,D,Q", [(8192, 4, 7, 70, 2500), (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100)])
+def test_subring_kernels_equal_the_n_point_kernels(N, L, K, D, Q):
+    """The same session and queries through the N-point kernels (hypervectors at an odd
+    byte offset) give the same ciphertexts, and so does a plaintext chunk of one plaintext
+    per group (the MAC adding into stored sums chunk after chunk)."""
+    o, e = make(N, L, D, K)
+    rng = np.random.default_rng(5 * N + K)
+    C = values(rng, 8, (K, D))
+    h = values(rng, 4, (Q, D))
+    sk = bfv.secret_key(o, 4)
+    model = bfv.encrypt_model(o, sk, C, 4)
+    fast = score(e, model, h)
+    assert np.array_equal(fast, score(e, model, h, stride_offset=1))
+    assert np.array_equal(fast, score(e, model, h, chunk_bytes=1))
+    G = o.groups(Q)
+    assert np.array_equal(fast[G - 1:], pipeline.score_ciphertexts(o, model, h, groups=[G - 1]))
+
+
+@pytest.mark.parametrize("N,L,K,D,g,s_,qb", [(8192, 4, 7, 130, 32, 14, 8), (4096, 3, 3, 200, 64, 12, 6)])
+def test_subring_with_scaling_op(N, L, K, D, g, s_, qb):
+    o, e = make(N, L, D, K, scale_every=g, scale_shift=s_, qbits=qb)
+    rng = np.random.default_rng(D + g)
+    C = values(rng, 8, (K, D))
+    h = values(rng, qb, (o.B + 77, D))
+    sk = bfv.secret_key(o, 6)
+    model = bfv.encrypt_model(o, sk, C, 6)
+    assert np.array_equal(score(e, model, h), pipeline.score_ciphertexts(o, model, h))
+
+
+def test_subring_queries_encoded_on_the_device():
+    """Features -> ephdc_encode_queries (hypervectors of B = N/K' queries per group) ->
+    subring scoring -> the oracle's scores."""
+    torch = torch_cuda()
+    o, e = make(8192, 4, 256, 7, F=128)
+    Q = 1500
+    x = synth.uniform_features(8, Q, o.F)
+    base = synth.base_hypervectors(8, o.F, o.D)
+    C = synth.class_hypervectors(8, o.K, o.D)
+    sk = bfv.secret_key(o, 8)
+    model = bfv.encrypt_model(o, sk, C, 8)
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=Q)
+    try:
+        d_hv = torch.empty((o.D, s.hv_stride(Q)), dtype=torch.int8, device="cuda")
+        ep.ephdc_encode_queries(s, to_dev(x), to_dev(base), Q, d_hv)
+        out = torch.empty((s.num_groups(Q), 2, o.L, o.N), dtype=torch.int32, device="cuda")
+        ep.ephdc_score_encrypted(s, d_hv, Q, out)
+        torch.cuda.synchronize()
+        got = to_host_u32(out)
+    finally:
+        s.close()
+    h = hdc.encode(x, base)
+    sc, _ = ep.ephdc_decrypt_scores(e, sk.astype(np.int8), got, Q)
+    assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))
+    assert np.array_equal(got[1:].astype(np.int64), pipeline.score_ciphertexts(o, model, h, groups=[1]))
+
+
+def test_subring_sessions_in_a_batch():
+    """A batch mixing a subring session with a contiguous one (the list kernels gather
+    through the scatter table): every request equals the oracle."""
+    torch = torch_cuda()
+    o1, e1 = make(4096, 3, 64, 3)
+    args2 = dict(N=4096, q=tuple(default_primes(4096, 3)), F=64, D=64, K=3)
+    o2, e2 = OParams(**args2), ep.Params(**args2)
+    rng = np.random.default_rng(10)
+    tenants = []
+    for o, e in ((o1, e1), (o2, e2)):
+        C = values(rng, 8, (o.K, o.D))
+        sk = bfv.secret_key(o, 10)
+        model = bfv.encrypt_model(o, sk, C, 10)
+        tenants.append((o, e, model, ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=2000)))
+    try:
+        reqs, want = [], []
+        for k, (ti, Q) in enumerate([(0, 1500), (1, 700), (0, 3), (1, 2000)]):
+            o, e, model, s = tenants[ti]
+            h = values(rng, 1, (Q, o.D))
+            d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
+            out = torch.zeros((s.num_groups(Q), 2, o.L, o.N), dtype=torch.int32, device="cuda")
+            reqs.append(ep.Request(s, d_hv, Q, out))
+            want.append(pipeline.score_ciphertexts(o, model, h))
+        b = ep.Batch(reqs)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+        for k, r in enumerate(reqs):
+            assert np.array_equal(to_host_u32(r.d_score_ct).astype(np.int64), want[k]), k
+    finally:
+        for t in tenants:
+            t[3].close()

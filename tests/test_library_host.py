@@ -228,3 +228,48 @@ def test_other_schemes_and_plaintext_primes_match_oracle(N, t, scheme):
     sc2, _ = ep.ephdc_decrypt_scores(e, run["s"].astype(np.int8), junk.astype(np.uint32), min(Qn, o.B))
     want2, _ = pipeline.decrypt_scores(o, run["s"], junk, min(Qn, o.B))
     assert np.array_equal(sc2, want2)
+
+
+def _sub_pair(N, L=3, D=16, K=3, F=16):
+    primes = default_primes(N, L)
+    kw = dict(N=N, q=tuple(primes), F=F, D=D, K=K, layout="subring")
+    return OParams(**kw), ep.Params(**kw)
+
+
+def test_subring_layout_sizes_and_validation():
+    for N, K in [(64, 3), (4096, 2), (8192, 7), (8192, 26), (2048, 8)]:
+        o, e = _sub_pair(N, K=K)
+        assert ep.ephdc_check_params(e) == ep.OK
+        assert ep.ephdc_queries_per_ct(e) == o.B == N // o.Kp
+        for Q in (1, o.B, o.B + 1, 4096):
+            assert ep.ephdc_num_groups(e, Q) == o.groups(Q)
+            assert ep.ephdc_hv_stride(e, Q) == o.groups(Q) * o.B
+    # r > 1 and K' > N/2 are refused; so is an unknown layout
+    _, e2 = _pair(64, L=4, D=16, K=2, r=4, alpha=2, dnum=2)
+    assert ep.ephdc_check_params(ep.Params(**{**e2.__dict__, "_keep": [], "layout": "subring"})) == ep.ERR_PARAMS
+    _, e3 = _sub_pair(16, K=9)
+    assert ep.ephdc_check_params(e3) == ep.ERR_PARAMS
+    c = _sub_pair(64)[1].c()
+    c.layout = 2
+    assert ep.lib().ephdc_check_params(ctypes.byref(c)) == ep.ERR_PARAMS
+
+
+@pytest.mark.parametrize("N,K,D", [(32, 3, 11), (64, 2, 16), (128, 7, 20), (64, 4, 9)])
+def test_subring_model_encryption_and_decryption_match_oracle(N, K, D):
+    o, e = _sub_pair(N, D=D, K=K)
+    C = synth.class_hypervectors(41, K, D)
+    sk, _ = ep.ephdc_keygen(e, 41)
+    got = ep.ephdc_encrypt_model(e, sk, C, 42)
+    want = bfv.encrypt_model(o, sk.astype(np.int64), C, 42)
+    assert np.array_equal(got.astype(np.int64), want)
+    Qn = 2 * o.B + 5
+    x = synth.uniform_features(43, Qn, o.F)
+    base = synth.base_hypervectors(43, o.F, o.D)
+    run = pipeline.run(o, x, base, C, seed=42)
+    sc, am = ep.ephdc_decrypt_scores(e, run["s"].astype(np.int8), run["score_ct"].astype(np.uint32), Qn)
+    assert np.array_equal(sc, run["scores"])
+    assert np.array_equal(am, run["argmax"])
+    assert np.array_equal(sc, hdc.scores_mod_t(run["h"], C, 65537))
+    for q_first, Q in [(3, o.B), (o.B - 1, 2)]:
+        sc2, _ = ep.ephdc_decrypt_scores_at(e, run["s"].astype(np.int8), run["score_ct"].astype(np.uint32), q_first, Q)
+        assert np.array_equal(sc2, run["scores"][q_first:q_first + Q])
