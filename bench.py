@@ -100,6 +100,7 @@ KERNEL_SOURCES = {k: ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", 
 KERNEL_SOURCES["batch_unpacked"] = ("kernels_ntt.hip", "device_ntt.hpp", "kernel_common.hpp", "launch.hpp",
                                     "kernels_hdc.hip", "batch.hip")
 KERNEL_SOURCES["k_hdc_encode"] = ("kernels_hdc.hip", "launch.hpp")
+KERNEL_SOURCES["k_mac_sub"] = KERNEL_SOURCES["k_encode_sub"] = KERNEL_SOURCES["k_mac"]
 
 
 def kernel_source_digest(kernel: str = "k_mac") -> str:
@@ -176,7 +177,8 @@ def cpu_baseline_all_cores(prm: ep.Params, C: np.ndarray, sample_m: int, t_hdc: 
     the slices' plaintexts per second give inferences/s as in the single-core leg."""
     import multiprocessing as mp
     from oracle.params import Params as OParams
-    kw = dict(N=prm.N, q=tuple(prm.q), p=tuple(prm.p), F=prm.F, K=prm.K, r=prm.r, dnum=prm.dnum)
+    kw = dict(N=prm.N, q=tuple(prm.q), p=tuple(prm.p), F=prm.F, K=prm.K, r=prm.r, dnum=prm.dnum,
+              layout=prm.layout)
     o = OParams(D=prm.D, **kw)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     nproc = max(1, min(cores, 16, o.M // sample_m))
@@ -224,7 +226,8 @@ def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np
     packings, the rotate-and-sum of that group, turned into inferences/s."""
     from oracle import bfv, hdc
     from oracle.params import Params as OParams
-    kw = dict(N=prm.N, q=tuple(prm.q), p=tuple(prm.p), F=prm.F, K=prm.K, r=prm.r, dnum=prm.dnum)
+    kw = dict(N=prm.N, q=tuple(prm.q), p=tuple(prm.p), F=prm.F, K=prm.K, r=prm.r, dnum=prm.dnum,
+              layout=prm.layout)
     o = OParams(D=prm.D, **kw)
     s = bfv.secret_key(o, 0)
     sample_m = min(sample_m, o.M)
@@ -775,60 +778,15 @@ def bench_dmax(args, w) -> int:
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-unpacked", action="store_true",
-                    help="batching workload: only its unpacked batch, eager, default schedule (for counter runs)")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="plain workload only: skip the batching workload's plain / batched / packed leg")
-    ap.add_argument("--cpu-sample-m", type=int, default=0,
-                    help="model ciphertexts in the oracle's timed sample (0: the workload's default)")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--duration", type=float, default=0.0, help="serving: trace length in seconds")
-    ap.add_argument("--schedule", default="", help="single-request workloads: mode,values_per_thread,limb_group,blocks "
-                                                  "(e.g. split,16,1,512; empty keeps the session's default)")
-    ap.add_argument("--rates", default="", help="serving: comma-separated extra arrival rates (req/s)")
-    ap.add_argument("--layout", default="contiguous", choices=["contiguous", "subring"],
-                    help="single-request workloads with r = 1: slot layout of the queries")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the path shards by query group or model slice, "
-              "but no multi-GPU run is part of this benchmark", file=sys.stderr)
-        return 2
-
+def run_single(args, w, layout: str):
+    """One single-request workload in one slot layout: the JSON fields of its line (without
+    the batching leg and the CPU baseline), plus the inputs the CPU baseline samples."""
     import torch
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        return 1
-    if args.calibrate_copy:
-        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}))
-        return 0
-    w = WORKLOADS[args.workload]
-    if "requests" in w:
-        return profile_unpacked(args, w) if args.profile_unpacked else bench_batched(args, w)
-    if w.get("serving"):
-        return bench_serving(args, w)
-    if w.get("dmax"):
-        return bench_dmax(args, w)
-    if w.get("detect"):
-        return bench_detect(args, w)
     N, L, Q = w["N"], w["L"], w["Q"]
     alpha, r = w.get("alpha", 0), w.get("r", 1)
     primes = ep.default_primes(N, L + alpha)
     prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=w["F"], D=w["D"], K=w["K"], r=r,
-                    dnum=w.get("dnum", 0), layout=args.layout)
+                    dnum=w.get("dnum", 0), layout=layout)
     M = ep.ephdc_num_model_ct(prm)
     seed = args.seed
     t0 = time.perf_counter()
@@ -875,7 +833,7 @@ def main() -> int:
     want = np.where(want > 32768, want - 65537, want)
     if not np.array_equal(scores, want):
         print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
-        return 3
+        return None
 
     sess.profile(True)
     stream = torch.cuda.current_stream()
@@ -905,6 +863,10 @@ def main() -> int:
     kern, stage = ("k_mac", "mac") if split else ("k_score", "score")
     modmuls, k_ms = per_launch(kern, stage)
     achieved = modmuls / (k_ms * 1e-3)
+    # subring layout with the n-point kernels (n = N/K' of 256..1024 under N = 2048..8192)
+    Kp = 1 << (w["K"] - 1).bit_length() if layout == "subring" else w["K"]
+    n_sub = N // Kp
+    sub = layout == "subring" and N in (2048, 4096, 8192) and 256 <= n_sub <= 1024 and n_sub < N
 
     def hbm(traffic, ms):
         """Achieved HBM bandwidth of a launch moving `traffic` bytes in `ms`, and its fraction of 8 TB/s."""
@@ -927,7 +889,7 @@ def main() -> int:
         "config": {"workload": f"{args.workload}: {w['desc']}", "queries_per_step": Q, "groups": G,
                    "queries_per_ciphertext": ep.ephdc_queries_per_ct(prm),
                    "model_ciphertexts": M, "rotations_per_group": int(math.log2(r)),
-                   "schedule": "split" if split else "fused"},
+                   "layout": layout, "schedule": ("subring n=%d" % n_sub) if sub else ("split" if split else "fused")},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
@@ -940,7 +902,26 @@ def main() -> int:
                      **hbm(recorded_traffic(kern, args.workload), k_ms),
                      "valu_issue": recorded_valu_issue(kern, args.workload)},
     }
-    if split:
+    if sub:
+        # the streaming MAC is bound by HBM: algorithmic bytes = the model once, the n-point
+        # transforms of every (group, plaintext, limb) once, and the score sums once
+        nl = prof["mac"][1] // args.steps
+        mac_bytes = (M * 2 * L * N + G * M * L * n_sub + G * 2 * L * N) * 4.0 / nl
+        mac_ms = prof["mac"][0] / prof["mac"][1]
+        tr = recorded_traffic("k_mac_sub", args.workload)
+        result["roofline"] = {"bound": "hbm", "kernel": "k_mac_sub", "achieved": round(mac_bytes / (mac_ms * 1e-3) / 1e9, 1),
+                              "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                              "frac": round(mac_bytes / (mac_ms * 1e-3) / HBM_PEAK, 4), "traffic": tr,
+                              "algorithmic_bytes": mac_bytes, "avg_launch_ms": round(mac_ms, 4)}
+        enc_ms = prof["encode_pt"][0] / prof["encode_pt"][1]
+        enc_ops = G * M * (1 + L) * transform_mults(n_sub) / nl
+        result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_sub",
+                                        "achieved": round(enc_ops / (enc_ms * 1e-3) / 1e12, 4),
+                                        "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
+                                        "frac": round(enc_ops / (enc_ms * 1e-3) / MODMUL_PEAK, 4),
+                                        "per_launch_modmuls": enc_ops, "avg_launch_ms": round(enc_ms, 4),
+                                        "traffic": recorded_traffic("k_encode_sub", args.workload)}
+    elif split:
         e_ops, e_ms = per_launch("k_encode_pt", "encode_pt")
         result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_pt",
                                         "achieved": round(e_ops / (e_ms * 1e-3) / 1e12, 4),
@@ -960,6 +941,72 @@ def main() -> int:
                                   "avg_launch_ms": round(h_ms, 4)}
     sess.close()
     del d_x, d_base, d_hv, d_out
+    return result, prm, x, base, C
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-unpacked", action="store_true",
+                    help="batching workload: only its unpacked batch, eager, default schedule (for counter runs)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="plain workload only: skip the batching workload's plain / batched / packed leg")
+    ap.add_argument("--cpu-sample-m", type=int, default=0,
+                    help="model ciphertexts in the oracle's timed sample (0: the workload's default)")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--duration", type=float, default=0.0, help="serving: trace length in seconds")
+    ap.add_argument("--schedule", default="", help="single-request workloads: mode,values_per_thread,limb_group,blocks "
+                                                  "(e.g. split,16,1,512; empty keeps the session's default)")
+    ap.add_argument("--rates", default="", help="serving: comma-separated extra arrival rates (req/s)")
+    ap.add_argument("--layout", default="auto", choices=["auto", "contiguous", "subring"],
+                    help="single-request workloads: slot layout of the queries (auto: the N = 8192 "
+                         "workload in the subring layout, with the contiguous layout measured beside it)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path shards by query group or model slice, "
+              "but no multi-GPU run is part of this benchmark", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}))
+        return 0
+    w = WORKLOADS[args.workload]
+    if "requests" in w:
+        return profile_unpacked(args, w) if args.profile_unpacked else bench_batched(args, w)
+    if w.get("serving"):
+        return bench_serving(args, w)
+    if w.get("dmax"):
+        return bench_dmax(args, w)
+    if w.get("detect"):
+        return bench_detect(args, w)
+    layouts = {"auto": ["subring", "contiguous"] if args.workload == "c2" else ["contiguous"]}.get(
+        args.layout, [args.layout])
+    runs = []
+    for lay in layouts:
+        r = run_single(args, w, lay)
+        if r is None:
+            return 3
+        runs.append(r)
+    result, prm, x, base, C = runs[0]
+    for other, *_ in runs[1:]:
+        keep = ("value", "ms_per_step", "latency_ms", "stages_ms_per_step", "roofline", "roofline_encode_pt",
+                "roofline_hdc", "config")
+        result["layout_" + other["config"]["layout"]] = {k: other[k] for k in keep if k in other}
     if args.workload == "c2" and not args.no_batched:
         # the metric's other half: the batching workload at the same N and limbs, its requests
         # scored one after another (plain), as one unpacked batch and as one packed batch

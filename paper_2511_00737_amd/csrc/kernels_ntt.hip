@@ -592,6 +592,11 @@ constexpr bool mac_prefetch() {
 // over log2 N bits of k < n is K' times the one over log2 n bits), and only the n^-1
 // constants differ (pct_sub).  One wave runs one n-point transform (n = 64 E), all of its
 // exchanges inside the wave's own LDS region.
+//
+// Two kernels: k_encode_sub turns each query plaintext into its L transformed n-point
+// vectors (a.pt[g][m - m_base][l][y], lazy in [0, 4 q_l), weighted by the scaling op), and
+// k_mac_sub streams the model once: a work item owns a block of evaluation positions of one
+// limb for up to four query groups.
 
 // LDS offset of the wave-local exchange buffer inside an exchange plan (see exchange()).
 template <int LOGN, int LE>
@@ -599,21 +604,40 @@ constexpr int local_exchange_offset() {
   return LdsPlan<LOGN, LE>::three ? 2 * Shape<LOGN, LE>::PADN : Shape<LOGN, LE>::PADN;
 }
 
-// Batch encoding: work item (split, g); wave w of the workgroup encodes plaintexts
-// m0 + w, m0 + w + waves, ... of the split into a.pt[g][m - m_base][0 .. n).
+// Values per thread of the n-point batch-encoding transforms: one wave per transform up to
+// n = 1024 (E = n/64), 16 values per thread above.
+constexpr int sub_le(int ls) { return ls <= 10 ? ls - 6 : 4; }
+
+// Threads of one batch-encoding workgroup: four one-wave transforms, or one transform of
+// n/E threads (n = 2048, 4096) whose first exchanges cross waves.
 template <int LOGn, int LEs>
-__global__ __launch_bounds__(256) void k_encode_sub(ScoreArgs a) {
+constexpr int encode_sub_threads() {
+  return Shape<LOGn, LEs>::T == 64 ? 256 : Shape<LOGn, LEs>::T;
+}
+template <int LOGn, int LEs>
+constexpr size_t encode_sub_lds_bytes() {
   using S = Shape<LOGn, LEs>;
-  static_assert(S::T == 64, "one wave per transform");
+  return (S::T == 64 ? 4 * S::PADN : LdsPlan<LOGn, LEs>::exchange_words) * sizeof(uint32_t);
+}
+
+// Work item (split, g); transform j of the workgroup takes plaintexts m0 + j, m0 + j + TPW, ...
+template <int LOGn, int LEs>
+__global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_sub(ScoreArgs a) {
+  using S = Shape<LOGn, LEs>;
   constexpr int E = S::E, n = S::N;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  LdsBufs b{0, wave * S::PADN - local_exchange_offset<LOGn, LEs>()};
+  constexpr bool one_wave = S::T == 64;
+  constexpr int TPW = encode_sub_threads<LOGn, LEs>() / S::T;  // transforms per workgroup
+  const int lane = threadIdx.x % S::T, wave = threadIdx.x / S::T;
+  LdsBufs b{0, one_wave ? wave * S::PADN - local_exchange_offset<LOGn, LEs>() : 0};
+  const int nwave = TPW;
   const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
   const uint32_t m0 = a.m_base + split * a.mchunk;
   const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
-  const uint32_t t = a.pct_sub.m;
+  const uint32_t t = a.pct_sub.m, L = a.L;
+  const uint32_t N = (uint32_t)n << a.sub_logk;
   const int8_t* hvg = a.hv + (size_t)g * a.B + (uint32_t)lane * E;  // queries g*B + lane*E + i
-  int32_t* dst = a.pt + ((size_t)g * a.m_len + (m0 - a.m_base)) * n;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + ((size_t)g * a.m_len + (m0 - a.m_base)) * L * n;
+  const uint32_t lo = (uint32_t)lane * E * 4u;  // byte offset of the lane's outputs
   for (uint32_t m = m0 + wave; m < m1; m += nwave) {
     uint32_t w[E / 4];
     const int8_t* src = hvg + (size_t)m * a.hv_stride;
@@ -633,113 +657,124 @@ __global__ __launch_bounds__(256) void k_encode_sub(ScoreArgs a) {
       v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));                 // h mod t
     }
     ntt_inverse<LOGn, LEs, true, true>(v, lane, a.inv_t, a.pct_sub, b);
-    int32_t* d = dst + (size_t)(m - m0) * n;
+    int32_t c[E];  // centred lift, coefficient layout lane + i*T
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const uint32_t mu = csub(v[i], t);
-      d[lane + i * 64] = mu > (t >> 1) ? (int32_t)mu - (int32_t)t : (int32_t)mu;
+      c[i] = mu > (t >> 1) ? (int32_t)mu - (int32_t)t : (int32_t)mu;
+    }
+    uint32_t* d = dst + (size_t)(m - m0) * L * n;
+    for (uint32_t l = 0; l < L; ++l) {
+      const PrimeConst pc = a.pcs[l];
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = pc.m + (uint32_t)c[i];  // |c| <= t/2: in [0, 2m), = c mod m
+      ntt_forward<LOGn, LEs, false, true>(v, lane, a.fwd_tw + (size_t)l * N, pc, b);
+      apply_scale(v, a.scale, m, l, pc);
+      uint32_t* dl = d + (size_t)l * n;
+#pragma unroll
+      for (int i = 0; i < E; i += 4)
+        st_at(reinterpret_cast<uint4*>(dl), lo + 4u * i, make_uint4(v[i], v[i + 1], v[i + 2], v[i + 3]));
     }
   }
 }
 
-// Word of n-point output y in a wave's LDS region (one pad word per 16 spreads the banks).
-__device__ __forceinline__ uint32_t sub_slot(uint32_t y) { return y + (y >> 4); }
+// MAC: work item (position block, limb, group tile, split).  Thread tid owns evaluation
+// positions x0 = blk*512 + 2*tid and x0 + 1, which share the n-point value y = x0 >> log2 K'
+// (K' >= 2), for the up to four groups of its tile: per model ciphertext two words of c0
+// and c1 and one transformed value per group, accumulated in 64-bit lazy sums as in
+// mac_item64 (folded every second plaintext).  The loads run kDepth ciphertexts ahead.
+constexpr int kSubGroups = 4, kSubThreads = 256, kSubDepth = 4;
 
-// MAC: work item (split, g, limb) as in k_mac with one limb per item; the workgroup's
-// threads own 8 consecutive evaluation positions each.  Per round, wave w transforms
-// plaintext r0 + w into its LDS region; after a barrier every thread accumulates the round's
-// plaintexts at its positions (64-bit lazy sums as in mac_item64); a second barrier frees
-// the regions for the next round.
-template <int LOGN, int LOGn, int LEs, bool SC>
-__global__ __launch_bounds__((1 << LOGN) >> 3) void k_mac_sub(ScoreArgs a) {
-  using Ss = Shape<LOGn, LEs>;
-  static_assert(Ss::T == 64, "one wave per transform");
-  constexpr int N = 1 << LOGN, E = 8, T = N / E, NW = T / 64, Es = Ss::E, n = Ss::N;
-  constexpr int LOGKP = LOGN - LOGn;
-  constexpr int NY = LOGKP >= 3 ? 1 : (E >> LOGKP);  // distinct n-point outputs per thread
-  const uint32_t wi = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
-  if (wi == 0xFFFFFFFFu) return;  // a slot past the last item: the whole workgroup leaves
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  LdsBufs b{0, wave * Ss::PADN - local_exchange_offset<LOGn, LEs>()};
-  uint32_t g, split;
-  const MacItem it = single_item<LOGN, 1>(a, wi, g, split);
-  const uint32_t l = it.l0;
+template <int LOGKP>
+__global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
+  static_assert(LOGKP >= 1, "two positions per thread share one n-point value");
+  const uint32_t N = (1u << a.sub_logn) << LOGKP, n = 1u << a.sub_logn, L = a.L;
+  const uint32_t nblk = N / (2 * kSubThreads), ntile = (a.G + kSubGroups - 1) / kSubGroups;
+  uint32_t w = blockIdx.x;
+  const uint32_t blk = w % nblk;
+  w /= nblk;
+  const uint32_t l = w % L;
+  w /= L;
+  const uint32_t tile = w % ntile, split = w / ntile;
+  const uint32_t g0 = tile * kSubGroups, ng = min((uint32_t)kSubGroups, a.G - g0);
+  const uint32_t m0 = a.m_base + split * a.mchunk;
+  const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
+  const uint32_t x0 = blk * 2 * kSubThreads + 2 * threadIdx.x, y = x0 >> LOGKP;
   const PrimeConst pc = a.pcs[l];
-  const int32_t* pt = a.pt + ((size_t)g * a.m_len + (it.m0 - a.m_base)) * n;
-  const uint32_t* tw = a.fwd_tw + (size_t)l * N;
-  const uint32_t eo = (uint32_t)tid * E * 4u;
-  const size_t cstride = (size_t)it.L * N;  // words from c0 to c1 of one ciphertext
+  // model words of (m, c): model + ((m * 2 + c) * L + l) * N + x0
+  const uint32_t* mod = a.model + (size_t)l * N + x0;
+  const size_t mstride = (size_t)2 * L * N, cstride = (size_t)L * N;
+  // transformed values of (g, m): pt + ((g * m_len + m - m_base) * L + l) * n + y
+  const uint32_t* pv = reinterpret_cast<const uint32_t*>(a.pt) + (size_t)l * n + y;
+  const size_t gstride = (size_t)a.m_len * L * n, pmstride = (size_t)L * n;
 
-  uint64_t acc[2][E];
+  uint64_t acc[kSubGroups][2][2];
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const uint32_t* src = it.slot + ((size_t)c * it.L + l) * N;
+  for (int k = 0; k < kSubGroups; ++k)
 #pragma unroll
-    for (int i = 0; i < E; ++i)
-      acc[c][i] = a.accumulate ? mont_mul(ld_at(src, eo + 4u * i), pc.r2, pc.m, pc.mneg_inv) : 0u;
-  }
-  // model values of the next plaintext, requested one plaintext ahead
-  uint32_t n0[E], n1[E];
-  auto load_model = [&](uint32_t m) {
-    const uint32_t* ct0 = it.model + ((size_t)m * 2 * it.L + l) * N;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      n0[i] = ld_at(ct0, eo + 4u * i);
-      n1[i] = ld_at(ct0 + cstride, eo + 4u * i);
+    for (int c = 0; c < 2; ++c) {
+      uint32_t s0 = 0, s1 = 0;
+      if (a.accumulate && (uint32_t)k < ng) {
+        const uint32_t* src = a.partial + (((size_t)(g0 + k) * a.S + split) * 2 * L + (size_t)c * L + l) * N + x0;
+        const uint2 s = *reinterpret_cast<const uint2*>(src);
+        s0 = mont_mul(s.x, pc.r2, pc.m, pc.mneg_inv);
+        s1 = mont_mul(s.y, pc.r2, pc.m, pc.mneg_inv);
+      }
+      acc[k][c][0] = s0;
+      acc[k][c][1] = s1;
     }
+
+  struct Stage {
+    uint2 c0, c1;
+    uint32_t p[kSubGroups];
   };
-  if (it.m0 < it.m1) load_model(it.m0);
-  uint32_t since_fold = 0;
-  for (uint32_t r0 = it.m0; r0 < it.m1; r0 += NW) {
-    const uint32_t m = r0 + wave;
-    if (m < it.m1) {
-      const int32_t* ptm = pt + (size_t)(m - it.m0) * n;
-      uint32_t v[Es];
+  auto load = [&](Stage& s, uint32_t m) {
+    const uint32_t* mm = mod + (size_t)m * mstride;
+    s.c0 = *reinterpret_cast<const uint2*>(mm);
+    s.c1 = *reinterpret_cast<const uint2*>(mm + cstride);
+    const uint32_t* pm = pv + (size_t)(m - a.m_base) * pmstride;
 #pragma unroll
-      for (int i = 0; i < Es; ++i) v[i] = pc.m + (uint32_t)ld_at(ptm, 4u * (uint32_t)(lane + i * 64));
-      ntt_forward<LOGn, LEs, false, true>(v, lane, tw, pc, b);
-      if constexpr (SC) apply_scale(v, it.scale, m, l, pc);
-      uint32_t* region = ephdc_lds + wave * Ss::PADN;
+    for (int k = 0; k < kSubGroups; ++k) s.p[k] = (uint32_t)k < ng ? pm[(size_t)(g0 + k) * gstride] : 0u;
+  };
+  Stage ring[kSubDepth];
 #pragma unroll
-      for (int i = 0; i < Es; ++i) region[sub_slot((uint32_t)lane * Es + i)] = v[i];
-    }
-    lds_barrier();
-    const uint32_t nr = min((uint32_t)NW, it.m1 - r0);
-    for (uint32_t j = 0; j < nr; ++j) {
-      const uint32_t mm = r0 + j;
-      uint32_t c0[E], c1[E];
+  for (int d = 0; d < kSubDepth; ++d)
+    if (m0 + d < m1) load(ring[d], m0 + d);
+  for (uint32_t mb = m0; mb < m1; mb += kSubDepth) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        c0[i] = n0[i];
-        c1[i] = n1[i];
-      }
-      if (mm + 1 < it.m1) load_model(mm + 1);
-      const uint32_t* region = ephdc_lds + j * Ss::PADN;
-      uint32_t p[NY];
+    for (int d = 0; d < kSubDepth; ++d) {
+      const uint32_t m = mb + d;
+      if (m < m1) {
+        const Stage s = ring[d];
+        if (m + kSubDepth < m1) load(ring[d], m + kSubDepth);
 #pragma unroll
-      for (int k = 0; k < NY; ++k) p[k] = region[sub_slot(((uint32_t)tid * E + (uint32_t)k * (E / NY)) >> LOGKP)];
+        for (int k = 0; k < kSubGroups; ++k) {
+          acc[k][0][0] += (uint64_t)s.c0.x * s.p[k];
+          acc[k][0][1] += (uint64_t)s.c0.y * s.p[k];
+          acc[k][1][0] += (uint64_t)s.c1.x * s.p[k];
+          acc[k][1][1] += (uint64_t)s.c1.y * s.p[k];
+        }
+        if (d & 1) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
-        const uint32_t pv = p[i / (E / NY)];
-        acc[0][i] += (uint64_t)c0[i] * pv;
-        acc[1][i] += (uint64_t)c1[i] * pv;
-      }
-      if (++since_fold == 2) {
-        since_fold = 0;
+          for (int k = 0; k < kSubGroups; ++k)
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-          acc[0][i] = fold64(acc[0][i], pc.r1);
-          acc[1][i] = fold64(acc[1][i], pc.r1);
+            for (int c = 0; c < 2; ++c) {
+              acc[k][c][0] = fold64(acc[k][c][0], pc.r1);
+              acc[k][c][1] = fold64(acc[k][c][1], pc.r1);
+            }
         }
       }
     }
-    lds_barrier();
   }
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    uint32_t* dst = it.slot + ((size_t)c * it.L + l) * N;
+  for (int k = 0; k < kSubGroups; ++k) {
+    if ((uint32_t)k >= ng) break;
 #pragma unroll
-    for (int i = 0; i < E; ++i) st_at(dst, eo + 4u * i, redc64(fold64(acc[c][i], pc.r1), pc.m, pc.mneg_inv));
+    for (int c = 0; c < 2; ++c) {
+      uint32_t* dst = a.partial + (((size_t)(g0 + k) * a.S + split) * 2 * L + (size_t)c * L + l) * N + x0;
+      *reinterpret_cast<uint2*>(dst) = make_uint2(redc64(fold64(acc[k][c][0], pc.r1), pc.m, pc.mneg_inv),
+                                                  redc64(fold64(acc[k][c][1], pc.r1), pc.m, pc.mneg_inv));
+    }
   }
 }
 
@@ -962,30 +997,12 @@ static hipError_t prepare_shape() {
   return e;
 }
 
-// The subring kernels: n-point shapes (one wave per transform) under each N of the MAC.
-template <int LN, int LS>
-static hipError_t prepare_sub_mac() {
-  if constexpr (LS < LN) {
-    const int bytes = (int)(((1 << LN) / 8 / 64) * Shape<LS, LS - 6>::PADN * sizeof(uint32_t));
-    hipError_t e = hipFuncSetAttribute((const void*)k_mac_sub<LN, LS, LS - 6, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_mac_sub<LN, LS, LS - 6, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              bytes);
-    return e;
-  } else {
-    return hipSuccess;
-  }
-}
-
+// The subring batch-encoding kernels (one wave per n-point transform).
 template <int LS>
 static hipError_t prepare_sub() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_encode_sub<LS, LS - 6>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(4 * Shape<LS, LS - 6>::PADN * sizeof(uint32_t)));
-  if (e == hipSuccess) e = prepare_sub_mac<11, LS>();
-  if (e == hipSuccess) e = prepare_sub_mac<12, LS>();
-  if (e == hipSuccess) e = prepare_sub_mac<13, LS>();
-  return e;
+  constexpr int LE = sub_le(LS);
+  return hipFuncSetAttribute((const void*)k_encode_sub<LS, LE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)encode_sub_lds_bytes<LS, LE>());
 }
 
 hipError_t prepare_kernels() {
@@ -995,6 +1012,8 @@ hipError_t prepare_kernels() {
     hipError_t e = prepare_sub<8>();
     if (e == hipSuccess) e = prepare_sub<9>();
     if (e == hipSuccess) e = prepare_sub<10>();
+    if (e == hipSuccess) e = prepare_sub<11>();
+    if (e == hipSuccess) e = prepare_sub<12>();
     if (e == hipSuccess) e = prepare_shape<11, 3>();
     if (e == hipSuccess) e = prepare_shape<12, 3>();
     if (e == hipSuccess) e = prepare_shape<13, 3>();
@@ -1121,7 +1140,7 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
 }
 
 bool subring_kernels(int logn, int sub_logn) {
-  return logn >= 11 && logn <= 13 && sub_logn >= 8 && sub_logn <= 10 && sub_logn < logn;
+  return logn >= 11 && logn <= 13 && sub_logn >= 8 && sub_logn <= 12 && sub_logn < logn;
 }
 
 template <class F>
@@ -1130,6 +1149,8 @@ hipError_t dispatch_sub(int sub_logn, F&& f) {
     case 8: return f(std::integral_constant<int, 8>{});
     case 9: return f(std::integral_constant<int, 9>{});
     case 10: return f(std::integral_constant<int, 10>{});
+    case 11: return f(std::integral_constant<int, 11>{});
+    case 12: return f(std::integral_constant<int, 12>{});
     default: return hipErrorInvalidValue;
   }
 }
@@ -1137,43 +1158,24 @@ hipError_t dispatch_sub(int sub_logn, F&& f) {
 hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
   return dispatch_sub(sub_logn, [&](auto lc) {
-    constexpr int LS = decltype(lc)::value;
-    using S = Shape<LS, LS - 6>;
-    k_encode_sub<LS, LS - 6><<<dim3(nblocks), dim3(256), 4 * S::PADN * sizeof(uint32_t), st>>>(a);
+    constexpr int LS = decltype(lc)::value, LE = sub_le(LS);
+    k_encode_sub<LS, LE><<<dim3(nblocks), dim3(encode_sub_threads<LS, LE>()), encode_sub_lds_bytes<LS, LE>(), st>>>(a);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
+hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
   if (!subring_kernels(logn, sub_logn)) return hipErrorInvalidValue;
-  ScoreArgs a = a0;
-  const XcdMap xm = make_xcd_map(nblocks);
-  a.xcd = xm.on;
-  a.nitems = nblocks;
-  const bool sc = a.scale.pow != nullptr;
-  return dispatch_sub(sub_logn, [&](auto lc) -> hipError_t {
-    constexpr int LS = decltype(lc)::value;
-    using S = Shape<LS, LS - 6>;
-    auto go = [&](auto lnc) -> hipError_t {
-      constexpr int LN = decltype(lnc)::value;
-      if constexpr (LS < LN) {
-        constexpr int T = (1 << LN) / 8;
-        const size_t sh = (size_t)(T / 64) * S::PADN * sizeof(uint32_t);
-        if (sc) k_mac_sub<LN, LS, LS - 6, true><<<dim3(xm.slots()), dim3(T), sh, st>>>(a);
-        else k_mac_sub<LN, LS, LS - 6, false><<<dim3(xm.slots()), dim3(T), sh, st>>>(a);
-        return hipGetLastError();
-      } else {
-        return hipErrorInvalidValue;
-      }
-    };
-    switch (logn) {
-      case 11: return go(std::integral_constant<int, 11>{});
-      case 12: return go(std::integral_constant<int, 12>{});
-      case 13: return go(std::integral_constant<int, 13>{});
-      default: return hipErrorInvalidValue;
-    }
-  });
+  switch (logn - sub_logn) {
+    case 1: k_mac_sub<1><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
+    case 2: k_mac_sub<2><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
+    case 3: k_mac_sub<3><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
+    case 4: k_mac_sub<4><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
+    case 5: k_mac_sub<5><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S_,

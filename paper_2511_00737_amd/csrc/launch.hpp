@@ -43,9 +43,10 @@ struct ScoreArgs {
   // XCD-aware order of the MAC / fused work items (see XcdMap); xcd = 0: block = item
   uint32_t xcd, nitems;
   ScaleOp scale;
-  // subring layout (sub_logn > 0): plaintexts are n = 2^sub_logn coefficients p~ of
-  // p(X) = p~(X^(N/n)), stored [G][m_len][n]; pct_sub holds the n-point constants of t
-  uint32_t sub_logn;
+  // subring layout (sub_logn > 0): query plaintexts p(X) = p~(X^K'), K' = 2^sub_logk, of
+  // n = 2^sub_logn coefficients; pt then holds their n-point transforms [G][m_len][L][n];
+  // pct_sub holds the n-point constants of t
+  uint32_t sub_logn, sub_logk;
   PrimeConst pct_sub;
 };
 
@@ -202,7 +203,8 @@ hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t n
 // split path: batch-encode every (g, m) plaintext of the launch into a.pt, then MAC
 hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
-// subring layout: n-point batch encoding (G x splits items) and MAC (G x S x L items)
+// subring layout: batch encoding with the n-point transforms of every limb (G x splits
+// items), and the streaming MAC (position blocks x L x group tiles x S items)
 bool subring_kernels(int logn, int sub_logn);
 hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);

@@ -112,6 +112,7 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   a.accumulate = 0;
   a.scale = scale_op(s);
   a.sub_logn = s->sub_logn;
+  a.sub_logk = s->sub_logn ? (uint32_t)P.logn - s->sub_logn : 0;
   a.pct_sub = s->pct_sub;
   return a;
 }
@@ -152,22 +153,24 @@ hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, size_t
   return hipSuccess;
 }
 
-// Subring layout with n-point kernels: the same chunking as score_split with plaintexts of
-// n words (a workspace that holds c N-word plaintexts holds c*N/n of them) and MAC items
-// of one limb each.
+// Subring layout: the batch-encoding kernel writes each query plaintext's n-point
+// transforms for every limb (L*n words; a workspace that holds c N-word plaintexts holds
+// c*N/(L*n) of them), then the streaming MAC reads the model once per chunk: work items of
+// 512 evaluation positions x one limb x up to four groups x one split of the chunk.
 hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_cap, Schedule& sc, hipStream_t hs) {
   const ParamSet& P = s->P;
   const uint32_t M = P.M(), n = 1u << s->sub_logn;
   sc.G = P.G(Q);
-  const uint32_t per = sc.G * P.L;
-  sc.S = std::min(M, std::max<uint32_t>(1, (s->target_blocks + per - 1) / per));
-  sc.mchunk = (M + sc.S - 1) / sc.S;
-  sc.S = (M + sc.mchunk - 1) / sc.mchunk;
-  a.S = sc.S;
-  a.NLG = P.L;
-  const size_t cap = pt_cap * (P.N / n);
+  const uint32_t tiles = (sc.G + 3) / 4, per = (P.N / 512) * P.L * tiles;
+  constexpr uint32_t kMacBlocks = 2048, kEncodeBlocks = 2048;
+  uint32_t S = std::max<uint32_t>(1, (kMacBlocks + per - 1) / per);
+  S = std::min({S, M, std::max<uint32_t>(1, kMaxBlocks / sc.G)});
+  const size_t cap = pt_cap * P.N / ((size_t)P.L * n);
   const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, cap / sc.G));
-  constexpr uint32_t kEncodeBlocks = 2048;  // 4 waves each: 8 per SIMD across the chip
+  // the splits of every chunk cover the chunk; S is the same for every chunk
+  S = std::min(S, mc);
+  sc.S = S;
+  a.S = S;
   for (uint32_t base = 0; base < M; base += mc) {
     const uint32_t len = std::min(mc, M - base);
     ScoreArgs c = a;
@@ -181,9 +184,9 @@ hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_
     hipError_t e = launch_encode_sub((int)s->sub_logn, c, sc.G * Se, hs);
     if (e != hipSuccess) return e;
     timed_end(s, kStEncodePt, t0, hs);
-    c.mchunk = (len + sc.S - 1) / sc.S;
+    c.mchunk = (len + S - 1) / S;
     t0 = timed_begin(s, hs);
-    e = launch_mac_sub(P.logn, (int)s->sub_logn, c, sc.G * sc.S * P.L, hs);
+    e = launch_mac_sub(P.logn, (int)s->sub_logn, c, per * S, hs);
     if (e != hipSuccess) return e;
     timed_end(s, kStMac, t0, hs);
   }

@@ -50,10 +50,11 @@ def score(e, model, h, stride_offset=0, chunk_bytes=0):
         s.close()
 
 
-# (N, L, K, D, Q): n = N/K' of 1024, 512 and 256 under N = 2048, 4096 and 8192; ragged
-# last groups
+# (N, L, K, D, Q): n = N/K' of 4096 and 2048 (transforms across waves), 1024, 512 and 256
+# (one wave each) under N = 2048, 4096 and 8192; ragged last groups
 CASES = [(8192, 4, 7, 70, 2500), (8192, 4, 12, 33, 1100), (8192, 4, 26, 21, 300), (4096, 3, 3, 64, 1500),
-         (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100), (2048, 2, 5, 31, 600)]
+         (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100), (2048, 2, 5, 31, 600), (8192, 4, 2, 24, 5000),
+         (4096, 3, 2, 40, 2100)]
 
 
 @pytest.mark.parametrize("N,L,K,D,Q", CASES)
@@ -71,7 +72,8 @@ def test_subring_scores_match_oracle(N, L, K, D, Q):
     assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))
 
 
-@pytest.mark.parametrize("N,L,K,D,Q", [(8192, 4, 7, 70, 2500), (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100)])
+@pytest.mark.parametrize("N,L,K,D,Q", [(8192, 4, 7, 70, 2500), (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100),
+                                       (8192, 4, 2, 24, 5000)])
 def test_subring_kernels_equal_the_n_point_kernels(N, L, K, D, Q):
     """The same session and queries through the N-point kernels (hypervectors at an odd
     byte offset) give the same ciphertexts, and so does a plaintext chunk of one plaintext
