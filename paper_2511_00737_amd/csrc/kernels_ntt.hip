@@ -594,7 +594,7 @@ constexpr bool mac_prefetch() {
 // exchanges inside the wave's own LDS region.
 //
 // Two kernels: k_encode_sub turns each query plaintext into its L transformed n-point
-// vectors (a.pt[g][m - m_base][l][y], lazy in [0, 4 q_l), weighted by the scaling op), and
+// vectors (a.pt[m - m_base][l][g][y], lazy in [0, 4 q_l), weighted by the scaling op), and
 // k_mac_sub streams the model once: a work item owns a block of evaluation positions of one
 // limb for up to four query groups.
 
@@ -636,7 +636,8 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   const uint32_t t = a.pct_sub.m, L = a.L;
   const uint32_t N = (uint32_t)n << a.sub_logk;
   const int8_t* hvg = a.hv + (size_t)g * a.B + (uint32_t)lane * E;  // queries g*B + lane*E + i
-  uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + ((size_t)g * a.m_len + (m0 - a.m_base)) * L * n;
+  // transformed plaintexts of the chunk: [m - m_base][l][g][y]
+  uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + ((size_t)(m0 - a.m_base) * L * a.G + g) * n;
   const uint32_t lo = (uint32_t)lane * E * 4u;  // byte offset of the lane's outputs
   for (uint32_t m = m0 + wave; m < m1; m += nwave) {
     uint32_t w[E / 4];
@@ -663,14 +664,14 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
       const uint32_t mu = csub(v[i], t);
       c[i] = mu > (t >> 1) ? (int32_t)mu - (int32_t)t : (int32_t)mu;
     }
-    uint32_t* d = dst + (size_t)(m - m0) * L * n;
+    uint32_t* d = dst + (size_t)(m - m0) * L * a.G * n;
     for (uint32_t l = 0; l < L; ++l) {
       const PrimeConst pc = a.pcs[l];
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = pc.m + (uint32_t)c[i];  // |c| <= t/2: in [0, 2m), = c mod m
       ntt_forward<LOGn, LEs, false, true>(v, lane, a.fwd_tw + (size_t)l * N, pc, b);
       apply_scale(v, a.scale, m, l, pc);
-      uint32_t* dl = d + (size_t)l * n;
+      uint32_t* dl = d + (size_t)l * a.G * n;
 #pragma unroll
       for (int i = 0; i < E; i += 4)
         st_at(reinterpret_cast<uint4*>(dl), lo + 4u * i, make_uint4(v[i], v[i + 1], v[i + 2], v[i + 3]));
@@ -704,9 +705,9 @@ __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
   // model words of (m, c): model + ((m * 2 + c) * L + l) * N + x0
   const uint32_t* mod = a.model + (size_t)l * N + x0;
   const size_t mstride = (size_t)2 * L * N, cstride = (size_t)L * N;
-  // transformed values of (g, m): pt + ((g * m_len + m - m_base) * L + l) * n + y
-  const uint32_t* pv = reinterpret_cast<const uint32_t*>(a.pt) + (size_t)l * n + y;
-  const size_t gstride = (size_t)a.m_len * L * n, pmstride = (size_t)L * n;
+  // transformed values of (g, m): pt + (((m - m_base) * L + l) * G + g) * n + y
+  const uint32_t* pv = reinterpret_cast<const uint32_t*>(a.pt) + ((size_t)l * a.G + g0) * n + y;
+  const size_t gstride = n, pmstride = (size_t)L * a.G * n;
 
   uint64_t acc[kSubGroups][2][2];
 #pragma unroll
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
     s.c1 = *reinterpret_cast<const uint2*>(mm + cstride);
     const uint32_t* pm = pv + (size_t)(m - a.m_base) * pmstride;
 #pragma unroll
-    for (int k = 0; k < kSubGroups; ++k) s.p[k] = (uint32_t)k < ng ? pm[(size_t)(g0 + k) * gstride] : 0u;
+    for (int k = 0; k < kSubGroups; ++k) s.p[k] = (uint32_t)k < ng ? pm[(size_t)k * gstride] : 0u;
   };
   Stage ring[kSubDepth];
 #pragma unroll
@@ -1162,6 +1163,18 @@ hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks,
     k_encode_sub<LS, LE><<<dim3(nblocks), dim3(encode_sub_threads<LS, LE>()), encode_sub_lds_bytes<LS, LE>(), st>>>(a);
     return hipGetLastError();
   });
+}
+
+uint32_t mac_sub_resident_blocks() {
+  static const uint32_t n = [] {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_mac_sub<3>, kSubThreads, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 2048u;
+    return (uint32_t)std::max(1, per_cu * cus);
+  }();
+  return n;
 }
 
 hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {

@@ -156,14 +156,17 @@ hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, size_t
 // Subring layout: the batch-encoding kernel writes each query plaintext's n-point
 // transforms for every limb (L*n words; a workspace that holds c N-word plaintexts holds
 // c*N/(L*n) of them), then the streaming MAC reads the model once per chunk: work items of
-// 512 evaluation positions x one limb x up to four groups x one split of the chunk.
+// 512 evaluation positions x one limb x up to four groups x one split of the chunk, as many
+// as fit the device at once.
 hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_cap, Schedule& sc, hipStream_t hs) {
   const ParamSet& P = s->P;
   const uint32_t M = P.M(), n = 1u << s->sub_logn;
   sc.G = P.G(Q);
   const uint32_t tiles = (sc.G + 3) / 4, per = (P.N / 512) * P.L * tiles;
-  constexpr uint32_t kMacBlocks = 2048, kEncodeBlocks = 2048;
-  uint32_t S = std::max<uint32_t>(1, (kMacBlocks + per - 1) / per);
+  constexpr uint32_t kEncodeBlocks = 2048;
+  // one round of resident MAC workgroups (splits of equal length end together)
+  const uint32_t mac_blocks = mac_sub_resident_blocks();
+  uint32_t S = std::max<uint32_t>(1, mac_blocks / per);
   S = std::min({S, M, std::max<uint32_t>(1, kMaxBlocks / sc.G)});
   const size_t cap = pt_cap * P.N / ((size_t)P.L * n);
   const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, cap / sc.G));
