@@ -264,7 +264,7 @@ def cpu_baseline(w: dict, prm: ep.Params, x: np.ndarray, base: np.ndarray, C: np
 
 
 def bench_batched(args, w) -> int:
-    res = run_batched(args, w)
+    res = run_batched(args, w, "subring" if args.layout in ("auto", "subring") else "contiguous")
     if res is None:
         return 3
     print(json.dumps(res), flush=True)
@@ -313,11 +313,22 @@ def profile_unpacked(args, w) -> int:
     return 0
 
 
-def run_batched(args, w):
+def request_modmuls(prm, G: int) -> float:
+    """Algorithmic modular multiplications of scoring G groups of one request: the plaintexts'
+    batch encoding, their transforms into every limb and the 2L*N ct x pt products each --
+    N-point transforms in the contiguous layout, N/K'-point ones in the subring layout."""
+    N, L, M = prm.N, prm.L, ep.ephdc_num_model_ct(prm)
+    if prm.layout == "subring":
+        n = N // (1 << (prm.K - 1).bit_length())
+        return float(G) * M * ((1 + L) * transform_mults(n) + 2 * L * N)
+    return algorithmic_modmuls("k_score", N, L, G, M)
+
+
+def run_batched(args, w, layout: str = "contiguous"):
     """The batching workload: all requests scored by one graph-captured batch (persistent
     launches over a shared work list, schedule from the autotuner) against the plain form,
-    the same requests one after another through the single-request entry points.  Returns
-    the result dict (None when a check fails)."""
+    the same requests one after another through the single-request entry points, in one slot
+    layout.  Returns the result dict (None when a check fails)."""
     import torch
     N, L, F, nreq = w["N"], w["L"], w["F"], w["requests"]
     primes = ep.default_primes(N, L)
@@ -329,7 +340,7 @@ def run_batched(args, w):
     d_pool = torch.from_numpy(pool).to(dev)
     tenants = []
     for k, (K, D) in enumerate(w["models"]):
-        prm = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K)
+        prm = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K, layout=layout)
         sk, _ = ep.ephdc_keygen(prm, seed + k)
         C = synth.class_hypervectors(seed + k, K, D)
         model = ep.ephdc_encrypt_model(prm, sk, C, seed + k)
@@ -426,14 +437,12 @@ def run_batched(args, w):
     work_unpacked = 0.0
     for i in range(nreq):
         t = tenants[int(midx[i])]
-        work_unpacked += algorithmic_modmuls("k_score", N, L, ep.ephdc_num_groups(t["prm"], int(sizes[i])),
-                                             ep.ephdc_num_model_ct(t["prm"]))
+        work_unpacked += request_modmuls(t["prm"], ep.ephdc_num_groups(t["prm"], int(sizes[i])))
     work_packed = 0.0
     for k, t in enumerate(tenants):
         Qk = int(sizes[midx == k].sum())
         if Qk:
-            work_packed += algorithmic_modmuls("k_score", N, L, ep.ephdc_num_groups(t["prm"], Qk),
-                                               ep.ephdc_num_model_ct(t["prm"]))
+            work_packed += request_modmuls(t["prm"], ep.ephdc_num_groups(t["prm"], Qk))
 
     def form(wall_s, lat_ms, work, desc, **extra):
         ms = wall_s * 1e3 / len(lat_ms)
@@ -457,7 +466,7 @@ def run_batched(args, w):
                   schedule=psched, autotune_s=round(t_ptune, 1))
     packed_eager = form(eager_wall, eager_lat, work_packed, "the packed batch enqueued launch by launch, no graph")
     # HBM bytes of one unpacked run, recorded by counter runs of --profile-unpacked
-    run_traffic = recorded_traffic("batch_unpacked", "c3")
+    run_traffic = recorded_traffic("batch_unpacked", "c3") if layout == "contiguous" else None
     unpacked["roofline"]["traffic"] = run_traffic
     if run_traffic is not None:
         gbps = run_traffic / (unpacked["ms_per_step"] * 1e-3)
@@ -467,7 +476,8 @@ def run_batched(args, w):
         "metric": METRIC, "value": packed["value"], "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": packed["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"c3: {w['desc']}", "requests": nreq, "queries_per_step": total_q},
+        "config": {"workload": f"c3: {w['desc']}", "requests": nreq, "queries_per_step": total_q,
+                   "layout": layout},
         "latency_ms": packed["latency_ms"], "roofline": packed["roofline"],
         "plain": plain, "batched_unpacked": unpacked, "packed": packed, "packed_eager": packed_eager,
         "speedup_unpacked_vs_plain": round(unpacked["value"] / plain["value"], 3),
@@ -1010,11 +1020,13 @@ def main() -> int:
     if args.workload == "c2" and not args.no_batched:
         # the metric's other half: the batching workload at the same N and limbs, its requests
         # scored one after another (plain), as one unpacked batch and as one packed batch
-        b = run_batched(args, WORKLOADS["c3"])
-        if b is None:
-            return 3
-        result["batched"] = {k: b[k] for k in ("config", "plain", "batched_unpacked", "packed", "packed_eager",
-                                               "speedup_unpacked_vs_plain", "speedup_packed_vs_plain")}
+        keys = ("config", "plain", "batched_unpacked", "packed", "packed_eager", "speedup_unpacked_vs_plain",
+                "speedup_packed_vs_plain")
+        for lay in layouts:
+            b = run_batched(args, WORKLOADS["c3"], lay)
+            if b is None:
+                return 3
+            result["batched" if lay == layouts[0] else "batched_" + lay] = {k: b[k] for k in keys}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, prm, x, base, C, args.cpu_sample_m or w.get("cpu_sample_m", 256))
     print(json.dumps(result), flush=True)

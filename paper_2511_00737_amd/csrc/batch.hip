@@ -40,6 +40,22 @@ struct Part {
   int32_t* d_pt = nullptr;
 };
 
+// The requests of one subring session (model) that take the n-point kernels: scored as
+// one list of virtual groups (every group of every request, request by request), so that
+// the streaming MAC reads the model once per four groups of all of them; each request keeps
+// its own ciphertexts.
+struct SubModel {
+  const ephdc_session* s = nullptr;
+  std::vector<uint32_t> reqs;  // indices into ephdc_batch::reqs
+  std::vector<SubGroup> vg;    // per virtual group: its queries
+  std::vector<ReqDesc> rd;     // per request: its output (for the finish kernel)
+  std::vector<FinishItem> fin;
+  uint32_t VG = 0, S = 1;
+  SubGroup* d_vg = nullptr;
+  ReqDesc* d_reqs = nullptr;
+  FinishItem* d_fin = nullptr;
+};
+
 }  // namespace
 
 struct ephdc_batch {
@@ -59,6 +75,10 @@ struct ephdc_batch {
   HdcTile* d_tiles = nullptr;
   CopyRange* d_copies = nullptr;
   std::vector<Part> parts;
+  std::vector<SubModel> subs;
+  uint32_t* d_sub_partial = nullptr;  // shared by the subring models (run one after another)
+  int32_t* d_sub_pt = nullptr;
+  size_t sub_pt_bytes = 0;
   std::vector<uint32_t*> rot_ws;  // per request: rotation workspace (r > 1), else nullptr
   int device = 0;
   size_t pt_bytes = 0;            // bound on each part's plaintext chunk buffer
@@ -92,11 +112,30 @@ int batch_le(const ephdc_batch* b, int logn) { return b->vpt ? ilog2(b->vpt) : (
 // Requests of one list share N, the ciphertext primes and t (their transform tables).
 bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q && a.t == b.t; }
 
-// Splits the requests into parameter sets.
+// Requests of subring sessions whose hypervectors the n-point kernels can read (16-byte
+// aligned; packed buffers are placed aligned) go to the subring models.
+bool takes_subring(const ephdc_batch* b, const ephdc_request& rq) {
+  return rq.session->sub_logn && (b->packed || ((uintptr_t)rq.d_hv & 15) == 0);
+}
+
+// Splits the requests into parameter sets, and the subring models.
 void group_parts(ephdc_batch* b) {
   b->parts.clear();
+  b->subs.clear();
   for (uint32_t i = 0; i < b->reqs.size(); ++i) {
     const ephdc_session* s = b->reqs[i].session;
+    if (takes_subring(b, b->reqs[i])) {
+      SubModel* sm = nullptr;
+      for (SubModel& x : b->subs)
+        if (x.s == s) sm = &x;
+      if (!sm) {
+        b->subs.emplace_back();
+        sm = &b->subs.back();
+        sm->s = s;
+      }
+      sm->reqs.push_back(i);
+      continue;
+    }
     Part* pt = nullptr;
     for (Part& p : b->parts)
       if (same_chain(p.ref->P, s->P)) pt = &p;
@@ -189,6 +228,44 @@ void build_part(const ephdc_batch* b, Part& pt) {
   if (begin < pt.segs.size()) pt.chunks.emplace_back(begin, (uint32_t)pt.segs.size());
 }
 
+// Host lists of the subring models; the splits fit the plaintext chunk buffer (which holds
+// at least S transformed plaintexts of every virtual group) and the partial sums buffer is
+// sized for the largest model.  Hypervector and output pointers are filled once placed.
+void build_subs(ephdc_batch* b) {
+  b->sub_pt_bytes = 0;
+  for (SubModel& sm : b->subs) {
+    const ParamSet& P = sm.s->P;
+    const uint32_t n = 1u << sm.s->sub_logn;
+    sm.VG = 0;
+    for (uint32_t ri : sm.reqs) sm.VG += P.G(b->reqs[ri].Q);
+    const size_t per_m = (size_t)sm.VG * P.L * n * 4;  // bytes of one ciphertext's transforms
+    const size_t cap_m = std::max<size_t>(1, b->pt_bytes / per_m);
+    sm.S = (uint32_t)std::max<size_t>(1, std::min<size_t>(sub_splits(P, sm.VG), cap_m));
+    const size_t chunk_m = std::max<size_t>(sm.S, std::min<size_t>(P.M(), cap_m));
+    b->sub_pt_bytes = std::max(b->sub_pt_bytes, chunk_m * per_m);
+    sm.vg.assign(sm.VG, SubGroup{});
+    sm.rd.assign(sm.reqs.size(), ReqDesc{});
+    sm.fin.clear();
+    uint32_t v = 0;
+    for (uint32_t li = 0; li < sm.reqs.size(); ++li) {
+      const ephdc_request& rq = b->reqs[sm.reqs[li]];
+      const uint32_t G = P.G(rq.Q);
+      sm.rd[li].out = rq.d_score_ct;
+      sm.rd[li].r = 1;
+      for (uint32_t g = 0; g < G; ++g, ++v) {
+        sm.vg[v] = SubGroup{rq.d_hv ? rq.d_hv + (size_t)g * P.B() : nullptr, G * P.B(), 0};
+        sm.fin.push_back(FinishItem{li, g, v * sm.S, sm.S});
+      }
+    }
+  }
+}
+
+size_t sub_partial_words(const ephdc_batch* b) {
+  size_t w = 0;
+  for (const SubModel& sm : b->subs) w = std::max(w, (size_t)sm.VG * sm.S * 2 * sm.s->P.L * sm.s->P.N);
+  return w;
+}
+
 // HDC work and output copies.  Only the counts are needed to place the arrays; the
 // pointers are filled once the batch's block is placed.  With packing, each request writes
 // exactly its own columns [off, off + Q) of its session's buffer (the session's last request
@@ -266,6 +343,13 @@ size_t carve(ephdc_batch* b, char* base) {
       rq.d_score_ct = (uint32_t*)take(G * 2 * P.L * P.N * 4);
     }
   }
+  for (SubModel& sm : b->subs) {
+    sm.d_vg = (SubGroup*)take(sm.vg.size() * sizeof(SubGroup));
+    sm.d_reqs = (ReqDesc*)take(sm.rd.size() * sizeof(ReqDesc));
+    sm.d_fin = (FinishItem*)take(sm.fin.size() * sizeof(FinishItem));
+  }
+  b->d_sub_partial = (uint32_t*)take(sub_partial_words(b) * 4);
+  b->d_sub_pt = (int32_t*)take(b->sub_pt_bytes);
   b->rot_ws.assign(b->reqs.size(), nullptr);
   for (uint32_t i = 0; i < b->reqs.size(); ++i) {
     const ephdc_request& rq = b->reqs[i];
@@ -283,6 +367,7 @@ size_t carve(ephdc_batch* b, char* base) {
 ephdc_status plan(ephdc_batch* b, hipStream_t hs) {
   drop_graph(b);
   for (Part& pt : b->parts) build_part(b, pt);
+  build_subs(b);
   build_aux(b);  // counts only: the packed buffers are not placed yet
   const size_t need = carve(b, nullptr);
   if (need > b->mem_bytes) {
@@ -313,6 +398,15 @@ ephdc_status plan(ephdc_batch* b, hipStream_t hs) {
       e = hipMemcpyAsync(pt.d_segs, pt.segs.data(), pt.segs.size() * sizeof(Segment), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
       e = hipMemcpyAsync(pt.d_fin, pt.fin.data(), pt.fin.size() * sizeof(FinishItem), hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "work list upload");
+  }
+  build_subs(b);  // now with the placed buffers
+  for (SubModel& sm : b->subs) {
+    hipError_t e = hipMemcpyAsync(sm.d_vg, sm.vg.data(), sm.vg.size() * sizeof(SubGroup), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sm.d_reqs, sm.rd.data(), sm.rd.size() * sizeof(ReqDesc), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sm.d_fin, sm.fin.data(), sm.fin.size() * sizeof(FinishItem), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "work list upload");
   }
   build_aux(b);  // now with the placed buffers
@@ -356,6 +450,25 @@ hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
   // HDC encoding of every request that brings features, in one launch
   hipError_t e = launch_hdc_encode_list(b->d_hdc, b->d_tiles, (uint32_t)b->tiles.size(), hs);
   if (e != hipSuccess) return e;
+  // subring models: the n-point kernels over each model's virtual groups, then the output
+  // transforms of all of them (the finish kernel of the lists)
+  for (const SubModel& sm : b->subs) {
+    const ephdc_session* s = sm.s;
+    const ParamSet& P = s->P;
+    ScoreArgs a = sub_group_args(s, sm.d_vg, sm.VG, sm.S, b->d_sub_partial, b->d_sub_pt);
+    e = run_sub(s, a, b->sub_pt_bytes / (4 * (size_t)P.N), nullptr, hs);
+    if (e != hipSuccess) return e;
+    ListArgs f{};
+    f.reqs = sm.d_reqs;
+    f.fin = sm.d_fin;
+    f.nfin = (uint32_t)sm.fin.size();
+    f.L = P.L;
+    f.partial = b->d_sub_partial;
+    f.inv_tw = s->d_inv;
+    f.pcs = s->d_pc;
+    e = launch_finish_list(P.logn, f, hs);
+    if (e != hipSuccess) return e;
+  }
   for (const Part& pt : b->parts) {
     const int le = batch_le(b, pt.logn);
     ListArgs a = list_args(b, pt);
@@ -501,6 +614,7 @@ size_t batch_bytes(const ephdc_request* reqs, uint32_t n_req, size_t pt_bytes, u
                    bool packed) {
   ephdc_batch* b = new_batch(reqs, n_req, pt_bytes, mode, seg_len, packed);
   for (Part& pt : b->parts) build_part(b, pt);
+  build_subs(b);
   build_aux(b);
   const size_t need = carve(b, nullptr);
   delete b;

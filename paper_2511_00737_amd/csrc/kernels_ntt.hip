@@ -635,13 +635,15 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
   const uint32_t t = a.pct_sub.m, L = a.L;
   const uint32_t N = (uint32_t)n << a.sub_logk;
-  const int8_t* hvg = a.hv + (size_t)g * a.B + (uint32_t)lane * E;  // queries g*B + lane*E + i
+  // queries of the group (lane*E + i), rows of pitch `stride`
+  const SubGroup sg = a.vg ? a.vg[g] : SubGroup{a.hv + (size_t)g * a.B, a.hv_stride, 0};
+  const int8_t* hvg = sg.hv + (uint32_t)lane * E;
   // transformed plaintexts of the chunk: [m - m_base][l][g][y]
   uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + ((size_t)(m0 - a.m_base) * L * a.G + g) * n;
   const uint32_t lo = (uint32_t)lane * E * 4u;  // byte offset of the lane's outputs
   for (uint32_t m = m0 + wave; m < m1; m += nwave) {
     uint32_t w[E / 4];
-    const int8_t* src = hvg + (size_t)m * a.hv_stride;
+    const int8_t* src = hvg + (size_t)m * sg.stride;
     if constexpr (E == 16) {
       const uint4 q = *reinterpret_cast<const uint4*>(src);
       w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
@@ -679,7 +681,7 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   }
 }
 
-// MAC: work item (position block, limb, group tile, split).  Thread tid owns evaluation
+// MAC: work item (group tile, limb, position block, split).  Thread tid owns evaluation
 // positions x0 = blk*512 + 2*tid and x0 + 1, which share the n-point value y = x0 >> log2 K'
 // (K' >= 2), for the up to four groups of its tile: per model ciphertext two words of c0
 // and c1 and one transformed value per group, accumulated in 64-bit lazy sums as in
@@ -691,12 +693,15 @@ __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
   static_assert(LOGKP >= 1, "two positions per thread share one n-point value");
   const uint32_t N = (1u << a.sub_logn) << LOGKP, n = 1u << a.sub_logn, L = a.L;
   const uint32_t nblk = N / (2 * kSubThreads), ntile = (a.G + kSubGroups - 1) / kSubGroups;
-  uint32_t w = blockIdx.x;
-  const uint32_t blk = w % nblk;
-  w /= nblk;
+  // item order: group tile, then limb, then position block, then split -- the tiles that
+  // read one model slice are neighbours, and the XCD map runs neighbours on one XCD
+  uint32_t w = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
+  if (w == 0xFFFFFFFFu) return;  // a slot past the last item: the whole workgroup leaves
+  const uint32_t tile = w % ntile;
+  w /= ntile;
   const uint32_t l = w % L;
   w /= L;
-  const uint32_t tile = w % ntile, split = w / ntile;
+  const uint32_t blk = w % nblk, split = w / nblk;
   const uint32_t g0 = tile * kSubGroups, ng = min((uint32_t)kSubGroups, a.G - g0);
   const uint32_t m0 = a.m_base + split * a.mchunk;
   const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
@@ -1177,15 +1182,20 @@ uint32_t mac_sub_resident_blocks() {
   return n;
 }
 
-hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
+hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
   if (!subring_kernels(logn, sub_logn)) return hipErrorInvalidValue;
+  ScoreArgs a = a0;
+  const XcdMap xm = make_xcd_map(nblocks);
+  a.xcd = xm.on;
+  a.nitems = nblocks;
+  const dim3 grid(xm.slots());
   switch (logn - sub_logn) {
-    case 1: k_mac_sub<1><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
-    case 2: k_mac_sub<2><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
-    case 3: k_mac_sub<3><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
-    case 4: k_mac_sub<4><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
-    case 5: k_mac_sub<5><<<dim3(nblocks), dim3(kSubThreads), 0, st>>>(a); break;
+    case 1: k_mac_sub<1><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 2: k_mac_sub<2><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 3: k_mac_sub<3><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 4: k_mac_sub<4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 5: k_mac_sub<5><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

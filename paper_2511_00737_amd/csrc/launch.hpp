@@ -22,6 +22,13 @@ struct ScaleOp {
   }
 };
 
+// Where the queries of one (virtual) query group of the subring kernels come from: the
+// group's first column in its request's hypervectors, and their row pitch.
+struct SubGroup {
+  const int8_t* hv;
+  uint32_t stride, pad;
+};
+
 // Arguments of the fused scoring kernel (and the debug plaintext kernel).
 struct ScoreArgs {
   const uint32_t* model;    // [M][2][L][N] evaluation domain, Montgomery form
@@ -48,6 +55,7 @@ struct ScoreArgs {
   // pct_sub holds the n-point constants of t
   uint32_t sub_logn, sub_logk;
   PrimeConst pct_sub;
+  const SubGroup* vg;  // subring kernels: per group its queries (nullptr: hv + g * B, hv_stride)
 };
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin (workgroup d runs on XCD
@@ -170,6 +178,7 @@ using ephdc_dev::HdcTile;
 using ephdc_dev::KsConst;
 using ephdc_dev::ListArgs;
 using ephdc_dev::ReqDesc;
+using ephdc_dev::SubGroup;
 using ephdc_dev::Segment;
 using ephdc_dev::XcdMap;
 using ephdc_dev::RotateArgs;

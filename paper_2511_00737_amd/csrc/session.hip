@@ -158,42 +158,19 @@ hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, size_t
 // c*N/(L*n) of them), then the streaming MAC reads the model once per chunk: work items of
 // 512 evaluation positions x one limb x up to four groups x one split of the chunk, as many
 // as fit the device at once.
-hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_cap, Schedule& sc, hipStream_t hs) {
+hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_cap, size_t partial_words,
+                           Schedule& sc, hipStream_t hs) {
   const ParamSet& P = s->P;
-  const uint32_t M = P.M(), n = 1u << s->sub_logn;
   sc.G = P.G(Q);
-  const uint32_t tiles = (sc.G + 3) / 4, per = (P.N / 512) * P.L * tiles;
-  constexpr uint32_t kEncodeBlocks = 2048;
-  // one round of resident MAC workgroups (splits of equal length end together)
-  const uint32_t mac_blocks = mac_sub_resident_blocks();
-  uint32_t S = std::max<uint32_t>(1, mac_blocks / per);
-  S = std::min({S, M, std::max<uint32_t>(1, kMaxBlocks / sc.G)});
-  const size_t cap = pt_cap * P.N / ((size_t)P.L * n);
-  const uint32_t mc = (uint32_t)std::max<size_t>(1, std::min<size_t>(M, cap / sc.G));
-  // the splits of every chunk cover the chunk; S is the same for every chunk
-  S = std::min(S, mc);
-  sc.S = S;
-  a.S = S;
-  for (uint32_t base = 0; base < M; base += mc) {
-    const uint32_t len = std::min(mc, M - base);
-    ScoreArgs c = a;
-    c.m_base = base;
-    c.m_len = len;
-    c.accumulate = base > 0;
-    uint32_t Se = std::max<uint32_t>(1, std::min(len, (kEncodeBlocks + sc.G - 1) / sc.G));
-    c.mchunk = (len + Se - 1) / Se;
-    Se = (len + c.mchunk - 1) / c.mchunk;
-    hipEvent_t t0 = timed_begin(s, hs);
-    hipError_t e = launch_encode_sub((int)s->sub_logn, c, sc.G * Se, hs);
-    if (e != hipSuccess) return e;
-    timed_end(s, kStEncodePt, t0, hs);
-    c.mchunk = (len + S - 1) / S;
-    t0 = timed_begin(s, hs);
-    e = launch_mac_sub(P.logn, (int)s->sub_logn, c, per * S, hs);
-    if (e != hipSuccess) return e;
-    timed_end(s, kStMac, t0, hs);
-  }
-  return hipSuccess;
+  const uint32_t n = 1u << s->sub_logn;
+  // the splits must fit the partial sums of the workspace and the smallest chunk the
+  // plaintext buffer allows
+  const size_t cap_pt = pt_cap * P.N / ((size_t)P.L * n);
+  const size_t fit = partial_words / ((size_t)sc.G * 2 * P.L * P.N);
+  sc.S = (uint32_t)std::max<size_t>(1, std::min<size_t>({sub_splits(P, sc.G), cap_pt / sc.G, fit}));
+  a.G = sc.G;
+  a.S = sc.S;
+  return run_sub(s, a, pt_cap, s, hs);
 }
 
 uint2 shoup_pair(uint64_t w, uint32_t m) {
@@ -258,9 +235,76 @@ std::vector<uint32_t> automorphism_perms(const ParamSet& P) {
 
 namespace ephdc {
 
+uint32_t sub_splits(const ParamSet& P, uint32_t G) {
+  const uint32_t per = (P.N / 512) * P.L * ((G + 3) / 4);
+  const uint32_t S = std::max<uint32_t>(1, mac_sub_resident_blocks() / per);
+  return std::min({S, P.M(), std::max<uint32_t>(1, kMaxBlocks / G)});
+}
+
+hipError_t run_sub(const ephdc_session* s, ScoreArgs a, size_t pt_cap, ephdc_session* timing, hipStream_t hs) {
+  const ParamSet& P = s->P;
+  const uint32_t M = P.M(), n = 1u << s->sub_logn, G = a.G, S = a.S;
+  const uint32_t per = (P.N / 512) * P.L * ((G + 3) / 4);
+  constexpr uint32_t kEncodeBlocks = 2048;
+  const size_t cap = pt_cap * P.N / ((size_t)P.L * n);
+  // chunks of mc ciphertexts; every chunk's MAC covers S splits (empty ones write or keep
+  // their sums), so S <= mc keeps each split non-empty in full chunks
+  const uint32_t mc = (uint32_t)std::max<size_t>(std::max<size_t>(1, S), std::min<size_t>(M, cap / G));
+  if ((size_t)mc * G > cap && mc > 1) return hipErrorInvalidValue;  // cannot happen: cap >= G * S
+  for (uint32_t base = 0; base < M; base += mc) {
+    const uint32_t len = std::min(mc, M - base);
+    ScoreArgs c = a;
+    c.m_base = base;
+    c.m_len = len;
+    c.accumulate = base > 0;
+    uint32_t Se = std::max<uint32_t>(1, std::min(len, (kEncodeBlocks + G - 1) / G));
+    c.mchunk = (len + Se - 1) / Se;
+    Se = (len + c.mchunk - 1) / c.mchunk;
+    hipEvent_t t0 = timing ? timed_begin(timing, hs) : nullptr;
+    hipError_t e = launch_encode_sub((int)s->sub_logn, c, G * Se, hs);
+    if (e != hipSuccess) return e;
+    if (timing) timed_end(timing, kStEncodePt, t0, hs);
+    c.mchunk = (len + S - 1) / S;
+    t0 = timing ? timed_begin(timing, hs) : nullptr;
+    e = launch_mac_sub(P.logn, (int)s->sub_logn, c, per * S, hs);
+    if (e != hipSuccess) return e;
+    if (timing) timed_end(timing, kStMac, t0, hs);
+  }
+  return hipSuccess;
+}
+
+ScoreArgs sub_group_args(const ephdc_session* s, const SubGroup* d_vg, uint32_t VG, uint32_t S, uint32_t* partial,
+                         int32_t* pt) {
+  const ParamSet& P = s->P;
+  ScoreArgs a{};
+  a.model = s->d_model;
+  a.fwd_tw = s->d_fwd;
+  a.inv_t = s->d_inv_t;
+  a.pcs = s->d_pc;
+  a.pct = s->pct;
+  a.L = P.L;
+  a.M = P.M();
+  a.D = P.D;
+  a.r = P.r;
+  a.B = P.B();
+  a.G = VG;
+  a.S = S;
+  a.NLG = P.L;
+  a.m_len = P.M();
+  a.partial = partial;
+  a.pt = pt;
+  a.scale = scale_op(s);
+  a.sub_logn = s->sub_logn;
+  a.sub_logk = (uint32_t)P.logn - s->sub_logn;
+  a.pct_sub = s->pct_sub;
+  a.vg = d_vg;
+  return a;
+}
+
 size_t score_partial_words(const ephdc_session* s, uint32_t Q) {
   const Schedule sc = schedule(s, Q);
-  return (size_t)sc.G * sc.S * 2 * s->P.L * s->P.N;
+  const uint32_t S = s->sub_logn ? std::max(sc.S, sub_splits(s->P, sc.G)) : sc.S;
+  return (size_t)sc.G * S * 2 * s->P.L * s->P.N;
 }
 
 ScaleOp scale_op(const ephdc_session* s) {
@@ -343,7 +387,7 @@ ephdc_status score_with(ephdc_session* s, const Workspace& ws, const int8_t* d_h
   if (sub) {
     size_t cap = ws.pt_cap;
     if (s->pt_bytes) cap = std::max<size_t>(sc.G, std::min(cap, s->pt_bytes / (4 * (size_t)P.N)));
-    HIP_TRY(score_split_sub(s, a, Q, cap, sc, hs), "subring score launch");
+    HIP_TRY(score_split_sub(s, a, Q, cap, ws.partial_words, sc, hs), "subring score launch");
   } else if (s->split) {
     size_t cap = ws.pt_cap;
     if (s->pt_bytes) cap = std::max<size_t>(sc.G, std::min(cap, s->pt_bytes / (4 * (size_t)P.N)));

@@ -121,6 +121,16 @@ ScaleOp scale_op(const ephdc_session* s);
 ephdc_status score_with(ephdc_session* s, const Workspace& ws, const int8_t* d_hv, uint32_t Q,
                         uint32_t* d_score_ct, hipStream_t hs);
 
+// Subring kernels (sessions with sub_logn > 0): splits of the model range for G groups,
+// and one scoring pass over the groups of `a` (a.G groups, a.S splits; a.vg may map them to
+// the queries of several requests) with a plaintext buffer of pt_cap N-word plaintexts,
+// which must hold G * S of the kernels' transformed plaintexts.  `timing`: the session whose
+// kernel timers record the launches, or nullptr.
+uint32_t sub_splits(const ParamSet& P, uint32_t G);
+hipError_t run_sub(const ephdc_session* s, ScoreArgs a, size_t pt_cap, ephdc_session* timing, hipStream_t hs);
+ScoreArgs sub_group_args(const ephdc_session* s, const SubGroup* d_vg, uint32_t VG, uint32_t S, uint32_t* partial,
+                         int32_t* pt);
+
 // Rotation workspace and arguments for G groups of a folded (r > 1) session.
 size_t rotate_words(const ParamSet& P, uint32_t G);
 RotateArgs rotate_args(const ephdc_session* s, uint32_t* workspace, uint32_t G);
