@@ -685,10 +685,11 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
 // positions x0 = blk*512 + 2*tid and x0 + 1, which share the n-point value y = x0 >> log2 K'
 // (K' >= 2), for the up to four groups of its tile: per model ciphertext two words of c0
 // and c1 and one transformed value per group, accumulated in 64-bit lazy sums as in
-// mac_item64 (folded every second plaintext).  The loads run kDepth ciphertexts ahead.
-constexpr int kSubGroups = 4, kSubThreads = 256, kSubDepth = 4;
+// mac_item64 (folded every second plaintext).  The loads run kSubDepth ciphertexts ahead.
+// Group tiles hold four groups, or eight when a launch scores more than four (batches).
+constexpr int kSubThreads = 256, kSubDepth = 4;
 
-template <int LOGKP>
+template <int LOGKP, int kSubGroups>
 __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
   static_assert(LOGKP >= 1, "two positions per thread share one n-point value");
   const uint32_t N = (1u << a.sub_logn) << LOGKP, n = 1u << a.sub_logn, L = a.L;
@@ -1145,6 +1146,8 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
   });
 }
 
+uint32_t sub_group_tile(uint32_t G) { return G > 4 ? 8u : 4u; }
+
 bool subring_kernels(int logn, int sub_logn) {
   return logn >= 11 && logn <= 13 && sub_logn >= 8 && sub_logn <= 12 && sub_logn < logn;
 }
@@ -1170,16 +1173,17 @@ hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks,
   });
 }
 
-uint32_t mac_sub_resident_blocks() {
-  static const uint32_t n = [] {
+uint32_t mac_sub_resident_blocks(uint32_t tile) {
+  auto count = [](const void* f) {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_mac_sub<3>, kSubThreads, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSubThreads, 0) != hipSuccess ||
         hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return 2048u;
+      return 1024u;
     return (uint32_t)std::max(1, per_cu * cus);
-  }();
-  return n;
+  };
+  static const uint32_t n4 = count((const void*)k_mac_sub<3, 4>), n8 = count((const void*)k_mac_sub<3, 8>);
+  return tile == 8 ? n8 : n4;
 }
 
 hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
@@ -1190,12 +1194,18 @@ hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t 
   a.xcd = xm.on;
   a.nitems = nblocks;
   const dim3 grid(xm.slots());
-  switch (logn - sub_logn) {
-    case 1: k_mac_sub<1><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
-    case 2: k_mac_sub<2><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
-    case 3: k_mac_sub<3><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
-    case 4: k_mac_sub<4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
-    case 5: k_mac_sub<5><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+  const bool wide = sub_group_tile(a.G) == 8;
+  switch ((logn - sub_logn) * 2 + (wide ? 1 : 0)) {
+    case 2: k_mac_sub<1, 4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 3: k_mac_sub<1, 8><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 4: k_mac_sub<2, 4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 5: k_mac_sub<2, 8><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 6: k_mac_sub<3, 4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 7: k_mac_sub<3, 8><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 8: k_mac_sub<4, 4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 9: k_mac_sub<4, 8><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 10: k_mac_sub<5, 4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
+    case 11: k_mac_sub<5, 8><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -217,7 +217,8 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nbl
 bool subring_kernels(int logn, int sub_logn);
 hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
-uint32_t mac_sub_resident_blocks();  // workgroups of the streaming MAC resident at once on the device
+uint32_t mac_sub_resident_blocks(uint32_t tile);  // streaming-MAC workgroups resident at once (tile: 4 or 8)
+uint32_t sub_group_tile(uint32_t G);  // groups per streaming-MAC work item for a launch of G groups
 bool supported_shape(int logn, int le);
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S,
                          uint32_t L, const uint32_t* itw, const PrimeConst* pcs, hipStream_t st);

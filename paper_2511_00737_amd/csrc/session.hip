@@ -236,15 +236,15 @@ std::vector<uint32_t> automorphism_perms(const ParamSet& P) {
 namespace ephdc {
 
 uint32_t sub_splits(const ParamSet& P, uint32_t G) {
-  const uint32_t per = (P.N / 512) * P.L * ((G + 3) / 4);
-  const uint32_t S = std::max<uint32_t>(1, mac_sub_resident_blocks() / per);
+  const uint32_t gt = sub_group_tile(G), per = (P.N / 512) * P.L * ((G + gt - 1) / gt);
+  const uint32_t S = std::max<uint32_t>(1, mac_sub_resident_blocks(gt) / per);
   return std::min({S, P.M(), std::max<uint32_t>(1, kMaxBlocks / G)});
 }
 
 hipError_t run_sub(const ephdc_session* s, ScoreArgs a, size_t pt_cap, ephdc_session* timing, hipStream_t hs) {
   const ParamSet& P = s->P;
   const uint32_t M = P.M(), n = 1u << s->sub_logn, G = a.G, S = a.S;
-  const uint32_t per = (P.N / 512) * P.L * ((G + 3) / 4);
+  const uint32_t gt = sub_group_tile(G), per = (P.N / 512) * P.L * ((G + gt - 1) / gt);
   constexpr uint32_t kEncodeBlocks = 2048;
   const size_t cap = pt_cap * P.N / ((size_t)P.L * n);
   // chunks of mc ciphertexts; every chunk's MAC covers S splits (empty ones write or keep

@@ -51,10 +51,11 @@ def score(e, model, h, stride_offset=0, chunk_bytes=0):
 
 
 # (N, L, K, D, Q): n = N/K' of 4096 and 2048 (transforms across waves), 1024, 512 and 256
-# (one wave each) under N = 2048, 4096 and 8192; ragged last groups
+# (one wave each) under N = 2048, 4096 and 8192; ragged last groups; nine groups (MAC work
+# items of eight groups, the second one ragged)
 CASES = [(8192, 4, 7, 70, 2500), (8192, 4, 12, 33, 1100), (8192, 4, 26, 21, 300), (4096, 3, 3, 64, 1500),
          (4096, 3, 9, 40, 700), (2048, 2, 2, 50, 2100), (2048, 2, 5, 31, 600), (8192, 4, 2, 24, 5000),
-         (4096, 3, 2, 40, 2100)]
+         (4096, 3, 2, 40, 2100), (2048, 2, 8, 40, 2200)]
 
 
 @pytest.mark.parametrize("N,L,K,D,Q", CASES)
@@ -163,3 +164,40 @@ def test_subring_sessions_in_a_batch():
     finally:
         for t in tenants:
             t[3].close()
+
+
+def test_subring_batch_of_many_groups_on_one_model():
+    """Eleven virtual groups of five requests on one subring model (MAC items of eight
+    groups, the second ragged), packed and unpacked: every request equals its single-request
+    ciphertexts, which equal the oracle's."""
+    torch = torch_cuda()
+    o, e = make(2048, 2, 40, 8)  # B = 256
+    rng = np.random.default_rng(12)
+    C = values(rng, 8, (o.K, o.D))
+    sk = bfv.secret_key(o, 12)
+    model = bfv.encrypt_model(o, sk, C, 12)
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=1024)
+    try:
+        sizes = [256, 300, 700, 1000, 3]  # groups 1 + 2 + 3 + 4 + 1
+        hs = [values(rng, 1, (Q, o.D)) for Q in sizes]
+        reqs, single = [], []
+        for h in hs:
+            Q = h.shape[0]
+            d_hv = to_dev(hv_layout(h, s.hv_stride(Q)))
+            out = torch.zeros((s.num_groups(Q), 2, o.L, o.N), dtype=torch.int32, device="cuda")
+            reqs.append(ep.Request(s, d_hv, Q, out))
+            one = torch.empty_like(out)
+            ep.ephdc_score_encrypted(s, d_hv, Q, one)
+            single.append(one)
+        b = ep.Batch(reqs)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+        for k, (r, one) in enumerate(zip(reqs, single)):
+            assert torch.equal(r.d_score_ct, one), k
+        assert np.array_equal(to_host_u32(single[3]).astype(np.int64), pipeline.score_ciphertexts(o, model, hs[3]))
+        assert np.array_equal(to_host_u32(single[4]).astype(np.int64), pipeline.score_ciphertexts(o, model, hs[4]))
+    finally:
+        s.close()
