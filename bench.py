@@ -922,7 +922,10 @@ def run_single(args, w, layout: str):
         result["roofline"] = {"bound": "hbm", "kernel": "k_mac_sub", "achieved": round(mac_bytes / (mac_ms * 1e-3) / 1e9, 1),
                               "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                               "frac": round(mac_bytes / (mac_ms * 1e-3) / HBM_PEAK, 4), "traffic": tr,
-                              "algorithmic_bytes": mac_bytes, "avg_launch_ms": round(mac_ms, 4)}
+                              "algorithmic_bytes": mac_bytes, "avg_launch_ms": round(mac_ms, 4),
+                              **({"traffic_gbps": round(tr / (mac_ms * 1e-3) / 1e9, 1),
+                                  "traffic_frac": round(tr / (mac_ms * 1e-3) / HBM_PEAK, 4)} if tr else {}),
+                              "valu_issue": recorded_valu_issue("k_mac_sub", "subring_" + args.workload)}
         enc_ms = prof["encode_pt"][0] / prof["encode_pt"][1]
         enc_ops = G * M * (1 + L) * transform_mults(n_sub) / nl
         result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_sub",
@@ -930,7 +933,9 @@ def run_single(args, w, layout: str):
                                         "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
                                         "frac": round(enc_ops / (enc_ms * 1e-3) / MODMUL_PEAK, 4),
                                         "per_launch_modmuls": enc_ops, "avg_launch_ms": round(enc_ms, 4),
-                                        "traffic": recorded_traffic("k_encode_sub", args.workload)}
+                                        "traffic": recorded_traffic("k_encode_sub", args.workload),
+                                        **hbm(recorded_traffic("k_encode_sub", args.workload), enc_ms),
+                                        "valu_issue": recorded_valu_issue("k_encode_sub", "subring_" + args.workload)}
     elif split:
         e_ops, e_ms = per_launch("k_encode_pt", "encode_pt")
         result["roofline_encode_pt"] = {"bound": "alu", "kernel": "k_encode_pt",
