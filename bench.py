@@ -508,8 +508,11 @@ def bench_serving(args, w) -> int:
             N, L, alpha, r, dnum = 8192, 4, 0, 1, 0
         else:
             N, L, alpha, r, dnum = 16384, 8, 2, 4, 4
+        # the N = 8192 tenants in the subring layout (auto), the folded ones contiguous (r = 4)
+        layout = "subring" if r == 1 and args.layout in ("auto", "subring") else "contiguous"
         primes = ep.default_primes(N, L + alpha)
-        prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum)
+        prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum,
+                        layout=layout)
         sk, gk = ep.ephdc_keygen(prm, seed + 100 + k)
         C = synth.class_hypervectors(seed + 100 + k, K, D)
         model = ep.ephdc_encrypt_model(prm, sk, C, seed + 100 + k)
@@ -600,7 +603,8 @@ def bench_serving(args, w) -> int:
         "steps": main_run["requests"], "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"c5: {w['desc']}", "rate_req_s": w["rate"], "tenants": len(tenants),
-                   "session_bytes": int(model_bytes)},
+                   "session_bytes": int(model_bytes),
+                   "layouts": sorted({t["prm"].layout for t in tenants})},
         "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
         "serving": main_run, "rate_sweep": sweep, "unpacked_at_same_rate": unpacked,
     }
@@ -621,7 +625,8 @@ def bench_detect(args, w) -> int:
     Q = ep.ephdc_hog_window_count(H, W, win, st)
     F = ep.ephdc_hog_feature_count(win)
     N, L, D, K = w["N"], w["L"], w["D"], w["K"]
-    prm = ep.Params(N=N, q=tuple(ep.default_primes(N, L)), F=F, D=D, K=K)
+    layout = "subring" if args.layout in ("auto", "subring") else "contiguous"
+    prm = ep.Params(N=N, q=tuple(ep.default_primes(N, L)), F=F, D=D, K=K, layout=layout)
     base = synth.base_hypervectors(args.seed, F, D)
     C = synth.class_hypervectors(args.seed, K, D)
     sk, _ = ep.ephdc_keygen(prm, args.seed)
@@ -677,19 +682,30 @@ def bench_detect(args, w) -> int:
     M = ep.ephdc_num_model_ct(prm)
     mac_ms = prof["mac"][0] / max(1, prof["mac"][1])
     mac_ops = algorithmic_modmuls("k_mac", N, L, G, M) * args.steps / max(1, prof["mac"][1])
+    n_sub = N // (1 << (K - 1).bit_length())
+    if layout == "subring":
+        # streaming MAC: the model once per launch's group tiles, the transformed plaintexts once
+        tiles = -(-G // (8 if G > 4 else 4))
+        mac_bytes = (tiles * M * 2 * L * N + G * M * L * n_sub + G * 2 * L * N) * 4.0 * args.steps / max(1, prof["mac"][1])
+        mac_roof = {"bound": "hbm", "kernel": "k_mac_sub", "achieved": round(mac_bytes / (mac_ms * 1e-3) / 1e9, 1),
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(mac_bytes / (mac_ms * 1e-3) / HBM_PEAK, 4),
+                    "traffic": None, "algorithmic_bytes": mac_bytes, "avg_launch_ms": round(mac_ms, 4)}
+    else:
+        mac_roof = {"bound": "alu", "kernel": "k_mac", "achieved": round(mac_ops / (mac_ms * 1e-3) / 1e12, 4),
+                    "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
+                    "frac": round(mac_ops / (mac_ms * 1e-3) / MODMUL_PEAK, 4), "traffic": None,
+                    "avg_launch_ms": round(mac_ms, 4)}
     result = {
         "metric": "windows/s from raw frames (HOG + HDC encoding + encrypted scoring)",
         "value": round(Q * args.steps / wall, 1), "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"detect: {w['desc']}", "windows_per_frame": Q, "features": F, "groups": G},
+        "config": {"workload": f"detect: {w['desc']}", "windows_per_frame": Q, "features": F, "groups": G,
+                   "layout": layout, "queries_per_ciphertext": ep.ephdc_queries_per_ct(prm)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4)},
         "stages_ms_per_step": {"hog": round(hog_ms, 4),
                                **{k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]}},
-        "roofline": {"bound": "alu", "kernel": "k_mac", "achieved": round(mac_ops / (mac_ms * 1e-3) / 1e12, 4),
-                     "peak": round(MODMUL_PEAK / 1e12, 4), "unit": "Tmodmul/s",
-                     "frac": round(mac_ops / (mac_ms * 1e-3) / MODMUL_PEAK, 4), "traffic": None,
-                     "avg_launch_ms": round(mac_ms, 4)},
+        "roofline": mac_roof,
         "roofline_hog": {"bound": "hbm", "kernel": "HOG cells + blocks + windows", "achieved":
                          round(hog_bytes / (hog_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                          "frac": round(hog_bytes / (hog_ms * 1e-3) / HBM_PEAK, 4), "traffic": None,
