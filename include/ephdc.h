@@ -192,8 +192,8 @@ typedef struct ephdc_session ephdc_session;
  * Device workspace of ephdc_score_encrypted for batches of up to max_Q queries, in bytes
  * (0 on invalid parameters): the work items' partial sums (sized for every schedule of
  * ephdc_session_tune), the rotation workspace when r > 1, and the split path's plaintext
- * chunk (the lifted plaintexts of all groups of max_Q queries, at most 512 MiB, at least one
- * plaintext per group).  Any buffer of at least the size without the 512 MiB chunk (one
+ * chunk (the lifted plaintexts of all groups of max_Q queries, at most 4 GiB, at least one
+ * plaintext per group).  Any buffer of at least the size without the 4 GiB chunk (one
  * plaintext per group of max_Q) is accepted; a larger chunk scores the model in fewer chunks.
  * Client side, homomorphic scoring (proposed method: client-side HE).
  */
@@ -297,8 +297,8 @@ ephdc_status ephdc_debug_polymul(ephdc_session* s, const uint32_t* d_a, const ui
  *                      N / values_per_thread threads)
  *   mode               1: one fused kernel batch-encodes and multiplies (the batch
  *                      encoding is repeated per limb group); 2: split path, a batch-encode
- *                      kernel writes each lifted plaintext once (into a session buffer of
- *                      at most 512 MiB, allocated on first use) and a MAC kernel reads it
+ *                      kernel writes each lifted plaintext once (into the plaintext chunk
+ *                      of the session's workspace) and a MAC kernel reads it
  * Results do not depend on the schedule.  Defaults: split path, one limb per work item,
  * 8 values per thread (16 at N = 16384), 256 workgroups from N = 8192 up (one per compute
  * unit of an MI355X) and 512 below.

@@ -117,7 +117,7 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   return a;
 }
 
-constexpr size_t kPtBytes = (size_t)512 << 20;  // default plaintext chunk of ephdc_workspace_bytes
+constexpr size_t kPtBytes = (size_t)4 << 30;  // default plaintext chunk of ephdc_workspace_bytes
 
 // Split path: the model range is processed in chunks of m_len ciphertexts so that the
 // lifted plaintexts of a chunk (G x m_len x N int32) fit the workspace's buffer; the MAC

@@ -169,7 +169,7 @@ def test_session_without_workspace_rejects_single_request_scoring():
     c = e.c()
     need = ep.ephdc_workspace_bytes(e, 10)
     G = 1
-    minimum = need - (min(G * o.M, (512 << 20) // (4 * o.N)) - G) * o.N * 4
+    minimum = need - (min(G * o.M, (4 << 30) // (4 * o.N)) - G) * o.N * 4
     ws = torch.empty(minimum - 1, dtype=torch.uint8, device="cuda")
     with pytest.raises(ep.EphdcError) as ei:
         ep.Session(e, to_dev(model), max_Q=10, workspace=ws)

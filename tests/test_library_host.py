@@ -182,7 +182,7 @@ def test_decrypt_at_an_offset_reads_the_same_rows():
 
 def test_workspace_size_formula():
     """ephdc_workspace_bytes = partial sums for 1024 + G work items of [2][L][N] words, the
-    rotation workspace of G groups (r > 1), and a plaintext chunk of min(G*M, 512 MiB / 4N)
+    rotation workspace of G groups (r > 1), and a plaintext chunk of min(G*M, 4 GiB / 4N)
     plaintexts (at least G), each of the first two regions rounded up to 256 bytes."""
     def a256(x):
         return -(-x // 256) * 256
@@ -196,7 +196,7 @@ def test_workspace_size_formula():
         G = o.groups(Q)
         partial = (1024 + G) * 2 * L * N * 4
         rot = G * N * (5 * L + dnum * (L + alpha) + 2 * (L + alpha) + 2 * alpha) * 4 if r > 1 else 0
-        cap = max(G, min(G * o.M, (512 << 20) // (4 * N)))
+        cap = max(G, min(G * o.M, (4 << 30) // (4 * N)))
         assert ep.ephdc_workspace_bytes(e, Q) == a256(partial) + a256(rot) + cap * N * 4, (N, Q)
     assert ep.ephdc_workspace_bytes(ep.Params(N=100, q=(7,), F=16, D=16, K=3), 10) == 0
 
