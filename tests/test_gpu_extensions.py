@@ -179,11 +179,13 @@ def test_session_without_workspace_rejects_single_request_scoring():
 
 
 
-def test_scaling_op_in_batches():
-    """Batches whose requests mix scaled and unscaled models (one list launch serves both),
-    Q-bit queries encoded inside the batch, segment lengths shorter and longer than a
-    scaling block, split and fused, unpacked and packed: every request equals the oracle's
-    ciphertexts of its own query sequence (unpacked) or of its model's sequence (packed)."""
+@pytest.mark.parametrize("layout", ["contiguous", "subring"])
+def test_scaling_op_in_batches(layout):
+    """Batches whose requests mix scaled and unscaled models (one list launch serves both;
+    in the subring layout the n-point kernels apply the weights), Q-bit queries encoded
+    inside the batch, segment lengths shorter and longer than a scaling block, split and
+    fused, unpacked and packed: every request equals the oracle's ciphertexts of its own
+    query sequence (unpacked) or of its model's sequence (packed)."""
     import synth
     torch = torch_cuda()
     # (N, L, t, D, K, scale_every, scale_shift, Q bits, qshift)
@@ -192,7 +194,7 @@ def test_scaling_op_in_batches():
     reqs_spec = [(0, 300), (1, 40), (2, 700), (0, 5), (2, 1), (1, 1200), (0, 900)]
     tenants, sessions = [], []
     for i, (N, L, t, D, K, g, s_, qb, qs) in enumerate(specs):
-        o, e = make(N, L, D, K=K, t=t, scale_every=g, scale_shift=s_, qbits=qb, qshift=qs)
+        o, e = make(N, L, D, K=K, t=t, scale_every=g, scale_shift=s_, qbits=qb, qshift=qs, layout=layout)
         C = values(np.random.default_rng(70 + i), 8, (K, D))
         sk = bfv.secret_key(o, 71 + i)
         model = bfv.encrypt_model(o, sk, C, 72 + i)

@@ -259,3 +259,69 @@ def test_ticket_count_stays_bounded_over_thousands_of_requests(tenants):
         ep.ephdc_score_encrypted(t.s, d_hv, Q, alone)
         torch.cuda.synchronize()
         assert np.array_equal(to_host_u32(out), to_host_u32(alone))
+
+
+def test_serving_subring_tenants_unpacked_and_packed():
+    """Tenants in the subring layout (scored per model as lists of virtual groups by the
+    n-point kernels) beside a contiguous tenant on the same primes: unpacked, each request
+    equals the request scored alone (and the oracle on a sample); packed, each decrypts at
+    its offset to its exact scores."""
+    torch = torch_cuda()
+    specs = [(4096, 3, 3, 64, "subring"), (4096, 3, 2, 64, "contiguous"), (8192, 4, 7, 64, "subring")]
+    ts = []
+    for i, (N, L, K, D, lay) in enumerate(specs):
+        kw = dict(N=N, q=tuple(default_primes(N, L)), F=F, D=D, K=K, layout=lay)
+        o, e = OParams(**kw), ep.Params(**kw)
+        sk = bfv.secret_key(o, 60 + i)
+        C = synth.class_hypervectors(61 + i, K, D)
+        model = bfv.encrypt_model(o, sk, C, 62 + i)
+        base = synth.base_hypervectors(63 + i, F, D)
+        ts.append(dict(o=o, e=e, sk=sk, C=C, model=model, base=base, d_base=to_dev(base),
+                       s=ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=1500)))
+    try:
+        for pack in (False, True):
+            rng = np.random.default_rng(31 + pack)
+            sv = ep.Server(1 << 30, streams=2, max_batch=8)
+            try:
+                if pack:
+                    sv.set_packing(True)
+                ids = [sv.add_tenant(t["s"], t["d_base"]) for t in ts]
+                jobs = []
+                for k in range(24):
+                    ti = int(rng.integers(0, len(ts)))
+                    Q = int(rng.integers(1, 1500))
+                    t = ts[ti]
+                    x = synth.uniform_features(1500 + k + 100 * pack, Q, F)
+                    d_x = to_dev(x)
+                    out = torch.zeros((t["s"].num_groups(Q) + (1 if pack else 0), 2, t["o"].L, t["o"].N),
+                                      dtype=torch.int32, device="cuda")
+                    jobs.append((sv.submit(ids[ti], d_x, Q, out), ti, Q, x, d_x, out))
+                    if k % 6 == 5:
+                        time.sleep(0.002)
+                sv.wait(0, timeout_s=120)
+                assert sv.stats()["completed"] == 24
+                for n, (tk, ti, Q, x, d_x, out) in enumerate(jobs):
+                    t = ts[ti]
+                    h = hdc.encode(x, t["base"])
+                    if pack:
+                        qf, nct = sv.result(tk)
+                        got = to_host_u32(out)[:nct]
+                        scores, _ = ep.ephdc_decrypt_scores_at(t["e"], t["sk"].astype(np.int8), got, qf, Q)
+                        assert np.array_equal(scores, hdc.scores_mod_t(h, t["C"], 65537)), n
+                        continue
+                    d_hv = torch.empty((t["o"].D, t["s"].hv_stride(Q)), dtype=torch.int8, device="cuda")
+                    alone = torch.empty_like(out)
+                    ep.ephdc_encode_queries(t["s"], d_x, t["d_base"], Q, d_hv)
+                    ep.ephdc_score_encrypted(t["s"], d_hv, Q, alone)
+                    torch.cuda.synchronize()
+                    got = to_host_u32(out).astype(np.int64)
+                    assert np.array_equal(got, to_host_u32(alone).astype(np.int64)), n
+                    if n % 6 == 0:
+                        G = t["o"].groups(Q)
+                        want = pipeline.score_ciphertexts(t["o"], t["model"], h, groups=[G - 1])
+                        assert np.array_equal(got[G - 1], want[0]), n
+            finally:
+                sv.close()
+    finally:
+        for t in ts:
+            t["s"].close()
