@@ -43,7 +43,7 @@ import numpy as np
 
 from . import ntt, prng, slots
 from .arith import inv
-from .layout import model_slots, query_slots
+from .layout import model_slots, query_slots, subring_gamma
 from .params import Params
 
 
@@ -262,7 +262,11 @@ def automorphism(a: np.ndarray, g: int, moduli) -> np.ndarray:
 
 
 def galois_elements(P: Params) -> list[int]:
-    """g_i = 3^(W * 2^i) mod 2N for i < log2 r: rotate each row left by W * 2^i slots."""
+    """Galois elements g_i, i < log2 r, of rotate-and-sum.  Contiguous layout:
+    3^(W * 2^i) mod 2N, which rotates each row left by W * 2^i slots.  Subring layout:
+    gamma^(2^i) mod 2N with gamma = 1 + 2n/r (layout module docstring)."""
+    if P.layout == "subring":
+        return [pow(subring_gamma(P), 1 << i, 2 * P.N) for i in range(P.log2r)]
     return [pow(3, P.W << i, 2 * P.N) for i in range(P.log2r)]
 
 

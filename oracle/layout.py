@@ -16,17 +16,28 @@ paper's packing):
 * query plaintext (g, m) holds h[g*B + rho*Bq + ql][m*r + u];
 * a missing query (index >= Q) or dimension (index >= D) contributes 0.
 
-Subring layout (P.layout == "subring", r = 1), with K' = P.Kp and B = N/K':
+Subring layout (P.layout == "subring"), with K' = P.Kp, n = N/K' = P.n orbits and
+B = n/r queries per ciphertext:
 
-* the slot exponents (odd residues e mod 2N, slots.slot_exponents) fall into the
-  orbits {e * h : h = 1 (mod 2B)} = {e + 2B*c : c < K'} of the subgroup of Z_2N^*
-  of order K'; query ql < B of a ciphertext takes the orbit of exponent
-  e_ql = 2*brev(ql) + 1 (brev: bit reversal over log2 B bits) and class c < K' the
-  slot of exponent e_ql + 2B*c mod 2N;
+* H = {h = 1 (mod 2n)}, a subgroup of Z_2N^* of order K', acts on the slot exponents
+  (odd residues e mod 2N, slots.slot_exponents); its orbits are the residue classes
+  mod 2n, and orbit y < n is the class of 2*brev_n(y) + 1 (brev_n: bit reversal over
+  log2 n bits).  A slot vector constant on every orbit is the evaluation of a
+  polynomial in X^K', whose n-point transform has the orbit's value at position y;
+* query ql < B and block v < r take orbit y = ql*r + v; the r orbits of query ql make
+  up one orbit of H' = {h = 1 (mod 2n/r)} (order K' r), the one of
+  e_ql = 2*brev_B(ql) + 1.  H' is cyclic with generator gamma = 1 + 2n/r (B >= 2);
+* class c < K' of (ql, v) is the exponent gamma^u * (e_ql + 2n*c) mod 2N, with u < r
+  the power for which gamma^u * e_ql lies in orbit ql*r + v (u = 0 at v = 0);
+* rotation i of rotate-and-sum uses the Galois element gamma^(2^i) mod 2N.  Slot
+  exponent e then receives the sum over k < r of the old values at e * gamma^k, which at
+  e = e_ql + 2n*c are the r blocks of (ql, c): block 0 holds each class's total (the
+  other blocks may mix classes and are not read);
 * query index inside group g is g*B + ql;
-* model ciphertext m holds C[c][m] at class c < K and 0 at the K' - K extra classes;
-* query plaintext (g, m) holds h[g*B + ql][m] at all K' slots of the orbit, so its
-  slot vector is constant on every orbit and the plaintext is a polynomial in X^K'.
+* model ciphertext m holds C[c][m*r + v] at class c < K and 0 at the K' - K extra classes
+  and at dimensions >= D;
+* query plaintext (g, m) holds h[g*B + ql][m*r + v] at all K' slots of orbit ql*r + v.
+For r = 1 every u is 0 and class c of query ql is exponent e_ql + 2n*c.
 """
 from __future__ import annotations
 
@@ -49,11 +60,38 @@ def _brev(x: np.ndarray, bits: int) -> np.ndarray:
     return out
 
 
-def subring_slot(P: Params, ql, c):
-    """Slot of (query ql, class c) in the subring layout (module docstring)."""
-    B = P.B
-    e = (2 * _brev(np.asarray(ql, dtype=np.int64), B.bit_length() - 1) + 1 + 2 * B * np.asarray(c)) % (2 * P.N)
-    return _exponent_to_slot(P.N)[e]
+def subring_gamma(P: Params) -> int:
+    """Generator 1 + 2n/r of H' = {h = 1 (mod 2n/r)} (module docstring)."""
+    return 1 + 2 * P.n // P.r
+
+
+@lru_cache(maxsize=None)
+def _block_power(N: int, Kp: int, r: int) -> np.ndarray:
+    """u[ql][v] < r with gamma^u * e_ql in orbit ql*r + v, found by trying every u."""
+    n = N // Kp
+    B = n // r
+    gamma = 1 + 2 * n // r
+    e = 2 * _brev(np.arange(B), B.bit_length() - 1) + 1
+    u_of = np.full((B, r), -1, dtype=np.int64)
+    for u in range(r):
+        res = pow(gamma, u, 2 * n) * e % (2 * n)
+        y = _brev((res - 1) // 2, n.bit_length() - 1)
+        v = y - np.arange(B) * r
+        assert ((v >= 0) & (v < r)).all()
+        u_of[np.arange(B), v] = u
+    assert (u_of >= 0).all()
+    return u_of
+
+
+def subring_slot(P: Params, ql, c, v=0):
+    """Slot of (query ql, block v, class c) in the subring layout (module docstring)."""
+    n, B, N = P.n, P.B, P.N
+    ql, c, v = np.broadcast_arrays(np.asarray(ql, dtype=np.int64), np.asarray(c, dtype=np.int64),
+                                   np.asarray(v, dtype=np.int64))
+    e = 2 * _brev(ql, B.bit_length() - 1) + 1
+    u = _block_power(N, P.Kp, P.r)[ql, v]
+    gu = np.array([pow(subring_gamma(P), int(k), 2 * N) for k in range(P.r)], dtype=np.int64)
+    return _exponent_to_slot(N)[gu[u] * ((e + 2 * n * c) % (2 * N)) % (2 * N)]
 
 
 @lru_cache(maxsize=None)
@@ -64,8 +102,8 @@ def _exponent_to_slot(N: int) -> np.ndarray:
 
 
 def _subring_grid(P: Params):
-    ql, c = np.meshgrid(np.arange(P.B), np.arange(P.Kp), indexing="ij")
-    return ql.ravel(), c.ravel()
+    ql, v, c = np.meshgrid(np.arange(P.B), np.arange(P.r), np.arange(P.Kp), indexing="ij")
+    return ql.ravel(), v.ravel(), c.ravel()
 
 
 def _grid(P: Params):
@@ -78,9 +116,10 @@ def model_slots(P: Params, C: np.ndarray, m: int) -> np.ndarray:
     """Slot vector (int64 [N], values in [-128, 127] or 0) of model ciphertext m."""
     v = np.zeros(P.N, dtype=np.int64)
     if P.layout == "subring":
-        ql, c = _subring_grid(P)
-        ok = (c < P.K) & (m < P.D)
-        v[subring_slot(P, ql[ok], c[ok])] = C[c[ok], m]
+        ql, u, c = _subring_grid(P)
+        j = m * P.r + u
+        ok = (c < P.K) & (j < P.D)
+        v[subring_slot(P, ql[ok], c[ok], u[ok])] = C[c[ok], j[ok]]
         return v
     rho, u, ql, c = _grid(P)
     j = m * P.r + u
@@ -94,10 +133,11 @@ def query_slots(P: Params, h: np.ndarray, g: int, m: int) -> np.ndarray:
     Qn = h.shape[0]
     v = np.zeros(P.N, dtype=np.int64)
     if P.layout == "subring":
-        ql, c = _subring_grid(P)
+        ql, u, c = _subring_grid(P)
         q = g * P.B + ql
-        ok = (q < Qn) & (m < P.D)
-        v[subring_slot(P, ql[ok], c[ok])] = h[q[ok], m]
+        j = m * P.r + u
+        ok = (q < Qn) & (j < P.D)
+        v[subring_slot(P, ql[ok], c[ok], u[ok])] = h[q[ok], j[ok]]
         return v
     rho, u, ql, c = _grid(P)
     q = g * P.B + rho * P.Bq + ql
@@ -108,7 +148,7 @@ def query_slots(P: Params, h: np.ndarray, g: int, m: int) -> np.ndarray:
 
 
 def read_scores(P: Params, slots: np.ndarray, g: int, Qn: int) -> tuple[np.ndarray, np.ndarray]:
-    """Query indices and their K scores from the decoded slot vector of group g (block u = 0)."""
+    """Query indices and their K scores from the decoded slot vector of group g (block 0)."""
     qi = np.arange(P.B)
     if P.layout == "subring":
         q = g * P.B + qi

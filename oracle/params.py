@@ -20,7 +20,8 @@ the paper's batch size); "subring" puts them on one orbit of the subgroup
 {h = 1 (mod 2N/K')} of Z_2N^* acting on the slot exponents, K' the power of two
 at or above K, so that every query plaintext lies in Z_t[X^K'] (the K' - K extra
 slots of an orbit carry the query value against zero model classes) and one
-ciphertext holds B = N/K' queries (r = 1 only).
+ciphertext holds B = N/(K' r) queries (layout.py states the slot map and the
+Galois elements of its rotations).
 
 The plaintext modulus t is any prime with t = 1 (mod 2N) (the paper sweeps
 log2 t; its optimised settings use log2 t = 16 and 17, optimisation table).
@@ -97,10 +98,15 @@ class Params:
         return self.W // self.K
 
     @property
+    def n(self) -> int:
+        """Orbits of the subring layout (N/K'): the length of its query plaintexts in X^K'."""
+        return self.N // self.Kp
+
+    @property
     def B(self) -> int:
-        """Queries per ciphertext (two rows of Bq, or N/K' orbits)."""
+        """Queries per ciphertext (two rows of Bq, or N/(K' r) groups of r orbits)."""
         if self.layout == "subring":
-            return self.N // self.Kp
+            return self.n // self.r
         return 2 * self.Bq
 
     @property
@@ -155,7 +161,7 @@ class Params:
             assert x < (1 << 30) and x % (2 * N) == 1 and is_prime(x)
         assert self.r >= 1 and self.r & (self.r - 1) == 0
         assert self.layout in ("contiguous", "subring")
-        assert self.layout == "contiguous" or (self.r == 1 and self.Kp <= N // 2)
+        assert self.layout == "contiguous" or self.B >= 2
         assert self.Bq >= 1
         if self.r > 1:
             assert self.dnum >= 1 and self.alpha >= 1

@@ -104,3 +104,96 @@ def test_subring_mac_matches_schoolbook_sum():
                 for l, q in enumerate(P.q):
                     want[c, l] = (want[c, l] + ntt.polymul_naive(model[m, c, l], p % q, q)) % q
         assert np.array_equal(acc, want)
+
+
+def fold(N=64, K=3, r=2, D=12, L=4):
+    primes = default_primes(N, L + 2)
+    return Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), D=D, K=K, F=8, r=r, dnum=2,
+                  layout="subring")
+
+
+FOLDS = [(64, 3, 2), (64, 2, 8), (128, 2, 4), (256, 5, 4), (256, 3, 8), (128, 7, 2)]
+
+
+@pytest.mark.parametrize("N,K,r", FOLDS)
+def test_folded_subring_slots_are_nested_orbits(N, K, r):
+    """With r > 1, block v of query ql is one orbit of H = {h = 1 (mod 2n)} (n = N/K'), the
+    residue class of n-point position ql*r + v; the r blocks of a query make up one orbit of
+    H' = {h = 1 (mod 2n/r)}; every slot is used once.  Brute force over both subgroups."""
+    P = fold(N=N, K=K, r=r)
+    P.validate()
+    n, Kp, B = P.n, P.Kp, P.B
+    assert n == N // Kp and B == n // r
+    H = [h for h in range(1, 2 * N, 2) if h % (2 * n) == 1]
+    H1 = [h for h in range(1, 2 * N, 2) if h % (2 * n // r) == 1]
+    assert len(H) == Kp and len(H1) == Kp * r
+    exps = slots.slot_exponents(N)
+    seen = set()
+    for ql in range(B):
+        whole = set()
+        for v in range(r):
+            got = {int(exps[s]) for s in layout.subring_slot(P, ql, np.arange(Kp), v)}
+            e0 = next(iter(got))
+            assert got == {e0 * h % (2 * N) for h in H}
+            y = ql * r + v
+            br = int(format(y, f"0{n.bit_length() - 1}b")[::-1], 2)
+            assert all(e % (2 * n) == 2 * br + 1 for e in got)
+            assert not (got & seen)
+            seen |= got
+            whole |= got
+        e0 = next(iter(whole))
+        assert whole == {e0 * h % (2 * N) for h in H1}
+    assert seen == {int(e) for e in exps}
+
+
+@pytest.mark.parametrize("N,K,r", FOLDS)
+def test_folded_subring_rotations_sum_blocks_into_block_zero(N, K, r):
+    """Rotate-and-sum with the layout's Galois elements, applied as the ring automorphism
+    X -> X^g to an encoded slot vector, leaves in slot (ql, block 0, c) the sum over the r
+    blocks of (ql, c), for every query and class."""
+    P = fold(N=N, K=K, r=r)
+    rng = np.random.default_rng(N * r + K)
+    z = rng.integers(0, 1000, N)
+    mu = slots.encode(z, T)
+    for g in bfv.galois_elements(P):
+        mu = (mu + bfv.automorphism_int(mu, g)) % T
+    out = slots.decode(mu, T)
+    for ql in range(P.B):
+        for c in range(P.Kp):
+            blocks = [int(z[layout.subring_slot(P, ql, c, v)]) for v in range(r)]
+            assert out[layout.subring_slot(P, ql, c, 0)] == sum(blocks) % T
+
+
+@pytest.mark.parametrize("N,K,r", [(64, 3, 2), (128, 7, 2), (256, 5, 4)])
+def test_folded_subring_plaintexts_are_polynomials_in_x_to_the_kp(N, K, r):
+    P = fold(N=N, K=K, r=r, D=9)
+    rng = np.random.default_rng(N + K + r)
+    h = rng.integers(-128, 128, (P.B + 3, P.D)).astype(np.int8)
+    off = np.arange(N) % P.Kp != 0
+    for g in range(2):
+        for m in range(P.M):
+            mu = slots.encode(layout.query_slots(P, h, g, m), T)
+            assert not mu[off].any(), (g, m)
+            assert mu.any()
+
+
+@pytest.mark.parametrize("N,K,r,D,Qn", [(64, 3, 2, 9, 11), (64, 2, 4, 13, 9), (128, 5, 2, 10, 70),
+                                        (128, 2, 8, 17, 10)])
+def test_folded_subring_pipeline_scores_equal_integer_dot_products(N, K, r, D, Qn):
+    """Whole protocol with rotations in the folded subring layout (key-switched Galois
+    rotations included) decrypts to the centred residues of h . C^T mod t, over ragged
+    groups and a dimension count that is not a multiple of r."""
+    P = fold(N=N, K=K, r=r, D=D)
+    x = synth.uniform_features(21, Qn, P.F)
+    base = synth.base_hypervectors(21, P.F, P.D)
+    C = synth.class_hypervectors(21, P.K, P.D)
+    out = pipeline.run(P, x, base, C, seed=21)
+    want = hdc.scores_mod_t(out["h"], C, T)
+    assert np.array_equal(out["scores"], want)
+    assert np.array_equal(out["argmax"], hdc.argmax(want))
+
+
+def test_folded_subring_needs_two_queries_per_ciphertext():
+    with pytest.raises(AssertionError):
+        fold(N=64, K=3, r=16).validate()  # n = 16, B = 1
+    fold(N=64, K=3, r=8).validate()
