@@ -899,10 +899,11 @@ def run_single(args, w, layout: str):
     kern, stage = ("k_mac", "mac") if split else ("k_score", "score")
     modmuls, k_ms = per_launch(kern, stage)
     achieved = modmuls / (k_ms * 1e-3)
-    # subring layout with the n-point kernels (n = N/K' of 256..1024 under N = 2048..8192)
+    # subring layout with the n-point kernels (n = N/K' of 256..4096 under N = 2048..16384,
+    # K' <= 32)
     Kp = 1 << (w["K"] - 1).bit_length() if layout == "subring" else w["K"]
     n_sub = N // Kp
-    sub = layout == "subring" and N in (2048, 4096, 8192) and 256 <= n_sub <= 1024 and n_sub < N
+    sub = layout == "subring" and 2048 <= N <= 16384 and 256 <= n_sub <= 4096 and 2 <= Kp <= 32
 
     def hbm(traffic, ms):
         """Achieved HBM bandwidth of a launch moving `traffic` bytes in `ms`, and its fraction of 8 TB/s."""
@@ -1004,8 +1005,8 @@ def main() -> int:
                                                   "(e.g. split,16,1,512; empty keeps the session's default)")
     ap.add_argument("--rates", default="", help="serving: comma-separated extra arrival rates (req/s)")
     ap.add_argument("--layout", default="auto", choices=["auto", "contiguous", "subring"],
-                    help="single-request workloads: slot layout of the queries (auto: the N = 8192 "
-                         "workload in the subring layout, with the contiguous layout measured beside it)")
+                    help="single-request workloads: slot layout of the queries (auto: the N = 8192 and "
+                         "N = 16384 workloads in the subring layout, with the contiguous layout measured beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy three times (calibrates FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -1035,7 +1036,7 @@ def main() -> int:
         return bench_dmax(args, w)
     if w.get("detect"):
         return bench_detect(args, w)
-    layouts = {"auto": ["subring", "contiguous"] if args.workload == "c2" else ["contiguous"]}.get(
+    layouts = {"auto": ["subring", "contiguous"] if args.workload in ("c2", "c4") else ["contiguous"]}.get(
         args.layout, [args.layout])
     runs = []
     for lay in layouts:

@@ -112,10 +112,11 @@ int batch_le(const ephdc_batch* b, int logn) { return b->vpt ? ilog2(b->vpt) : (
 // Requests of one list share N, the ciphertext primes and t (their transform tables).
 bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q && a.t == b.t; }
 
-// Requests of subring sessions whose hypervectors the n-point kernels can read (16-byte
-// aligned; packed buffers are placed aligned) go to the subring models.
+// Requests of unfolded subring sessions whose hypervectors the n-point kernels can read
+// (16-byte aligned; packed buffers are placed aligned) go to the subring models; folded
+// ones (r > 1) take the request lists, which rotate.
 bool takes_subring(const ephdc_batch* b, const ephdc_request& rq) {
-  return rq.session->sub_logn && (b->packed || ((uintptr_t)rq.d_hv & 15) == 0);
+  return rq.session->sub_logn && rq.session->P.r == 1 && (b->packed || ((uintptr_t)rq.d_hv & 15) == 0);
 }
 
 // Splits the requests into parameter sets, and the subring models.

@@ -61,8 +61,8 @@ ephdc_status ParamSet::load(const ephdc_params* prm) {
   if (N / (2 * r) < K) return fail(EPHDC_ERR_PARAMS, "N/(2r) must be >= K (at least one query per row)");
   if (qshift > 31) return fail(EPHDC_ERR_PARAMS, "qshift must be <= 31");
   if (layout > EPHDC_LAYOUT_SUBRING) return fail(EPHDC_ERR_PARAMS, "layout must be contiguous or subring");
-  if (subring() && (r != 1 || Kp() > N / 2))
-    return fail(EPHDC_ERR_PARAMS, "the subring layout needs r = 1 and K' <= N/2");
+  if (subring() && (Kp() > N / 2 || B() < 2))
+    return fail(EPHDC_ERR_PARAMS, "the subring layout needs N/(K' r) >= 2 (K' the power of two at or above K)");
   if (r > 1) {
     if (alpha < 1 || dnum < 1 || dnum > L) return fail(EPHDC_ERR_PARAMS, "r > 1 needs alpha >= 1 and 1 <= dnum <= L");
     if (scheme == EPHDC_BGV) return fail(EPHDC_ERR_PARAMS, "BGV takes r = 1 (no key switching)");
@@ -88,9 +88,21 @@ std::vector<uint32_t> slot_positions(uint32_t N) {
   return pos;
 }
 
-SubringSlots::SubringSlots(const ParamSet& P) : of_exp(2 * P.N, 0), N(P.N), B(P.B()), logb(ilog2(P.B())) {
+SubringSlots::SubringSlots(const ParamSet& P)
+    : of_exp(2 * P.N, 0), u_of((size_t)P.n(), 0), gpow(P.r), N(P.N), n(P.n()), B(P.B()), r(P.r), logb(ilog2(P.B())) {
   const std::vector<uint32_t> e = slot_exponents(P.N);
   for (uint32_t s = 0; s < P.N; ++s) of_exp[e[s]] = s;
+  const uint64_t gamma = 1 + 2ull * n / r;
+  const int logn = ilog2(n);
+  for (uint32_t u = 0; u < r; ++u) {
+    gpow[u] = powmod64(gamma, u, 2ull * N);
+    const uint64_t gu = powmod64(gamma, u, 2ull * n);
+    for (uint32_t ql = 0; ql < B; ++ql) {  // orbit of gamma^u * e_ql: block v = y - ql*r
+      const uint64_t res = gu * (2ull * bitrev(ql, logb) + 1) % (2ull * n);
+      const uint32_t y = bitrev((uint32_t)((res - 1) / 2), logn);
+      u_of[y] = u;
+    }
+  }
 }
 
 std::vector<uint32_t> query_scatter_table(const ParamSet& P) {
@@ -99,7 +111,8 @@ std::vector<uint32_t> query_scatter_table(const ParamSet& P) {
   if (P.subring()) {  // every slot of query ql's orbit carries its value
     const SubringSlots ss(P);
     for (uint32_t ql = 0; ql < P.B(); ++ql)
-      for (uint32_t c = 0; c < P.Kp(); ++c) tab[pos[ss.slot_of(ql, c)]] = ql;
+      for (uint32_t v = 0; v < P.r; ++v)
+        for (uint32_t c = 0; c < P.Kp(); ++c) tab[pos[ss.slot_of(ql, c, v)]] = ql | (v << 16);
     return tab;
   }
   for (uint32_t rho = 0; rho < 2; ++rho)
@@ -351,11 +364,12 @@ ephdc_status encrypt_model_host(const ParamSet& P, const int8_t* sk, const int8_
     // slot vector of ciphertext m, placed at transform positions, then mu = Encode(v)
     std::vector<uint32_t> mu(N, 0);
     if (subring) {
-      for (uint32_t ql = 0; ql < P.B(); ++ql)
-        for (uint32_t c = 0; c < P.K; ++c) {
-          int v = class_hv[(size_t)c * P.D + m];
-          mu[H.pos[subring->slot_of(ql, c)]] = v < 0 ? (uint32_t)(P.t + v) : (uint32_t)v;
-        }
+      for (uint32_t u = 0; u < P.r && m * P.r + u < P.D; ++u)
+        for (uint32_t ql = 0; ql < P.B(); ++ql)
+          for (uint32_t c = 0; c < P.K; ++c) {
+            int v = class_hv[(size_t)c * P.D + m * P.r + u];
+            mu[H.pos[subring->slot_of(ql, c, u)]] = v < 0 ? (uint32_t)(P.t + v) : (uint32_t)v;
+          }
     }
     for (uint32_t rho = 0; rho < 2 && !subring; ++rho)
       for (uint32_t u = 0; u < P.r; ++u) {

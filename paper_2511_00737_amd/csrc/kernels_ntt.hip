@@ -584,8 +584,9 @@ constexpr bool mac_prefetch() {
 // ------------------------------------------------------------------ subring layout
 // In the subring layout every query plaintext is p(X) = p~(X^K'), K' = N/n, so
 //  * its batch encoding is the n-point inverse transform (root zeta^K') of its n orbit
-//    values, and query ql of the group sits at n-point evaluation position ql: a lane's
-//    inputs are E consecutive bytes of the group's hypervector row;
+//    values; block v of query ql of the group sits at n-point evaluation position
+//    ql*r + v and holds dimension m*r + v (r = 1: a lane's inputs are E consecutive bytes
+//    of the group's hypervector row);
 //  * its transform mod q_l is the n-point forward transform of p~ (root psi^K'), and the
 //    value at N-point evaluation position x is the n-point output at position x >> log2 K'.
 // The n-point twiddle tables are the first n entries of the N-point ones (the bit reversal
@@ -641,23 +642,34 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   // transformed plaintexts of the chunk: [m - m_base][l][g][y]
   uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + ((size_t)(m0 - a.m_base) * L * a.G + g) * n;
   const uint32_t lo = (uint32_t)lane * E * 4u;  // byte offset of the lane's outputs
+  const uint32_t r = a.r, lr = __builtin_ctz(r);
   for (uint32_t m = m0 + wave; m < m1; m += nwave) {
-    uint32_t w[E / 4];
-    const int8_t* src = hvg + (size_t)m * sg.stride;
-    if constexpr (E == 16) {
-      const uint4 q = *reinterpret_cast<const uint4*>(src);
-      w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-    } else if constexpr (E == 8) {
-      const uint2 q = *reinterpret_cast<const uint2*>(src);
-      w[0] = q.x; w[1] = q.y;
-    } else {
-      w[0] = *reinterpret_cast<const uint32_t*>(src);
-    }
     uint32_t v[E];
+    if (r == 1) {
+      uint32_t w[E / 4];
+      const int8_t* src = hvg + (size_t)m * sg.stride;
+      if constexpr (E == 16) {
+        const uint4 q = *reinterpret_cast<const uint4*>(src);
+        w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+      } else if constexpr (E == 8) {
+        const uint2 q = *reinterpret_cast<const uint2*>(src);
+        w[0] = q.x; w[1] = q.y;
+      } else {
+        w[0] = *reinterpret_cast<const uint32_t*>(src);
+      }
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int h = (int)(w[i >> 2] << (24 - 8 * (i & 3))) >> 24;  // signed byte i
-      v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));                 // h mod t
+      for (int i = 0; i < E; ++i) {
+        const int h = (int)(w[i >> 2] << (24 - 8 * (i & 3))) >> 24;  // signed byte i
+        v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));                 // h mod t
+      }
+    } else {
+      // folded: position y holds query y >> log2 r at dimension m*r + (y mod r), zero past D
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t y = (uint32_t)lane * E + i, j = m * r + (y & (r - 1));
+        const int h = j < a.D ? (int)sg.hv[j * sg.stride + (y >> lr)] : 0;
+        v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));
+      }
     }
     ntt_inverse<LOGn, LEs, true, true>(v, lane, a.inv_t, a.pct_sub, b);
     int32_t c[E];  // centred lift, coefficient layout lane + i*T
@@ -1149,7 +1161,7 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
 uint32_t sub_group_tile(uint32_t G) { return G > 4 ? 8u : 4u; }
 
 bool subring_kernels(int logn, int sub_logn) {
-  return logn >= 11 && logn <= 13 && sub_logn >= 8 && sub_logn <= 12 && sub_logn < logn;
+  return logn >= 11 && logn <= 14 && sub_logn >= 8 && sub_logn <= 12 && sub_logn < logn && logn - sub_logn <= 5;
 }
 
 template <class F>

@@ -28,7 +28,8 @@ struct ParamSet {
   bool subring() const { return layout == EPHDC_LAYOUT_SUBRING; }
   uint32_t Kp() const { return subring() ? 1u << ilog2(K) : K; }  // class slots per query (ilog2 rounds up)
   uint32_t Bq() const { return W() / K; }              // queries per row (contiguous layout)
-  uint32_t B() const { return subring() ? N / Kp() : 2 * Bq(); }  // queries per ciphertext
+  uint32_t n() const { return N / Kp(); }               // orbits of the subring layout
+  uint32_t B() const { return subring() ? n() / r : 2 * Bq(); }  // queries per ciphertext
   uint32_t M() const { return (D + r - 1) / r; }       // model ciphertexts
   uint32_t G(uint32_t Q) const { return (Q + B() - 1) / B(); }
   uint32_t log2r() const { return (uint32_t)ilog2(r); }
@@ -64,16 +65,23 @@ inline uint32_t slot_index(const ParamSet& P, uint32_t rho, uint32_t u, uint32_t
   return rho * (P.N / 2) + u * P.W() + ql * P.K + c;
 }
 
-// Slots of the subring layout: slot_of(ql, c) is the slot of exponent
-// 2*brev(ql) + 1 + 2B*c mod 2N (query ql < B, class c < K').
+// Slots of the subring layout.  With n = N/K' orbits of H = {h = 1 (mod 2n)} (orbit y: the
+// exponents = 2*brev(y) + 1 mod 2n, position y of the n-point transform), block v of query
+// ql < B = n/r takes orbit ql*r + v, and class c < K' of it is the exponent
+// gamma^u * (e_ql + 2n*c) mod 2N, with gamma = 1 + 2n/r, e_ql = 2*brev(ql) + 1 over log2 B
+// bits and u < r the power for which gamma^u * e_ql lies in orbit ql*r + v (u = 0 at
+// v = 0).  The Galois elements gamma^(2^i) of rotate-and-sum then gather the r blocks of
+// each class into block 0.
 struct SubringSlots {
   std::vector<uint32_t> of_exp;  // odd exponent -> slot
-  uint32_t N = 0, B = 0;
+  std::vector<uint32_t> u_of;    // [ql * r + v] -> u
+  std::vector<uint64_t> gpow;    // gamma^u mod 2N, u < r
+  uint32_t N = 0, n = 0, B = 0, r = 1;
   int logb = 0;
   explicit SubringSlots(const ParamSet& P);
-  uint32_t slot_of(uint32_t ql, uint32_t c) const {
-    const uint64_t e = (2ull * bitrev(ql, logb) + 1 + 2ull * B * c) % (2ull * N);
-    return of_exp[e];
+  uint32_t slot_of(uint32_t ql, uint32_t c, uint32_t v = 0) const {
+    const uint64_t e = (2ull * bitrev(ql, logb) + 1 + 2ull * n * c) % (2ull * N);
+    return of_exp[gpow[u_of[(size_t)ql * r + v]] * e % (2ull * N)];
   }
 };
 
@@ -82,8 +90,10 @@ struct SubringSlots {
 ephdc_status encrypt_model_host(const ParamSet& P, const int8_t* sk, const int8_t* class_hv, uint64_t seed,
                                 uint32_t* model_ct);
 
-// Galois element of rotate-and-sum step i: 3^(W * 2^i) mod 2N.
+// Galois element of rotate-and-sum step i: 3^(W * 2^i) mod 2N (contiguous layout: rotates
+// each row by W * 2^i slots), or gamma^(2^i) mod 2N with gamma = 1 + 2n/r (subring layout).
 inline uint32_t galois_element(const ParamSet& P, uint32_t i) {
+  if (P.subring()) return (uint32_t)powmod64(1 + 2 * P.n() / P.r, 1ull << i, 2ull * P.N);
   return (uint32_t)powmod64(3, (uint64_t)P.W() << i, 2ull * P.N);
 }
 

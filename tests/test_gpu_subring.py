@@ -201,3 +201,75 @@ def test_subring_batch_of_many_groups_on_one_model():
         assert np.array_equal(to_host_u32(single[4]).astype(np.int64), pipeline.score_ciphertexts(o, model, hs[4]))
     finally:
         s.close()
+
+
+def make_fold(N, L, D, K, r, dnum, alpha=2, F=64):
+    primes = default_primes(N, L + alpha)
+    args = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum, layout="subring")
+    o = OParams(**args)
+    o.validate()
+    return o, ep.Params(**args)
+
+
+def score_fold(e, model, gk, h, stride_offset=0):
+    torch = torch_cuda()
+    Q = h.shape[0]
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), to_dev(gk.astype(np.uint32)), max_Q=Q)
+    try:
+        stride = s.hv_stride(Q)
+        lay = hv_layout(h, stride).reshape(-1)
+        buf = torch.zeros(lay.size + 64, dtype=torch.int8, device="cuda")
+        buf[stride_offset:stride_offset + lay.size] = to_dev(lay)
+        out = torch.empty((s.num_groups(Q), 2, e.L, e.N), dtype=torch.int32, device="cuda")
+        ep.ephdc_score_encrypted(s, buf[stride_offset:stride_offset + lay.size], Q, out)
+        torch.cuda.synchronize()
+        return to_host_u32(out).astype(np.int64)
+    finally:
+        s.close()
+
+
+# (N, L, K, D, Q, r, dnum): folded subring layout, n = N/K' of 1024 and 256, D not a
+# multiple of r, ragged last groups, five groups (work items of eight groups)
+FOLD_CASES = [(4096, 3, 3, 37, 700, 4, 2), (8192, 4, 7, 30, 1500, 2, 2), (2048, 2, 2, 21, 300, 8, 2),
+              (8192, 4, 26, 20, 300, 4, 4)]
+
+
+@pytest.mark.parametrize("N,L,K,D,Q,r,dnum", FOLD_CASES)
+def test_folded_subring_scores_match_oracle(N, L, K, D, Q, r, dnum):
+    """Folded subring layout (n-point kernels, then rotate-and-sum with the layout's Galois
+    elements): score ciphertexts word for word against the oracle, the same ciphertexts
+    through the N-point kernels (hypervectors at an odd byte offset), exact decrypted scores."""
+    o, e = make_fold(N, L, D, K, r, dnum)
+    rng = np.random.default_rng(N + K + D + r)
+    C = values(rng, 8, (K, D))
+    h = values(rng, 1, (Q, D))
+    sk = bfv.secret_key(o, 5)
+    model = bfv.encrypt_model(o, sk, C, 5)
+    gk = bfv.galois_keys(o, sk, 6)
+    got = score_fold(e, model, gk, h)
+    want = pipeline.score_ciphertexts(o, model, h, gk)
+    assert np.array_equal(got, want)
+    assert np.array_equal(score_fold(e, model, gk, h, stride_offset=3), want)
+    sc, _ = ep.ephdc_decrypt_scores(e, sk.astype(np.int8), got.astype(np.uint32), Q)
+    assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))
+
+
+def test_folded_subring_at_the_rotation_workload_shape():
+    """N = 16384, 8 limbs + 2 special primes, 4 digits, K = 26 (K' = 32, n = 512), r = 8
+    (64 queries per ciphertext): the last group matches the oracle bit for bit, every group
+    equals the N-point kernels' result, and every score decrypts exactly."""
+    N, L, K, D, Q, r = 16384, 8, 26, 40, 300, 8
+    o, e = make_fold(N, L, D, K, r, dnum=4)
+    rng = np.random.default_rng(26)
+    C = values(rng, 8, (K, D))
+    h = values(rng, 1, (Q, D))
+    sk = bfv.secret_key(o, 7)
+    model = bfv.encrypt_model(o, sk, C, 7)
+    gk = bfv.galois_keys(o, sk, 8)
+    got = score_fold(e, model, gk, h)
+    G = o.groups(Q)
+    want = pipeline.score_ciphertexts(o, model, h, gk, groups=[G - 1])
+    assert np.array_equal(got[G - 1], want[0])
+    assert np.array_equal(score_fold(e, model, gk, h, stride_offset=5), got)
+    sc, _ = ep.ephdc_decrypt_scores(e, sk.astype(np.int8), got.astype(np.uint32), Q)
+    assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))

@@ -230,9 +230,11 @@ def test_other_schemes_and_plaintext_primes_match_oracle(N, t, scheme):
     assert np.array_equal(sc2, want2)
 
 
-def _sub_pair(N, L=3, D=16, K=3, F=16):
-    primes = default_primes(N, L)
-    kw = dict(N=N, q=tuple(primes), F=F, D=D, K=K, layout="subring")
+def _sub_pair(N, L=3, D=16, K=3, F=16, r=1):
+    primes = default_primes(N, L + (2 if r > 1 else 0))
+    kw = dict(N=N, q=tuple(primes[:L]), F=F, D=D, K=K, layout="subring")
+    if r > 1:
+        kw.update(r=r, p=tuple(primes[L:]), dnum=2)
     return OParams(**kw), ep.Params(**kw)
 
 
@@ -244,8 +246,15 @@ def test_subring_layout_sizes_and_validation():
         for Q in (1, o.B, o.B + 1, 4096):
             assert ep.ephdc_num_groups(e, Q) == o.groups(Q)
             assert ep.ephdc_hv_stride(e, Q) == o.groups(Q) * o.B
-    # r > 1 and K' > N/2 are refused; so is an unknown layout
-    _, e2 = _pair(64, L=4, D=16, K=2, r=4, alpha=2, dnum=2)
+    # folded: N/(K' r) queries per ciphertext
+    for N, K, r in [(64, 3, 2), (16384, 26, 8), (16384, 26, 4), (8192, 7, 2), (64, 2, 16)]:
+        o, e = _sub_pair(N, L=4, K=K, r=r)
+        assert ep.ephdc_check_params(e) == ep.OK
+        assert ep.ephdc_queries_per_ct(e) == o.B == N // (o.Kp * r)
+        for Q in (1, o.B + 1, 16384):
+            assert ep.ephdc_num_groups(e, Q) == o.groups(Q)
+    # K' > N/2 and fewer than two queries per ciphertext are refused; so is an unknown layout
+    _, e2 = _pair(64, L=4, D=16, K=2, r=32, alpha=2, dnum=2)
     assert ep.ephdc_check_params(ep.Params(**{**e2.__dict__, "_keep": [], "layout": "subring"})) == ep.ERR_PARAMS
     _, e3 = _sub_pair(16, K=9)
     assert ep.ephdc_check_params(e3) == ep.ERR_PARAMS
@@ -273,3 +282,22 @@ def test_subring_model_encryption_and_decryption_match_oracle(N, K, D):
     for q_first, Q in [(3, o.B), (o.B - 1, 2)]:
         sc2, _ = ep.ephdc_decrypt_scores_at(e, run["s"].astype(np.int8), run["score_ct"].astype(np.uint32), q_first, Q)
         assert np.array_equal(sc2, run["scores"][q_first:q_first + Q])
+
+
+@pytest.mark.parametrize("N,K,D,r", [(64, 3, 11, 2), (64, 2, 13, 4), (128, 5, 20, 2), (128, 2, 17, 8)])
+def test_folded_subring_encryption_keys_and_decryption_match_oracle(N, K, D, r):
+    """Folded subring layout on the host: model ciphertexts, Galois keys (the layout's own
+    elements) and decrypted scores after rotate-and-sum equal the oracle's."""
+    o, e = _sub_pair(N, L=4, D=D, K=K, r=r)
+    C = synth.class_hypervectors(51, K, D)
+    sk, gk = ep.ephdc_keygen(e, 51)
+    assert np.array_equal(ep.ephdc_encrypt_model(e, sk, C, 51).astype(np.int64),
+                          bfv.encrypt_model(o, sk.astype(np.int64), C, 51))
+    assert np.array_equal(gk.astype(np.int64).reshape(-1), bfv.galois_keys(o, sk.astype(np.int64), 51).reshape(-1))
+    Qn = 2 * o.B + 3
+    x = synth.uniform_features(52, Qn, o.F)
+    base = synth.base_hypervectors(52, o.F, o.D)
+    run = pipeline.run(o, x, base, C, seed=51)
+    sc, am = ep.ephdc_decrypt_scores(e, run["s"].astype(np.int8), run["score_ct"].astype(np.uint32), Qn)
+    assert np.array_equal(sc, run["scores"])
+    assert np.array_equal(sc, hdc.scores_mod_t(run["h"], C, 65537))
