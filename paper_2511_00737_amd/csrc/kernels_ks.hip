@@ -113,6 +113,24 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_moddown_ntt(const uint32_
   const int tid = threadIdx.x;
   const PrimeConst pq = pcs[i];
   const uint32_t q2 = 2 * pq.m;
+  // the operands of the last step, in the transform's output layout (positions tid*E + e):
+  // requested together at the start, so that each lane's run is read in one burst and the
+  // loads overlap the conversion and the transform
+  const uint32_t off = (uint32_t)tid * S::E * 4u;
+  const uint32_t* ks = KS + (((size_t)g * 2 + c) * k.nmod + i) * S::N;
+  const uint32_t* r0 = R + (((size_t)g * 2 + 0) * k.L + i) * S::N;
+  uint32_t* a = acc + (((size_t)g * 2 + c) * k.L + i) * S::N;
+  uint32_t kv[S::E], av[S::E], rv[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; e += 4) {
+    const uint4 x = ld_at(reinterpret_cast<const uint4*>(ks), off + 4u * e);
+    const uint4 y = ld_at(reinterpret_cast<const uint4*>(a), off + 4u * e);
+    kv[e] = x.x; kv[e + 1] = x.y; kv[e + 2] = x.z; kv[e + 3] = x.w;
+    av[e] = y.x; av[e + 1] = y.y; av[e + 2] = y.z; av[e + 3] = y.w;
+    uint4 z = make_uint4(0, 0, 0, 0);
+    if (c == 0) z = ld_at(reinterpret_cast<const uint4*>(r0), off + 4u * e);
+    rv[e] = z.x; rv[e + 1] = z.y; rv[e + 2] = z.z; rv[e + 3] = z.w;
+  }
   uint32_t v[S::E];
 #pragma unroll
   for (int e = 0; e < S::E; ++e) v[e] = 0;
@@ -130,19 +148,15 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_moddown_ntt(const uint32_
 #pragma unroll
   for (int e = 0; e < S::E; ++e) v[e] = csub(v[e], pq.m);
   ntt_forward<LOGN, LE>(v, tid, fwd_tw + (size_t)i * S::N, pq, b);
-  const size_t off = (size_t)tid * S::E;
-  const uint32_t* ks = KS + (((size_t)g * 2 + c) * k.nmod + i) * S::N + off;
-  const uint32_t* r0 = R + (((size_t)g * 2 + 0) * k.L + i) * S::N + off;
-  uint32_t* a = acc + (((size_t)g * 2 + c) * k.L + i) * S::N + off;
   const uint2 pinv = k.pinv[i];
 #pragma unroll
   for (int e = 0; e < S::E; ++e) {
     const uint32_t conv = reduce4(v[e], pq.m);
-    const uint32_t d = csub(mul_shoup(ks[e] + pq.m - conv, pinv.x, pinv.y, pq.m), pq.m);
-    uint32_t s = csub(a[e] + d, pq.m);
-    if (c == 0) s = csub(s + r0[e], pq.m);
-    a[e] = s;
+    const uint32_t d = csub(mul_shoup(kv[e] + pq.m - conv, pinv.x, pinv.y, pq.m), pq.m);
+    v[e] = csub(csub(av[e] + d, pq.m) + rv[e], pq.m);  // rv = 0 for c = 1
   }
+#pragma unroll
+  for (int e = 0; e < S::E; e += 4) st_at(reinterpret_cast<uint4*>(a), off + 4u * e, make_uint4(v[e], v[e + 1], v[e + 2], v[e + 3]));
 }
 
 }  // namespace ephdc_dev

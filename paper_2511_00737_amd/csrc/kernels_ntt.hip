@@ -595,9 +595,16 @@ constexpr bool mac_prefetch() {
 // exchanges inside the wave's own LDS region.
 //
 // Two kernels: k_encode_sub turns each query plaintext into its L transformed n-point
-// vectors (a.pt[m - m_base][l][g][y], lazy in [0, 4 q_l), weighted by the scaling op), and
+// vectors (a.pt[m - m_base][l][blk][g][y mod ypi], weighted by the scaling op; in [0, q_l)
+// for launches of more than four groups, else in [0, 2 q_l)), and
 // k_mac_sub streams the model once: a work item owns a block of evaluation positions of one
 // limb for up to four query groups.
+
+// Streaming MAC work items: kSubThreads threads over 2 * kSubThreads evaluation positions,
+// which read the n-point positions [blk * ypi, (blk + 1) * ypi) with ypi = 2 * kSubThreads / K'.
+// The transformed plaintexts are stored [m - m_base][l][blk][g][ypi], so that the values an
+// item reads for one ciphertext and its groups are contiguous.
+constexpr int kSubThreads = 256;
 
 // LDS offset of the wave-local exchange buffer inside an exchange plan (see exchange()).
 template <int LOGN, int LE>
@@ -621,7 +628,9 @@ constexpr size_t encode_sub_lds_bytes() {
   return (S::T == 64 ? 4 * S::PADN : LdsPlan<LOGn, LEs>::exchange_words) * sizeof(uint32_t);
 }
 
-// Work item (split, g); transform j of the workgroup takes plaintexts m0 + j, m0 + j + TPW, ...
+// Work item (split, group quad): transform j of the workgroup takes group TPW * quad + j
+// and every plaintext of the split, so that the workgroup's stores of one plaintext fill
+// the adjacent slots [blk][g .. g + TPW) of the MAC's layout at about the same time.
 template <int LOGn, int LEs>
 __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_sub(ScoreArgs a) {
   using S = Shape<LOGn, LEs>;
@@ -630,8 +639,9 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   constexpr int TPW = encode_sub_threads<LOGn, LEs>() / S::T;  // transforms per workgroup
   const int lane = threadIdx.x % S::T, wave = threadIdx.x / S::T;
   LdsBufs b{0, one_wave ? wave * S::PADN - local_exchange_offset<LOGn, LEs>() : 0};
-  const int nwave = TPW;
-  const uint32_t g = blockIdx.x % a.G, split = blockIdx.x / a.G;
+  const uint32_t nq = (a.G + TPW - 1) / TPW;
+  const uint32_t g = blockIdx.x % nq * TPW + wave, split = blockIdx.x / nq;
+  if (g >= a.G) return;  // a one-wave transform past the last group (no workgroup barrier follows)
   const uint32_t m0 = a.m_base + split * a.mchunk;
   const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
   const uint32_t t = a.pct_sub.m, L = a.L;
@@ -639,11 +649,14 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   // queries of the group (lane*E + i), rows of pitch `stride`
   const SubGroup sg = a.vg ? a.vg[g] : SubGroup{a.hv + (size_t)g * a.B, a.hv_stride, 0};
   const int8_t* hvg = sg.hv + (uint32_t)lane * E;
-  // transformed plaintexts of the chunk: [m - m_base][l][g][y]
-  uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + ((size_t)(m0 - a.m_base) * L * a.G + g) * n;
-  const uint32_t lo = (uint32_t)lane * E * 4u;  // byte offset of the lane's outputs
+  // transformed plaintexts of the chunk: [m - m_base][l][blk][g][y mod ypi]; a lane's E
+  // outputs lie in one block (E <= ypi for K' <= 32)
+  uint32_t* dst = reinterpret_cast<uint32_t*>(a.pt) + (size_t)(m0 - a.m_base) * L * a.G * n;
+  const uint32_t ypi = (2u * kSubThreads) >> a.sub_logk, y0 = (uint32_t)lane * E;
+  const uint32_t lo = ((y0 / ypi) * a.G * ypi + g * ypi + y0 % ypi) * 4u;  // byte offset of the lane's outputs
+  const bool full = a.G > 4;  // the MAC's eight-group tiles take fully reduced values
   const uint32_t r = a.r, lr = __builtin_ctz(r);
-  for (uint32_t m = m0 + wave; m < m1; m += nwave) {
+  for (uint32_t m = m0; m < m1; ++m) {
     uint32_t v[E];
     if (r == 1) {
       uint32_t w[E / 4];
@@ -685,6 +698,12 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
       for (int i = 0; i < E; ++i) v[i] = pc.m + (uint32_t)c[i];  // |c| <= t/2: in [0, 2m), = c mod m
       ntt_forward<LOGn, LEs, false, true>(v, lane, a.fwd_tw + (size_t)l * N, pc, b);
       apply_scale(v, a.scale, m, l, pc);
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = csub(v[i], 2 * pc.m);
+      if (full) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = csub(v[i], pc.m);
+      }
       uint32_t* dl = d + (size_t)l * a.G * n;
 #pragma unroll
       for (int i = 0; i < E; i += 4)
@@ -693,19 +712,38 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   }
 }
 
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+// Buffer resource for raw loads at a uniform address (no range limit): the base lives in
+// scalar registers and every load adds a lane offset and a scalar offset, so no per-lane
+// address arithmetic is needed.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, -1, 0x00020000);
+}
+
 // MAC: work item (group tile, limb, position block, split).  Thread tid owns evaluation
 // positions x0 = blk*512 + 2*tid and x0 + 1, which share the n-point value y = x0 >> log2 K'
-// (K' >= 2), for the up to four groups of its tile: per model ciphertext two words of c0
-// and c1 and one transformed value per group, accumulated in 64-bit lazy sums as in
-// mac_item64 (folded every second plaintext).  The loads run kSubDepth ciphertexts ahead.
-// Group tiles hold four groups, or eight when a launch scores more than four (batches).
-constexpr int kSubThreads = 256, kSubDepth = 4;
+// (K' >= 2), for the four or eight groups of its tile: per model ciphertext two words of c0
+// and c1 and one transformed value per group, accumulated in 64-bit lazy sums.  The model
+// word is below q < 2^30; the transformed value is below 2q for four-group tiles (a product
+// below 2^61: four products fit above a folded sum, < 2^62 + 2^32) and below q for
+// eight-group tiles (below 2^60: eight fit), so the sums fold every fourth or eighth
+// ciphertext.  The loads run kSubDepth ciphertexts ahead through buffer resources at
+// uniform bases; a tile's groups past the last one read the last group's values (their
+// sums are not stored).  Tiles hold four groups, or eight when a launch scores more than
+// four (batches, folded models).
+constexpr int kSubDepth = 4;
 
 template <int LOGKP, int kSubGroups>
 __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
   static_assert(LOGKP >= 1, "two positions per thread share one n-point value");
+  constexpr int kFoldRounds = kSubGroups == 8 ? 2 : 1;
+  static_assert(kSubDepth * kFoldRounds == (kSubGroups == 8 ? 8 : 4), "products between folds");
   const uint32_t N = (1u << a.sub_logn) << LOGKP, n = 1u << a.sub_logn, L = a.L;
   const uint32_t nblk = N / (2 * kSubThreads), ntile = (a.G + kSubGroups - 1) / kSubGroups;
+  constexpr uint32_t ypi = (2u * kSubThreads) >> LOGKP;
   // item order: group tile, then limb, then position block, then split -- the tiles that
   // read one model slice are neighbours, and the XCD map runs neighbours on one XCD
   uint32_t w = XcdMap{a.xcd, a.nitems}.item(blockIdx.x);
@@ -720,12 +758,15 @@ __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
   const uint32_t m1 = min(a.m_base + a.m_len, m0 + a.mchunk);
   const uint32_t x0 = blk * 2 * kSubThreads + 2 * threadIdx.x, y = x0 >> LOGKP;
   const PrimeConst pc = a.pcs[l];
-  // model words of (m, c): model + ((m * 2 + c) * L + l) * N + x0
-  const uint32_t* mod = a.model + (size_t)l * N + x0;
+  // model words of (m, c): model + ((m * 2 + c) * L + l) * N + x0 (lane byte offset mo)
+  const uint32_t* mod = a.model + (size_t)l * N;
+  const uint32_t mo = x0 * 4u;
   const size_t mstride = (size_t)2 * L * N, cstride = (size_t)L * N;
-  // transformed values of (g, m): pt + (((m - m_base) * L + l) * G + g) * n + y
-  const uint32_t* pv = reinterpret_cast<const uint32_t*>(a.pt) + ((size_t)l * a.G + g0) * n + y;
-  const size_t gstride = n, pmstride = (size_t)L * a.G * n;
+  // transformed values of (g, m): pt + (((m - m_base) * L + l) * nblk + blk) * G * ypi +
+  // g * ypi + y mod ypi (lane byte offset po)
+  const uint32_t* pv = reinterpret_cast<const uint32_t*>(a.pt) + ((size_t)l * nblk + blk) * a.G * ypi + (size_t)g0 * ypi;
+  const uint32_t po = (y % ypi) * 4u;
+  const size_t pmstride = (size_t)L * a.G * n;
 
   uint64_t acc[kSubGroups][2][2];
 #pragma unroll
@@ -743,47 +784,72 @@ __global__ __launch_bounds__(kSubThreads) void k_mac_sub(ScoreArgs a) {
       acc[k][c][1] = s1;
     }
 
+  // byte strides of the loads: ciphertext m and component c of the model, plaintext m and
+  // group k of the transformed values
+  const uint32_t mb_ = (uint32_t)mstride * 4u, cb = (uint32_t)cstride * 4u, pb = (uint32_t)pmstride * 4u,
+                 gb = ypi * 4u;
   struct Stage {
-    uint2 c0, c1;
+    v2u c0, c1;
     uint32_t p[kSubGroups];
   };
-  auto load = [&](Stage& s, uint32_t m) {
-    const uint32_t* mm = mod + (size_t)m * mstride;
-    s.c0 = *reinterpret_cast<const uint2*>(mm);
-    s.c1 = *reinterpret_cast<const uint2*>(mm + cstride);
-    const uint32_t* pm = pv + (size_t)(m - a.m_base) * pmstride;
+  // the loads of ciphertext d of a round: buffer resources at the round's uniform bases,
+  // the lane's byte offset in a register and the ciphertext's and group's in scalars
+  auto load = [&](Stage& st, const __amdgpu_buffer_rsrc_t& rm, const __amdgpu_buffer_rsrc_t& rp, int d) {
+    st.c0 = __builtin_amdgcn_raw_buffer_load_b64(rm, mo, d * mb_, 0);
+    st.c1 = __builtin_amdgcn_raw_buffer_load_b64(rm, mo, d * mb_ + cb, 0);
 #pragma unroll
-    for (int k = 0; k < kSubGroups; ++k) s.p[k] = (uint32_t)k < ng ? pm[(size_t)k * gstride] : 0u;
+    for (int k = 0; k < kSubGroups; ++k)
+      st.p[k] = __builtin_amdgcn_raw_buffer_load_b32(rp, po, d * pb + min((uint32_t)k, ng - 1) * gb, 0);
   };
-  Stage ring[kSubDepth];
+  auto mac = [&](const Stage& st) {
 #pragma unroll
-  for (int d = 0; d < kSubDepth; ++d)
-    if (m0 + d < m1) load(ring[d], m0 + d);
-  for (uint32_t mb = m0; mb < m1; mb += kSubDepth) {
+    for (int k = 0; k < kSubGroups; ++k) {
+      acc[k][0][0] += (uint64_t)st.c0.x * st.p[k];
+      acc[k][0][1] += (uint64_t)st.c0.y * st.p[k];
+      acc[k][1][0] += (uint64_t)st.c1.x * st.p[k];
+      acc[k][1][1] += (uint64_t)st.c1.y * st.p[k];
+    }
+  };
+  auto fold = [&] {
+#pragma unroll
+    for (int k = 0; k < kSubGroups; ++k)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        acc[k][c][0] = fold64(acc[k][c][0], pc.r1);
+        acc[k][c][1] = fold64(acc[k][c][1], pc.r1);
+      }
+  };
+  auto rsrc_model = [&](uint32_t m) { return uniform_rsrc(mod + (size_t)m * mstride); };
+  auto rsrc_pt = [&](uint32_t m) { return uniform_rsrc(pv + (size_t)(m - a.m_base) * pmstride); };
+  Stage ring[kSubDepth];
+  uint32_t m = m0, round = 0;
+  if (m < m1) {
+    const auto rm = rsrc_model(m), rp = rsrc_pt(m);
+#pragma unroll
+    for (int d = 0; d < kSubDepth; ++d)
+      if (m + d < m1) load(ring[d], rm, rp, d);
+  }
+  // full rounds whose next round is full too: each slot is used, then refilled for the
+  // ciphertext kSubDepth ahead, without branches
+  for (; m + 2 * kSubDepth <= m1; m += kSubDepth, ++round) {
+    const auto rm = rsrc_model(m + kSubDepth), rp = rsrc_pt(m + kSubDepth);
 #pragma unroll
     for (int d = 0; d < kSubDepth; ++d) {
-      const uint32_t m = mb + d;
-      if (m < m1) {
-        const Stage s = ring[d];
-        if (m + kSubDepth < m1) load(ring[d], m + kSubDepth);
-#pragma unroll
-        for (int k = 0; k < kSubGroups; ++k) {
-          acc[k][0][0] += (uint64_t)s.c0.x * s.p[k];
-          acc[k][0][1] += (uint64_t)s.c0.y * s.p[k];
-          acc[k][1][0] += (uint64_t)s.c1.x * s.p[k];
-          acc[k][1][1] += (uint64_t)s.c1.y * s.p[k];
-        }
-        if (d & 1) {
-#pragma unroll
-          for (int k = 0; k < kSubGroups; ++k)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              acc[k][c][0] = fold64(acc[k][c][0], pc.r1);
-              acc[k][c][1] = fold64(acc[k][c][1], pc.r1);
-            }
-        }
-      }
+      mac(ring[d]);
+      load(ring[d], rm, rp, d);
     }
+    if (round % kFoldRounds == kFoldRounds - 1) fold();
+  }
+  // the last one or two rounds
+  for (; m < m1; m += kSubDepth, ++round) {
+    const uint32_t next = m + kSubDepth;
+    const auto rm = rsrc_model(next < m1 ? next : m), rp = rsrc_pt(next < m1 ? next : m);
+#pragma unroll
+    for (int d = 0; d < kSubDepth; ++d) {
+      if (m + d < m1) mac(ring[d]);
+      if (next + d < m1) load(ring[d], rm, rp, d);
+    }
+    if (round % kFoldRounds == kFoldRounds - 1) fold();
   }
 #pragma unroll
   for (int k = 0; k < kSubGroups; ++k) {
@@ -1158,7 +1224,13 @@ hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a0, uint32_t nb
   });
 }
 
-uint32_t sub_group_tile(uint32_t G) { return G > 4 ? 8u : 4u; }
+// Groups per streaming-MAC tile for a launch of G groups: four, or eight above four.
+static uint32_t sub_tile(uint32_t G) { return G > 4 ? 8u : 4u; }
+
+uint32_t mac_sub_items(uint32_t N, uint32_t L, uint32_t G) {
+  const uint32_t gt = sub_tile(G);
+  return (N / (2 * kSubThreads)) * L * ((G + gt - 1) / gt);
+}
 
 bool subring_kernels(int logn, int sub_logn) {
   return logn >= 11 && logn <= 14 && sub_logn >= 8 && sub_logn <= 12 && sub_logn < logn && logn - sub_logn <= 5;
@@ -1176,16 +1248,18 @@ hipError_t dispatch_sub(int sub_logn, F&& f) {
   }
 }
 
-hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st) {
-  if (nblocks == 0) return hipSuccess;
+hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t splits, hipStream_t st) {
+  if (splits == 0 || a.G == 0) return hipSuccess;
   return dispatch_sub(sub_logn, [&](auto lc) {
     constexpr int LS = decltype(lc)::value, LE = sub_le(LS);
-    k_encode_sub<LS, LE><<<dim3(nblocks), dim3(encode_sub_threads<LS, LE>()), encode_sub_lds_bytes<LS, LE>(), st>>>(a);
+    constexpr uint32_t TPW = encode_sub_threads<LS, LE>() / Shape<LS, LE>::T;
+    const dim3 grid((a.G + TPW - 1) / TPW * splits);
+    k_encode_sub<LS, LE><<<grid, dim3(encode_sub_threads<LS, LE>()), encode_sub_lds_bytes<LS, LE>(), st>>>(a);
     return hipGetLastError();
   });
 }
 
-uint32_t mac_sub_resident_blocks(uint32_t tile) {
+uint32_t mac_sub_resident_blocks(uint32_t G) {
   auto count = [](const void* f) {
     int per_cu = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSubThreads, 0) != hipSuccess ||
@@ -1195,7 +1269,7 @@ uint32_t mac_sub_resident_blocks(uint32_t tile) {
     return (uint32_t)std::max(1, per_cu * cus);
   };
   static const uint32_t n4 = count((const void*)k_mac_sub<3, 4>), n8 = count((const void*)k_mac_sub<3, 8>);
-  return tile == 8 ? n8 : n4;
+  return sub_tile(G) == 8 ? n8 : n4;
 }
 
 hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t nblocks, hipStream_t st) {
@@ -1206,7 +1280,7 @@ hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a0, uint32_t 
   a.xcd = xm.on;
   a.nitems = nblocks;
   const dim3 grid(xm.slots());
-  const bool wide = sub_group_tile(a.G) == 8;
+  const bool wide = sub_tile(a.G) == 8;
   switch ((logn - sub_logn) * 2 + (wide ? 1 : 0)) {
     case 2: k_mac_sub<1, 4><<<grid, dim3(kSubThreads), 0, st>>>(a); break;
     case 3: k_mac_sub<1, 8><<<grid, dim3(kSubThreads), 0, st>>>(a); break;

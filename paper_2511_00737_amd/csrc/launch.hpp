@@ -212,13 +212,14 @@ hipError_t launch_score(int logn, int le, int lg, const ScoreArgs& a, uint32_t n
 // split path: batch-encode every (g, m) plaintext of the launch into a.pt, then MAC
 hipError_t launch_encode_pt(int logn, int le, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
 hipError_t launch_mac(int logn, int le, int lg, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
-// subring layout: batch encoding with the n-point transforms of every limb (G x splits
-// items), and the streaming MAC (position blocks x L x group tiles x S items)
+// subring layout: batch encoding with the n-point transforms of every limb (G groups x
+// `splits` ranges of a.mchunk plaintexts), and the streaming MAC (position blocks x L x
+// group tiles x S items)
 bool subring_kernels(int logn, int sub_logn);
-hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
+hipError_t launch_encode_sub(int sub_logn, const ScoreArgs& a, uint32_t splits, hipStream_t st);
 hipError_t launch_mac_sub(int logn, int sub_logn, const ScoreArgs& a, uint32_t nblocks, hipStream_t st);
-uint32_t mac_sub_resident_blocks(uint32_t tile);  // streaming-MAC workgroups resident at once (tile: 4 or 8)
-uint32_t sub_group_tile(uint32_t G);  // groups per streaming-MAC work item for a launch of G groups
+uint32_t mac_sub_resident_blocks(uint32_t G);  // streaming-MAC workgroups resident at once for G groups
+uint32_t mac_sub_items(uint32_t N, uint32_t L, uint32_t G);  // streaming-MAC work items per split of G groups
 bool supported_shape(int logn, int le);
 hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_t* out, uint32_t G, uint32_t S,
                          uint32_t L, const uint32_t* itw, const PrimeConst* pcs, hipStream_t st);

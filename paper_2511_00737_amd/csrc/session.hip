@@ -155,9 +155,9 @@ hipError_t score_split(ephdc_session* s, ScoreArgs a, const Schedule& sc, size_t
 
 // Subring layout: the batch-encoding kernel writes each query plaintext's n-point
 // transforms for every limb (L*n words; a workspace that holds c N-word plaintexts holds
-// c*N/(L*n) of them), then the streaming MAC reads the model once per chunk: work items of
-// 512 evaluation positions x one limb x up to four groups x one split of the chunk, as many
-// as fit the device at once.
+// c*N/(L*n) of them), then the streaming MAC reads the model once per chunk and group
+// tile: work items of 512 evaluation positions x one limb x one to three tiles of four or
+// eight groups x one split of the chunk, as many as fit the device at once.
 hipError_t score_split_sub(ephdc_session* s, ScoreArgs a, uint32_t Q, size_t pt_cap, size_t partial_words,
                            Schedule& sc, hipStream_t hs) {
   const ParamSet& P = s->P;
@@ -236,17 +236,21 @@ std::vector<uint32_t> automorphism_perms(const ParamSet& P) {
 namespace ephdc {
 
 uint32_t sub_splits(const ParamSet& P, uint32_t G) {
-  const uint32_t gt = sub_group_tile(G), per = (P.N / 512) * P.L * ((G + gt - 1) / gt);
-  const uint32_t S = std::max<uint32_t>(1, mac_sub_resident_blocks(gt) / per);
+  const uint32_t per = mac_sub_items(P.N, P.L, G);
+  const uint32_t S = std::max<uint32_t>(1, mac_sub_resident_blocks(G) / per);
   return std::min({S, P.M(), std::max<uint32_t>(1, kMaxBlocks / G)});
 }
 
 hipError_t run_sub(const ephdc_session* s, ScoreArgs a, size_t pt_cap, ephdc_session* timing, hipStream_t hs) {
   const ParamSet& P = s->P;
   const uint32_t M = P.M(), n = 1u << s->sub_logn, G = a.G, S = a.S;
-  const uint32_t gt = sub_group_tile(G), per = (P.N / 512) * P.L * ((G + gt - 1) / gt);
-  constexpr uint32_t kEncodeBlocks = 2048;
+  const uint32_t per = mac_sub_items(P.N, P.L, G);
+  constexpr uint32_t kEncodeTransforms = 8192;
   const size_t cap = pt_cap * P.N / ((size_t)P.L * n);
+  // the MAC's loads take 32-bit byte offsets from a round's first ciphertext: four
+  // ciphertexts of transformed values (and of the model) must span less than 4 GiB
+  if ((4 * (uint64_t)P.L * G + G) * n * 4 >= (1ull << 32) || 8ull * P.L * P.N * 4 >= (1ull << 32))
+    return hipErrorInvalidValue;
   // chunks of mc ciphertexts; every chunk's MAC covers S splits (empty ones write or keep
   // their sums), so S <= mc keeps each split non-empty in full chunks
   const uint32_t mc = (uint32_t)std::max<size_t>(std::max<size_t>(1, S), std::min<size_t>(M, cap / G));
@@ -257,11 +261,12 @@ hipError_t run_sub(const ephdc_session* s, ScoreArgs a, size_t pt_cap, ephdc_ses
     c.m_base = base;
     c.m_len = len;
     c.accumulate = base > 0;
-    uint32_t Se = std::max<uint32_t>(1, std::min(len, (kEncodeBlocks + G - 1) / G));
+    // batch encoding: about kEncodeTransforms transforms in flight, one per (group, split)
+    uint32_t Se = std::max<uint32_t>(1, std::min(len, (kEncodeTransforms + G - 1) / G));
     c.mchunk = (len + Se - 1) / Se;
     Se = (len + c.mchunk - 1) / c.mchunk;
     hipEvent_t t0 = timing ? timed_begin(timing, hs) : nullptr;
-    hipError_t e = launch_encode_sub((int)s->sub_logn, c, G * Se, hs);
+    hipError_t e = launch_encode_sub((int)s->sub_logn, c, Se, hs);
     if (e != hipSuccess) return e;
     if (timing) timed_end(timing, kStEncodePt, t0, hs);
     c.mchunk = (len + S - 1) / S;
