@@ -21,15 +21,12 @@
 
 namespace ephdc_dev {
 
-// out[p][x] = in[p][perm[x]] for every polynomial p of the batch.
+// out[p][x] = in[p][perm[x]] for every polynomial p of the batch: grid (N / 256, npolys).
 __global__ void k_automorph(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                            const uint32_t* __restrict__ perm, size_t npolys, uint32_t N) {
-  const size_t total = npolys * N;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const size_t poly = i / N;
-    const uint32_t x = (uint32_t)(i - poly * N);
-    out[i] = in[poly * N + perm[x]];
-  }
+                            const uint32_t* __restrict__ perm, uint32_t N) {
+  const size_t base = (size_t)blockIdx.y * N;
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  out[base + x] = in[base + perm[x]];
 }
 
 // Y[g][j][m] = NTT_m( sum_{i in I_j} [D[g][i] * (Q_j/q_i)^-1]_{q_i} * (Q_j/q_i mod m) ) for
@@ -72,32 +69,38 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_modup_ntt(const uint32_t*
 }
 
 // KS[g][c][m] = sum_j ksk[j][c][m] (Montgomery form) * (m in I_j ? R[g][1][m] : Y[g][j][m]).
+// Grid (N / 1024, G * nmod) of 256 threads; a thread takes four consecutive positions and
+// both components, so each digit value is read once.
 __global__ void k_ks_inner(const uint32_t* __restrict__ R, const uint32_t* __restrict__ Y,
                            const uint32_t* __restrict__ ksk, uint32_t* __restrict__ KS, KsConst k,
                            const PrimeConst* __restrict__ pcs, uint32_t N) {
-  const size_t total = (size_t)k.G * 2 * k.nmod * N;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t x = (uint32_t)(idx % N);
-    const size_t rest = idx / N;
-    const uint32_t m = (uint32_t)(rest % k.nmod);
-    const uint32_t c = (uint32_t)((rest / k.nmod) % 2);
-    const uint32_t g = (uint32_t)(rest / (2 * k.nmod));
-    const PrimeConst pc = pcs[m];
-    uint32_t acc = 0;
-    for (uint32_t j = 0; j < k.dnum; ++j) {
-      const uint32_t i0 = j * k.ds, i1 = min(k.L, i0 + k.ds);
-      const uint32_t src = (m >= i0 && m < i1) ? R[(((size_t)g * 2 + 1) * k.L + m) * N + x]
-                                               : Y[(((size_t)g * k.dnum + j) * k.nmod + m) * N + x];
-      const uint32_t key = ksk[(((size_t)j * 2 + c) * k.nmod + m) * N + x];
-      acc = csub(acc + mont_mul(key, src, pc.m, pc.mneg_inv), 2 * pc.m);
+  const uint32_t m = blockIdx.y % k.nmod, g = blockIdx.y / k.nmod;
+  const uint32_t xo = (blockIdx.x * blockDim.x + threadIdx.x) * 16u;  // byte offset of 4 positions
+  const PrimeConst pc = pcs[m];
+  uint32_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
+  for (uint32_t j = 0; j < k.dnum; ++j) {
+    const uint32_t i0 = j * k.ds, i1 = min(k.L, i0 + k.ds);
+    const uint32_t* src = (m >= i0 && m < i1) ? R + (((size_t)g * 2 + 1) * k.L + m) * N
+                                              : Y + (((size_t)g * k.dnum + j) * k.nmod + m) * N;
+    const uint4 sv = ld_at(reinterpret_cast<const uint4*>(src), xo);
+    const uint4 k0 = ld_at(reinterpret_cast<const uint4*>(ksk + (((size_t)j * 2 + 0) * k.nmod + m) * N), xo);
+    const uint4 k1 = ld_at(reinterpret_cast<const uint4*>(ksk + (((size_t)j * 2 + 1) * k.nmod + m) * N), xo);
+    const uint32_t sx[4] = {sv.x, sv.y, sv.z, sv.w}, kx0[4] = {k0.x, k0.y, k0.z, k0.w},
+                   kx1[4] = {k1.x, k1.y, k1.z, k1.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a0[e] = csub(a0[e] + mont_mul(kx0[e], sx[e], pc.m, pc.mneg_inv), 2 * pc.m);
+      a1[e] = csub(a1[e] + mont_mul(kx1[e], sx[e], pc.m, pc.mneg_inv), 2 * pc.m);
     }
-    KS[idx] = csub(acc, pc.m);
   }
+  uint32_t* out0 = KS + (((size_t)g * 2 + 0) * k.nmod + m) * N;
+  uint32_t* out1 = KS + (((size_t)g * 2 + 1) * k.nmod + m) * N;
+  st_at(reinterpret_cast<uint4*>(out0), xo,
+        make_uint4(csub(a0[0], pc.m), csub(a0[1], pc.m), csub(a0[2], pc.m), csub(a0[3], pc.m)));
+  st_at(reinterpret_cast<uint4*>(out1), xo,
+        make_uint4(csub(a1[0], pc.m), csub(a1[1], pc.m), csub(a1[2], pc.m), csub(a1[3], pc.m)));
 }
 
-// acc[g][c][i] += (c == 0 ? R[g][0][i] : 0) + (KS[g][c][i] - NTT_i(conv_P(XP[g][c]))) * P^-1 mod q_i,
-// where conv_P(x) = sum_k [x_k * (P/p_k)^-1]_{p_k} * (P/p_k mod q_i).
 template <int LOGN, int LE>
 __global__ __launch_bounds__((1 << LOGN) >> LE) void k_moddown_ntt(const uint32_t* __restrict__ XP,
                                                                     const uint32_t* __restrict__ KS,
@@ -176,14 +179,14 @@ hipError_t prepare_ks_kernels() {
   return e;
 }
 
-static unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 65536); }
-
 hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipStream_t st) {
   const KsConst& k = r.k;
   const uint32_t N = 1u << logn;
   const size_t acc_polys = (size_t)k.G * 2 * k.L;
+  // grid shapes below: y counts polynomials (automorphism) and (group, modulus) pairs
+  if (N % 1024 != 0 || acc_polys > 65535u || (size_t)k.G * k.nmod > 65535u) return hipErrorInvalidValue;
   // R = sigma_g(acc)
-  k_automorph<<<grid_for(acc_polys * N), 256, 0, st>>>(r.acc, r.R, r.perm + (size_t)step * N, acc_polys, N);
+  k_automorph<<<dim3(N / 256, (unsigned)acc_polys), 256, 0, st>>>(r.acc, r.R, r.perm + (size_t)step * N, N);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // D = iNTT(R[g][1][l]) for every group and limb
@@ -202,7 +205,7 @@ hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipS
   if (e != hipSuccess) return e;
   // KS = inner product with the switching keys of this step
   const uint32_t* ksk = r.ksk + (size_t)step * k.dnum * 2 * k.nmod * N;
-  k_ks_inner<<<grid_for((size_t)k.G * 2 * k.nmod * N), 256, 0, st>>>(r.R, r.Y, ksk, r.KS, k, r.pcs, N);
+  k_ks_inner<<<dim3(N / 1024, k.G * k.nmod), 256, 0, st>>>(r.R, r.Y, ksk, r.KS, k, r.pcs, N);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // XP = iNTT of the special limbs of KS
