@@ -61,7 +61,7 @@ enum {
   EPHDC_LAYOUT_CONTIGUOUS = 0, /* the K copies of a query in K consecutive slots of a row; B = 2 floor(N/(2rK)) */
   EPHDC_LAYOUT_SUBRING = 1     /* the K' copies of a query (K' the power of two >= K) on one orbit of
                                   {h = 1 mod 2N/K'} acting on the slot exponents: every query plaintext
-                                  is a polynomial in X^K'; B = N/K'; r = 1 only */
+                                  is a polynomial in X^K'; B = N/(K' r) */
 };
 
 /*
@@ -91,17 +91,22 @@ enum {
  *          is multiplied by the plaintext scalar c = centred (2^scale_shift)^-1 mod t, which
  *          divides the plaintext by 2^scale_shift wherever it is divisible.  A trailing
  *          block of fewer than g additions is not scaled.  0 <= scale_shift < 32.
- *   layout EPHDC_LAYOUT_CONTIGUOUS (the default) or EPHDC_LAYOUT_SUBRING.  Subring layout:
- *          query ql < B = N/K' of a ciphertext takes the slots of exponents
- *          2*brev(ql) + 1 + 2B*c mod 2N (brev over log2 B bits), class c < K' (slot s < N/2
- *          is the exponent 3^s mod 2N, slot N/2 + s its negation); the model holds class c's
+ *   layout EPHDC_LAYOUT_CONTIGUOUS (the default) or EPHDC_LAYOUT_SUBRING.  Subring layout,
+ *          with n = N/K' and B = n/r: block v < r of query ql < B of a ciphertext holds
+ *          dimension m*r + v on the K' slots of exponents gamma^u * (e + 2n*c) mod 2N, class
+ *          c < K', where e = 2*brev(ql) + 1 (brev over log2 B bits), gamma = 1 + 2n/r and u < r
+ *          is the power for which gamma^u * e = 2*brev(ql*r + v) + 1 (mod 2n), brev over
+ *          log2 n bits (u = 0 at v = 0; for r = 1 the exponents are e + 2n*c).  Slot s < N/2
+ *          is the exponent 3^s mod 2N, slot N/2 + s its negation.  The model holds class c's
  *          value at c < K and 0 at K <= c < K', the query plaintext the query's value at all
- *          K' slots.  Its plaintexts are polynomials in X^K', so their transforms are
- *          N/K'-point transforms (scoring runs that shorter transform where the kernels
- *          implement it).  Needs r = 1 and K' <= N/2.
+ *          K' slots.  Rotation step i uses the Galois element gamma^(2^i) mod 2N, which sums
+ *          the r blocks of each class into block 0 (where the scores are read).  Its
+ *          plaintexts are polynomials in X^K', so their transforms are n-point transforms
+ *          (scoring runs that shorter transform where the kernels implement it: 256 <= n <=
+ *          4096 and K' <= 32).  Needs B >= 2.
  *
  * Derived: Bq = floor(W/K) queries per row, B = 2*Bq queries per ciphertext (subring: B =
- * N/K'), M = ceil(D/r) model ciphertexts, G = ceil(Q/B) score ciphertexts for Q queries.
+ * N/(K' r)), M = ceil(D/r) model ciphertexts, G = ceil(Q/B) score ciphertexts for Q queries.
  */
 typedef struct {
   uint32_t N, L, alpha, dnum;
@@ -145,8 +150,9 @@ ephdc_status ephdc_gaussian_cdt(uint64_t out[39]);
  *                (seed, tag 4), value (u mod 3) - 1
  *   galois_keys  out, uint32 [log2 r][dnum][2][L+alpha][N], coefficient domain, limbs in
  *                the order q[0..L-1], p[0..alpha-1]; component 0 is b, 1 is a.  May be NULL
- *                when r == 1.  Key (i, j) switches from sigma_g(s), g = 3^(W*2^i) mod 2N,
- *                to s for digit j: b = -a*s + e + G_j*sigma_g(s), G_j = P (product of the
+ *                when r == 1.  Key (i, j) switches from sigma_g(s) to s for digit j, g the
+ *                layout's Galois element of step i (contiguous: 3^(W*2^i) mod 2N; subring:
+ *                gamma^(2^i) mod 2N, gamma = 1 + 2n/r): b = -a*s + e + G_j*sigma_g(s), G_j = P (product of the
  *                special primes) on the digit's limbs and 0 on all others; a uniform per
  *                limb and e discrete Gaussian from stream (seed, tag 6), draws starting at
  *                ((i*dnum + j) * (L+alpha+1)) * N.
