@@ -274,16 +274,18 @@ def bench_batched(args, w) -> int:
 def profile_unpacked(args, w) -> int:
     """For counter runs: the batching workload's unpacked batch alone, enqueued launch by launch
     (no graph, no autotuner: the default schedule, which the autotuner keeps at this size),
-    `--steps` runs after `--warmup`; prints ms per run."""
+    `--steps` runs after `--warmup`; prints ms per run.  Contiguous layout unless
+    `--layout subring`."""
     import torch
     N, L, F, nreq = w["N"], w["L"], w["F"], w["requests"]
+    layout = "subring" if args.layout == "subring" else "contiguous"
     primes = ep.default_primes(N, L)
     sizes, midx = synth.batch_mix(args.seed, nreq, len(w["models"]))
     dev = torch.device("cuda")
     d_pool = torch.from_numpy(synth.blob_images(args.seed, 4096)).to(dev)
     sessions, bases = [], []
     for k, (K, D) in enumerate(w["models"]):
-        prm = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K)
+        prm = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K, layout=layout)
         sk, _ = ep.ephdc_keygen(prm, args.seed + k)
         model = ep.ephdc_encrypt_model(prm, sk, synth.class_hypervectors(args.seed + k, K, D), args.seed + k)
         sessions.append(ep.Session(prm, torch.from_numpy(model.view(np.int32)).to(dev), max_Q=4096, workspace=None))
@@ -305,7 +307,7 @@ def profile_unpacked(args, w) -> int:
         batch.run(stream)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
-    print(json.dumps({"form": "unpacked batch, eager", "runs": args.steps, "warmup": args.warmup,
+    print(json.dumps({"form": "unpacked batch, eager", "layout": layout, "runs": args.steps, "warmup": args.warmup,
                       "ms_per_run": round(ms, 4), "schedule": batch.schedule()}), flush=True)
     batch.close()
     for s in sessions:
@@ -466,7 +468,7 @@ def run_batched(args, w, layout: str = "contiguous"):
                   schedule=psched, autotune_s=round(t_ptune, 1))
     packed_eager = form(eager_wall, eager_lat, work_packed, "the packed batch enqueued launch by launch, no graph")
     # HBM bytes of one unpacked run, recorded by counter runs of --profile-unpacked
-    run_traffic = recorded_traffic("batch_unpacked", "c3") if layout == "contiguous" else None
+    run_traffic = recorded_traffic("batch_unpacked", "c3" if layout == "contiguous" else "c3_subring")
     unpacked["roofline"]["traffic"] = run_traffic
     if run_traffic is not None:
         gbps = run_traffic / (unpacked["ms_per_step"] * 1e-3)
