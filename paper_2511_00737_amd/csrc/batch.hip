@@ -254,7 +254,8 @@ void build_subs(ephdc_batch* b) {
       sm.rd[li].out = rq.d_score_ct;
       sm.rd[li].r = 1;
       for (uint32_t g = 0; g < G; ++g, ++v) {
-        sm.vg[v] = SubGroup{rq.d_hv ? rq.d_hv + (size_t)g * P.B() : nullptr, G * P.B(), 0};
+        sm.vg[v] = SubGroup{rq.d_hv ? rq.d_hv + (size_t)g * P.B() : nullptr, G * P.B(),
+                            std::min(P.B(), rq.Q - g * P.B())};
         sm.fin.push_back(FinishItem{li, g, v * sm.S, sm.S});
       }
     }
@@ -271,7 +272,8 @@ size_t sub_partial_words(const ephdc_batch* b) {
 // pointers are filled once the batch's block is placed.  With packing, each request writes
 // exactly its own columns [off, off + Q) of its session's buffer (the session's last request
 // also zeroes the padding up to the end of the rows), so the tiles of all requests can run
-// in one launch without overlapping writes.
+// in one launch without overlapping writes.  Requests scored by the subring models write
+// their Q columns only: the n-point batch encoding reads the padding as zero.
 void build_aux(ephdc_batch* b) {
   b->hdc.clear();
   b->tiles.clear();
@@ -301,8 +303,8 @@ void build_aux(ephdc_batch* b) {
       const ephdc_request& v = b->reqs[b->vreq[i]];
       const ParamSet& P = rq.session->P;
       const uint32_t stride = P.G(v.Q) * P.B(), off = b->qoff[i];
-      const bool last = off + rq.Q == v.Q;
-      add(rq, v.d_hv ? v.d_hv + off : nullptr, stride, last ? stride - off : rq.Q);
+      const bool pad = off + rq.Q == v.Q && !takes_subring(b, v);
+      add(rq, v.d_hv ? v.d_hv + off : nullptr, stride, pad ? stride - off : rq.Q);
       const uint32_t g0 = off / P.B(), g1 = (off + rq.Q - 1) / P.B();
       const size_t ct_words = (size_t)2 * P.L * P.N;
       CopyRange c{v.d_score_ct ? v.d_score_ct + g0 * ct_words : nullptr, rq.d_score_ct, (g1 - g0 + 1) * ct_words};
@@ -314,7 +316,7 @@ void build_aux(ephdc_batch* b) {
       if (!rq.d_x) continue;
       const ParamSet& P = rq.session->P;
       const uint32_t stride = P.G(rq.Q) * P.B();
-      add(rq, rq.d_hv, stride, stride);
+      add(rq, rq.d_hv, stride, takes_subring(b, rq) ? rq.Q : stride);
     }
   }
 }

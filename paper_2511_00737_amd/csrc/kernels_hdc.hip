@@ -39,10 +39,12 @@ constexpr uint32_t RSRC_WORD3 = 0x00020000u;  // raw (untyped) buffer access on 
 __device__ __forceinline__ int lds_at(int r, int c) { return r * HK + 16 * (c ^ ((r >> 2) & 3)); }
 
 // Global operands of one contraction chunk, held in registers so that the next chunk's
-// loads are in flight while the current chunk runs on the matrix cores.
+// loads are in flight while the current chunk runs on the matrix cores.  QT: queries per
+// tile (128 or 256).
+template <int QT>
 struct HdcStage {
-  uint32_t d[2][4];  // base: two 4 x 4 byte blocks (4 features x 4 dimensions)
-  uint4 xv[2];       // features: two 16-byte runs (raw bytes; the offset is applied at the store)
+  uint32_t d[2][4];     // base: two 4 x 4 byte blocks (4 features x 4 dimensions)
+  uint4 xv[QT / 64];    // features: 16-byte runs (raw bytes; the offset is applied at the store)
 };
 
 struct HdcSrc {
@@ -50,7 +52,8 @@ struct HdcSrc {
   uint32_t F, D, j0;
 };
 
-__device__ __forceinline__ void hdc_load(HdcStage& st, const HdcSrc& src, uint32_t f0, int tid) {
+template <int QT>
+__device__ __forceinline__ void hdc_load(HdcStage<QT>& st, const HdcSrc& src, uint32_t f0, int tid) {
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int blk = tid + NT * k;
@@ -60,7 +63,10 @@ __device__ __forceinline__ void hdc_load(HdcStage& st, const HdcSrc& src, uint32
 #pragma unroll
     for (int a = 0; a < 4; ++a)
       st.d[k][a] = __builtin_amdgcn_raw_buffer_load_b32(src.base, (f0 + 4 * fq + a) * src.D + j, 0, 0);
-    const int row = blk >> 2, ch = blk & 3;  // 128 queries x 4 runs of 16 features
+  }
+#pragma unroll
+  for (int k = 0; k < QT / 64; ++k) {
+    const int blk = tid + NT * k, row = blk >> 2, ch = blk & 3;  // QT queries x 4 runs of 16 features
     const v4i v = __builtin_amdgcn_raw_buffer_load_b128(src.x, row * src.F + f0 + 16 * ch, 0, 0);
     st.xv[k] = make_uint4(v[0], v[1], v[2], v[3]);
   }
@@ -68,7 +74,8 @@ __device__ __forceinline__ void hdc_load(HdcStage& st, const HdcSrc& src, uint32
 
 // base rows [f][j] -> a_lds[32 * (j % 4) + j / 4][f] (4 x 4 byte-block transposes);
 // features -> b_lds[q][f] as x - 128 (x ^ 0x80 on each byte)
-__device__ __forceinline__ void hdc_store(const HdcStage& st, uint8_t* a_lds, uint8_t* b_lds, int tid) {
+template <int QT>
+__device__ __forceinline__ void hdc_store(const HdcStage<QT>& st, uint8_t* a_lds, uint8_t* b_lds, int tid) {
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int blk = tid + NT * k;
@@ -87,25 +94,31 @@ __device__ __forceinline__ void hdc_store(const HdcStage& st, uint8_t* a_lds, ui
       const int r = 32 * bb + jq;
       *reinterpret_cast<uint32_t*>(a_lds + lds_at(r, fq >> 2) + 4 * (fq & 3)) = col[bb];
     }
-    const int row = blk >> 2, ch = blk & 3;
+  }
+#pragma unroll
+  for (int k = 0; k < QT / 64; ++k) {
+    const int blk = tid + NT * k, row = blk >> 2, ch = blk & 3;
     uint4 v = st.xv[k];
     v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
     *reinterpret_cast<uint4*>(b_lds + lds_at(row, ch)) = v;
   }
 }
 
-// One 128 x 128 output tile (dimensions j0.., queries q0..).
+// One 128 x QT output tile (dimensions j0.., queries q0..); each wave computes a 64 x QT/2
+// quarter as 4 x QT/32 MFMA tiles.
+template <int QT>
 __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
                                          int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
                                          uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift,
                                          uint32_t j0, uint32_t q0) {
+  constexpr int SUBQ = QT / 2 / 16;
   // two LDS buffers per operand: chunk k is read from buffer k % 2 while chunk k + 1 is stored
   // into the other, so one barrier per chunk suffices
   __shared__ __attribute__((aligned(16))) uint8_t a_lds[2][HT * HK];  // [32 * (j % 4) + j / 4][f]
-  __shared__ __attribute__((aligned(16))) uint8_t b_lds[2][HT * HK];  // [q][f]
+  __shared__ __attribute__((aligned(16))) uint8_t b_lds[2][QT * HK];  // [q][f]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wj = (wave >> 1) * (HT / 2), wq = (wave & 1) * (HT / 2);
+  const int wj = (wave >> 1) * (HT / 2), wq = (wave & 1) * (QT / 2);
 
   HdcSrc src;
   // the resources must live in scalar registers: the row base and its length are uniform
@@ -116,16 +129,16 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
   src.base = __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(base), 0, (int)(F * D), RSRC_WORD3);
   src.F = F; src.D = D; src.j0 = j0;
 
-  v4i acc[SUB][SUB];
+  v4i acc[SUB][SUBQ];
 #pragma unroll
   for (int a = 0; a < SUB; ++a)
 #pragma unroll
-    for (int b = 0; b < SUB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    for (int b = 0; b < SUBQ; ++b) acc[a][b] = v4i{0, 0, 0, 0};
 
   // a tile whose queries all lie past Q (padding columns of the last query group) holds
   // zeros only: it skips the contraction and goes straight to the stores
   const uint32_t F_run = q0 < Q ? F : 0u;
-  HdcStage st;
+  HdcStage<QT> st;
   if (F_run) {
     hdc_load(st, src, 0, tid);
     hdc_store(st, a_lds[0], b_lds[0], tid);
@@ -136,17 +149,17 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
     // buffer `cur` holds chunk f0 (stored by every wave), and every wave is done reading the
     // other buffer (chunk f0 - HK)
     __syncthreads();
-    v4i av[SUB], bv[SUB];
+    v4i av[SUB], bv[SUBQ];
 #pragma unroll
     for (int a = 0; a < SUB; ++a)
       av[a] = *reinterpret_cast<const v4i*>(a_lds[cur] + lds_at(wj + 16 * a + (lane & 15), lane >> 4));
 #pragma unroll
-    for (int b = 0; b < SUB; ++b)
+    for (int b = 0; b < SUBQ; ++b)
       bv[b] = *reinterpret_cast<const v4i*>(b_lds[cur] + lds_at(wq + 16 * b + (lane & 15), lane >> 4));
 #pragma unroll
     for (int a = 0; a < SUB; ++a)
 #pragma unroll
-      for (int b = 0; b < SUB; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv[b], av[a], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < SUBQ; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv[b], av[a], acc[a][b], 0, 0, 0);
     // while the matrix cores work: chunk f0 + HK (loaded an iteration ago) into the other
     // buffer, and the loads of chunk f0 + 2 HK
     if (f0 + HK < F) {
@@ -165,7 +178,7 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
     const int r = wj + 16 * a + (lane & 15);
     const uint32_t j = j0 + 4 * (r & 31) + (r >> 5);
 #pragma unroll
-    for (int b = 0; b < SUB; ++b) {
+    for (int b = 0; b < SUBQ; ++b) {
       const uint32_t q = q0 + wq + 16 * b + 4 * (lane >> 4);
       if (j >= D || q >= ncols) continue;
       uint32_t w = 0;
@@ -186,10 +199,10 @@ __device__ __forceinline__ void hdc_tile(const uint8_t* __restrict__ x, const in
   }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_hdc_encode(const uint8_t* __restrict__ x, const int8_t* __restrict__ base,
                                                     int8_t* __restrict__ hv, uint32_t Q, uint32_t F, uint32_t D,
                                                     uint32_t stride, uint32_t ncols, uint32_t qbits, uint32_t qshift) {
-  hdc_tile(x, base, hv, Q, F, D, stride, ncols, qbits, qshift, blockIdx.x * HT, blockIdx.y * HT);
+  hdc_tile<2 * HT>(x, base, hv, Q, F, D, stride, ncols, qbits, qshift, blockIdx.x * HT, blockIdx.y * 2 * HT);
 }
 
 // Many requests in one launch: workgroup w encodes tile tiles[w] of request reqs[tile.req].
@@ -197,7 +210,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                          const HdcTile* __restrict__ tiles) {
   const HdcTile t = tiles[blockIdx.x];
   const HdcReq r = reqs[t.req];
-  hdc_tile(r.x, r.base, r.hv, r.Q, r.F, r.D, r.stride, r.ncols, r.qbits, r.qshift, t.j0, t.q0);
+  hdc_tile<HT>(r.x, r.base, r.hv, r.Q, r.F, r.D, r.stride, r.ncols, r.qbits, r.qshift, t.j0, t.q0);
 }
 
 // Copies of many word ranges in one launch (16-byte moves; every range is a multiple of
@@ -234,7 +247,7 @@ hipError_t launch_hdc_encode(const uint8_t* x, const int8_t* base, int8_t* hv, u
                              uint32_t stride, uint32_t qbits, uint32_t qshift, hipStream_t st, uint32_t ncols) {
   if (ncols == 0 || ncols > stride) ncols = stride;
   if (ncols == 0) return hipSuccess;
-  dim3 grid((D + ephdc_dev::HT - 1) / ephdc_dev::HT, (ncols + ephdc_dev::HT - 1) / ephdc_dev::HT);
+  dim3 grid((D + ephdc_dev::HT - 1) / ephdc_dev::HT, (ncols + 2 * ephdc_dev::HT - 1) / (2 * ephdc_dev::HT));
   ephdc_dev::k_hdc_encode<<<grid, dim3(256), 0, st>>>(x, base, hv, Q, F, D, stride, ncols, qbits, qshift);
   return hipGetLastError();
 }

@@ -647,7 +647,7 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   const uint32_t t = a.pct_sub.m, L = a.L;
   const uint32_t N = (uint32_t)n << a.sub_logk;
   // queries of the group (lane*E + i), rows of pitch `stride`
-  const SubGroup sg = a.vg ? a.vg[g] : SubGroup{a.hv + (size_t)g * a.B, a.hv_stride, 0};
+  const SubGroup sg = a.vg ? a.vg[g] : SubGroup{a.hv + (size_t)g * a.B, a.hv_stride, a.B};
   const int8_t* hvg = sg.hv + (uint32_t)lane * E;
   // transformed plaintexts of the chunk: [m - m_base][l][blk][g][y mod ypi]; a lane's E
   // outputs lie in one block (E <= ypi for K' <= 32)
@@ -672,15 +672,16 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
       }
 #pragma unroll
       for (int i = 0; i < E; ++i) {
-        const int h = (int)(w[i >> 2] << (24 - 8 * (i & 3))) >> 24;  // signed byte i
-        v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));                 // h mod t
+        int h = (int)(w[i >> 2] << (24 - 8 * (i & 3))) >> 24;  // signed byte i
+        if ((uint32_t)lane * E + i >= sg.nq) h = 0;              // no query at this position
+        v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));           // h mod t
       }
     } else {
       // folded: position y holds query y >> log2 r at dimension m*r + (y mod r), zero past D
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         const uint32_t y = (uint32_t)lane * E + i, j = m * r + (y & (r - 1));
-        const int h = j < a.D ? (int)sg.hv[j * sg.stride + (y >> lr)] : 0;
+        const int h = j < a.D && (y >> lr) < sg.nq ? (int)sg.hv[j * sg.stride + (y >> lr)] : 0;
         v[i] = (uint32_t)h + (t & (uint32_t)(h >> 31));
       }
     }

@@ -23,10 +23,12 @@ struct ScaleOp {
 };
 
 // Where the queries of one (virtual) query group of the subring kernels come from: the
-// group's first column in its request's hypervectors, and their row pitch.
+// group's first column in its request's hypervectors, their row pitch, and how many of the
+// group's B query positions hold queries (the batch encoding reads the others as zero, so
+// their columns need not be written).
 struct SubGroup {
   const int8_t* hv;
-  uint32_t stride, pad;
+  uint32_t stride, nq;
 };
 
 // Arguments of the fused scoring kernel (and the debug plaintext kernel).

@@ -273,3 +273,59 @@ def test_folded_subring_at_the_rotation_workload_shape():
     assert np.array_equal(score_fold(e, model, gk, h, stride_offset=5), got)
     sc, _ = ep.ephdc_decrypt_scores(e, sk.astype(np.int8), got.astype(np.uint32), Q)
     assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))
+
+
+def test_subring_batch_encodes_queries_without_touching_padding():
+    """Batches that encode their queries on the device (HDC in the batch) write only the Q
+    columns of a subring request's hypervectors: the n-point batch encoding reads the other
+    positions of the last group as zero.  Buffers filled with nonzero bytes beforehand still
+    give the oracle's ciphertexts; packed, where the sequence's padding is not written either,
+    every request still decrypts to its own exact scores."""
+    torch = torch_cuda()
+    from oracle import hdc as ohdc
+    o, e = make(2048, 2, 64, 3, F=48)  # K' = 4, B = 512 (the encoder takes D % 64 == 0)
+    rng = np.random.default_rng(14)
+    C = values(rng, 8, (o.K, o.D))
+    sk = bfv.secret_key(o, 14)
+    model = bfv.encrypt_model(o, sk, C, 14)
+    base = synth.base_hypervectors(14, o.F, o.D)
+    d_base = to_dev(base)
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), max_Q=1200)
+    sizes = [700, 3, 1100, 512]
+    xs = [synth.uniform_features(20 + k, Q, o.F) for k, Q in enumerate(sizes)]
+    hs = [ohdc.encode(x, base, o.qbits, o.qshift) for x in xs]
+    try:
+        reqs = []
+        for Q, x in zip(sizes, xs):
+            d_hv = torch.full((o.D, s.hv_stride(Q)), 77, dtype=torch.int8, device="cuda")
+            out = torch.zeros((s.num_groups(Q), 2, o.L, o.N), dtype=torch.int32, device="cuda")
+            reqs.append(ep.Request(s, d_hv, Q, out, d_x=to_dev(x), d_base=d_base))
+        b = ep.Batch(reqs)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+        for k, (r, h) in enumerate(zip(reqs, hs)):
+            Q = h.shape[0]
+            assert (r.d_hv.cpu().numpy()[:, Q:] == 77).all(), k  # the padding columns were not written
+            assert np.array_equal(to_host_u32(r.d_score_ct).astype(np.int64), pipeline.score_ciphertexts(o, model, h)), k
+        # packed: one query sequence for the four requests
+        preqs = []
+        for Q, x in zip(sizes, xs):
+            out = torch.zeros((s.num_groups(Q) + 1, 2, o.L, o.N), dtype=torch.int32, device="cuda")
+            preqs.append(ep.Request(s, None, Q, out, d_x=to_dev(x), d_base=d_base))
+        b = ep.Batch(preqs, packed=True)
+        try:
+            for rep in range(2):
+                b.run()
+                torch.cuda.synchronize()
+                for k, (r, h) in enumerate(zip(preqs, hs)):
+                    off, qf, nct = b.packing(k)
+                    got = to_host_u32(r.d_score_ct)[:nct]
+                    scores, _ = ep.ephdc_decrypt_scores_at(e, sk.astype(np.int8), got, qf, h.shape[0])
+                    assert np.array_equal(scores, ohdc.scores_mod_t(h, C, o.t)), (rep, k)
+        finally:
+            b.close()
+    finally:
+        s.close()
