@@ -396,8 +396,19 @@ __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcn
 // three-buffer plan).
 struct LdsBufs {
   int sel;
-  int base = 0;  // word offset added to every exchange buffer (several transforms per workgroup)
+  int base = 0;      // word offset added to every exchange buffer (several transforms per workgroup)
+  bool one = false;  // every exchange in one buffer, behind a workgroup barrier (see one_buffer())
 };
+
+// Kernels with one transform per workgroup and few registers may run every exchange in a
+// single buffer (a barrier before each exchange) where the plan's two buffers would keep a
+// CU to one workgroup: at N = 16384 two 1024-thread workgroups then share a CU, so one's
+// memory phases overlap the other's transform.  The kernel's dynamic LDS is then PADN words.
+template <int LOGN, int LE>
+constexpr bool one_buffer() {
+  constexpr int bytes = Shape<LOGN, LE>::PADN * 4;
+  return !LdsPlan<LOGN, LE>::three && 4 * bytes > 160 * 1024 && 2 * bytes <= 160 * 1024;
+}
 
 template <int LOGN, int LE, int PF, int PT>
 __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int tid) {
@@ -409,7 +420,10 @@ __device__ __forceinline__ void exchange(uint32_t (&v)[1 << LE], LdsBufs& b, int
   static_assert(layout_conflicts<LOGN, LE, PF>(pd) == 0 && layout_conflicts<LOGN, LE, PT>(pd) == 0,
                 "exchange layouts must hit 64 distinct banks per register");
   int off;
-  if constexpr (local) {
+  if (b.one) {
+    off = 0;
+    lds_barrier();  // every wave has finished reading the previous exchange
+  } else if constexpr (local) {
     off = LdsPlan<LOGN, LE>::three ? 2 * P : P;
   } else if constexpr (LdsPlan<LOGN, LE>::three) {
     off = b.sel * P;

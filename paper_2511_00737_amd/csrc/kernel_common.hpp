@@ -17,6 +17,13 @@ inline size_t lds_bytes() {
   return sizeof(uint32_t) * LdsPlan<LOGN, LE>::words;
 }
 
+// Dynamic LDS of the kernels that run one transform per workgroup without the table and
+// take the single-buffer exchanges where one_buffer() holds.
+template <int LOGN, int LE>
+inline size_t lds_bytes_one_transform() {
+  return one_buffer<LOGN, LE>() ? sizeof(uint32_t) * Shape<LOGN, LE>::PADN : lds_bytes<LOGN, LE>();
+}
+
 // Calls f with the compile-time shape (LOGN, LE) of a supported ring degree; `le` selects
 // the values per thread (0: the default of the degree).
 template <class F>

@@ -42,7 +42,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_modup_ntt(const uint32_t*
   const uint32_t g = blockIdx.x / (k.nmod * k.dnum);
   const uint32_t i0 = j * k.ds, i1 = min(k.L, i0 + k.ds);
   if (m >= i0 && m < i1) return;  // the digit's own limbs are taken from R directly
-  LdsBufs b{0};
+  LdsBufs b{0, 0, one_buffer<LOGN, LE>()};
   const int tid = threadIdx.x;
   const PrimeConst pm = pcs[m];
   const uint32_t m2 = 2 * pm.m;
@@ -198,7 +198,7 @@ hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipS
   // Y = NTT(ModUp(D)) per digit and target modulus
   e = dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
-    k_modup_ntt<LN, LEv><<<dim3(k.G * k.dnum * k.nmod), dim3(Shape<LN, LEv>::T), lds_bytes<LN, LEv>(), st>>>(
+    k_modup_ntt<LN, LEv><<<dim3(k.G * k.dnum * k.nmod), dim3(Shape<LN, LEv>::T), lds_bytes_one_transform<LN, LEv>(), st>>>(
         r.D, r.Y, k, r.fwd_tw, r.pcs);
     return hipGetLastError();
   });

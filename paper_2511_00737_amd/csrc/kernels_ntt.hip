@@ -34,7 +34,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_fwd_batch(const uint32_t*
                                                                   uint32_t nlimb, uint32_t limb_base, int mont,
                                                                   PolyMap pm) {
   using S = Shape<LOGN, LE>;
-  LdsBufs b{0};
+  LdsBufs b{0, 0, one_buffer<LOGN, LE>()};
   const int tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
@@ -60,7 +60,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_inv_batch(const uint32_t*
                                                                   const PrimeConst* __restrict__ pcs,
                                                                   uint32_t nlimb, uint32_t limb_base, PolyMap pm) {
   using S = Shape<LOGN, LE>;
-  LdsBufs b{0};
+  LdsBufs b{0, 0, one_buffer<LOGN, LE>()};
   const int tid = threadIdx.x;
   const size_t poly = blockIdx.x;
   const uint32_t limb = limb_base + (uint32_t)(poly % nlimb);
@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LE) void k_finish(const uint32_t* __
     for (int i = 0; i < S::E; ++i) v[i] = csub(v[i] + src[i], pc.m);
   }
   if constexpr (INVERT) {
-    LdsBufs b{0};
+    LdsBufs b{0, 0, one_buffer<LOGN, LE>()};
     ntt_inverse<LOGN, LE, true>(v, tid, inv_tw + (size_t)l * S::N, pc, b);
     uint32_t* dst = out + (size_t)poly * S::N;
 #pragma unroll
@@ -1134,7 +1134,7 @@ hipError_t launch_fwd_batch(int logn, const uint32_t* in, uint32_t* out, size_t 
   if (npolys == 0) return hipSuccess;
   return dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
-    const size_t sh = lds_bytes<LN, LEv>();
+    const size_t sh = lds_bytes_one_transform<LN, LEv>();
     k_fwd_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(
         in, out, tw, pcs, nlimb, limb_base, mont ? 1 : 0, make_map(map, 1u << LN));
     return hipGetLastError();
@@ -1147,7 +1147,7 @@ hipError_t launch_inv_batch(int logn, const uint32_t* in, uint32_t* out, size_t 
   if (npolys == 0) return hipSuccess;
   return dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
-    const size_t sh = lds_bytes<LN, LEv>();
+    const size_t sh = lds_bytes_one_transform<LN, LEv>();
     k_inv_batch<LN, LEv><<<dim3((unsigned)npolys), dim3(Shape<LN, LEv>::T), sh, st>>>(
         in, out, itw, pcs, nlimb, limb_base, make_map(map, 1u << LN));
     return hipGetLastError();
@@ -1304,7 +1304,7 @@ hipError_t launch_finish(int logn, bool invert, const uint32_t* partial, uint32_
   return dispatch(logn, [&](auto lnc, auto lec) {
     constexpr int LN = decltype(lnc)::value, LEv = decltype(lec)::value;
     const dim3 grid(G * 2 * L), block(Shape<LN, LEv>::T);
-    const size_t sh = lds_bytes<LN, LEv>();
+    const size_t sh = lds_bytes_one_transform<LN, LEv>();
     if (invert)
       k_finish<LN, LEv, true><<<grid, block, sh, st>>>(partial, out, S_, L, itw, pcs);
     else
