@@ -510,8 +510,8 @@ def bench_serving(args, w) -> int:
             N, L, alpha, r, dnum = 8192, 4, 0, 1, 0
         else:
             N, L, alpha, r, dnum = 16384, 8, 2, 4, 4
-        # the N = 8192 tenants in the subring layout (auto), the folded ones contiguous (r = 4)
-        layout = "subring" if r == 1 and args.layout in ("auto", "subring") else "contiguous"
+        # every tenant in the subring layout (auto), the folded N = 16384 ones included
+        layout = "subring" if args.layout in ("auto", "subring") else "contiguous"
         primes = ep.default_primes(N, L + alpha)
         prm = ep.Params(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum,
                         layout=layout)

@@ -112,11 +112,10 @@ int batch_le(const ephdc_batch* b, int logn) { return b->vpt ? ilog2(b->vpt) : (
 // Requests of one list share N, the ciphertext primes and t (their transform tables).
 bool same_chain(const ParamSet& a, const ParamSet& b) { return a.N == b.N && a.q == b.q && a.t == b.t; }
 
-// Requests of unfolded subring sessions whose hypervectors the n-point kernels can read
-// (16-byte aligned; packed buffers are placed aligned) go to the subring models; folded
-// ones (r > 1) take the request lists, which rotate.
+// Requests of subring sessions whose hypervectors the n-point kernels can read (16-byte
+// aligned; packed buffers are placed aligned) go to the subring models.
 bool takes_subring(const ephdc_batch* b, const ephdc_request& rq) {
-  return rq.session->sub_logn && rq.session->P.r == 1 && (b->packed || ((uintptr_t)rq.d_hv & 15) == 0);
+  return rq.session->sub_logn && (b->packed || ((uintptr_t)rq.d_hv & 15) == 0);
 }
 
 // Splits the requests into parameter sets, and the subring models.
@@ -249,10 +248,14 @@ void build_subs(ephdc_batch* b) {
     sm.fin.clear();
     uint32_t v = 0;
     for (uint32_t li = 0; li < sm.reqs.size(); ++li) {
-      const ephdc_request& rq = b->reqs[sm.reqs[li]];
+      const uint32_t ri = sm.reqs[li];
+      const ephdc_request& rq = b->reqs[ri];
       const uint32_t G = P.G(rq.Q);
-      sm.rd[li].out = rq.d_score_ct;
-      sm.rd[li].r = 1;
+      // folded requests: the summed accumulators go to their rotation workspace (placed by
+      // carve(); absent while only measuring)
+      const bool ws = P.r > 1 && ri < b->rot_ws.size() && b->rot_ws[ri];
+      sm.rd[li].out = ws ? b->rot_ws[ri] : rq.d_score_ct;
+      sm.rd[li].r = P.r;
       for (uint32_t g = 0; g < G; ++g, ++v) {
         sm.vg[v] = SubGroup{rq.d_hv ? rq.d_hv + (size_t)g * P.B() : nullptr, G * P.B(),
                             std::min(P.B(), rq.Q - g * P.B())};
@@ -449,6 +452,25 @@ ListArgs list_args(const ephdc_batch* b, const Part& pt) {
 
 namespace ephdc {
 
+// Folded requests among `reqs`: rotate-and-sum on their own workspace (which the finish
+// kernel filled with the summed accumulators), then the output transform.
+static hipError_t rotate_folded(const ephdc_batch* b, const std::vector<uint32_t>& reqs, hipStream_t hs) {
+  hipError_t e = hipSuccess;
+  for (uint32_t ri : reqs) {
+    const ephdc_request& rq = b->reqs[ri];
+    const ephdc_session* s = rq.session;
+    const ParamSet& P = s->P;
+    if (P.r == 1) continue;
+    const uint32_t G = P.G(rq.Q);
+    RotateArgs ra = rotate_args(s, b->rot_ws[ri], G);
+    for (uint32_t i = 0; i < P.log2r() && e == hipSuccess; ++i) e = launch_rotate_step(P.logn, ra, i, hs);
+    if (e == hipSuccess)
+      e = launch_inv_batch(P.logn, ra.acc, rq.d_score_ct, (size_t)G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
   // HDC encoding of every request that brings features, in one launch
   hipError_t e = launch_hdc_encode_list(b->d_hdc, b->d_tiles, (uint32_t)b->tiles.size(), hs);
@@ -471,6 +493,7 @@ hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
     f.pcs = s->d_pc;
     e = launch_finish_list(P.logn, f, hs);
     if (e != hipSuccess) return e;
+    if ((e = rotate_folded(b, sm.reqs, hs)) != hipSuccess) return e;
   }
   for (const Part& pt : b->parts) {
     const int le = batch_le(b, pt.logn);
@@ -491,19 +514,7 @@ hipError_t batch_enqueue(const ephdc_batch* b, hipStream_t hs) {
     }
     e = launch_finish_list(pt.logn, a, hs);
     if (e != hipSuccess) return e;
-    // folded requests: rotate-and-sum on their own workspace, then the output transform
-    for (uint32_t ri : pt.reqs) {
-      const ephdc_request& rq = b->reqs[ri];
-      const ephdc_session* s = rq.session;
-      const ParamSet& P = s->P;
-      if (P.r == 1) continue;
-      const uint32_t G = P.G(rq.Q);
-      RotateArgs ra = rotate_args(s, b->rot_ws[ri], G);
-      for (uint32_t i = 0; i < P.log2r() && e == hipSuccess; ++i) e = launch_rotate_step(P.logn, ra, i, hs);
-      if (e == hipSuccess)
-        e = launch_inv_batch(P.logn, ra.acc, rq.d_score_ct, (size_t)G * 2 * P.L, s->d_inv, s->d_pc, P.L, 0, hs);
-      if (e != hipSuccess) return e;
-    }
+    if ((e = rotate_folded(b, pt.reqs, hs)) != hipSuccess) return e;
   }
   // packing: every request receives the ciphertexts of its session's sequence that hold
   // its queries, all copies in one launch

@@ -329,3 +329,73 @@ def test_subring_batch_encodes_queries_without_touching_padding():
             b.close()
     finally:
         s.close()
+
+
+def test_folded_subring_requests_in_batches():
+    """Folded subring sessions in one batch with an unfolded one: their groups run through the
+    subring models' n-point kernels, the finish kernel leaves the sums in each request's
+    rotation workspace, and rotate-and-sum and the output transform follow per request.
+    Unpacked (queries encoded beforehand), every request's ciphertexts equal the oracle's;
+    packed (queries encoded in the batch), every request decrypts to its exact scores, over
+    two runs of the batch."""
+    torch = torch_cuda()
+    from oracle import hdc as ohdc
+    F = 48
+    shapes = [(4096, 3, 3, 128, 2, 2), (2048, 2, 2, 64, 4, 2), (2048, 2, 5, 64, 1, 0)]  # N, L, K, D, r, dnum
+    tenants = []
+    for k, (N, L, K, D, r, dnum) in enumerate(shapes):
+        if r > 1:
+            o, e = make_fold(N, L, D, K, r, dnum, F=F)
+        else:
+            o, e = make(N, L, D, K, F=F)
+        rng = np.random.default_rng(40 + k)
+        C = values(rng, 8, (K, D))
+        sk = bfv.secret_key(o, 40 + k)
+        model = bfv.encrypt_model(o, sk, C, 40 + k)
+        gk = bfv.galois_keys(o, sk, 50 + k) if r > 1 else None
+        s = ep.Session(e, to_dev(model.astype(np.uint32)), to_dev(gk.astype(np.uint32)) if gk is not None else None,
+                       max_Q=1500)
+        base = synth.base_hypervectors(60 + k, F, D)
+        tenants.append(dict(o=o, e=e, C=C, sk=sk, model=model, gk=gk, s=s, base=base, d_base=to_dev(base)))
+    plan = [(0, 700), (1, 300), (2, 400), (0, 3), (1, 1000), (2, 30)]
+    try:
+        rng = np.random.default_rng(46)
+        hs = [values(rng, 1, (Q, tenants[ti]["o"].D)) for ti, Q in plan]
+        reqs = []
+        for (ti, Q), h in zip(plan, hs):
+            t = tenants[ti]
+            out = torch.zeros((t["s"].num_groups(Q), 2, t["o"].L, t["o"].N), dtype=torch.int32, device="cuda")
+            reqs.append(ep.Request(t["s"], to_dev(hv_layout(h, t["s"].hv_stride(Q))), Q, out))
+        b = ep.Batch(reqs)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+        for k, ((ti, Q), h, r) in enumerate(zip(plan, hs, reqs)):
+            t = tenants[ti]
+            want = pipeline.score_ciphertexts(t["o"], t["model"], h, t["gk"])
+            assert np.array_equal(to_host_u32(r.d_score_ct).astype(np.int64), want), k
+        xs = [synth.uniform_features(70 + k, Q, F) for k, (ti, Q) in enumerate(plan)]
+        preqs = []
+        for (ti, Q), x in zip(plan, xs):
+            t = tenants[ti]
+            out = torch.zeros((t["s"].num_groups(Q) + 1, 2, t["o"].L, t["o"].N), dtype=torch.int32, device="cuda")
+            preqs.append(ep.Request(t["s"], None, Q, out, d_x=to_dev(x), d_base=t["d_base"]))
+        b = ep.Batch(preqs, packed=True)
+        try:
+            for rep in range(2):
+                b.run()
+                torch.cuda.synchronize()
+                for k, ((ti, Q), x, r) in enumerate(zip(plan, xs, preqs)):
+                    t = tenants[ti]
+                    h = ohdc.encode(x, t["base"], t["o"].qbits, t["o"].qshift)
+                    off, qf, nct = b.packing(k)
+                    got = to_host_u32(r.d_score_ct)[:nct]
+                    scores, _ = ep.ephdc_decrypt_scores_at(t["e"], t["sk"].astype(np.int8), got, qf, Q)
+                    assert np.array_equal(scores, ohdc.scores_mod_t(h, t["C"], t["o"].t)), (rep, k)
+        finally:
+            b.close()
+    finally:
+        for t in tenants:
+            t["s"].close()
