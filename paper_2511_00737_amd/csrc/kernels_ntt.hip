@@ -647,7 +647,7 @@ __global__ __launch_bounds__((encode_sub_threads<LOGn, LEs>())) void k_encode_su
   const uint32_t t = a.pct_sub.m, L = a.L;
   const uint32_t N = (uint32_t)n << a.sub_logk;
   // queries of the group (lane*E + i), rows of pitch `stride`
-  const SubGroup sg = a.vg ? a.vg[g] : SubGroup{a.hv + (size_t)g * a.B, a.hv_stride, a.B};
+  const SubGroup sg = a.vg ? a.vg[g] : SubGroup{a.hv + (size_t)g * a.B, a.hv_stride, g + 1 == a.G ? a.q_last : a.B};
   const int8_t* hvg = sg.hv + (uint32_t)lane * E;
   // transformed plaintexts of the chunk: [m - m_base][l][blk][g][y mod ypi]; a lane's E
   // outputs lie in one block (E <= ypi for K' <= 32)

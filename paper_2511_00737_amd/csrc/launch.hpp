@@ -58,6 +58,7 @@ struct ScoreArgs {
   uint32_t sub_logn, sub_logk;
   PrimeConst pct_sub;
   const SubGroup* vg;  // subring kernels: per group its queries (nullptr: hv + g * B, hv_stride)
+  uint32_t q_last;     // without vg: queries in the last group (the others hold B)
 };
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin (workgroup d runs on XCD

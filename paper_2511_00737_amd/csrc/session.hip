@@ -103,6 +103,7 @@ ScoreArgs score_args(const ephdc_session* s, const int8_t* d_hv, uint32_t Q, con
   a.hv_stride = P.G(Q) * P.B();
   a.B = P.B();
   a.G = sc.G;
+  a.q_last = Q ? Q - (P.G(Q) - 1) * P.B() : 0;
   a.S = sc.S;
   a.mchunk = sc.mchunk;
   a.NLG = s->nlg;

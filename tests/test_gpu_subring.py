@@ -399,3 +399,31 @@ def test_folded_subring_requests_in_batches():
     finally:
         for t in tenants:
             t["s"].close()
+
+
+@pytest.mark.parametrize("N,L,K,D,Q,r", [(4096, 3, 3, 37, 700, 1), (2048, 2, 2, 21, 300, 4)])
+def test_single_request_reads_padding_as_zero(N, L, K, D, Q, r):
+    """The n-point batch encoding of a single request reads the positions past Q of its last
+    group as zero: nonzero bytes in the padding columns leave the ciphertexts equal to the
+    oracle's (whose missing queries are zero)."""
+    torch = torch_cuda()
+    o, e = make_fold(N, L, D, K, r, dnum=2) if r > 1 else make(N, L, D, K)
+    rng = np.random.default_rng(N + Q)
+    C = values(rng, 8, (K, D))
+    h = values(rng, 1, (Q, D))
+    sk = bfv.secret_key(o, 8)
+    model = bfv.encrypt_model(o, sk, C, 8)
+    gk = bfv.galois_keys(o, sk, 9) if r > 1 else None
+    s = ep.Session(e, to_dev(model.astype(np.uint32)), to_dev(gk.astype(np.uint32)) if gk is not None else None,
+                   max_Q=Q)
+    try:
+        stride = s.hv_stride(Q)
+        assert stride > Q
+        lay = hv_layout(h, stride).reshape(D, stride).copy()
+        lay[:, Q:] = 55
+        out = torch.empty((s.num_groups(Q), 2, o.L, o.N), dtype=torch.int32, device="cuda")
+        ep.ephdc_score_encrypted(s, to_dev(lay), Q, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(out).astype(np.int64), pipeline.score_ciphertexts(o, model, h, gk))
+    finally:
+        s.close()
