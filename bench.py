@@ -656,27 +656,24 @@ def bench_detect(args, w) -> int:
         ep.ephdc_encode_queries(sess, d_x, d_base, Q, d_hv)
         ep.ephdc_score_encrypted(sess, d_hv, Q, d_out)
 
-    for k in range(max(1, args.warmup)):
+    for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
-    # check this launch configuration: decrypted scores of every window equal h . C mod t
-    hv = d_hv.cpu().numpy()[:, :Q].T.astype(np.float64)
-    scores, _ = ep.ephdc_decrypt_scores(prm, sk, d_out.cpu().numpy().view(np.uint32), Q)
-    want = (hv @ C.astype(np.float64).T).astype(np.int64) % 65537
-    if not np.array_equal(scores, np.where(want > 32768, want - 65537, want)):
-        print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
-        return 3
-    # throughput and latency without the session's kernel timers, then the same steps with
-    # them (and the HOG stage's events) for the per-stage times
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # throughput: the frames back to back between two synchronisations; then the same
+    # frames with an event pair each for the latency percentiles, and again with the
+    # session's kernel timers (and the HOG stage's events) for the per-stage times
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for k in range(args.steps):
         ev[k][0].record(stream)
         step(k)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     sess.profile(True)
     for k in range(args.steps):
@@ -684,6 +681,14 @@ def bench_detect(args, w) -> int:
     torch.cuda.synchronize()
     prof = sess.profile_read()
     sess.profile(False)
+    # check this launch configuration (after the timed passes, which follow the warm-up
+    # directly): decrypted scores of every window of the last frame equal h . C mod t
+    hv = d_hv.cpu().numpy()[:, :Q].T.astype(np.float64)
+    scores, _ = ep.ephdc_decrypt_scores(prm, sk, d_out.cpu().numpy().view(np.uint32), Q)
+    want = (hv @ C.astype(np.float64).T).astype(np.int64) % 65537
+    if not np.array_equal(scores, np.where(want > 32768, want - 65537, want)):
+        print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
+        return 3
     hog_ms = float(np.mean([a.elapsed_time(b) for a, b in hog_ev]))
     hog_bytes = H * W + Q * F  # frame read once, feature rows written once (histograms and blocks are small)
     M = ep.ephdc_num_model_ct(prm)
@@ -854,11 +859,37 @@ def run_single(args, w, layout: str):
         ep.ephdc_encode_queries(sess, d_x, d_base, Q, d_hv)
         ep.ephdc_score_encrypted(sess, d_hv, Q, d_out)
 
-    for _ in range(max(1, args.warmup)):  # at least one run: it is checked below
+    for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # correctness check of this exact launch configuration: decrypted scores of every
-    # query equal the exact integer similarity (mod t) of the device-computed hypervectors
+
+    # throughput: the timed steps back to back between two synchronisations, with nothing
+    # else on the stream (a timing event recorded between two steps stalls the GPU for tens
+    # of microseconds); then the same steps with an event pair each for the latency
+    # percentiles, and again with the session's kernel timers for the per-stage times
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    sess.profile(True)
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = sess.profile_read()
+    sess.profile(False)
+    # correctness check of this exact launch configuration (after the timed passes, so that
+    # the timed steps follow the warm-up directly): decrypted scores of every query of the
+    # last step equal the exact integer similarity (mod t) of the device-computed hypervectors
     out = d_out.cpu().numpy().view(np.uint32)
     hv = d_hv.cpu().numpy()[:, :Q].T.astype(np.float64)
     scores, _ = ep.ephdc_decrypt_scores(prm, sk, out, Q)
@@ -867,26 +898,6 @@ def run_single(args, w, layout: str):
     if not np.array_equal(scores, want):
         print("[bench] decrypted scores differ from h.C mod t", file=sys.stderr)
         return None
-
-    # the timed steps (throughput and latency) run without the session's kernel timers; a
-    # second run of the same steps with them gives the per-kernel times
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        step()
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = np.array([a.elapsed_time(b) for a, b in ev])
-    sess.profile(True)
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    prof = sess.profile_read()
-    sess.profile(False)
     ms_step = wall * 1e3 / args.steps
     value = Q * args.steps / wall
 
