@@ -183,11 +183,15 @@ hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipS
   const KsConst& k = r.k;
   const uint32_t N = 1u << logn;
   const size_t acc_polys = (size_t)k.G * 2 * k.L;
-  // grid shapes below: y counts polynomials (automorphism) and (group, modulus) pairs
-  if (N % 1024 != 0 || acc_polys > 65535u || (size_t)k.G * k.nmod > 65535u) return hipErrorInvalidValue;
-  // R = sigma_g(acc)
-  k_automorph<<<dim3(N / 256, (unsigned)acc_polys), 256, 0, st>>>(r.acc, r.R, r.perm + (size_t)step * N, N);
-  hipError_t e = hipGetLastError();
+  if (N % 1024 != 0) return hipErrorInvalidValue;  // the grids below tile N by 256 and 1024
+  // R = sigma_g(acc); the grid's second dimension counts polynomials, at most kMaxGridY a launch
+  constexpr size_t kMaxGridY = 65535;
+  hipError_t e = hipSuccess;
+  for (size_t p0 = 0; p0 < acc_polys && e == hipSuccess; p0 += kMaxGridY) {
+    const unsigned np = (unsigned)std::min(kMaxGridY, acc_polys - p0);
+    k_automorph<<<dim3(N / 256, np), 256, 0, st>>>(r.acc + p0 * N, r.R + p0 * N, r.perm + (size_t)step * N, N);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return e;
   // D = iNTT(R[g][1][l]) for every group and limb
   BatchMap dmap;
@@ -205,8 +209,15 @@ hipError_t launch_rotate_step(int logn, const RotateArgs& r, uint32_t step, hipS
   if (e != hipSuccess) return e;
   // KS = inner product with the switching keys of this step
   const uint32_t* ksk = r.ksk + (size_t)step * k.dnum * 2 * k.nmod * N;
-  k_ks_inner<<<dim3(N / 1024, k.G * k.nmod), 256, 0, st>>>(r.R, r.Y, ksk, r.KS, k, r.pcs, N);
-  e = hipGetLastError();
+  // groups in launches of at most kMaxGridY (group, modulus) pairs
+  const uint32_t gstep = std::max<uint32_t>(1, (uint32_t)(kMaxGridY / k.nmod));
+  for (uint32_t g0 = 0; g0 < k.G && e == hipSuccess; g0 += gstep) {
+    const uint32_t ng = std::min(gstep, k.G - g0);
+    k_ks_inner<<<dim3(N / 1024, ng * k.nmod), 256, 0, st>>>(
+        r.R + (size_t)g0 * 2 * k.L * N, r.Y + (size_t)g0 * k.dnum * k.nmod * N, ksk, r.KS + (size_t)g0 * 2 * k.nmod * N,
+        k, r.pcs, N);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return e;
   // XP = iNTT of the special limbs of KS
   BatchMap xmap;
