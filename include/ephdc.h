@@ -245,8 +245,8 @@ ephdc_status ephdc_encode_queries(ephdc_session* s, const uint8_t* d_x, const in
 
 /*
  * Homomorphic scoring of Q query hypervectors (d_hv as written by ephdc_encode_queries,
- * stride ephdc_hv_stride(Q); the n-point kernels of subring sessions read the padding
- * columns q >= Q as zero, the other paths read them) against the encrypted model (proposed method, client-side HE:
+ * stride ephdc_hv_stride(Q); the padding columns q >= Q are taken as zero and not read)
+ * against the encrypted model (proposed method, client-side HE:
  * batch encoding of every query element into its own plaintext, D ct x pt products per
  * batch): for every group g of B queries and every model ciphertext m, batch-encode the
  * query plaintext (slot scatter and inverse transform mod t, centred lift), multiply it
@@ -409,8 +409,7 @@ typedef struct {
   const uint8_t* d_x;      /* [Q][F] features to HDC-encode first, or NULL when d_hv holds them */
   const int8_t* d_base;    /* [F][D] base hypervectors (read only with d_x) */
   int8_t* d_hv;            /* [D][ephdc_hv_stride(Q)] query hypervectors; with d_x the batch writes
-                              columns [0, Q) (and the zero padding where its kernels read it:
-                              contiguous-layout sessions) */
+                              columns [0, Q) (the padding columns are read as zero, never read) */
   uint32_t Q;              /* 1 <= Q <= the session's max_Q */
   uint32_t* d_score_ct;    /* out: [G][2][L][N] score ciphertexts, coefficient domain */
 } ephdc_request;

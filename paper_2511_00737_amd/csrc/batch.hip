@@ -175,6 +175,7 @@ void build_part(const ephdc_batch* b, Part& pt) {
     d.r = P.r;
     d.B = P.B();
     d.hv_stride = G * P.B();
+    d.Q = rq.Q;
     d.scale = scale_op(rq.session);
     pt.rd.push_back(d);
     // S near-equal ranges of at most seg_len ciphertexts, none of them empty
@@ -273,10 +274,9 @@ size_t sub_partial_words(const ephdc_batch* b) {
 
 // HDC work and output copies.  Only the counts are needed to place the arrays; the
 // pointers are filled once the batch's block is placed.  With packing, each request writes
-// exactly its own columns [off, off + Q) of its session's buffer (the session's last request
-// also zeroes the padding up to the end of the rows), so the tiles of all requests can run
-// in one launch without overlapping writes.  Requests scored by the subring models write
-// their Q columns only: the n-point batch encoding reads the padding as zero.
+// exactly its own columns [off, off + Q) of its session's buffer, so the tiles of all requests can run
+// in one launch without overlapping writes.  Only the Q columns of a request are written:
+// every batch encoding reads the positions past a group's queries as zero.
 void build_aux(ephdc_batch* b) {
   b->hdc.clear();
   b->tiles.clear();
@@ -306,8 +306,7 @@ void build_aux(ephdc_batch* b) {
       const ephdc_request& v = b->reqs[b->vreq[i]];
       const ParamSet& P = rq.session->P;
       const uint32_t stride = P.G(v.Q) * P.B(), off = b->qoff[i];
-      const bool pad = off + rq.Q == v.Q && !takes_subring(b, v);
-      add(rq, v.d_hv ? v.d_hv + off : nullptr, stride, pad ? stride - off : rq.Q);
+      add(rq, v.d_hv ? v.d_hv + off : nullptr, stride, rq.Q);
       const uint32_t g0 = off / P.B(), g1 = (off + rq.Q - 1) / P.B();
       const size_t ct_words = (size_t)2 * P.L * P.N;
       CopyRange c{v.d_score_ct ? v.d_score_ct + g0 * ct_words : nullptr, rq.d_score_ct, (g1 - g0 + 1) * ct_words};
@@ -319,7 +318,7 @@ void build_aux(ephdc_batch* b) {
       if (!rq.d_x) continue;
       const ParamSet& P = rq.session->P;
       const uint32_t stride = P.G(rq.Q) * P.B();
-      add(rq, rq.d_hv, stride, takes_subring(b, rq) ? rq.Q : stride);
+      add(rq, rq.d_hv, stride, rq.Q);
     }
   }
 }

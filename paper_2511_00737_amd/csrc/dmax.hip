@@ -359,6 +359,7 @@ ephdc_status ephdc_find_dmax(const ephdc_params* prm, uint64_t seed, uint32_t tr
     a.hv_stride = B;
     a.B = B;
     a.G = 1;
+    a.q_last = B;  // the trial's one group is full
     a.m_base = 0;
     a.m_len = d_cap;
     const uint32_t Se = std::min<uint32_t>(d_cap, 512);

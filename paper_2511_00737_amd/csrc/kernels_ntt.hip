@@ -115,22 +115,25 @@ __device__ __forceinline__ uint32_t table_entry(const uint32_t* __restrict__ sca
 struct QuerySrc {
   const int8_t* hvg;
   uint32_t D, r, hv_stride;
+  uint32_t nq;  // queries of the group: later query positions read as zero
 };
 
 // Constants of the plaintext side (mod t).
 using TSide = TSideArgs;
 
 // Per position, from its scatter-table entry: the dimension offset u of the slot feeding it
-// (all ones for an unused slot) and the byte offset of that slot's hv entry inside the
-// group's block at m = 0.
+// (all ones for an unused slot or a query position past the group's queries, which then
+// reads as zero) and the byte offset of that slot's hv entry inside the group's block at
+// m = 0.
 template <int LOGN, int LE>
 __device__ __forceinline__ void scatter_offsets(uint32_t (&du)[1 << LE], uint32_t (&off)[1 << LE],
                                                 const uint32_t (&ent)[1 << LE], const QuerySrc& q) {
 #pragma unroll
   for (int i = 0; i < (1 << LE); ++i) {
     const uint32_t e = ent[i];
-    du[i] = e == 0xFFFFFFFFu ? 0xFFFFFFFFu : e >> 16;
-    off[i] = e == 0xFFFFFFFFu ? 0u : (e >> 16) * q.hv_stride + (e & 0xFFFFu);
+    const bool none = e == 0xFFFFFFFFu || (e & 0xFFFFu) >= q.nq;
+    du[i] = none ? 0xFFFFFFFFu : e >> 16;
+    off[i] = none ? 0u : (e >> 16) * q.hv_stride + (e & 0xFFFFu);
   }
 }
 
@@ -498,7 +501,7 @@ __device__ __forceinline__ void mac_item(const MacItem& it, const int32_t* __res
 __device__ __forceinline__ TSide tside(const ScoreArgs& a) { return TSide{a.inv_t, a.pct}; }
 
 __device__ __forceinline__ QuerySrc query_src(const ScoreArgs& a, uint32_t g) {
-  return QuerySrc{a.hv + (size_t)g * a.B, a.D, a.r, a.hv_stride};
+  return QuerySrc{a.hv + (size_t)g * a.B, a.D, a.r, a.hv_stride, g + 1 == a.G ? a.q_last : a.B};
 }
 
 template <int LOGN, int LG>
@@ -879,7 +882,7 @@ __device__ __forceinline__ void restage(const uint32_t* scatter, const uint32_t*
 }
 
 __device__ __forceinline__ QuerySrc query_src(const ReqDesc& r, uint32_t g) {
-  return QuerySrc{r.hv + (size_t)g * r.B, r.D, r.r, r.hv_stride};
+  return QuerySrc{r.hv + (size_t)g * r.B, r.D, r.r, r.hv_stride, min(r.B, r.Q - g * r.B)};
 }
 
 template <int LOGN, int LE, int LG>

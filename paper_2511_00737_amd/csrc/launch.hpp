@@ -58,7 +58,7 @@ struct ScoreArgs {
   uint32_t sub_logn, sub_logk;
   PrimeConst pct_sub;
   const SubGroup* vg;  // subring kernels: per group its queries (nullptr: hv + g * B, hv_stride)
-  uint32_t q_last;     // without vg: queries in the last group (the others hold B)
+  uint32_t q_last;     // queries in the last group (the others hold B; subring kernels: without vg)
 };
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin (workgroup d runs on XCD
@@ -89,6 +89,7 @@ struct ReqDesc {
   const uint32_t* scatter;  // [N] slot source table of the request's (K, r)
   uint32_t* out;
   uint32_t D, r, B, hv_stride;
+  uint32_t Q;  // queries (the batch encoding reads later positions of the last group as zero)
   ScaleOp scale;
 };
 

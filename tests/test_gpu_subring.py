@@ -275,15 +275,16 @@ def test_folded_subring_at_the_rotation_workload_shape():
     assert np.array_equal(sc, hdc.scores_mod_t(h, C, o.t))
 
 
-def test_subring_batch_encodes_queries_without_touching_padding():
+@pytest.mark.parametrize("layout", ["subring", "contiguous"])
+def test_batch_encodes_queries_without_touching_padding(layout):
     """Batches that encode their queries on the device (HDC in the batch) write only the Q
-    columns of a subring request's hypervectors: the n-point batch encoding reads the other
-    positions of the last group as zero.  Buffers filled with nonzero bytes beforehand still
-    give the oracle's ciphertexts; packed, where the sequence's padding is not written either,
-    every request still decrypts to its own exact scores."""
+    columns of a request's hypervectors: every batch encoding reads the other positions of
+    the last group as zero.  Buffers filled with nonzero bytes beforehand still give the
+    oracle's ciphertexts; packed, where the sequence's padding is not written either, every
+    request still decrypts to its own exact scores."""
     torch = torch_cuda()
     from oracle import hdc as ohdc
-    o, e = make(2048, 2, 64, 3, F=48)  # K' = 4, B = 512 (the encoder takes D % 64 == 0)
+    o, e = make_layout(2048, 2, 64, 3, 1, layout, F=48)  # the encoder takes D % 64 == 0
     rng = np.random.default_rng(14)
     C = values(rng, 8, (o.K, o.D))
     sk = bfv.secret_key(o, 14)
@@ -401,13 +402,26 @@ def test_folded_subring_requests_in_batches():
             t["s"].close()
 
 
-@pytest.mark.parametrize("N,L,K,D,Q,r", [(4096, 3, 3, 37, 700, 1), (2048, 2, 2, 21, 300, 4)])
-def test_single_request_reads_padding_as_zero(N, L, K, D, Q, r):
-    """The n-point batch encoding of a single request reads the positions past Q of its last
-    group as zero: nonzero bytes in the padding columns leave the ciphertexts equal to the
-    oracle's (whose missing queries are zero)."""
+def make_layout(N, L, D, K, r, layout, F=64):
+    primes = default_primes(N, L + (2 if r > 1 else 0))
+    args = dict(N=N, q=tuple(primes[:L]), F=F, D=D, K=K, r=r, layout=layout)
+    if r > 1:
+        args.update(p=tuple(primes[L:]), dnum=2)
+    o = OParams(**args)
+    o.validate()
+    return o, ep.Params(**args)
+
+
+@pytest.mark.parametrize("N,L,K,D,Q,r,layout", [(4096, 3, 3, 37, 700, 1, "subring"), (2048, 2, 2, 21, 300, 4, "subring"),
+                                                (4096, 3, 3, 37, 700, 1, "contiguous"),
+                                                (2048, 2, 2, 21, 300, 4, "contiguous")])
+def test_single_request_reads_padding_as_zero(N, L, K, D, Q, r, layout):
+    """The batch encoding of a single request (n-point kernels of the subring layout, N-point
+    kernels of the contiguous one) reads the positions past Q of its last group as zero:
+    nonzero bytes in the padding columns leave the ciphertexts equal to the oracle's (whose
+    missing queries are zero)."""
     torch = torch_cuda()
-    o, e = make_fold(N, L, D, K, r, dnum=2) if r > 1 else make(N, L, D, K)
+    o, e = make_layout(N, L, D, K, r, layout)
     rng = np.random.default_rng(N + Q)
     C = values(rng, 8, (K, D))
     h = values(rng, 1, (Q, D))
