@@ -409,7 +409,7 @@ typedef struct {
   const uint8_t* d_x;      /* [Q][F] features to HDC-encode first, or NULL when d_hv holds them */
   const int8_t* d_base;    /* [F][D] base hypervectors (read only with d_x) */
   int8_t* d_hv;            /* [D][ephdc_hv_stride(Q)] query hypervectors; with d_x the batch writes
-                              columns [0, Q) (the padding columns are read as zero, never read) */
+                              columns [0, Q) (the padding columns are taken as zero and never read) */
   uint32_t Q;              /* 1 <= Q <= the session's max_Q */
   uint32_t* d_score_ct;    /* out: [G][2][L][N] score ciphertexts, coefficient domain */
 } ephdc_request;
