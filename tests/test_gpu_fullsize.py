@@ -1,8 +1,8 @@
 """The workloads at their full sizes, in the launch configuration the benchmark times,
 checked where the oracle can follow them: the tiny workload word for word; the plain-path
-workload (N = 8192, 4 limbs, F = 2304, D = 4096, K = 7, 4096 queries) with sampled
-hypervectors, its whole last group word for word and every group decrypted against the
-exact integer scores; the rotation and batching workloads as stated at their tests.
+workload (N = 8192, 4 limbs, F = 2304, D = 4096, K = 7, 4096 queries) in both slot layouts
+with sampled hypervectors, its whole last group word for word and every group decrypted
+against the exact integer scores; the rotation and batching workloads as stated at their tests.
 
 The encrypted model comes from the library's host-side encryption (bit-exact with the
 oracle's on the CPU tests); every expected value here is computed by the oracle from it.
@@ -22,11 +22,15 @@ pytestmark = pytest.mark.gpu
 N, L, F, D, K, Q = 8192, 4, 2304, 4096, 7, 4096
 
 
-def test_plain_workload_at_full_size_sampled():
+@pytest.mark.parametrize("layout", ["contiguous", "subring"])
+def test_plain_workload_at_full_size_sampled(layout):
+    """Both slot layouts; the subring session runs the n-point kernels (n = 1024, four full
+    groups of 1024 queries) that the benchmark's headline line times."""
     torch = torch_cuda()
     primes = default_primes(N, L)
-    o = OParams(N=N, q=tuple(primes), F=F, D=D, K=K)
-    e = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K)
+    o = OParams(N=N, q=tuple(primes), F=F, D=D, K=K, layout=layout)
+    o.validate()
+    e = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K, layout=layout)
     sk, _ = ep.ephdc_keygen(e, 0)
     C = synth.class_hypervectors(0, K, D)
     model = ep.ephdc_encrypt_model(e, sk, C, 0)
@@ -52,7 +56,8 @@ def test_plain_workload_at_full_size_sampled():
     qs = np.sort(rng.choice(Q, 48, replace=False))
     assert np.array_equal(h[qs], hdc.encode(x[qs], base))
 
-    # the whole last (ragged) group, every word of both components and all limbs, against
+    # the whole last group (ragged in the contiguous layout), every word of both components
+    # and all limbs, against
     # the oracle's multiply-accumulate over all 4096 model ciphertexts
     mdl = model.astype(np.int64)
     g = G - 1
