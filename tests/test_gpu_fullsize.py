@@ -2,7 +2,8 @@
 checked where the oracle can follow them: the tiny workload word for word; the plain-path
 workload (N = 8192, 4 limbs, F = 2304, D = 4096, K = 7, 4096 queries) in both slot layouts
 with sampled hypervectors, its whole last group word for word and every group decrypted
-against the exact integer scores; the rotation and batching workloads as stated at their tests.
+against the exact integer scores; the rotation and batching workloads, in both slot layouts
+as well, as stated at their tests.
 
 The encrypted model comes from the library's host-side encryption (bit-exact with the
 oracle's on the CPU tests); every expected value here is computed by the oracle from it.
@@ -107,17 +108,20 @@ def test_tiny_workload_at_full_size():
     assert np.array_equal(sc2, scores) and np.array_equal(am2, am)
 
 
-def test_rotation_workload_at_full_size_sampled():
+@pytest.mark.parametrize("layout", ["contiguous", "subring"])
+def test_rotation_workload_at_full_size_sampled(layout):
     """The rotation workload at its full size (N = 16384, 8 limbs + 2 special primes,
-    dnum = 4, r = 8, F = 2304, D = 10240, K = 26, 16384 queries: 211 groups, three
-    rotate-and-sum steps each) in the benchmark's launch configuration: sampled
+    dnum = 4, r = 8, F = 2304, D = 10240, K = 26, 16384 queries: 211 groups in the
+    contiguous layout, 256 of 64 queries in the folded subring layout, three rotate-and-sum
+    steps each) in the benchmark's launch configuration: sampled
     hypervectors against the oracle's encoding, sampled groups decrypted by the oracle,
     and every query's scores equal to the exact integer scores mod t."""
     torch = torch_cuda()
     N, L, alpha, dnum, r, F, D, K, Q = 16384, 8, 2, 4, 8, 2304, 10240, 26, 16384
     primes = default_primes(N, L + alpha)
-    kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum)
+    kw = dict(N=N, q=tuple(primes[:L]), p=tuple(primes[L:]), F=F, D=D, K=K, r=r, dnum=dnum, layout=layout)
     o, e = OParams(**kw), ep.Params(**kw)
+    o.validate()
     sk, gk = ep.ephdc_keygen(e, 0)
     C = synth.class_hypervectors(0, K, D)
     model = ep.ephdc_encrypt_model(e, sk, C, 0)
@@ -156,11 +160,12 @@ def test_rotation_workload_at_full_size_sampled():
     assert np.array_equal(argmax, hdc.argmax(want))
 
 
-def test_batching_workload_at_full_size_sampled():
+@pytest.mark.parametrize("layout", ["contiguous", "subring"])
+def test_batching_workload_at_full_size_sampled(layout):
     """The batching workload at its full size (256 requests of log-uniform sizes on six
-    models, K in {2, 7} x D in {2048, 4096, 10240}, N = 8192, 4 limbs), in the launch
-    configuration the benchmark times: autotuned, graph-captured batches, unpacked and
-    packed. The unpacked batch reproduces every request's single-request ciphertexts bit
+    models, K in {2, 7} x D in {2048, 4096, 10240}, N = 8192, 4 limbs), in both slot layouts
+    and the launch configuration the benchmark times: autotuned, graph-captured batches,
+    unpacked and packed. The unpacked batch reproduces every request's single-request ciphertexts bit
     for bit; every request decrypts (unpacked, and packed at its offset) to the exact
     scores of its hypervectors, which match the oracle's encoding on sampled requests; the
     oracle decrypts sampled requests itself."""
@@ -173,12 +178,12 @@ def test_batching_workload_at_full_size_sampled():
     d_pool = to_dev(pool)
     tenants = []
     for k, (K, D) in enumerate(models):
-        e = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K)
+        e = ep.Params(N=N, q=tuple(primes), F=F, D=D, K=K, layout=layout)
         sk, _ = ep.ephdc_keygen(e, k)
         C = synth.class_hypervectors(k, K, D)
         sess = ep.Session(e, to_dev(ep.ephdc_encrypt_model(e, sk, C, k)), max_Q=4096)
         base = synth.base_hypervectors(0, F, D)
-        tenants.append(dict(e=e, o=OParams(N=N, q=tuple(primes), F=F, D=D, K=K), sk=sk, C=C, s=sess,
+        tenants.append(dict(e=e, o=OParams(N=N, q=tuple(primes), F=F, D=D, K=K, layout=layout), sk=sk, C=C, s=sess,
                             base=base, d_base=to_dev(base)))
     try:
         reqs, offs = [], []
