@@ -141,23 +141,32 @@ def test_admission_by_device_memory(tenants):
 
 def test_packed_serving_gives_each_request_its_scores(tenants):
     """With packing, requests of a tenant share ciphertexts; each request's output holds the
-    ciphertexts with its queries, and decrypting them at its offset gives its own scores."""
+    ciphertexts with its queries, and decrypting them at its offset gives its own scores.
+    The requests are submitted on a caller stream held by a chain of matrix products: the
+    first batches wait for it on both server streams, so the rest queue and later batches
+    take several requests of a tenant, which then share ciphertexts."""
     torch = tenants[0].torch
     rng = np.random.default_rng(77)
+    specs = []
+    for k in range(30):
+        ti = int(rng.integers(0, len(tenants)))
+        Q = int(rng.integers(1, 700))
+        t = tenants[ti]
+        x = synth.uniform_features(1300 + k, Q, F)
+        out = torch.zeros((t.s.num_groups(Q) + 1, 2, t.o.L, t.o.N), dtype=torch.int32, device="cuda")
+        specs.append((ti, Q, x, to_dev(x), out))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
     sv = ep.Server(1 << 30, streams=2, max_batch=16)
     try:
         sv.set_packing(True)
         ids = [sv.add_tenant(t.s, t.d_base) for t in tenants]
-        jobs = []
-        for k in range(30):
-            ti = int(rng.integers(0, len(tenants)))
-            Q = int(rng.integers(1, 700))
-            t = tenants[ti]
-            x = synth.uniform_features(1300 + k, Q, F)
-            out = torch.zeros((t.s.num_groups(Q) + 1, 2, t.o.L, t.o.N), dtype=torch.int32, device="cuda")
-            jobs.append((sv.submit(ids[ti], to_dev(x), Q, out), ti, Q, x, out))
-            if k % 6 == 5:
-                time.sleep(0.002)
+        with torch.cuda.stream(side):
+            big = torch.randn((4096, 4096), device="cuda")
+            for _ in range(16):
+                big = big @ big
+                big = big / big.abs().max()
+            jobs = [(sv.submit(ids[ti], d_x, Q, out, stream=side), ti, Q, x, out) for ti, Q, x, d_x, out in specs]
         sv.wait(0, timeout_s=120)
         assert sv.stats()["completed"] == 30
         shared = 0
